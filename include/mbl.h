@@ -1,0 +1,198 @@
+/*
+ * mbl.h -- C ABI of libmbl, an MI355X (gfx950) shift-invert eigensolver for the
+ * periodic random-field Heisenberg chain
+ *
+ *     H = J sum_{i=1..L} S_i . S_{i+1} + sum_i h_i S^z_i ,   S_{L+1} = S_1,
+ *
+ * (Eq. (1) of Luitz, Laflorencie, Alet, "Many-body localization edge in the
+ * random-field Heisenberg chain", 2014), restricted to the S^z = 0 sector.
+ * For one disorder realization (L, h, seed) and an energy-density target eps
+ * it computes the nev eigenpairs nearest sigma = E_min + eps (E_max - E_min)
+ * with a sparse LU of (H - sigma) driving a Krylov method on (H - sigma)^-1,
+ * and the eigenvector observables (section "Numerical method" and section
+ * "Characterization of ergodic and localized regimes").
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: int status, MBL_OK (0) or a negative MBL_E* code; nothing
+ *     else crosses the ABI on failure (no exceptions).  mbl_strerror() names a
+ *     code; mbl_last_error() gives a message for the last failure on the
+ *     calling thread.
+ *   - Basis order: the S^z = 0 sector is the set of L-bit words with L/2 bits
+ *     set, in ascending integer order; bit i is site i+1, bit set = spin up.
+ *     Every vector of length dim = C(L, L/2) is in this order.
+ *   - Fields: h_i = h (2 u_i - 1), u_i = (z_i >> 11) 2^-53 where z_i is the
+ *     i-th output of SplitMix64 (Steele, Lea, Flood 2014) started from state
+ *     = seed (uniform distribution on [-h, h], the sentence after Eq. (1)).
+ *   - Pointers named *_host are host memory owned by the caller; pointers
+ *     named *_dev are device memory on the context's device, owned by the
+ *     caller.  The library owns all device memory it allocates itself and
+ *     releases it in mbl_destroy().
+ *   - All work runs on the context's HIP stream; calls returning host results
+ *     synchronise that stream before returning.
+ *   - A context is not safe for concurrent calls from several threads except
+ *     for mbl_submit / mbl_poll / mbl_wait, which are.
+ */
+#ifndef MBL_H
+#define MBL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define MBL_OK        0
+#define MBL_EINVAL   -1   /* bad argument: odd or out-of-range L, nev > dim, eps not in [0,1], NULL */
+#define MBL_ENOMEM   -2   /* device allocation failed or footprint above the context budget */
+#define MBL_ENOTCONV -3   /* fewer than nev pairs reached the tolerance; partial results are valid */
+#define MBL_ENUMERIC -4   /* shifted solve could not be refined to the target backward error */
+#define MBL_EDEVICE  -5   /* HIP runtime error */
+#define MBL_EBUSY    -6   /* request queue full */
+#define MBL_ENOTFOUND -7  /* unknown ticket */
+
+#define MBL_L_MAX 22      /* largest even L with a 32-bit sector word and int32 indices */
+
+/* ---- precision of the sparse LU ------------------------------------------ */
+typedef enum {
+    MBL_FP64 = 0,        /* LU factors in FP64 ("plain" shift-invert) */
+    MBL_FP32_IR64 = 1    /* LU factors in FP32 on MFMA, every solve refined in FP64 */
+} mbl_precision;
+
+/* ---- request flags -------------------------------------------------------- */
+#define MBL_WANT_VECTORS  1u  /* copy eigenvectors to result.evecs */
+#define MBL_WANT_OBS      2u  /* compute r, S_1, S_E into result (default on in mbl_problem_init) */
+#define MBL_WANT_OBS_EXTRA 4u /* also S_2, F, f and KL (result.s2, .fluct, .dynfrac, .kl) */
+
+/* One shift-invert eigenproblem (section "Numerical method"). */
+typedef struct {
+    int L;                 /* even, 2 <= L <= MBL_L_MAX */
+    double J;              /* exchange coupling (1.0 in the paper's model); 0 allowed */
+    double h;              /* disorder strength: h_i uniform in [-h, h] */
+    uint64_t seed;         /* SplitMix64 seed of the fields */
+    const double *fields;  /* optional host array[L]; when non-NULL it replaces (h, seed) */
+    double eps;            /* energy-density target in [0, 1]; sigma = E_min + eps (E_max - E_min) */
+    double sigma;          /* NaN: derive from eps; finite: use this shift directly */
+    int nev;               /* eigenpairs wanted, 1 <= nev <= dim */
+    int prec;              /* mbl_precision */
+    double tol;            /* residual target ||H psi - E psi|| <= tol ||H||_2; 0 -> 1e-10 */
+    uint32_t flags;        /* MBL_WANT_* */
+    int block;             /* Krylov block size b (right-hand sides per LU pass); 0 -> default */
+    int ncv;               /* Krylov basis size; 0 -> default from nev and block */
+    int max_restarts;      /* 0 -> default */
+} mbl_problem;
+
+/* Results; every pointer is a caller-owned host buffer or NULL (not wanted). */
+typedef struct {
+    double *evals;         /* [nev] ascending */
+    double *evecs;         /* [nev * dim], eigenvector j at evecs + j*dim (basis order) */
+    double *resid;         /* [nev] ||H psi - E psi||_2 / ||H||_2, FP64 SpMV */
+    double *r;             /* [nev - 2] gap ratios of the consecutive levels (item (i)) */
+    double *s1;            /* [nev] participation entropy S_1 (item (iii)) */
+    double *se;            /* [nev] half-chain entanglement entropy, A = sites 1..L/2 (item (ii)) */
+    double *s2;            /* [nev] participation entropy S_2         (MBL_WANT_OBS_EXTRA) */
+    double *fluct;         /* [nev] bipartite fluctuations of S^z_A  (MBL_WANT_OBS_EXTRA) */
+    double *dynfrac;       /* [nev] dynamical spin fraction f          (MBL_WANT_OBS_EXTRA) */
+    double *kl;            /* [nev - 1] KL divergence of neighbours    (MBL_WANT_OBS_EXTRA) */
+    /* outputs */
+    double emin, emax, sigma, hnorm; /* extremal energies, shift, ||H||_2 = max(|E_min|, |E_max|) */
+    double r_mean;         /* mean of the finite r values */
+    double max_resid;      /* max of resid[] */
+    int nconv;             /* pairs that met tol (== nev on success) */
+    int n_restarts;        /* Krylov restarts */
+    int n_opapply;         /* right-hand sides pushed through the shifted solve */
+    int ir_iters_max;      /* largest number of refinement sweeps of one solve */
+    int n_perturbed;       /* pivots replaced by the static-pivot threshold */
+    int fallback;          /* 0 none; 1 FP32 refinement stalled -> FP64 LU used */
+    double t_phase[8];     /* seconds: 0 assemble, 1 extremal, 2 symbolic, 3 factor,
+                              4 Krylov (solves + orthogonalisation), 5 observables,
+                              6 total, 7 of which shifted solves */
+} mbl_result;
+
+/* Statistics of the per-L symbolic analysis (fill-reducing nested dissection,
+ * assembly tree of dense fronts). */
+typedef struct {
+    int64_t dim, nnz_h;    /* sector dimension, nonzeros of H */
+    int64_t n_fronts, n_levels;
+    int64_t max_front, max_pivots;   /* largest front order m = p + c, largest p */
+    int64_t nnz_factor;    /* entries of L and U (p^2 + 2 p c summed over fronts) */
+    int64_t front_entries; /* sum of m^2 (storage of all dense fronts) */
+    double flops_factor;   /* sum over fronts of (2/3) p^3 + 2 p^2 c + 2 p c^2 (LU) */
+    double seconds;        /* host time of the analysis */
+} mbl_symbolic_info;
+
+/* Diagnostics of one shifted solve. */
+typedef struct {
+    int ir_iters;          /* refinement sweeps of the worst right-hand side */
+    int n_perturbed;       /* perturbed pivots in the factorisation */
+    double backward_error; /* max_k ||b - (H - sigma) x|| / (||H - sigma|| ||x|| + ||b||) */
+    double t_factor, t_solve;
+} mbl_solve_info;
+
+/* ---- context ------------------------------------------------------------- */
+typedef struct mbl_ctx mbl_ctx;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the device
+ * memory the context may hold (0 = 90% of the free memory).  hip_stream is a
+ * hipStream_t to run on (NULL = the context creates its own). */
+int mbl_create(int device, size_t hbm_budget_bytes, void *hip_stream, mbl_ctx **out);
+int mbl_destroy(mbl_ctx *ctx);
+const char *mbl_strerror(int code);
+const char *mbl_last_error(void);
+void mbl_problem_init(mbl_problem *p);   /* defaults: J = 1, sigma = NaN, prec FP64, MBL_WANT_OBS */
+
+/* ---- single steps (parity hooks; each runs the same kernels as mbl_solve) -- */
+int64_t mbl_sector_dim(int L);                                  /* C(L, L/2), or -1 */
+int mbl_fields(int L, double h, uint64_t seed, double *out_host); /* SplitMix64 fields */
+/* Sector words in basis order, enumerated on the device. */
+int mbl_basis(mbl_ctx *ctx, int L, uint32_t *out_host);
+/* Index of each word in the sector (-1 for a word outside it), on the device. */
+int mbl_rank(mbl_ctx *ctx, int L, const uint32_t *words_host, int64_t count, int64_t *ranks_host);
+/* CSR of H assembled on the device: rowptr[dim+1], col[nnz], val[nnz] (diagonal
+ * included, columns ascending).  Any output may be NULL; *nnz_out gets nnz. */
+int mbl_hamiltonian(mbl_ctx *ctx, int L, double J, const double *fields_host,
+                    int32_t *rowptr_host, int32_t *col_host, double *val_host, int64_t *nnz_out);
+/* y = H x for nvec vectors (column-major dim x nvec), FP64, on the device. */
+int mbl_spmv(mbl_ctx *ctx, int L, double J, const double *fields_host, int nvec,
+             const double *x_host, double *y_host);
+/* Extremal eigenvalues by Lanczos on H. */
+int mbl_extremal(mbl_ctx *ctx, int L, double J, const double *fields_host,
+                 double *emin, double *emax);
+/* Fill-reducing ordering and front tree for L (cached in the context). */
+int mbl_symbolic(mbl_ctx *ctx, int L, mbl_symbolic_info *info);
+/* Fill-reducing permutation: perm_host[k] = basis index eliminated k-th. */
+int mbl_ordering(mbl_ctx *ctx, int L, int32_t *perm_host);
+/* x = (H - sigma)^-1 b for nrhs right-hand sides (column-major dim x nrhs):
+ * multifrontal LU of H - sigma in precision prec, then forward/back solves
+ * with FP64 iterative refinement. */
+int mbl_shift_solve(mbl_ctx *ctx, int L, double J, const double *fields_host, double sigma,
+                    int prec, int nrhs, const double *b_host, double *x_host,
+                    mbl_solve_info *info);
+/* Observables of given unit vectors (nev columns of length dim, ascending
+ * energies evals[nev]): r[nev-2], s1[nev], se[nev]; NULL outputs are skipped. */
+int mbl_observables(mbl_ctx *ctx, int L, int nev, const double *evals_host,
+                    const double *evecs_host, double *r_host, double *s1_host, double *se_host);
+/* S_2, F, f, KL of given vectors (the remaining indicators of the paper). */
+int mbl_observables_extra(mbl_ctx *ctx, int L, int nev, const double *evecs_host,
+                          double *s2_host, double *fluct_host, double *dynfrac_host,
+                          double *kl_host);
+
+/* ---- the whole path ------------------------------------------------------ */
+/* Fields -> assembly -> E_min/E_max -> sigma -> LU of H - sigma -> block
+ * Krylov-Schur on (H - sigma)^-1 -> nev pairs nearest sigma -> observables. */
+int mbl_solve(mbl_ctx *ctx, const mbl_problem *prob, mbl_result *res);
+/* Predicted device bytes of one request (factor fronts + Krylov basis + work). */
+int mbl_footprint(mbl_ctx *ctx, int L, int prec, int nev, int block, size_t *bytes);
+
+/* ---- serving: requests of mixed sizes admitted as device memory frees up -- */
+/* The problem and result structs (and the buffers they point to) must stay
+ * valid until mbl_wait returns for the ticket. */
+int mbl_submit(mbl_ctx *ctx, const mbl_problem *prob, mbl_result *res, uint64_t *ticket);
+int mbl_poll(mbl_ctx *ctx, uint64_t ticket, int *done);
+int mbl_wait(mbl_ctx *ctx, uint64_t ticket, int *status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MBL_H */

@@ -66,6 +66,8 @@ def lib():
         L.orc_eigh_full.argtypes = [_l, _pd, _pd, _pd]
         L.orc_nearest_eigenpairs.restype = _i
         L.orc_nearest_eigenpairs.argtypes = [_l, _pd, _d, _d, _l, _pd, _pd, _pd, _pd]
+        L.orc_nearest_eigenpairs_multi.restype = _i
+        L.orc_nearest_eigenpairs_multi.argtypes = [_l, _pd, _l, _pd, _pd, _l, _pd, _pd, _pd, _pd]
         L.orc_gap_ratios.restype = _d
         L.orc_gap_ratios.argtypes = [_l, _pd, _pd]
         L.orc_participation_entropy.restype = _d
@@ -266,3 +268,44 @@ def solve(L: int, h: float, seed: int, eps: float, nev: int, J: float = 1.0,
     if not vectors:
         out.pop("evecs", None)
     return out
+
+
+def solve_targets(L: int, h: float, seed: int, eps_list, nev: int, J: float = 1.0,
+                  fields_in: np.ndarray | None = None, observables: bool = True,
+                  vectors: bool = False):
+    """One realization, several targets from a single dense spectrum (the
+    paper's eps grid per disorder sample).  Returns one dict per target."""
+    f = fields(L, h, seed) if fields_in is None else _f64(fields_in)
+    b = basis(L)
+    n = b.size
+    nev = min(nev, n)
+    A = np.array(dense_H(L, J, f, b), order="F")
+    eps = _f64(eps_list)
+    nt = eps.size
+    sig = np.full(nt, math.nan)
+    ev = np.zeros(nt * nev)
+    Z = np.zeros(nt * nev * n)
+    o3 = np.zeros(3 * nt)
+    rc = lib().orc_nearest_eigenpairs_multi(n, A.ctypes.data_as(_pd), nt, _p(eps), _p(sig), nev,
+                                            _p(ev), _p(Z), None, _p(o3))
+    assert rc == 0
+    del A
+    outs = []
+    for t in range(nt):
+        out = dict(L=L, h=h, seed=seed, eps=float(eps[t]), nev=nev, fields=f,
+                   evals=ev[t * nev:(t + 1) * nev].copy(),
+                   emin=o3[3 * t], emax=o3[3 * t + 1], sigma=o3[3 * t + 2])
+        out["hnorm"] = max(abs(out["emin"]), abs(out["emax"]))
+        Zt = Z[t * nev * n:(t + 1) * nev * n].reshape(nev, n).T
+        out["r"], out["r_mean"] = gap_ratios(out["evals"])
+        if observables:
+            out["s1"] = np.array([participation_entropy(Zt[:, j], 1.0) for j in range(nev)])
+            out["s2"] = np.array([participation_entropy(Zt[:, j], 2.0) for j in range(nev)])
+            out["se"] = np.array([entanglement_entropy(L, Zt[:, j], b) for j in range(nev)])
+            out["fluct"] = np.array([bipartite_fluct(L, Zt[:, j], b) for j in range(nev)])
+            out["dynfrac"] = np.array([dynamical_fraction(L, Zt[:, j], b) for j in range(nev)])
+            out["kl"] = np.array([kl_divergence(Zt[:, j], Zt[:, j + 1]) for j in range(nev - 1)])
+        if vectors:
+            out["evecs"] = np.ascontiguousarray(Zt)
+        outs.append(out)
+    return outs

@@ -451,46 +451,57 @@ static int orc_cmp_pair(const void *a, const void *b)
     return (x->lam > y->lam) - (x->lam < y->lam);
 }
 
-int orc_nearest_eigenpairs(long dim, double *H, double eps, double sigma_in,
-                           long nev, double *evals, double *evecs,
-                           double *all_evals, double *out3)
+int orc_nearest_eigenpairs_multi(long dim, double *H, long nt, const double *eps,
+                                 const double *sigma_in, long nev, double *evals,
+                                 double *evecs, double *all_evals, double *out3)
 {
     double *d = malloc(sizeof(double) * dim), *e = malloc(sizeof(double) * dim);
     double *tau = malloc(sizeof(double) * dim), *w = malloc(sizeof(double) * dim);
+    double *ew = malloc(sizeof(double) * dim);
     orc_pair *pr = malloc(sizeof(orc_pair) * dim);
     int rc = 0;
-    if (dim == 1) { d[0] = H[0]; }
-    else {
-        orc_tridiagonalize(dim, H, d, e, tau, -1);
-    }
+    if (dim == 1) d[0] = H[0];
+    else orc_tridiagonalize(dim, H, d, e, tau, -1);
     memcpy(w, d, sizeof(double) * dim);
-    double *ew = malloc(sizeof(double) * dim);
     memcpy(ew, e, sizeof(double) * dim);
     if (dim > 1) rc = orc_tridiag_qr(dim, w, ew, NULL, 0);
     qsort(w, (size_t)dim, sizeof(double), orc_cmp_double);
     double emin = w[0], emax = w[dim - 1];
-    double sigma = isfinite(sigma_in) ? sigma_in : emin + eps * (emax - emin);
-    for (long i = 0; i < dim; i++) { pr[i].dist = fabs(w[i] - sigma); pr[i].lam = w[i]; }
-    qsort(pr, (size_t)dim, sizeof(orc_pair), orc_cmp_pair);
-    for (long i = 0; i < nev; i++) evals[i] = pr[i].lam;
-    qsort(evals, (size_t)nev, sizeof(double), orc_cmp_double);
     if (all_evals) memcpy(all_evals, w, sizeof(double) * dim);
-    if (out3) { out3[0] = emin; out3[1] = emax; out3[2] = sigma; }
-    if (evecs) {
-        if (dim == 1) evecs[0] = 1.0;
-        else {
-            orc_tridiag_invit(dim, d, e, nev, evals, evecs);
-            orc_backtransform(dim, H, tau, nev, evecs);
-            for (long j = 0; j < nev; j++) {     /* normalise in FP64 */
-                double *z = evecs + j * dim, s = 0.0;
-                for (long i = 0; i < dim; i++) s += z[i] * z[i];
-                s = sqrt(s);
-                for (long i = 0; i < dim; i++) z[i] /= s;
+    for (long t = 0; t < nt; t++) {
+        double sg = sigma_in ? sigma_in[t] : NAN;
+        double sigma = isfinite(sg) ? sg : emin + eps[t] * (emax - emin);
+        double *ev = evals + t * nev;
+        for (long i = 0; i < dim; i++) { pr[i].dist = fabs(w[i] - sigma); pr[i].lam = w[i]; }
+        qsort(pr, (size_t)dim, sizeof(orc_pair), orc_cmp_pair);
+        for (long i = 0; i < nev; i++) ev[i] = pr[i].lam;
+        qsort(ev, (size_t)nev, sizeof(double), orc_cmp_double);
+        if (out3) { out3[3 * t] = emin; out3[3 * t + 1] = emax; out3[3 * t + 2] = sigma; }
+        if (evecs) {
+            double *Z = evecs + t * nev * dim;
+            if (dim == 1) Z[0] = 1.0;
+            else {
+                orc_tridiag_invit(dim, d, e, nev, ev, Z);
+                orc_backtransform(dim, H, tau, nev, Z);
+                for (long j = 0; j < nev; j++) {     /* normalise in FP64 */
+                    double *z = Z + j * dim, s = 0.0;
+                    for (long i = 0; i < dim; i++) s += z[i] * z[i];
+                    s = sqrt(s);
+                    for (long i = 0; i < dim; i++) z[i] /= s;
+                }
             }
         }
     }
     free(d); free(e); free(tau); free(w); free(pr); free(ew);
     return rc;
+}
+
+int orc_nearest_eigenpairs(long dim, double *H, double eps, double sigma_in,
+                           long nev, double *evals, double *evecs,
+                           double *all_evals, double *out3)
+{
+    return orc_nearest_eigenpairs_multi(dim, H, 1, &eps, &sigma_in, nev, evals,
+                                        evecs, all_evals, out3);
 }
 
 /* ------------------------------------------------------------------------ */

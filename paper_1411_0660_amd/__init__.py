@@ -1,0 +1,301 @@
+"""Python binding of libmbl, the MI355X shift-invert eigensolver for the
+random-field Heisenberg chain (Eq. (1) of Luitz, Laflorencie, Alet 2014).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+``libmbl.so`` behind the C ABI declared in ``include/mbl.h``.  The functions
+keep the C names (``mbl_solve``, ``mbl_basis``, ...); :class:`Context` wraps
+a context handle for convenience.  There is no fallback: if the library is
+missing or no GPU is visible the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmbl.so")
+
+MBL_OK, MBL_EINVAL, MBL_ENOMEM, MBL_ENOTCONV = 0, -1, -2, -3
+MBL_ENUMERIC, MBL_EDEVICE, MBL_EBUSY, MBL_ENOTFOUND = -4, -5, -6, -7
+MBL_FP64, MBL_FP32_IR64 = 0, 1
+MBL_WANT_VECTORS, MBL_WANT_OBS, MBL_WANT_OBS_EXTRA = 1, 2, 4
+MBL_L_MAX = 22
+
+# every symbol include/mbl.h declares
+EXPORTS = ("mbl_create", "mbl_destroy", "mbl_strerror", "mbl_last_error", "mbl_problem_init",
+           "mbl_sector_dim", "mbl_fields", "mbl_basis", "mbl_rank", "mbl_hamiltonian",
+           "mbl_spmv", "mbl_extremal", "mbl_symbolic", "mbl_ordering", "mbl_shift_solve",
+           "mbl_observables", "mbl_observables_extra", "mbl_solve", "mbl_footprint",
+           "mbl_submit", "mbl_poll", "mbl_wait")
+
+_d = ctypes.c_double
+_pd = ctypes.POINTER(ctypes.c_double)
+_i64 = ctypes.c_int64
+
+
+class mbl_problem(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int), ("J", _d), ("h", _d), ("seed", ctypes.c_uint64),
+                ("fields", _pd), ("eps", _d), ("sigma", _d), ("nev", ctypes.c_int),
+                ("prec", ctypes.c_int), ("tol", _d), ("flags", ctypes.c_uint32),
+                ("block", ctypes.c_int), ("ncv", ctypes.c_int), ("max_restarts", ctypes.c_int)]
+
+
+class mbl_result(ctypes.Structure):
+    _fields_ = [("evals", _pd), ("evecs", _pd), ("resid", _pd), ("r", _pd), ("s1", _pd),
+                ("se", _pd), ("s2", _pd), ("fluct", _pd), ("dynfrac", _pd), ("kl", _pd),
+                ("emin", _d), ("emax", _d), ("sigma", _d), ("hnorm", _d), ("r_mean", _d),
+                ("max_resid", _d), ("nconv", ctypes.c_int), ("n_restarts", ctypes.c_int),
+                ("n_opapply", ctypes.c_int), ("ir_iters_max", ctypes.c_int),
+                ("n_perturbed", ctypes.c_int), ("fallback", ctypes.c_int),
+                ("t_phase", _d * 8)]
+
+
+class mbl_symbolic_info(ctypes.Structure):
+    _fields_ = [("dim", _i64), ("nnz_h", _i64), ("n_fronts", _i64), ("n_levels", _i64),
+                ("max_front", _i64), ("max_pivots", _i64), ("nnz_factor", _i64),
+                ("front_entries", _i64), ("flops_factor", _d), ("seconds", _d)]
+
+
+class mbl_solve_info(ctypes.Structure):
+    _fields_ = [("ir_iters", ctypes.c_int), ("n_perturbed", ctypes.c_int),
+                ("backward_error", _d), ("t_factor", _d), ("t_solve", _d)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmbl.so (built in-tree by ``paper_1411_0660_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1411_0660_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    L.mbl_create.argtypes = [ctypes.c_int, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.mbl_destroy.argtypes = [vp]
+    L.mbl_strerror.restype = ctypes.c_char_p
+    L.mbl_strerror.argtypes = [ctypes.c_int]
+    L.mbl_last_error.restype = ctypes.c_char_p
+    L.mbl_problem_init.argtypes = [ctypes.POINTER(mbl_problem)]
+    L.mbl_problem_init.restype = None
+    L.mbl_sector_dim.restype = _i64
+    L.mbl_sector_dim.argtypes = [ctypes.c_int]
+    L.mbl_fields.argtypes = [ctypes.c_int, _d, ctypes.c_uint64, _pd]
+    L.mbl_basis.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint32)]
+    L.mbl_rank.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint32), _i64,
+                           ctypes.POINTER(_i64)]
+    L.mbl_hamiltonian.argtypes = [vp, ctypes.c_int, _d, _pd, ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int32), _pd, ctypes.POINTER(_i64)]
+    L.mbl_spmv.argtypes = [vp, ctypes.c_int, _d, _pd, ctypes.c_int, _pd, _pd]
+    L.mbl_extremal.argtypes = [vp, ctypes.c_int, _d, _pd, _pd, _pd]
+    L.mbl_symbolic.argtypes = [vp, ctypes.c_int, ctypes.POINTER(mbl_symbolic_info)]
+    L.mbl_ordering.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]
+    L.mbl_shift_solve.argtypes = [vp, ctypes.c_int, _d, _pd, _d, ctypes.c_int, ctypes.c_int, _pd,
+                                  _pd, ctypes.POINTER(mbl_solve_info)]
+    L.mbl_observables.argtypes = [vp, ctypes.c_int, ctypes.c_int, _pd, _pd, _pd, _pd, _pd]
+    L.mbl_observables_extra.argtypes = [vp, ctypes.c_int, ctypes.c_int, _pd, _pd, _pd, _pd, _pd]
+    L.mbl_solve.argtypes = [vp, ctypes.POINTER(mbl_problem), ctypes.POINTER(mbl_result)]
+    L.mbl_footprint.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                ctypes.POINTER(ctypes.c_size_t)]
+    L.mbl_submit.argtypes = [vp, ctypes.POINTER(mbl_problem), ctypes.POINTER(mbl_result),
+                             ctypes.POINTER(ctypes.c_uint64)]
+    L.mbl_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
+    L.mbl_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
+    _lib = L
+    return L
+
+
+class MblError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = lib().mbl_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {lib().mbl_strerror(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+def _check(code: int, where: str, allow=()):
+    if code != MBL_OK and code not in allow:
+        raise MblError(code, where)
+    return code
+
+
+def _pd_of(a):
+    return None if a is None else a.ctypes.data_as(_pd)
+
+
+# ------------------------------------------------------------------ functions
+def mbl_sector_dim(L: int) -> int:
+    return int(lib().mbl_sector_dim(L))
+
+
+def mbl_fields(L: int, h: float, seed: int) -> np.ndarray:
+    out = np.zeros(L)
+    _check(lib().mbl_fields(L, h, seed, _pd_of(out)), "mbl_fields")
+    return out
+
+
+class Context:
+    """A libmbl context on one HIP device (``mbl_create`` / ``mbl_destroy``)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, stream=None):
+        self._h = ctypes.c_void_p()
+        s = ctypes.c_void_p(stream) if stream else None
+        _check(lib().mbl_create(device, hbm_budget, s, ctypes.byref(self._h)), "mbl_create")
+
+    def close(self):
+        if self._h:
+            lib().mbl_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- single steps
+    def mbl_basis(self, L: int) -> np.ndarray:
+        out = np.zeros(mbl_sector_dim(L), dtype=np.uint32)
+        _check(lib().mbl_basis(self._h, L, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))),
+               "mbl_basis")
+        return out
+
+    def mbl_rank(self, L: int, words) -> np.ndarray:
+        w = np.ascontiguousarray(words, dtype=np.uint32)
+        r = np.zeros(w.size, dtype=np.int64)
+        _check(lib().mbl_rank(self._h, L, w.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), w.size,
+                              r.ctypes.data_as(ctypes.POINTER(_i64))), "mbl_rank")
+        return r
+
+    def mbl_hamiltonian(self, L: int, J: float, fields):
+        f = np.ascontiguousarray(fields, dtype=np.float64)
+        n = mbl_sector_dim(L)
+        nnz = _i64()
+        _check(lib().mbl_hamiltonian(self._h, L, J, _pd_of(f), None, None, None, ctypes.byref(nnz)),
+               "mbl_hamiltonian")
+        rp = np.zeros(n + 1, dtype=np.int32)
+        col = np.zeros(nnz.value, dtype=np.int32)
+        val = np.zeros(nnz.value)
+        _check(lib().mbl_hamiltonian(self._h, L, J, _pd_of(f),
+                                     rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     col.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     _pd_of(val), ctypes.byref(nnz)), "mbl_hamiltonian")
+        return rp, col, val
+
+    def mbl_spmv(self, L: int, J: float, fields, x) -> np.ndarray:
+        f = np.ascontiguousarray(fields, dtype=np.float64)
+        x = np.asfortranarray(x, dtype=np.float64)
+        nvec = 1 if x.ndim == 1 else x.shape[1]
+        y = np.zeros_like(x)
+        _check(lib().mbl_spmv(self._h, L, J, _pd_of(f), nvec, _pd_of(x), _pd_of(y)), "mbl_spmv")
+        return y
+
+    def mbl_extremal(self, L: int, J: float, fields):
+        f = np.ascontiguousarray(fields, dtype=np.float64)
+        a, b = _d(), _d()
+        _check(lib().mbl_extremal(self._h, L, J, _pd_of(f), ctypes.byref(a), ctypes.byref(b)),
+               "mbl_extremal")
+        return a.value, b.value
+
+    def mbl_symbolic(self, L: int) -> dict:
+        info = mbl_symbolic_info()
+        _check(lib().mbl_symbolic(self._h, L, ctypes.byref(info)), "mbl_symbolic")
+        return {k: getattr(info, k) for k, _ in info._fields_}
+
+    def mbl_ordering(self, L: int) -> np.ndarray:
+        out = np.zeros(mbl_sector_dim(L), dtype=np.int32)
+        _check(lib().mbl_ordering(self._h, L, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+               "mbl_ordering")
+        return out
+
+    def mbl_shift_solve(self, L: int, J: float, fields, sigma: float, b, prec: int = MBL_FP64):
+        f = np.ascontiguousarray(fields, dtype=np.float64)
+        b = np.asfortranarray(b, dtype=np.float64)
+        nrhs = 1 if b.ndim == 1 else b.shape[1]
+        x = np.zeros_like(b)
+        info = mbl_solve_info()
+        _check(lib().mbl_shift_solve(self._h, L, J, _pd_of(f), sigma, prec, nrhs, _pd_of(b),
+                                     _pd_of(x), ctypes.byref(info)), "mbl_shift_solve")
+        return x, {k: getattr(info, k) for k, _ in info._fields_}
+
+    def mbl_observables(self, L: int, evals, evecs):
+        Z = np.asfortranarray(evecs, dtype=np.float64)
+        nev = Z.shape[1]
+        E = np.ascontiguousarray(evals, dtype=np.float64)
+        r = np.zeros(max(nev - 2, 1))
+        s1 = np.zeros(nev)
+        se = np.zeros(nev)
+        _check(lib().mbl_observables(self._h, L, nev, _pd_of(E), _pd_of(Z), _pd_of(r), _pd_of(s1),
+                                     _pd_of(se)), "mbl_observables")
+        return r[:max(nev - 2, 0)], s1, se
+
+    def mbl_observables_extra(self, L: int, evecs):
+        Z = np.asfortranarray(evecs, dtype=np.float64)
+        nev = Z.shape[1]
+        s2, fl, df, kl = np.zeros(nev), np.zeros(nev), np.zeros(nev), np.zeros(max(nev - 1, 1))
+        _check(lib().mbl_observables_extra(self._h, L, nev, _pd_of(Z), _pd_of(s2), _pd_of(fl),
+                                           _pd_of(df), _pd_of(kl)), "mbl_observables_extra")
+        return s2, fl, df, kl[:max(nev - 1, 0)]
+
+    # -- whole path
+    def mbl_solve(self, L: int, h: float, seed: int, eps: float, nev: int, *, J: float = 1.0,
+                  prec: int = MBL_FP64, fields=None, sigma: float = math.nan, tol: float = 0.0,
+                  vectors: bool = False, extra: bool = False, block: int = 0, ncv: int = 0,
+                  entanglement: bool = True, allow_notconv: bool = False) -> dict:
+        pr = mbl_problem()
+        lib().mbl_problem_init(ctypes.byref(pr))
+        pr.L, pr.J, pr.h, pr.seed, pr.eps, pr.sigma, pr.nev = L, J, h, seed, eps, sigma, nev
+        pr.prec, pr.tol, pr.block, pr.ncv = prec, tol, block, ncv
+        f = None
+        if fields is not None:
+            f = np.ascontiguousarray(fields, dtype=np.float64)
+            pr.fields = _pd_of(f)
+        pr.flags = MBL_WANT_OBS | (MBL_WANT_VECTORS if vectors else 0) | \
+            (MBL_WANT_OBS_EXTRA if extra else 0)
+        n = mbl_sector_dim(L)
+        bufs = dict(evals=np.zeros(nev), resid=np.zeros(nev), r=np.zeros(max(nev - 2, 1)),
+                    s1=np.zeros(nev))
+        if entanglement:
+            bufs["se"] = np.zeros(nev)
+        if vectors:
+            bufs["evecs"] = np.zeros((nev, n))
+        if extra:
+            bufs.update(s2=np.zeros(nev), fluct=np.zeros(nev), dynfrac=np.zeros(nev),
+                        kl=np.zeros(max(nev - 1, 1)))
+        res = mbl_result()
+        for k, v in bufs.items():
+            setattr(res, k, _pd_of(v))
+        code = lib().mbl_solve(self._h, ctypes.byref(pr), ctypes.byref(res))
+        _check(code, "mbl_solve", allow=(MBL_ENOTCONV,) if allow_notconv else ())
+        out = {k: v for k, v in bufs.items()}
+        out["r"] = out["r"][:max(nev - 2, 0)]
+        if "kl" in out:
+            out["kl"] = out["kl"][:max(nev - 1, 0)]
+        if vectors:
+            out["evecs"] = out["evecs"].T.copy()      # dim x nev
+        for k in ("emin", "emax", "sigma", "hnorm", "r_mean", "max_resid", "nconv", "n_restarts",
+                  "n_opapply", "ir_iters_max", "n_perturbed", "fallback"):
+            out[k] = getattr(res, k)
+        out["t_phase"] = list(res.t_phase)
+        out["status"] = code
+        return out
+
+    def mbl_footprint(self, L: int, prec: int, nev: int, block: int = 0) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().mbl_footprint(self._h, L, prec, nev, block, ctypes.byref(b)), "mbl_footprint")
+        return b.value

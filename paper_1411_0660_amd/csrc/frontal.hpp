@@ -1,0 +1,115 @@
+// frontal.hpp -- device-side descriptors of the multifrontal LU and the
+// launch wrappers of its kernels (factorisation: k_front.hip, solves:
+// k_trsv.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mbl {
+
+// Panel width of the blocked partial LU of every front; also the block size
+// of the triangular solves (the row interchanges of a panel stay inside it).
+constexpr int FNB = 64;
+// Diagonal block of the triangular solves (a multiple of FNB); these blocks of
+// L11 and U11 are stored inverted after the factorisation.
+constexpr int SB = 4 * FNB;
+
+struct FrontDesc {
+    int64_t off;      // first element of the dense m x m front (column-major) in the arena
+    int64_t voff;     // first element of the front's solve vector block (m x nrhs)
+    int32_t m, p;     // order, number of pivots
+    int32_t first;    // new index of the first pivot
+    int32_t cptr;     // offset of the contribution-row list (new indices)
+    int32_t mapoff;   // offset of this front's rows inside its parent (relative map), -1 at roots
+    int32_t parent;
+    int32_t child0, nchild;  // children in FactorTables::child_ids[child0 .. child0 + nchild)
+    int64_t poff;     // offset of the front's U12 partial products in the level scratch
+    int32_t cptr_inv; // offset of the front's inverse relative map (m + 1 row pointers)
+    int32_t pad_;
+};
+
+// A set of fronts processed by one launch and the prefix sums of the work
+// items (tiles, columns, rows) each front contributes.
+struct TaskList {
+    const int32_t *fronts;   // front ids
+    const int64_t *prefix;   // prefix[k] = first work item of fronts[k]; prefix[n] = total
+    int32_t n;
+    int64_t total;
+};
+
+template <class T>
+struct FrontArgs {
+    T *arena;
+    const FrontDesc *fd;
+};
+
+// ---- factorisation ----------------------------------------------------------
+template <class T>
+void launch_front_zero(T *arena, int64_t lo, int64_t hi, hipStream_t s);
+// original entries: F[pos] += (src >= 0 ? diag[src] - sigma : offv)
+template <class T>
+void launch_front_assemble(T *arena, const FrontDesc *fd, int64_t count, const int32_t *efront,
+                           const int32_t *epos, const int32_t *esrc, const double *diag,
+                           double sigma, double offv, hipStream_t s);
+// parent += child contribution block, for one child per parent (list over children)
+template <class T>
+void launch_extend_add(T *arena, const FrontDesc *fd, const int32_t *relmap, TaskList tl,
+                       hipStream_t s);
+// step t of the blocked partial LU on every listed front
+template <class T>
+void launch_panel(T *arena, const FrontDesc *fd, int32_t *ipiv, int32_t *nperturbed, TaskList tl,
+                  int t, double thresh, hipStream_t s);
+template <class T>
+void launch_trsm_u(T *arena, const FrontDesc *fd, const int32_t *ipiv, TaskList tl, int t,
+                   hipStream_t s);
+template <class T>
+void launch_trsm_l(T *arena, const FrontDesc *fd, TaskList tl, int t, hipStream_t s);
+template <class T>
+void launch_schur(T *arena, const FrontDesc *fd, TaskList tl, int t, hipStream_t s);
+
+// tile sizes used by the work-item counts of the task lists
+constexpr int TRSM_U_COLS = 128;   // columns per work item of the U12 solve
+constexpr int TRSM_L_ROWS = 256;   // rows per work item of the L21 solve
+constexpr int SCHUR_TILE = 64;     // square tile of the Schur update
+int64_t schur_tiles(int64_t rest);
+
+template <class T>
+void launch_invert_diag(T *arena, const FrontDesc *fd, const int32_t *ipiv, int32_t *prow,
+                        TaskList tl, hipStream_t s);
+
+// ---- triangular solves (vectors FP64, factors T) ------------------------------
+// forward right-hand side of every listed front, one thread per row:
+// v_f = P([b(pivots); 0] + children's updates), the children's rows found
+// through the inverse relative map (inv_ptr / inv_src = (child, child row))
+void launch_fwd_gather(const FrontDesc *fd, const int32_t *perm, const int32_t *prow,
+                       const int32_t *inv_ptr, const int2 *inv_src, TaskList tl, int nrhs,
+                       const double *b, int64_t ldb, double *vec, hipStream_t s);
+// v_t = Linv_tt v_t (lower) or Uinv_tt v_t (upper) in place, one workgroup per front
+template <class T>
+void launch_diag_apply(const T *arena, const FrontDesc *fd, TaskList tl, int t, int nrhs,
+                       bool lower, double *vec, hipStream_t s);
+// rows below solve block t -= L[rows, t] v_t   (64-row work items)
+template <class T>
+void launch_fwd_update(const T *arena, const FrontDesc *fd, TaskList tl, int t, int nrhs,
+                       double *vec, hipStream_t s);
+// backward: v_f[p:m] = x(contribution rows)
+void launch_bwd_gather(const FrontDesc *fd, const int32_t *contrib, TaskList tl, int nrhs,
+                       const double *xnew, int64_t n, double *vec, hipStream_t s);
+// partial products U12 x_c over 64 x SB tiles, then their fixed-order sum into v_f[0:p]
+template <class T>
+void launch_bwd_u12(const T *arena, const FrontDesc *fd, TaskList tl, int nrhs,
+                    const double *vec, double *part, hipStream_t s);
+void launch_bwd_u12_reduce(const FrontDesc *fd, TaskList tl, int nrhs, double *vec,
+                           const double *part, hipStream_t s);
+// rows above solve block t -= U[rows, t] x_t   (64-row work items)
+template <class T>
+void launch_bwd_update(const T *arena, const FrontDesc *fd, TaskList tl, int t, int nrhs,
+                       double *vec, hipStream_t s);
+// x_new[first..] = v_f[0:p] and x_out[perm[first..]] = v_f[0:p]
+void launch_bwd_scatter(const FrontDesc *fd, const int32_t *perm, TaskList tl, int nrhs,
+                        const double *vec, double *xnew, int64_t n, double *xout, int64_t ldx,
+                        hipStream_t s);
+
+}  // namespace mbl

@@ -1,0 +1,336 @@
+// k_blas.hip -- FP64 sparse matrix-vector products with H and the tall-skinny
+// dense kernels of the Krylov method (projections, block updates) on gfx950.
+//
+// H is stored as its CSR pattern (diagonal included, int32 columns) plus a
+// per-realization FP64 diagonal; every off-diagonal entry of Eq. (1) has the
+// same value (J/2, or J for the doubled bond of L = 2), so it is passed as a
+// scalar instead of streaming a value array.
+//
+// All reductions use a fixed grid and a fixed combination order so results are
+// bitwise reproducible run to run and independent of what else is in flight.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mbl {
+namespace {
+
+constexpr int BS = 256;
+
+inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+__global__ __launch_bounds__(BS) void k_spmv(int64_t n, const int32_t *__restrict__ rowptr,
+                                             const int32_t *__restrict__ col,
+                                             const double *__restrict__ diag, double offv,
+                                             double shift, int nvec, const double *__restrict__ x,
+                                             double *__restrict__ y) {
+    int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (k >= n) return;
+    int32_t a = rowptr[k], e = rowptr[k + 1];
+    double dk = diag[k] - shift;
+    for (int v = 0; v < nvec; v++) {
+        const double *xv = x + (int64_t)v * n;
+        double acc = 0.0;
+        for (int32_t p = a; p < e; p++) {
+            int32_t c = col[p];
+            if (c != k) acc += xv[c];
+        }
+        y[(int64_t)v * n + k] = dk * xv[k] + offv * acc;
+    }
+}
+
+// r = b - (H - shift) x; per-block partial sums of r^2, x^2, b^2 per vector
+__global__ __launch_bounds__(BS) void k_residual(int64_t n, const int32_t *__restrict__ rowptr,
+                                                 const int32_t *__restrict__ col,
+                                                 const double *__restrict__ diag, double offv,
+                                                 double shift, int nvec,
+                                                 const double *__restrict__ b,
+                                                 const double *__restrict__ x,
+                                                 double *__restrict__ r,
+                                                 double *__restrict__ partials) {
+    __shared__ double red[3][BS];
+    for (int v = 0; v < nvec; v++) {
+        const double *xv = x + (int64_t)v * n;
+        const double *bv = b + (int64_t)v * n;
+        double sr = 0.0, sx = 0.0, sb = 0.0;
+        for (int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x; k < n;
+             k += (int64_t)gridDim.x * BS) {
+            int32_t a = rowptr[k], e = rowptr[k + 1];
+            double acc = 0.0;
+            for (int32_t p = a; p < e; p++) {
+                int32_t c = col[p];
+                if (c != k) acc += xv[c];
+            }
+            double xk = xv[k], bk = bv[k];
+            double rk = bk - ((diag[k] - shift) * xk + offv * acc);
+            r[(int64_t)v * n + k] = rk;
+            sr += rk * rk; sx += xk * xk; sb += bk * bk;
+        }
+        red[0][threadIdx.x] = sr; red[1][threadIdx.x] = sx; red[2][threadIdx.x] = sb;
+        __syncthreads();
+        for (int off = BS / 2; off > 0; off >>= 1) {
+            if (threadIdx.x < off)
+                for (int q = 0; q < 3; q++) red[q][threadIdx.x] += red[q][threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x < 3)
+            partials[((int64_t)blockIdx.x * nvec + v) * 3 + threadIdx.x] = red[threadIdx.x][0];
+        __syncthreads();
+    }
+}
+
+// C = A^T B: each block reduces a fixed contiguous row range into k*b partials
+constexpr int TN_ROWS = 32;
+constexpr int TN_MAXACC = 16;  // k*b <= 16 * BS
+
+__global__ __launch_bounds__(BS) void k_gemm_tn_part(int64_t n, int k, int b,
+                                                     const double *__restrict__ A, int64_t lda,
+                                                     const double *__restrict__ B, int64_t ldb,
+                                                     double *__restrict__ partials,
+                                                     int64_t rows_per_part) {
+    extern __shared__ double sm[];
+    double *sA = sm;                   // [TN_ROWS][k]
+    double *sB = sm + TN_ROWS * k;     // [TN_ROWS][b]
+    int64_t r0 = (int64_t)blockIdx.x * rows_per_part;
+    int64_t r1 = r0 + rows_per_part;
+    if (r1 > n) r1 = n;
+    int kb = k * b;
+    double acc[TN_MAXACC];
+#pragma unroll
+    for (int q = 0; q < TN_MAXACC; q++) acc[q] = 0.0;
+    for (int64_t r = r0; r < r1; r += TN_ROWS) {
+        int nr = (int)((r1 - r) < TN_ROWS ? (r1 - r) : TN_ROWS);
+        for (int t = threadIdx.x; t < TN_ROWS * k; t += BS) {
+            int rr = t % TN_ROWS, i = t / TN_ROWS;
+            sA[rr * k + i] = (rr < nr) ? A[r + rr + (int64_t)i * lda] : 0.0;
+        }
+        for (int t = threadIdx.x; t < TN_ROWS * b; t += BS) {
+            int rr = t % TN_ROWS, j = t / TN_ROWS;
+            sB[rr * b + j] = (rr < nr) ? B[r + rr + (int64_t)j * ldb] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < TN_MAXACC; q++) {
+            int o = threadIdx.x + q * BS;
+            if (o < kb) {
+                int i = o % k, j = o / k;
+                double s = 0.0;
+                for (int rr = 0; rr < TN_ROWS; rr++) s += sA[rr * k + i] * sB[rr * b + j];
+                acc[q] += s;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < TN_MAXACC; q++) {
+        int o = threadIdx.x + q * BS;
+        if (o < kb) partials[(int64_t)blockIdx.x * kb + o] = acc[q];
+    }
+}
+
+__global__ void k_sum_parts(int kb, int nparts, const double *__restrict__ partials,
+                            double *__restrict__ C) {
+    int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= kb) return;
+    double s = 0.0;
+    for (int p = 0; p < nparts; p++) s += partials[(int64_t)p * kb + o];
+    C[o] = s;
+}
+
+// C = beta C + alpha A Y for up to 16 output columns per launch
+constexpr int NN_MAXB = 16;
+
+__global__ __launch_bounds__(BS) void k_gemm_nn(int64_t n, int k, int b, double alpha,
+                                                const double *__restrict__ A, int64_t lda,
+                                                const double *__restrict__ Y, int ldy, double beta,
+                                                double *__restrict__ C, int64_t ldc) {
+    extern __shared__ double sY[];    // [k][b]
+    for (int t = threadIdx.x; t < k * b; t += BS) {
+        int i = t % k, j = t / k;
+        sY[i * b + j] = Y[i + (int64_t)j * ldy];
+    }
+    __syncthreads();
+    int64_t row = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (row >= n) return;
+    double acc[NN_MAXB];
+#pragma unroll
+    for (int j = 0; j < NN_MAXB; j++) acc[j] = 0.0;
+    for (int i = 0; i < k; i++) {
+        double a = A[row + (int64_t)i * lda];
+#pragma unroll
+        for (int j = 0; j < NN_MAXB; j++)
+            if (j < b) acc[j] += a * sY[i * b + j];
+    }
+#pragma unroll
+    for (int j = 0; j < NN_MAXB; j++)
+        if (j < b) {
+            double *c = C + row + (int64_t)j * ldc;
+            *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * acc[j];
+        }
+}
+
+__global__ void k_gather(int64_t n, int nvec, const int32_t *__restrict__ idx,
+                         const double *__restrict__ x, double *__restrict__ y) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t s = idx[i];
+    for (int v = 0; v < nvec; v++) y[(int64_t)v * n + i] = x[(int64_t)v * n + s];
+}
+
+// start block: components u - 1/2 with u from SplitMix64 (counter based)
+__global__ void k_fill_start(int64_t n, int nvec, uint64_t seed, double *v) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * nvec) return;
+    uint64_t z = seed + (uint64_t)(e + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    v[e] = (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
+__global__ void k_copy(int64_t count, const double *__restrict__ x, double *__restrict__ y) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) y[i] = x[i];
+}
+
+__global__ void k_axpy(int64_t count, double a, const double *__restrict__ x,
+                       double *__restrict__ y) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) y[i] += a * x[i];
+}
+
+// out[j] = sum_i A[i, j] B[i, j] for j < ncol (partials per block, fixed order)
+__global__ __launch_bounds__(BS) void k_coldot_part(int64_t n, int ncol, const double *__restrict__ A,
+                                                    int64_t lda, const double *__restrict__ B,
+                                                    int64_t ldb, double *__restrict__ part) {
+    __shared__ double red[BS];
+    int j = blockIdx.y;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
+        s += A[i + (int64_t)j * lda] * B[i + (int64_t)j * ldb];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = BS / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ void k_coldot_sum(int ncol, int nparts, const double *__restrict__ part,
+                             double *__restrict__ out) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ncol) return;
+    double s = 0.0;
+    for (int p = 0; p < nparts; p++) s += part[(int64_t)j * nparts + p];
+    out[j] = s;
+}
+
+// Y[:, j] -= e[j] X[:, j]
+__global__ void k_sub_scaled_cols(int64_t n, int ncol, const double *__restrict__ e,
+                                  const double *__restrict__ X, int64_t ldx, double *__restrict__ Y,
+                                  int64_t ldy) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y;
+    if (i < n) Y[i + (int64_t)j * ldy] -= e[j] * X[i + (int64_t)j * ldx];
+}
+
+}  // namespace
+
+void launch_coldot(int64_t n, int ncol, const double *A, int64_t lda, const double *B, int64_t ldb,
+                   double *out, double *partials, int nparts, hipStream_t s) {
+    if (ncol == 0) return;
+    hipLaunchKernelGGL(k_coldot_part, dim3(nparts, ncol), dim3(BS), 0, s, n, ncol, A, lda, B, ldb,
+                       partials);
+    MBL_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_coldot_sum, dim3(grid_for(ncol, 64)), dim3(64), 0, s, ncol, nparts,
+                       partials, out);
+    MBL_CHECK_LAUNCH();
+}
+
+void launch_sub_scaled_cols(int64_t n, int ncol, const double *e, const double *X, int64_t ldx,
+                            double *Y, int64_t ldy, hipStream_t s) {
+    if (ncol == 0 || n == 0) return;
+    hipLaunchKernelGGL(k_sub_scaled_cols, dim3(grid_for(n, 256), ncol), dim3(256), 0, s, n, ncol, e,
+                       X, ldx, Y, ldy);
+    MBL_CHECK_LAUNCH();
+}
+
+void launch_spmv(int64_t n, const int32_t *rowptr, const int32_t *col, const double *diag,
+                 double offv, double shift, int nvec, const double *x, double *y, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_spmv, dim3(grid_for(n, BS)), dim3(BS), 0, s, n, rowptr, col, diag, offv,
+                       shift, nvec, x, y);
+    MBL_CHECK_LAUNCH();
+}
+
+void launch_residual(int64_t n, const int32_t *rowptr, const int32_t *col, const double *diag,
+                     double offv, double shift, int nvec, const double *b, const double *x,
+                     double *r, double *partials, int nparts, hipStream_t s) {
+    hipLaunchKernelGGL(k_residual, dim3(nparts), dim3(BS), 0, s, n, rowptr, col, diag, offv, shift,
+                       nvec, b, x, r, partials);
+    MBL_CHECK_LAUNCH();
+}
+
+int gemm_tn_parts(int64_t n) {
+    int64_t p = (n + 2047) / 2048;      // ~2048 rows per block
+    if (p < 1) p = 1;
+    if (p > 512) p = 512;
+    return (int)p;
+}
+
+void launch_gemm_tn(int64_t n, int k, int b, const double *A, int64_t lda, const double *B,
+                    int64_t ldb, double *C, double *partials, int nparts, hipStream_t s) {
+    MBL_REQUIRE(k * b <= TN_MAXACC * BS, MBL_EINVAL, "gemm_tn: k*b too large");
+    if (k == 0 || b == 0) return;
+    int64_t rpp = (n + nparts - 1) / nparts;
+    rpp = (rpp + TN_ROWS - 1) / TN_ROWS * TN_ROWS;
+    size_t sh = sizeof(double) * TN_ROWS * (size_t)(k + b);
+    hipLaunchKernelGGL(k_gemm_tn_part, dim3(nparts), dim3(BS), sh, s, n, k, b, A, lda, B, ldb,
+                       partials, rpp);
+    MBL_CHECK_LAUNCH();
+    int kb = k * b;
+    hipLaunchKernelGGL(k_sum_parts, dim3(grid_for(kb, 256)), dim3(256), 0, s, kb, nparts, partials,
+                       C);
+    MBL_CHECK_LAUNCH();
+}
+
+void launch_gemm_nn(int64_t n, int k, int b, double alpha, const double *A, int64_t lda,
+                    const double *Y, int ldy, double beta, double *C, int64_t ldc, hipStream_t s) {
+    if (n == 0 || b == 0) return;
+    for (int j0 = 0; j0 < b; j0 += NN_MAXB) {
+        int bb = (b - j0) < NN_MAXB ? (b - j0) : NN_MAXB;
+        size_t sh = sizeof(double) * (size_t)k * bb;
+        MBL_REQUIRE(sh <= 64 * 1024, MBL_EINVAL, "gemm_nn: k too large");
+        hipLaunchKernelGGL(k_gemm_nn, dim3(grid_for(n, BS)), dim3(BS), sh, s, n, k, bb, alpha, A,
+                           lda, Y + (int64_t)j0 * ldy, ldy, beta, C + (int64_t)j0 * ldc, ldc);
+        MBL_CHECK_LAUNCH();
+    }
+}
+
+void launch_gather(int64_t n, int nvec, const int32_t *idx, const double *x, double *y,
+                   hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(n, 256)), dim3(256), 0, s, n, nvec, idx, x, y);
+    MBL_CHECK_LAUNCH();
+}
+
+void launch_fill_start(int64_t n, int nvec, uint64_t seed, double *v, hipStream_t s) {
+    if (n * nvec == 0) return;
+    hipLaunchKernelGGL(k_fill_start, dim3(grid_for(n * nvec, 256)), dim3(256), 0, s, n, nvec, seed,
+                       v);
+    MBL_CHECK_LAUNCH();
+}
+
+void launch_copy(int64_t count, const double *x, double *y, hipStream_t s) {
+    if (count == 0) return;
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(count, 256)), dim3(256), 0, s, count, x, y);
+    MBL_CHECK_LAUNCH();
+}
+
+void launch_axpy(int64_t count, double a, const double *x, double *y, hipStream_t s) {
+    if (count == 0) return;
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(count, 256)), dim3(256), 0, s, count, a, x, y);
+    MBL_CHECK_LAUNCH();
+}
+
+}  // namespace mbl

@@ -1,0 +1,537 @@
+// k_front.hip -- numeric multifrontal LU of H - sigma on gfx950.
+//
+// The paper's shift-invert step rests on a parallel sparse LU of H - E
+// (section "Numerical method").  Here every node of the nested-dissection tree
+// is a dense front F (m x m, column-major, pivots first).  A front is
+// assembled from the original entries of H - sigma and the contribution blocks
+// of its children (extend-add), then partially factored: a right-looking
+// blocked LU over its p pivot columns, panel width FNB.
+//
+// Pivoting: partial pivoting restricted to the FNB x FNB diagonal block of the
+// current panel (rows outside the block are not candidates), with static pivot
+// perturbation |u_jj| < thresh -> +-thresh.  The interchanges are applied to
+// the block and, inside the U12 solve, to the columns right of the panel; the
+// L entries left of the panel are left in place, and the forward solve applies
+// the block permutation after the updates from earlier blocks, which is the
+// same operator (see k_trsv.hip).  FP64 iterative refinement on the host side
+// of each solve absorbs the perturbations.
+//
+// Every launch covers all fronts of one tree level (independent subtrees), so
+// the number of launches grows with the tree height times the panel count of
+// the largest front per level, not with the number of fronts.
+#include "common.hpp"
+#include "frontal.hpp"
+
+namespace mbl {
+namespace {
+
+__device__ __forceinline__ int find_task(const int64_t *prefix, int n, int64_t w) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= w) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <class T>
+__global__ void k_front_zero(T *a, int64_t lo, int64_t hi) {
+    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = T(0);
+}
+
+template <class T>
+__global__ void k_front_assemble(T *arena, const FrontDesc *__restrict__ fd, int64_t count,
+                                 const int32_t *__restrict__ efront,
+                                 const int32_t *__restrict__ epos,
+                                 const int32_t *__restrict__ esrc,
+                                 const double *__restrict__ diag, double sigma, double offv) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    int32_t src = esrc[e];
+    double v = (src >= 0) ? diag[src] - sigma : offv;
+    T *F = arena + fd[efront[e]].off;
+    F[epos[e]] += (T)v;
+}
+
+// one work item = one column of one child's contribution block
+template <class T>
+__global__ __launch_bounds__(256) void k_extend_add(T *arena, const FrontDesc *__restrict__ fd,
+                                                    const int32_t *__restrict__ relmap,
+                                                    TaskList tl) {
+    int k = find_task(tl.prefix, tl.n, blockIdx.x);
+    int ch = tl.fronts[k];
+    int j = (int)(blockIdx.x - tl.prefix[k]);
+    FrontDesc c = fd[ch];
+    FrontDesc P = fd[c.parent];
+    const int32_t *map = relmap + c.mapoff;
+    int cc = c.m - c.p;
+    const T *src = arena + c.off + (int64_t)(c.p + j) * c.m + c.p;
+    T *dst = arena + P.off + (int64_t)map[j] * P.m;
+    for (int i = threadIdx.x; i < cc; i += blockDim.x) dst[map[i]] += src[i];
+}
+
+// LU with partial pivoting of the kb x kb diagonal block of panel t (one
+// workgroup per front, block in LDS)
+template <class T>
+__global__ __launch_bounds__(256) void k_panel(T *arena, const FrontDesc *__restrict__ fd,
+                                               int32_t *__restrict__ ipiv,
+                                               int32_t *__restrict__ nperturbed, TaskList tl,
+                                               int t, double thresh) {
+    __shared__ T D[FNB][FNB + 1];
+    __shared__ int piv[FNB];
+    FrontDesc d = fd[tl.fronts[blockIdx.x]];
+    int k0 = t * FNB;
+    int kb = min(FNB, d.p - k0);
+    int m = d.m;
+    T *F = arena + d.off;
+    for (int e = threadIdx.x; e < FNB * FNB; e += blockDim.x) {
+        int i = e % FNB, j = e / FNB;
+        D[i][j] = (i < kb && j < kb) ? F[(int64_t)(k0 + i) + (int64_t)(k0 + j) * m] : T(0);
+    }
+    __syncthreads();
+    const T th = (T)thresh;
+    for (int j = 0; j < kb; j++) {
+        if (threadIdx.x < 64) {           // wave 0: argmax |D[i][j]|, i in [j, kb)
+            int i = threadIdx.x;
+            T v = (i >= j && i < kb) ? fabs(D[i][j]) : T(-1);
+            int idx = i;
+            for (int off = 32; off > 0; off >>= 1) {
+                T ov = __shfl_xor(v, off);
+                int oi = __shfl_xor(idx, off);
+                if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+            }
+            if (threadIdx.x == 0) piv[j] = idx;
+        }
+        __syncthreads();
+        int r = piv[j];
+        if (r != j)
+            for (int c = threadIdx.x; c < kb; c += blockDim.x) {
+                T a = D[j][c];
+                D[j][c] = D[r][c];
+                D[r][c] = a;
+            }
+        __syncthreads();
+        T pv = D[j][j];
+        bool pert = fabs(pv) < th;
+        if (pert) pv = (pv >= T(0)) ? th : -th;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            D[j][j] = pv;
+            if (pert) atomicAdd(nperturbed, 1);
+        }
+        T rp = T(1) / pv;
+        for (int i = j + 1 + threadIdx.x; i < kb; i += blockDim.x) D[i][j] *= rp;
+        __syncthreads();
+        int w = kb - j - 1;
+        for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
+            int i = j + 1 + e % w, c = j + 1 + e / w;
+            D[i][c] -= D[i][j] * D[j][c];
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
+        int i = e % kb, j = e / kb;
+        F[(int64_t)(k0 + i) + (int64_t)(k0 + j) * m] = D[i][j];
+    }
+    for (int j = threadIdx.x; j < kb; j += blockDim.x) ipiv[d.first + k0 + j] = piv[j];
+}
+
+// Row interchanges of panel t applied to every column outside the panel (the
+// L columns to the left, so that P A = L U holds with one row permutation per
+// front), and U12 of panel t: the permuted block rows right of the panel
+// solved with the unit lower L_tt.  One thread per column.
+template <class T>
+__global__ __launch_bounds__(TRSM_U_COLS) void k_trsm_u(T *arena, const FrontDesc *__restrict__ fd,
+                                                        const int32_t *__restrict__ ipiv,
+                                                        TaskList tl, int t) {
+    __shared__ T Ls[FNB][FNB + 1];
+    __shared__ int src[FNB];
+    int k = find_task(tl.prefix, tl.n, blockIdx.x);
+    FrontDesc d = fd[tl.fronts[k]];
+    int chunk = (int)(blockIdx.x - tl.prefix[k]);
+    int k0 = t * FNB, kb = min(FNB, d.p - k0), k1 = k0 + kb, m = d.m;
+    int nleft = (k0 + TRSM_U_COLS - 1) / TRSM_U_COLS;
+    T *F = arena + d.off;
+    for (int e = threadIdx.x; e < FNB * FNB; e += blockDim.x) {
+        int i = e % FNB, j = e / FNB;
+        Ls[i][j] = (i < kb && j < i) ? F[(int64_t)(k0 + i) + (int64_t)(k0 + j) * m] : T(0);
+    }
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < FNB; i++) src[i] = i;
+        for (int j = 0; j < kb; j++) {
+            int r = ipiv[d.first + k0 + j];
+            int a = src[j]; src[j] = src[r]; src[r] = a;
+        }
+    }
+    __syncthreads();
+    bool left = chunk < nleft;
+    int col = left ? chunk * TRSM_U_COLS + threadIdx.x
+                   : k1 + (chunk - nleft) * TRSM_U_COLS + threadIdx.x;
+    if (col >= (left ? k0 : m)) return;
+    T *Fc = F + (int64_t)col * m + k0;
+    T x[FNB];
+#pragma unroll
+    for (int i = 0; i < FNB; i++) x[i] = (i < kb) ? Fc[src[i]] : T(0);
+    if (!left) {
+#pragma unroll
+        for (int i = 1; i < FNB; i++) {
+            T s = x[i];
+#pragma unroll
+            for (int j = 0; j < i; j++) s -= Ls[i][j] * x[j];
+            x[i] = s;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < FNB; i++)
+        if (i < kb) Fc[i] = x[i];
+}
+
+// In-place inverses of the SB x SB diagonal blocks of L11 (unit lower) and
+// U11 (upper) of every front, after its factorisation, so that each diagonal
+// block of the triangular solves is a dense matrix-vector product instead of
+// a sequential substitution; plus the composite row permutation of the block
+// (prow: final position -> front-local row before the interchanges).
+// Blocked by 32 x 32 sub-blocks:  Linv_ij = -Linv_ii sum_{k=j..i-1} L_ik Linv_kj
+// (i > j, by ascending j), Uinv_ij = -Uinv_ii sum_{k=i+1..j} U_ik Uinv_kj
+// (i < j, by descending j).  Arithmetic in FP64 whatever T is.
+constexpr int ISB = 32;
+
+template <class T>
+__global__ __launch_bounds__(256) void k_invert_diag(T *arena, const FrontDesc *__restrict__ fd,
+                                                     const int32_t *__restrict__ ipiv,
+                                                     int32_t *__restrict__ prow, TaskList tl) {
+    __shared__ double tmp[ISB][ISB + 1];
+    int k = find_task(tl.prefix, tl.n, blockIdx.x);
+    FrontDesc d = fd[tl.fronts[k]];
+    int blk = (int)(blockIdx.x - tl.prefix[k]);
+    int b0 = blk * SB, sz = min(SB, d.p - b0), m = d.m;
+    T *F = arena + d.off + (int64_t)b0 * m + b0;     // block origin, leading dimension m
+    int nsb = (sz + ISB - 1) / ISB;
+    int tid = threadIdx.x;
+    // composite row permutation of the panels inside this block
+    if (tid < SB / FNB) {
+        int q0 = b0 + tid * FNB;
+        if (q0 < d.p) {
+            int kb = min(FNB, d.p - q0);
+            int src[FNB];
+            for (int i = 0; i < FNB; i++) src[i] = i;
+            for (int j = 0; j < kb; j++) {
+                int r = ipiv[d.first + q0 + j];
+                int a = src[j]; src[j] = src[r]; src[r] = a;
+            }
+            for (int i = 0; i < kb; i++) prow[d.first + q0 + i] = q0 + src[i];
+        }
+    }
+    auto at = [&](int r, int c) -> T & { return F[(int64_t)r + (int64_t)c * m]; };
+    // phase 1: diagonal 32 x 32 sub-blocks (thread = sub-block i, column j)
+    {
+        int i = tid / ISB, j = tid % ISB;
+        int r0 = i * ISB, ns = min(ISB, sz - r0);
+        double xl[ISB], xu[ISB];
+        bool act = i < nsb && j < ns;
+        // every read below stays inside the ns x ns sub-block (rows, columns < ns)
+#pragma unroll
+        for (int r = 0; r < ISB; r++) {              // L: unit lower, column j
+            double v = (r == j) ? 1.0 : 0.0;
+            if (act && r < ns && r > j) {
+#pragma unroll
+                for (int q = 0; q < r; q++) v -= (double)at(r0 + r, r0 + q) * xl[q];
+            }
+            xl[r] = (act && r >= j && r < ns) ? v : 0.0;
+        }
+#pragma unroll
+        for (int r = ISB - 1; r >= 0; r--) {         // U: upper, column j
+            double v = 0.0;
+            if (act && r <= j) {
+                v = (r == j) ? 1.0 : 0.0;
+#pragma unroll
+                for (int q = r + 1; q < ISB; q++)
+                    if (q < ns) v -= (double)at(r0 + r, r0 + q) * xu[q];
+                v /= (double)at(r0 + r, r0 + r);
+            }
+            xu[r] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < ISB; r++)
+            if (act && r < ns) at(r0 + r, r0 + j) = (T)(r > j ? xl[r] : xu[r]);
+        __syncthreads();
+    }
+    int tc = tid % ISB, tr = tid / ISB;              // tile coordinates: 8 row groups
+    // phase 2: L off-diagonal sub-blocks
+    for (int i = 1; i < nsb; i++) {
+        int ri = i * ISB, ni = min(ISB, sz - ri);
+        for (int j = 0; j < i; j++) {
+            int cj = j * ISB;
+            // tmp = sum_{k=j}^{i-1} L_ik Linv_kj   (Linv_jj unit lower)
+            for (int q = 0; q < 4; q++) {
+                int r = tr + 8 * q;
+                double acc = 0.0;
+                if (r < ni) {
+                    for (int kk = j; kk < i; kk++) {
+                        int ck = kk * ISB;
+                        for (int c2 = 0; c2 < ISB; c2++) {
+                            int row_k = ck + c2;           // row inside block kk
+                            double lin;                    // Linv_{kk,j}(c2, tc)
+                            if (kk == j) lin = (c2 == tc) ? 1.0 : (c2 > tc ? (double)at(row_k, cj + tc) : 0.0);
+                            else lin = (double)at(row_k, cj + tc);
+                            acc += (double)at(ri + r, ck + c2) * lin;
+                        }
+                    }
+                }
+                tmp[r][tc] = acc;
+            }
+            __syncthreads();
+            // Linv_ij = -Linv_ii tmp
+            double out[4];
+            for (int q = 0; q < 4; q++) {
+                int r = tr + 8 * q;
+                double acc = 0.0;
+                if (r < ni) {
+                    acc = tmp[r][tc];
+                    for (int c2 = 0; c2 < r; c2++) acc += (double)at(ri + r, ri + c2) * tmp[c2][tc];
+                }
+                out[q] = -acc;
+            }
+            __syncthreads();
+            for (int q = 0; q < 4; q++) {
+                int r = tr + 8 * q;
+                if (r < ni) at(ri + r, cj + tc) = (T)out[q];
+            }
+            __syncthreads();
+        }
+    }
+    // phase 3: U off-diagonal sub-blocks
+    for (int i = nsb - 2; i >= 0; i--) {
+        int ri = i * ISB;
+        for (int j = nsb - 1; j > i; j--) {
+            int cj = j * ISB, nj = min(ISB, sz - cj);
+            // tmp = sum_{k=i+1}^{j} U_ik Uinv_kj
+            for (int q = 0; q < 4; q++) {
+                int r = tr + 8 * q;
+                double acc = 0.0;
+                if (tc < nj) {
+                    for (int kk = i + 1; kk <= j; kk++) {
+                        int ck = kk * ISB, nk = min(ISB, sz - ck);
+                        for (int c2 = 0; c2 < nk; c2++) {
+                            double uin;                    // Uinv_{kk,j}(c2, tc)
+                            if (kk == j) uin = (c2 <= tc) ? (double)at(ck + c2, cj + tc) : 0.0;
+                            else uin = (double)at(ck + c2, cj + tc);
+                            acc += (double)at(ri + r, ck + c2) * uin;
+                        }
+                    }
+                }
+                tmp[r][tc] = acc;
+            }
+            __syncthreads();
+            double out[4];
+            for (int q = 0; q < 4; q++) {
+                int r = tr + 8 * q;
+                double acc = 0.0;
+                if (tc < nj)
+                    for (int c2 = r; c2 < ISB; c2++) acc += (double)at(ri + r, ri + c2) * tmp[c2][tc];
+                out[q] = -acc;
+            }
+            __syncthreads();
+            for (int q = 0; q < 4; q++) {
+                int r = tr + 8 * q;
+                if (tc < nj) at(ri + r, cj + tc) = (T)out[q];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// L21 of panel t: every row below the panel times U_tt^-1.  One thread per row.
+template <class T>
+__global__ __launch_bounds__(TRSM_L_ROWS) void k_trsm_l(T *arena, const FrontDesc *__restrict__ fd,
+                                                        TaskList tl, int t) {
+    __shared__ T Us[FNB][FNB + 1];
+    __shared__ T rd[FNB];
+    int k = find_task(tl.prefix, tl.n, blockIdx.x);
+    FrontDesc d = fd[tl.fronts[k]];
+    int chunk = (int)(blockIdx.x - tl.prefix[k]);
+    int k0 = t * FNB, kb = min(FNB, d.p - k0), k1 = k0 + kb, m = d.m;
+    T *F = arena + d.off;
+    for (int e = threadIdx.x; e < FNB * FNB; e += blockDim.x) {
+        int i = e % FNB, j = e / FNB;
+        Us[i][j] = (i < kb && j < kb && i <= j) ? F[(int64_t)(k0 + i) + (int64_t)(k0 + j) * m] : T(0);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < FNB; j += blockDim.x) rd[j] = (j < kb) ? T(1) / Us[j][j] : T(0);
+    __syncthreads();
+    int row = k1 + chunk * TRSM_L_ROWS + threadIdx.x;
+    if (row >= m) return;
+    T *Fr = F + row + (int64_t)k0 * m;
+    T x[FNB];
+#pragma unroll
+    for (int j = 0; j < FNB; j++) x[j] = (j < kb) ? Fr[(int64_t)j * m] : T(0);
+#pragma unroll
+    for (int j = 0; j < FNB; j++) {
+        T s = x[j];
+#pragma unroll
+        for (int i = 0; i < j; i++) s -= x[i] * Us[i][j];
+        x[j] = s * rd[j];
+    }
+#pragma unroll
+    for (int j = 0; j < FNB; j++)
+        if (j < kb) Fr[(int64_t)j * m] = x[j];
+}
+
+// trailing update F[k1:m, k1:m] -= F[k1:m, k0:k1] F[k0:k1, k1:m], 64 x 64 tiles
+template <class T>
+__global__ __launch_bounds__(256) void k_schur(T *arena, const FrontDesc *__restrict__ fd,
+                                               TaskList tl, int t) {
+    __shared__ T As[SCHUR_TILE][FNB + 1];
+    __shared__ T Bs[FNB][SCHUR_TILE];
+    int k = find_task(tl.prefix, tl.n, blockIdx.x);
+    FrontDesc d = fd[tl.fronts[k]];
+    int64_t tile = blockIdx.x - tl.prefix[k];
+    int k0 = t * FNB, kb = min(FNB, d.p - k0), k1 = k0 + kb, m = d.m;
+    int rest = m - k1;
+    int nt = (rest + SCHUR_TILE - 1) / SCHUR_TILE;
+    int ti = (int)(tile % nt), tj = (int)(tile / nt);
+    int r0 = k1 + ti * SCHUR_TILE, c0 = k1 + tj * SCHUR_TILE;
+    T *F = arena + d.off;
+    for (int e = threadIdx.x; e < SCHUR_TILE * FNB; e += blockDim.x) {
+        int i = e % SCHUR_TILE, kk = e / SCHUR_TILE;
+        int r = r0 + i;
+        As[i][kk] = (r < m && kk < kb) ? F[r + (int64_t)(k0 + kk) * m] : T(0);
+    }
+    for (int e = threadIdx.x; e < SCHUR_TILE * FNB; e += blockDim.x) {
+        int kk = e % FNB, j = e / FNB;
+        int c = c0 + j;
+        Bs[kk][j] = (c < m && kk < kb) ? F[(int64_t)(k0 + kk) + (int64_t)c * m] : T(0);
+    }
+    __syncthreads();
+    int tr = threadIdx.x % 16, tc = threadIdx.x / 16;
+    T acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) acc[a][b] = T(0);
+    for (int kk = 0; kk < kb; kk++) {
+        T av[4], bv[4];
+#pragma unroll
+        for (int a = 0; a < 4; a++) av[a] = As[tr + 16 * a][kk];
+#pragma unroll
+        for (int b = 0; b < 4; b++) bv[b] = Bs[kk][tc + 16 * b];
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int b = 0; b < 4; b++) acc[a][b] += av[a] * bv[b];
+    }
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+        int c = c0 + tc + 16 * b;
+        if (c >= m) continue;
+#pragma unroll
+        for (int a = 0; a < 4; a++) {
+            int r = r0 + tr + 16 * a;
+            if (r < m) F[r + (int64_t)c * m] -= acc[a][b];
+        }
+    }
+}
+
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace
+
+int64_t schur_tiles(int64_t rest) {
+    int64_t nt = (rest + SCHUR_TILE - 1) / SCHUR_TILE;
+    return nt * nt;
+}
+
+template <class T>
+void launch_front_zero(T *arena, int64_t lo, int64_t hi, hipStream_t s) {
+    if (hi <= lo) return;
+    int64_t n = hi - lo;
+    unsigned g = cdiv(n, 256 * 8);
+    if (g > 16384) g = 16384;
+    hipLaunchKernelGGL(k_front_zero<T>, dim3(g), dim3(256), 0, s, arena, lo, hi);
+    MBL_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_front_assemble(T *arena, const FrontDesc *fd, int64_t count, const int32_t *efront,
+                           const int32_t *epos, const int32_t *esrc, const double *diag,
+                           double sigma, double offv, hipStream_t s) {
+    if (count == 0) return;
+    hipLaunchKernelGGL(k_front_assemble<T>, dim3(cdiv(count, 256)), dim3(256), 0, s, arena, fd,
+                       count, efront, epos, esrc, diag, sigma, offv);
+    MBL_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_extend_add(T *arena, const FrontDesc *fd, const int32_t *relmap, TaskList tl,
+                       hipStream_t s) {
+    if (tl.total == 0) return;
+    hipLaunchKernelGGL(k_extend_add<T>, dim3((unsigned)tl.total), dim3(256), 0, s, arena, fd,
+                       relmap, tl);
+    MBL_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_panel(T *arena, const FrontDesc *fd, int32_t *ipiv, int32_t *nperturbed, TaskList tl,
+                  int t, double thresh, hipStream_t s) {
+    if (tl.n == 0) return;
+    hipLaunchKernelGGL(k_panel<T>, dim3(tl.n), dim3(256), 0, s, arena, fd, ipiv, nperturbed, tl, t,
+                       thresh);
+    MBL_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_trsm_u(T *arena, const FrontDesc *fd, const int32_t *ipiv, TaskList tl, int t,
+                   hipStream_t s) {
+    if (tl.total == 0) return;
+    hipLaunchKernelGGL(k_trsm_u<T>, dim3((unsigned)tl.total), dim3(TRSM_U_COLS), 0, s, arena, fd,
+                       ipiv, tl, t);
+    MBL_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_invert_diag(T *arena, const FrontDesc *fd, const int32_t *ipiv, int32_t *prow,
+                        TaskList tl, hipStream_t s) {
+    if (tl.total == 0) return;
+    hipLaunchKernelGGL(k_invert_diag<T>, dim3((unsigned)tl.total), dim3(256), 0, s, arena, fd, ipiv,
+                       prow, tl);
+    MBL_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_trsm_l(T *arena, const FrontDesc *fd, TaskList tl, int t, hipStream_t s) {
+    if (tl.total == 0) return;
+    hipLaunchKernelGGL(k_trsm_l<T>, dim3((unsigned)tl.total), dim3(TRSM_L_ROWS), 0, s, arena, fd,
+                       tl, t);
+    MBL_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_schur(T *arena, const FrontDesc *fd, TaskList tl, int t, hipStream_t s) {
+    if (tl.total == 0) return;
+    hipLaunchKernelGGL(k_schur<T>, dim3((unsigned)tl.total), dim3(256), 0, s, arena, fd, tl, t);
+    MBL_CHECK_LAUNCH();
+}
+
+#define MBL_INST_FRONT(T)                                                                       \
+    template void launch_front_zero<T>(T *, int64_t, int64_t, hipStream_t);                    \
+    template void launch_front_assemble<T>(T *, const FrontDesc *, int64_t, const int32_t *,    \
+                                           const int32_t *, const int32_t *, const double *,    \
+                                           double, double, hipStream_t);                        \
+    template void launch_extend_add<T>(T *, const FrontDesc *, const int32_t *, TaskList,       \
+                                       hipStream_t);                                            \
+    template void launch_panel<T>(T *, const FrontDesc *, int32_t *, int32_t *, TaskList, int,  \
+                                  double, hipStream_t);                                         \
+    template void launch_trsm_u<T>(T *, const FrontDesc *, const int32_t *, TaskList, int,      \
+                                   hipStream_t);                                                \
+    template void launch_trsm_l<T>(T *, const FrontDesc *, TaskList, int, hipStream_t);         \
+    template void launch_invert_diag<T>(T *, const FrontDesc *, const int32_t *, int32_t *,      \
+                                        TaskList, hipStream_t);                                  \
+    template void launch_schur<T>(T *, const FrontDesc *, TaskList, int, hipStream_t);
+
+MBL_INST_FRONT(float)
+MBL_INST_FRONT(double)
+
+}  // namespace mbl

@@ -1,0 +1,49 @@
+// kernels.hpp -- host-callable launch wrappers of the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mbl {
+
+// ---- basis, ranking, assembly (k_basis.hip) ---------------------------------
+void launch_fields(int L, double h, uint64_t seed, double *out, hipStream_t s);
+void launch_basis(int L, int64_t dim, uint32_t *basis, hipStream_t s);
+void launch_rank(int L, const uint32_t *words, int64_t count, int64_t *ranks, hipStream_t s);
+// rowptr[dim+1] (exclusive scan of per-row counts); scratch >= scan_scratch_bytes(dim)
+size_t scan_scratch_bytes(int64_t n);
+void launch_row_ptr(int L, int64_t dim, const uint32_t *basis, int32_t *rowptr,
+                    void *scratch, hipStream_t s);
+void launch_fill_csr(int L, int64_t dim, const uint32_t *basis, const int32_t *rowptr,
+                     int32_t *col, hipStream_t s);
+void launch_diag(int L, double J, const double *fields, int64_t dim, const uint32_t *basis,
+                 double *diag, hipStream_t s);
+
+// ---- sparse and dense FP64 level-1/2/3 helpers (k_blas.hip) -----------------
+// y = (H - shift) x for nvec column-major vectors; off-diagonal value offv.
+void launch_spmv(int64_t n, const int32_t *rowptr, const int32_t *col, const double *diag,
+                 double offv, double shift, int nvec, const double *x, double *y, hipStream_t s);
+// r = b - (H - shift) x, plus per-block partial sums of |r|^2, |x|^2, |b|^2
+void launch_residual(int64_t n, const int32_t *rowptr, const int32_t *col, const double *diag,
+                     double offv, double shift, int nvec, const double *b, const double *x,
+                     double *r, double *partials, int nparts, hipStream_t s);
+// C[k x b] = A[n x k]^T B[n x b], deterministic two-level reduction
+void launch_gemm_tn(int64_t n, int k, int b, const double *A, int64_t lda, const double *B,
+                    int64_t ldb, double *C, double *partials, int nparts, hipStream_t s);
+int gemm_tn_parts(int64_t n);
+// C[n x b] = beta C + alpha A[n x k] Y[k x b] (Y in device memory, column-major ldy)
+void launch_gemm_nn(int64_t n, int k, int b, double alpha, const double *A, int64_t lda,
+                    const double *Y, int ldy, double beta, double *C, int64_t ldc, hipStream_t s);
+// x[idx[i]] style permutations for nvec vectors
+void launch_gather(int64_t n, int nvec, const int32_t *idx, const double *x, double *y,
+                   hipStream_t s);
+void launch_fill_start(int64_t n, int nvec, uint64_t seed, double *v, hipStream_t s);
+void launch_copy(int64_t count, const double *x, double *y, hipStream_t s);
+void launch_axpy(int64_t count, double a, const double *x, double *y, hipStream_t s);
+void launch_coldot(int64_t n, int ncol, const double *A, int64_t lda, const double *B, int64_t ldb,
+                   double *out, double *partials, int nparts, hipStream_t s);
+void launch_sub_scaled_cols(int64_t n, int ncol, const double *e, const double *X, int64_t ldx,
+                            double *Y, int64_t ldy, hipStream_t s);
+
+}  // namespace mbl

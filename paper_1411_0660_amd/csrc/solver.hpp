@@ -1,0 +1,133 @@
+// solver.hpp -- per-L plans, the numeric multifrontal factor/solve drivers and
+// the Krylov-Schur eigensolver that sit between the C ABI and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+#include "frontal.hpp"
+#include "obs.hpp"
+#include "symbolic.hpp"
+
+namespace mbl {
+
+struct StepTasks {                    // one panel of the blocked LU
+    TaskList panel, trsm_u, rows_below, schur;
+};
+
+struct LevelTasks {
+    int64_t zlo = 0, zhi = 0;          // arena range of the level's fronts
+    int64_t ebegin = 0, ecount = 0;    // original entries of the level
+    TaskList all;                      // every front, one item each
+    TaskList gather, scatter;          // row chunks
+    std::vector<TaskList> ext;         // extend-add, one list per child slot
+    std::vector<StepTasks> steps;
+    // triangular solves, one list per SB-wide solve block
+    std::vector<TaskList> diag, fupd, bupd;
+    TaskList fgather;                  // forward right-hand sides, 256-row items
+    TaskList u12, u12red;              // U12 x_c tiles and their reduction
+    int64_t part_elems = 0;            // level scratch of the U12 partial products
+};
+
+struct Plan {
+    int L = 0;
+    int64_t dim = 0, nnz = 0;
+    DevBuf basis, rowptr, col;
+    std::vector<int32_t> h_rowptr, h_col;
+    bool have_symbolic = false;
+    FrontTree tree;
+    std::vector<FrontDesc> h_fd;
+    int64_t arena_elems = 0, vec_elems = 0;
+    std::vector<LevelTasks> levels;
+    TaskList inv;                      // SB diagonal blocks of every front (inversion)
+    int64_t part_elems = 0;            // max over levels
+    DevBuf d_fd, d_perm, d_contrib, d_relmap, d_child_ids, d_tfronts, d_tprefix;
+    DevBuf d_efront, d_epos, d_esrc, d_inv_ptr, d_inv_src;
+};
+
+template <class T>
+struct Factor {
+    int L = -1;
+    DevBuf arena, ipiv, prow, npert;
+    bool valid = false;
+    double sigma = 0.0;
+};
+
+struct SolveStats {
+    int ir_iters = 0;
+    int n_perturbed = 0;
+    double backward_error = 0.0;
+    double t_factor = 0.0, t_solve = 0.0;
+    int n_rhs = 0;
+};
+
+class Context {
+  public:
+    Context(int device, size_t budget, hipStream_t stream);
+    ~Context();
+
+    int device;
+    hipStream_t stream;
+    bool own_stream;
+    Budget budget;
+    std::recursive_mutex mu;
+
+    Plan &plan(int L);                 // basis + CSR on the device (cached)
+    void ensure_symbolic(Plan &p);     // ordering + front tables (cached)
+
+    // realization state: fields + diagonal of H on the device
+    void set_realization(Plan &p, double J, const double *fields_host, double h, uint64_t seed,
+                         bool use_seed);
+    double J = 1.0, offv = 0.5;
+    DevBuf d_fields, d_diag;
+    std::vector<double> h_fields;
+
+    void spmv(Plan &p, double shift, int nvec, const double *x, double *y);
+    // extremal eigenvalues by Krylov-Schur on H
+    void extremal(Plan &p, double &emin, double &emax, int &napply);
+
+    // shifted LU + refined solves
+    void factor(Plan &p, int prec, double sigma, double anorm, SolveStats &st);
+    // X = (H - sigma)^-1 B (device, original basis order, ld = dim), refined in FP64
+    void shift_solve(Plan &p, int prec, int nrhs, const double *B, double *X, SolveStats &st);
+
+    // block Krylov-Schur on an operator; Ritz vectors of the nwant selected
+    // values (priority order) land in out (dim x nwant)
+    enum class Want { LargestAbs, BothEnds };
+    struct KSOut {
+        std::vector<double> theta, rho;
+        double tmin = 0.0, tmax = 0.0;   // extreme Ritz values of the last Rayleigh-Ritz
+        int restarts = 0, napply = 0, nconv = 0;
+    };
+    KSOut krylov_schur(int64_t n, int b, int ncv, int nkeep, int nwant, Want want,
+                       const std::function<void(const double *, double *, int)> &op,
+                       const std::function<bool(double, double)> &conv, int max_restarts,
+                       uint64_t seed, double *out);
+
+    ObsWork obs;
+    DevBuf d_psi, d_psi2, d_hpsi, d_e, d_cpart, d_obs, d_r_out, d_se;
+    double anorm_ = 1.0;               // ||H - sigma|| estimate of the current factor
+    double hnorm_ = 1.0;
+
+  private:
+    std::map<int, std::unique_ptr<Plan>> plans_;
+    Factor<float> f32_;
+    Factor<double> f64_;
+    DevBuf d_vec, d_upart, d_xnew, d_r, d_d, d_part, d_V, d_V2, d_W, d_small, d_tnpart;
+    template <class T> void factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel,
+                                     SolveStats &st);
+    template <class T> void lu_apply(Plan &p, Factor<T> &f, int nrhs, const double *b,
+                                     int64_t ldb, double *x, int64_t ldx);
+    template <class T> void refine(Plan &p, Factor<T> &f, int nrhs, const double *B, double *X,
+                                   SolveStats &st);
+};
+
+void solve_problem(Context &ctx, const mbl_problem &prob, mbl_result &res);
+
+}  // namespace mbl

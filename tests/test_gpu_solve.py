@@ -1,0 +1,137 @@
+"""GPU parity of the whole shift-invert path (mbl_solve) against the oracle:
+eigenvalues within 1e-10 ||H||, residuals <= 1e-9 ||H||, r / S_1 / S_E within
+1e-8 where the levels are separated (the readings of the comparison rules are
+listed in the design doc), at sizes the oracle finishes in seconds."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1411_0660_amd as mbl
+
+pytestmark = pytest.mark.gpu
+
+EIG_TOL = 1e-10     # |E_gpu - E_oracle| <= EIG_TOL * ||H||_2
+RES_TOL = 1e-9      # ||H psi - E psi|| <= RES_TOL * ||H||_2
+OBS_TOL = 1e-8      # r, S_1, S_E on eigenpairs separated by >= GAP_MIN ||H||
+GAP_MIN = 1e-6
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = mbl.Context(0)
+    yield c
+    c.close()
+
+
+def compare(g, o, hn, nev, check_vectors=None):
+    E = o["evals"]
+    assert np.abs(g["evals"] - E).max() <= EIG_TOL * hn, np.abs(g["evals"] - E).max() / hn
+    assert g["max_resid"] <= RES_TOL
+    gaps = np.diff(E)
+    sep = np.ones(nev, dtype=bool)              # separated from both neighbours
+    sep[:-1] &= gaps >= GAP_MIN * hn
+    sep[1:] &= gaps >= GAP_MIN * hn
+    for key in ("s1", "se"):
+        d = np.abs(g[key] - o[key])[sep]
+        assert d.max(initial=0.0) <= OBS_TOL, (key, d.max())
+    if nev >= 3:
+        rmask = np.minimum(gaps[:-1], gaps[1:]) >= GAP_MIN * hn
+        d = np.abs(g["r"] - o["r"])[rmask]
+        assert d.max(initial=0.0) <= OBS_TOL
+    if check_vectors is not None:
+        Zg, Zo = check_vectors
+        ov = np.abs(np.sum(Zg * Zo, axis=0))[sep]
+        assert np.all(ov >= 1 - 1e-8)
+
+
+@pytest.mark.parametrize("L,h,seed,eps,nev", [
+    (12, 3.0, 0, 0.5, 20),      # the L = 12 reference configuration
+    (8, 1.0, 1, 0.5, 10),
+    (10, 5.0, 2, 0.1, 16),
+    (10, 0.5, 3, 0.9, 30),
+    (12, 1.0, 4, 0.3, 50),
+    (12, 4.0, 5, 0.7, 7),
+])
+def test_solve_fp64_vs_oracle(ctx, L, h, seed, eps, nev):
+    say("solve", L, h, seed, eps, nev)
+    o = oracle.solve(L, h, seed, eps, nev)
+    g = ctx.mbl_solve(L, h, seed, eps, nev, vectors=True)
+    hn = o["hnorm"]
+    assert abs(g["emin"] - o["emin"]) <= 1e-12 * hn and abs(g["emax"] - o["emax"]) <= 1e-12 * hn
+    assert abs(g["sigma"] - o["sigma"]) <= 1e-12 * hn
+    compare(g, o, hn, nev, check_vectors=(g["evecs"], o["evecs"]))
+
+
+@pytest.mark.parametrize("L,h,seed,eps,nev", [(12, 3.0, 0, 0.5, 20), (12, 2.0, 7, 0.2, 40)])
+def test_solve_fp32_refined_vs_oracle(ctx, L, h, seed, eps, nev):
+    say("solve fp32", L)
+    o = oracle.solve(L, h, seed, eps, nev)
+    g = ctx.mbl_solve(L, h, seed, eps, nev, prec=mbl.MBL_FP32_IR64)
+    compare(g, o, o["hnorm"], nev)
+
+
+@pytest.mark.parametrize("L,nev", [(2, 1), (2, 2), (4, 6), (4, 3), (6, 20)])
+def test_tiny_sectors_full_space(ctx, L, nev):
+    say("tiny", L, nev)
+    o = oracle.solve(L, 2.0, 3, 0.5, nev)
+    g = ctx.mbl_solve(L, 2.0, 3, 0.5, nev)
+    compare(g, o, o["hnorm"], nev)
+
+
+def test_J0_diagonal_limit(ctx):
+    L, nev = 10, 12
+    o = oracle.solve(L, 2.0, 5, 0.5, nev, J=0.0)
+    g = ctx.mbl_solve(L, 2.0, 5, 0.5, nev, J=0.0)
+    assert np.abs(g["evals"] - o["evals"]).max() <= 1e-12 * o["hnorm"]
+    assert np.allclose(g["s1"], 0.0, atol=1e-10) and np.allclose(g["se"], 0.0, atol=1e-10)
+
+
+@pytest.mark.parametrize("eps", [0.0, 1.0])
+def test_spectrum_edges(ctx, eps):
+    o = oracle.solve(10, 3.0, 1, eps, 8)
+    g = ctx.mbl_solve(10, 3.0, 1, eps, 8)
+    compare(g, o, o["hnorm"], 8)
+
+
+def test_explicit_sigma_and_fields(ctx):
+    L = 10
+    f = np.linspace(-1, 1, L)
+    o = oracle.solve(L, 0.0, 0, 0.5, 9, fields_in=f, sigma=0.25)
+    g = ctx.mbl_solve(L, 0.0, 0, 0.5, 9, fields=f, sigma=0.25)
+    compare(g, o, o["hnorm"], 9)
+
+
+def test_extra_observables_vs_oracle(ctx):
+    L, nev = 12, 12
+    o = oracle.solve(L, 2.5, 8, 0.5, nev)
+    g = ctx.mbl_solve(L, 2.5, 8, 0.5, nev, extra=True)
+    gaps = np.diff(o["evals"])
+    sep = np.ones(nev, dtype=bool)
+    sep[:-1] &= gaps >= GAP_MIN * o["hnorm"]
+    sep[1:] &= gaps >= GAP_MIN * o["hnorm"]
+    for key in ("s2", "fluct", "dynfrac"):
+        assert np.abs(g[key] - o[key])[sep].max() <= OBS_TOL, key
+    ksep = sep[:-1] & sep[1:]
+    assert np.abs(g["kl"] - o["kl"])[ksep].max() <= 1e-7
+
+
+@pytest.mark.parametrize("bad", [dict(L=11), dict(L=24), dict(nev=0), dict(nev=253), dict(eps=1.5)])
+def test_invalid_arguments(ctx, bad):
+    args = dict(L=8, h=1.0, seed=0, eps=0.5, nev=5)
+    args.update(bad)
+    with pytest.raises(mbl.MblError) as ei:
+        ctx.mbl_solve(args["L"], args["h"], args["seed"], args["eps"], args["nev"])
+    assert ei.value.code == mbl.MBL_EINVAL
+
+
+def test_bitwise_reproducible(ctx):
+    a = ctx.mbl_solve(12, 3.0, 11, 0.5, 20)
+    b = ctx.mbl_solve(12, 3.0, 11, 0.5, 20)
+    assert np.array_equal(a["evals"], b["evals"]) and np.array_equal(a["se"], b["se"])
