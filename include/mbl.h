@@ -185,6 +185,23 @@ int mbl_solve(mbl_ctx *ctx, const mbl_problem *prob, mbl_result *res);
 /* Predicted device bytes of one request (factor fronts + Krylov basis + work). */
 int mbl_footprint(mbl_ctx *ctx, int L, int prec, int nev, int block, size_t *bytes);
 
+/* ---- measurement ---------------------------------------------------------- */
+/* Per-launch timing of one kernel class with HIP events on the context's
+ * stream, plus the algorithmic bytes and flops of the timed launches (what the
+ * method must move or compute, not what the hardware counters report).
+ * Classes: "schur" (trailing update of the frontal LU), "fwd_update",
+ * "bwd_update", "diag" (diagonal-block products of the solves), "spmv". */
+typedef struct {
+    int64_t launches;      /* launches timed since mbl_profile_enable */
+    double seconds;        /* sum of their durations */
+    double bytes;          /* algorithmic HBM bytes of those launches */
+    double flops;          /* algorithmic flops of those launches */
+} mbl_kernel_profile;
+/* Start timing `kernel_class` (NULL or "" stops timing); clears the counters. */
+int mbl_profile_enable(mbl_ctx *ctx, const char *kernel_class);
+/* Synchronises the stream and returns the counters. */
+int mbl_profile_read(mbl_ctx *ctx, mbl_kernel_profile *out);
+
 /* ---- serving: requests of mixed sizes admitted as device memory frees up -- */
 /* The problem and result structs (and the buffers they point to) must stay
  * valid until mbl_wait returns for the ticket. */

@@ -29,7 +29,7 @@ EXPORTS = ("mbl_create", "mbl_destroy", "mbl_strerror", "mbl_last_error", "mbl_p
            "mbl_sector_dim", "mbl_fields", "mbl_basis", "mbl_rank", "mbl_hamiltonian",
            "mbl_spmv", "mbl_extremal", "mbl_symbolic", "mbl_ordering", "mbl_shift_solve",
            "mbl_observables", "mbl_observables_extra", "mbl_solve", "mbl_footprint",
-           "mbl_submit", "mbl_poll", "mbl_wait")
+           "mbl_submit", "mbl_poll", "mbl_wait", "mbl_profile_enable", "mbl_profile_read")
 
 _d = ctypes.c_double
 _pd = ctypes.POINTER(ctypes.c_double)
@@ -57,6 +57,10 @@ class mbl_symbolic_info(ctypes.Structure):
     _fields_ = [("dim", _i64), ("nnz_h", _i64), ("n_fronts", _i64), ("n_levels", _i64),
                 ("max_front", _i64), ("max_pivots", _i64), ("nnz_factor", _i64),
                 ("front_entries", _i64), ("flops_factor", _d), ("seconds", _d)]
+
+
+class mbl_kernel_profile(ctypes.Structure):
+    _fields_ = [("launches", _i64), ("seconds", _d), ("bytes", _d), ("flops", _d)]
 
 
 class mbl_solve_info(ctypes.Structure):
@@ -107,6 +111,8 @@ def lib() -> ctypes.CDLL:
                              ctypes.POINTER(ctypes.c_uint64)]
     L.mbl_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
     L.mbl_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
+    L.mbl_profile_enable.argtypes = [vp, ctypes.c_char_p]
+    L.mbl_profile_read.argtypes = [vp, ctypes.POINTER(mbl_kernel_profile)]
     _lib = L
     return L
 
@@ -294,6 +300,15 @@ class Context:
         out["t_phase"] = list(res.t_phase)
         out["status"] = code
         return out
+
+    def mbl_profile_enable(self, kernel_class: str | None):
+        _check(lib().mbl_profile_enable(self._h, kernel_class.encode() if kernel_class else None),
+               "mbl_profile_enable")
+
+    def mbl_profile_read(self) -> dict:
+        p = mbl_kernel_profile()
+        _check(lib().mbl_profile_read(self._h, ctypes.byref(p)), "mbl_profile_read")
+        return {k: getattr(p, k) for k, _ in p._fields_}
 
     def mbl_footprint(self, L: int, prec: int, nev: int, block: int = 0) -> int:
         b = ctypes.c_size_t()

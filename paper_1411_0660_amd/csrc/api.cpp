@@ -373,6 +373,31 @@ int mbl_footprint(mbl_ctx *ctx, int L, int prec, int nev, int block, size_t *byt
     });
 }
 
+int mbl_profile_enable(mbl_ctx *ctx, const char *kernel_class) {
+    if (!ctx) return MBL_EINVAL;
+    return guarded([&] {
+        std::lock_guard<std::recursive_mutex> lk(ctx->c->mu);
+        Context &c = *ctx->c;
+        c.prof_collect();
+        c.prof.cls = kernel_class ? kernel_class : "";
+        c.prof.launches = 0;
+        c.prof.bytes = c.prof.flops = c.prof.seconds = 0.0;
+    });
+}
+
+int mbl_profile_read(mbl_ctx *ctx, mbl_kernel_profile *out) {
+    if (!ctx || !out) return MBL_EINVAL;
+    return guarded([&] {
+        std::lock_guard<std::recursive_mutex> lk(ctx->c->mu);
+        Context &c = *ctx->c;
+        c.prof_collect();
+        out->launches = c.prof.launches;
+        out->seconds = c.prof.seconds;
+        out->bytes = c.prof.bytes;
+        out->flops = c.prof.flops;
+    });
+}
+
 int mbl_submit(mbl_ctx *ctx, const mbl_problem *prob, mbl_result *res, uint64_t *ticket) {
     if (!ctx || !prob || !res || !ticket) return MBL_EINVAL;
     return guarded([&] {

@@ -37,6 +37,9 @@ struct TaskList {
     const int64_t *prefix;   // prefix[k] = first work item of fronts[k]; prefix[n] = total
     int32_t n;
     int64_t total;
+    double elems;            // factor entries the launch streams (algorithmic)
+    double rows;             // vector rows it reads and writes (per right-hand side)
+    double flops;            // multiply-adds x 2 (Schur update)
 };
 
 template <class T>

@@ -66,8 +66,39 @@ Context::Context(int dev, size_t budget_bytes, hipStream_t s) : device(dev) {
 
 Context::~Context() {
     (void)hipStreamSynchronize(stream);
+    for (auto &e : prof.pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     plans_.clear();
     if (own_stream) (void)hipStreamDestroy(stream);
+}
+
+void Context::prof_begin() {
+    if (prof.used == prof.pool.size()) {
+        hipEvent_t a, b;
+        MBL_HIP(hipEventCreate(&a));
+        MBL_HIP(hipEventCreate(&b));
+        prof.pool.push_back({a, b});
+    }
+    MBL_HIP(hipEventRecord(prof.pool[prof.used].first, stream));
+}
+
+void Context::prof_end(double bytes, double flops) {
+    MBL_HIP(hipEventRecord(prof.pool[prof.used].second, stream));
+    prof.used++;
+    prof.launches++;
+    prof.bytes += bytes;
+    prof.flops += flops;
+    if (prof.used >= 4096) prof_collect();
+}
+
+void Context::prof_collect() {
+    if (prof.used == 0) return;
+    MBL_HIP(hipStreamSynchronize(stream));
+    for (size_t i = 0; i < prof.used; i++) {
+        float ms = 0.0f;
+        MBL_HIP(hipEventElapsedTime(&ms, prof.pool[i].first, prof.pool[i].second));
+        prof.seconds += 1e-3 * (double)ms;
+    }
+    prof.used = 0;
 }
 
 Plan &Context::plan(int L) {
@@ -301,6 +332,12 @@ void Context::ensure_symbolic(Plan &p) {
             tb.add(S.trsm_u, act, tu);
             tb.add(S.rows_below, act, rb);
             tb.add(S.schur, act, sh);
+            for (int f : act) {
+                const FrontDesc &d = p.h_fd[f];
+                double k0 = st * FNB, kb = std::min(FNB, d.p - st * FNB), rest = d.m - k0 - kb;
+                S.schur.flops += 2.0 * rest * rest * kb;
+                S.schur.elems += 2.0 * rest * rest + 2.0 * rest * kb;   // C read + write, A, B
+            }
         }
         {
             std::vector<int64_t> gi;
@@ -325,6 +362,14 @@ void Context::ensure_symbolic(Plan &p) {
             tb.add(lv.diag[st], da, di);
             tb.add(lv.fupd[st], fa, fi);
             tb.add(lv.bupd[st], ba, bi);
+            for (int f : da) {
+                const FrontDesc &d = p.h_fd[f];
+                double t0 = st * SB, sw = std::min(SB, d.p - st * SB), tend = t0 + sw;
+                lv.diag[st].elems += 0.5 * sw * (sw + 1);
+                lv.diag[st].rows += sw;
+                if (d.m > tend) { lv.fupd[st].elems += (d.m - tend) * sw; lv.fupd[st].rows += d.m - tend; }
+                if (st >= 1) { lv.bupd[st].elems += t0 * sw; lv.bupd[st].rows += t0; }
+            }
         }
     }
     // upload
@@ -382,8 +427,13 @@ void Context::set_realization(Plan &p, double J_, const double *fields_host, dou
 }
 
 void Context::spmv(Plan &p, double shift, int nvec, const double *x, double *y) {
+    bool pr = prof_on("spmv");
+    if (pr) prof_begin();
     launch_spmv(p.dim, p.rowptr.ptr<int32_t>(), p.col.ptr<int32_t>(), d_diag.ptr<double>(), offv,
                 shift, nvec, x, y, stream);
+    // per vector: columns (4 B/nnz), rowptr, diagonal, x gathered, y written
+    if (pr) prof_end(4.0 * p.nnz + 4.0 * p.dim + 8.0 * p.dim + nvec * 16.0 * p.dim,
+                     2.0 * nvec * (double)p.nnz);
 }
 
 // ---------------------------------------------------------------- factor
@@ -418,7 +468,10 @@ void Context::factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel, S
                             S.panel, (int)t, thresh, s);
             launch_trsm_u<T>(A, fd, f.ipiv.template ptr<int32_t>(), S.trsm_u, (int)t, s);
             launch_trsm_l<T>(A, fd, S.rows_below, (int)t, s);
+            bool pr = prof_on("schur") && S.schur.total > 0;
+            if (pr) prof_begin();
             launch_schur<T>(A, fd, S.schur, (int)t, s);
+            if (pr) prof_end(S.schur.elems * sizeof(T), S.schur.flops);
         }
     }
     launch_invert_diag<T>(A, fd, f.ipiv.template ptr<int32_t>(), f.prow.template ptr<int32_t>(),
@@ -457,8 +510,15 @@ void Context::lu_apply(Plan &p, Factor<T> &f, int nrhs, const double *b, int64_t
         launch_fwd_gather(fd, p.d_perm.ptr<int32_t>(), f.prow.template ptr<int32_t>(),
                           p.d_inv_ptr.ptr<int32_t>(), isrc, lv.fgather, nrhs, b, ldb, vec, s);
         for (size_t t = 0; t < lv.diag.size(); t++) {
+            bool pd = prof_on("diag") && lv.diag[t].n > 0;
+            if (pd) prof_begin();
             launch_diag_apply<T>(A, fd, lv.diag[t], (int)t, nrhs, true, vec, s);
+            if (pd) prof_end(lv.diag[t].elems * sizeof(T) + 16.0 * nrhs * lv.diag[t].rows, 0.0);
+            bool pu = prof_on("fwd_update") && lv.fupd[t].total > 0;
+            if (pu) prof_begin();
             launch_fwd_update<T>(A, fd, lv.fupd[t], (int)t, nrhs, vec, s);
+            if (pu) prof_end(lv.fupd[t].elems * sizeof(T) + 16.0 * nrhs * lv.fupd[t].rows,
+                             2.0 * nrhs * lv.fupd[t].elems);
         }
     }
     for (size_t l = p.levels.size(); l-- > 0;) {
@@ -467,8 +527,17 @@ void Context::lu_apply(Plan &p, Factor<T> &f, int nrhs, const double *b, int64_t
         launch_bwd_u12<T>(A, fd, lv.u12, nrhs, vec, part, s);
         launch_bwd_u12_reduce(fd, lv.u12red, nrhs, vec, part, s);
         for (size_t t = lv.diag.size(); t-- > 0;) {
+            bool pd = prof_on("diag") && lv.diag[t].n > 0;
+            if (pd) prof_begin();
             launch_diag_apply<T>(A, fd, lv.diag[t], (int)t, nrhs, false, vec, s);
-            if (t >= 1) launch_bwd_update<T>(A, fd, lv.bupd[t], (int)t, nrhs, vec, s);
+            if (pd) prof_end(lv.diag[t].elems * sizeof(T) + 16.0 * nrhs * lv.diag[t].rows, 0.0);
+            if (t >= 1) {
+                bool pu = prof_on("bwd_update") && lv.bupd[t].total > 0;
+                if (pu) prof_begin();
+                launch_bwd_update<T>(A, fd, lv.bupd[t], (int)t, nrhs, vec, s);
+                if (pu) prof_end(lv.bupd[t].elems * sizeof(T) + 16.0 * nrhs * lv.bupd[t].rows,
+                                 2.0 * nrhs * lv.bupd[t].elems);
+            }
         }
         launch_bwd_scatter(fd, p.d_perm.ptr<int32_t>(), lv.scatter, nrhs, vec, xnew, p.dim, x, ldx,
                            s);

@@ -8,6 +8,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -109,6 +110,19 @@ class Context {
                        const std::function<void(const double *, double *, int)> &op,
                        const std::function<bool(double, double)> &conv, int max_restarts,
                        uint64_t seed, double *out);
+
+    // per-launch timing of one kernel class (mbl_profile_enable)
+    struct Prof {
+        std::string cls;
+        std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+        size_t used = 0;
+        int64_t launches = 0;
+        double bytes = 0.0, flops = 0.0, seconds = 0.0;
+    } prof;
+    bool prof_on(const char *cls) const { return !prof.cls.empty() && prof.cls == cls; }
+    void prof_begin();
+    void prof_end(double bytes, double flops);
+    void prof_collect();
 
     ObsWork obs;
     DevBuf d_psi, d_psi2, d_hpsi, d_e, d_cpart, d_obs, d_r_out, d_se;
