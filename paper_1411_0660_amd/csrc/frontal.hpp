@@ -28,6 +28,7 @@ struct FrontDesc {
     int64_t poff;     // offset of the front's U12 partial products in the level scratch
     int32_t cptr_inv; // offset of the front's inverse relative map (m + 1 row pointers)
     int32_t pad_;
+    int64_t yoff;     // first element of the front's forward-solution block (p x nrhs, ld p)
 };
 
 // A set of fronts processed by one launch and the prefix sums of the work
@@ -69,18 +70,28 @@ void launch_trsm_u(T *arena, const FrontDesc *fd, const int32_t *ipiv, TaskList 
                    hipStream_t s);
 template <class T>
 void launch_trsm_l(T *arena, const FrontDesc *fd, TaskList tl, int t, hipStream_t s);
+// inner (panel t, K = 64, inside its outer block) or outer-block (block t,
+// K = 256, everything right of and below it) trailing update
 template <class T>
-void launch_schur(T *arena, const FrontDesc *fd, TaskList tl, int t, hipStream_t s);
+void launch_schur(T *arena, const FrontDesc *fd, TaskList tl, int t, bool big, hipStream_t s);
+
 
 // tile sizes used by the work-item counts of the task lists
 constexpr int TRSM_U_COLS = 128;   // columns per work item of the U12 solve
-constexpr int TRSM_L_ROWS = 256;   // rows per work item of the L21 solve
-constexpr int SCHUR_TILE = 64;     // square tile of the Schur update
+constexpr int TRSM_L_ROWS = 64;    // rows per work item of the L21 solve
+constexpr int SCHUR_TILE = 128;    // square tile of the Schur update
 int64_t schur_tiles(int64_t rest);
 
+// L~ = L[., t] Linv_tt below each diagonal block, U~ = U[., t] Uinv_tt above it
+template <class T>
+void launch_xform(T *arena, const FrontDesc *fd, TaskList tl, hipStream_t s);
+int64_t xform_items(int m, int p);
+// mode bits: 1 invert the unit-lower parts, 2 the upper parts (and write the
+// composite row permutation); fixed_blk >= 0 selects one block per front,
+// otherwise the items are the blocks
 template <class T>
 void launch_invert_diag(T *arena, const FrontDesc *fd, const int32_t *ipiv, int32_t *prow,
-                        TaskList tl, hipStream_t s);
+                        TaskList tl, int mode, int fixed_blk, hipStream_t s);
 
 // ---- triangular solves (vectors FP64, factors T) ------------------------------
 // forward right-hand side of every listed front, one thread per row:
@@ -89,14 +100,10 @@ void launch_invert_diag(T *arena, const FrontDesc *fd, const int32_t *ipiv, int3
 void launch_fwd_gather(const FrontDesc *fd, const int32_t *perm, const int32_t *prow,
                        const int32_t *inv_ptr, const int2 *inv_src, TaskList tl, int nrhs,
                        const double *b, int64_t ldb, double *vec, hipStream_t s);
-// v_t = Linv_tt v_t (lower) or Uinv_tt v_t (upper) in place, one workgroup per front
+// solve block t of every listed front (forward or backward, see k_trsv.hip)
 template <class T>
-void launch_diag_apply(const T *arena, const FrontDesc *fd, TaskList tl, int t, int nrhs,
-                       bool lower, double *vec, hipStream_t s);
-// rows below solve block t -= L[rows, t] v_t   (64-row work items)
-template <class T>
-void launch_fwd_update(const T *arena, const FrontDesc *fd, TaskList tl, int t, int nrhs,
-                       double *vec, hipStream_t s);
+void launch_solve_step(const T *arena, const FrontDesc *fd, TaskList tl, int t, int nrhs, bool fwd,
+                       double *vec, double *yv, hipStream_t s);
 // backward: v_f[p:m] = x(contribution rows)
 void launch_bwd_gather(const FrontDesc *fd, const int32_t *contrib, TaskList tl, int nrhs,
                        const double *xnew, int64_t n, double *vec, hipStream_t s);
@@ -104,12 +111,8 @@ void launch_bwd_gather(const FrontDesc *fd, const int32_t *contrib, TaskList tl,
 template <class T>
 void launch_bwd_u12(const T *arena, const FrontDesc *fd, TaskList tl, int nrhs,
                     const double *vec, double *part, hipStream_t s);
-void launch_bwd_u12_reduce(const FrontDesc *fd, TaskList tl, int nrhs, double *vec,
+void launch_bwd_u12_reduce(const FrontDesc *fd, TaskList tl, int nrhs, double *yv,
                            const double *part, hipStream_t s);
-// rows above solve block t -= U[rows, t] x_t   (64-row work items)
-template <class T>
-void launch_bwd_update(const T *arena, const FrontDesc *fd, TaskList tl, int t, int nrhs,
-                       double *vec, hipStream_t s);
 // x_new[first..] = v_f[0:p] and x_out[perm[first..]] = v_f[0:p]
 void launch_bwd_scatter(const FrontDesc *fd, const int32_t *perm, TaskList tl, int nrhs,
                         const double *vec, double *xnew, int64_t n, double *xout, int64_t ldx,

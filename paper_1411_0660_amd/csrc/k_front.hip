@@ -10,15 +10,15 @@
 // Pivoting: partial pivoting restricted to the FNB x FNB diagonal block of the
 // current panel (rows outside the block are not candidates), with static pivot
 // perturbation |u_jj| < thresh -> +-thresh.  The interchanges are applied to
-// the block and, inside the U12 solve, to the columns right of the panel; the
-// L entries left of the panel are left in place, and the forward solve applies
-// the block permutation after the updates from earlier blocks, which is the
-// same operator (see k_trsv.hip).  FP64 iterative refinement on the host side
-// of each solve absorbs the perturbations.
+// every column of the front (P A = L U with one row permutation per front,
+// applied to the right-hand side by the forward solve).  FP64 iterative
+// refinement of each solve absorbs the perturbations.
 //
 // Every launch covers all fronts of one tree level (independent subtrees), so
 // the number of launches grows with the tree height times the panel count of
 // the largest front per level, not with the number of fronts.
+#include <algorithm>
+
 #include "common.hpp"
 #include "frontal.hpp"
 
@@ -138,10 +138,10 @@ __global__ __launch_bounds__(256) void k_panel(T *arena, const FrontDesc *__rest
     for (int j = threadIdx.x; j < kb; j += blockDim.x) ipiv[d.first + k0 + j] = piv[j];
 }
 
-// Row interchanges of panel t applied to every column outside the panel (the
-// L columns to the left, so that P A = L U holds with one row permutation per
-// front), and U12 of panel t: the permuted block rows right of the panel
-// solved with the unit lower L_tt.  One thread per column.
+// Row interchanges of panel t applied to every column outside the panel (so
+// that P A = L U holds with one row permutation per front), and the U rows of
+// panel t: the permuted block rows right of the panel solved with the unit
+// lower L_tt.  One thread per column.
 template <class T>
 __global__ __launch_bounds__(TRSM_U_COLS) void k_trsm_u(T *arena, const FrontDesc *__restrict__ fd,
                                                         const int32_t *__restrict__ ipiv,
@@ -166,15 +166,17 @@ __global__ __launch_bounds__(TRSM_U_COLS) void k_trsm_u(T *arena, const FrontDes
         }
     }
     __syncthreads();
-    bool left = chunk < nleft;
-    int col = left ? chunk * TRSM_U_COLS + threadIdx.x
-                   : k1 + (chunk - nleft) * TRSM_U_COLS + threadIdx.x;
-    if (col >= (left ? k0 : m)) return;
+    int col, lim;
+    bool solve = false;
+    if (chunk < nleft) { col = chunk * TRSM_U_COLS; lim = k0; }
+    else { col = k1 + (chunk - nleft) * TRSM_U_COLS; lim = m; solve = true; }
+    col += threadIdx.x;
+    if (col >= lim) return;
     T *Fc = F + (int64_t)col * m + k0;
     T x[FNB];
 #pragma unroll
     for (int i = 0; i < FNB; i++) x[i] = (i < kb) ? Fc[src[i]] : T(0);
-    if (!left) {
+    if (solve) {
 #pragma unroll
         for (int i = 1; i < FNB; i++) {
             T s = x[i];
@@ -201,17 +203,19 @@ constexpr int ISB = 32;
 template <class T>
 __global__ __launch_bounds__(256) void k_invert_diag(T *arena, const FrontDesc *__restrict__ fd,
                                                      const int32_t *__restrict__ ipiv,
-                                                     int32_t *__restrict__ prow, TaskList tl) {
+                                                     int32_t *__restrict__ prow, TaskList tl,
+                                                     int mode, int fixed_blk) {
     __shared__ double tmp[ISB][ISB + 1];
     int k = find_task(tl.prefix, tl.n, blockIdx.x);
     FrontDesc d = fd[tl.fronts[k]];
-    int blk = (int)(blockIdx.x - tl.prefix[k]);
+    int blk = fixed_blk >= 0 ? fixed_blk : (int)(blockIdx.x - tl.prefix[k]);
+    const bool doL = mode & 1, doU = mode & 2;
     int b0 = blk * SB, sz = min(SB, d.p - b0), m = d.m;
     T *F = arena + d.off + (int64_t)b0 * m + b0;     // block origin, leading dimension m
     int nsb = (sz + ISB - 1) / ISB;
     int tid = threadIdx.x;
     // composite row permutation of the panels inside this block
-    if (tid < SB / FNB) {
+    if (doU && tid < SB / FNB) {
         int q0 = b0 + tid * FNB;
         if (q0 < d.p) {
             int kb = min(FNB, d.p - q0);
@@ -256,12 +260,12 @@ __global__ __launch_bounds__(256) void k_invert_diag(T *arena, const FrontDesc *
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < ISB; r++)
-            if (act && r < ns) at(r0 + r, r0 + j) = (T)(r > j ? xl[r] : xu[r]);
+            if (act && r < ns && (r > j ? doL : doU)) at(r0 + r, r0 + j) = (T)(r > j ? xl[r] : xu[r]);
         __syncthreads();
     }
     int tc = tid % ISB, tr = tid / ISB;              // tile coordinates: 8 row groups
     // phase 2: L off-diagonal sub-blocks
-    for (int i = 1; i < nsb; i++) {
+    for (int i = 1; doL && i < nsb; i++) {
         int ri = i * ISB, ni = min(ISB, sz - ri);
         for (int j = 0; j < i; j++) {
             int cj = j * ISB;
@@ -304,7 +308,7 @@ __global__ __launch_bounds__(256) void k_invert_diag(T *arena, const FrontDesc *
         }
     }
     // phase 3: U off-diagonal sub-blocks
-    for (int i = nsb - 2; i >= 0; i--) {
+    for (int i = nsb - 2; doU && i >= 0; i--) {
         int ri = i * ISB;
         for (int j = nsb - 1; j > i; j--) {
             int cj = j * ISB, nj = min(ISB, sz - cj);
@@ -344,100 +348,254 @@ __global__ __launch_bounds__(256) void k_invert_diag(T *arena, const FrontDesc *
     }
 }
 
-// L21 of panel t: every row below the panel times U_tt^-1.  One thread per row.
+// L21 of panel t: every row below the panel times U_tt^-1.  Each workgroup
+// inverts U_tt in LDS (one column per lane of wave 0) and multiplies its 64
+// rows by the inverse.
 template <class T>
-__global__ __launch_bounds__(TRSM_L_ROWS) void k_trsm_l(T *arena, const FrontDesc *__restrict__ fd,
-                                                        TaskList tl, int t) {
-    __shared__ T Us[FNB][FNB + 1];
-    __shared__ T rd[FNB];
+__global__ __launch_bounds__(256) void k_trsm_l(T *arena, const FrontDesc *__restrict__ fd,
+                                                TaskList tl, int t) {
+    __shared__ double Us[FNB][FNB + 1];
+    __shared__ double Ui[FNB][FNB + 1];
+    __shared__ double As[FNB][FNB + 1];     // As[k][i]: row i of the chunk, panel column k
     int k = find_task(tl.prefix, tl.n, blockIdx.x);
     FrontDesc d = fd[tl.fronts[k]];
     int chunk = (int)(blockIdx.x - tl.prefix[k]);
     int k0 = t * FNB, kb = min(FNB, d.p - k0), k1 = k0 + kb, m = d.m;
+    int r0 = k1 + chunk * TRSM_L_ROWS, nr = min(TRSM_L_ROWS, m - r0);
     T *F = arena + d.off;
     for (int e = threadIdx.x; e < FNB * FNB; e += blockDim.x) {
         int i = e % FNB, j = e / FNB;
-        Us[i][j] = (i < kb && j < kb && i <= j) ? F[(int64_t)(k0 + i) + (int64_t)(k0 + j) * m] : T(0);
+        bool in = i < kb && j < kb;
+        Us[i][j] = (in && i <= j) ? (double)F[(int64_t)(k0 + i) + (int64_t)(k0 + j) * m]
+                                  : (i == j ? 1.0 : 0.0);
+        As[j][i] = (i < nr && j < kb) ? (double)F[(int64_t)(r0 + i) + (int64_t)(k0 + j) * m] : 0.0;
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < FNB; j += blockDim.x) rd[j] = (j < kb) ? T(1) / Us[j][j] : T(0);
-    __syncthreads();
-    int row = k1 + chunk * TRSM_L_ROWS + threadIdx.x;
-    if (row >= m) return;
-    T *Fr = F + row + (int64_t)k0 * m;
-    T x[FNB];
+    if (threadIdx.x < FNB) {                 // column j of U_tt^-1 by back substitution
+        int j = threadIdx.x;
+        double x[FNB];
 #pragma unroll
-    for (int j = 0; j < FNB; j++) x[j] = (j < kb) ? Fr[(int64_t)j * m] : T(0);
+        for (int i = FNB - 1; i >= 0; i--) {
+            double v = (i == j) ? 1.0 : 0.0;
 #pragma unroll
-    for (int j = 0; j < FNB; j++) {
-        T s = x[j];
+            for (int q = i + 1; q < FNB; q++) v -= Us[i][q] * x[q];
+            x[i] = (i <= j) ? v / Us[i][i] : 0.0;
+        }
 #pragma unroll
-        for (int i = 0; i < j; i++) s -= x[i] * Us[i][j];
-        x[j] = s * rd[j];
+        for (int i = 0; i < FNB; i++) Ui[i][j] = x[i];
     }
+    __syncthreads();
+    int i = threadIdx.x % TRSM_L_ROWS, jb = (threadIdx.x / TRSM_L_ROWS) * 16;
+    double acc[16];
 #pragma unroll
-    for (int j = 0; j < FNB; j++)
-        if (j < kb) Fr[(int64_t)j * m] = x[j];
+    for (int q = 0; q < 16; q++) acc[q] = 0.0;
+    for (int kk = 0; kk < kb; kk++) {
+        double a = As[kk][i];
+#pragma unroll
+        for (int q = 0; q < 16; q++) acc[q] += a * Ui[kk][jb + q];
+    }
+    if (i < nr)
+#pragma unroll
+        for (int q = 0; q < 16; q++)
+            if (jb + q < kb) F[(int64_t)(r0 + i) + (int64_t)(k0 + jb + q) * m] = (T)acc[q];
 }
 
-// trailing update F[k1:m, k1:m] -= F[k1:m, k0:k1] F[k0:k1, k1:m], 64 x 64 tiles
+// trailing update F[k1:m, k1:m] -= F[k1:m, k0:k1] F[k0:k1, k1:m] on the matrix
+// cores: 128 x 128 output tile per workgroup, each wave a 64 x 64 quarter as
+// 4 x 4 MFMA 16x16x4 blocks (FP64 or FP32 by T), the A and B panels staged in
+// LDS k-major, and the read-modify-write of C routed through LDS so that it
+// is coalesced down the columns.
+template <class T> struct MfmaAcc;
+// Operand layout of both 16x16x4 instructions: lane l holds A[l%16][l/16] and
+// B[l/16][l%16].  Result element v of lane l is row_of(l/16, v), column l%16
+// (checked on gfx950: FP32 packs four consecutive rows per lane group, FP64
+// strides them by four).
+template <> struct MfmaAcc<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row_of(int lk, int v) { return lk + 4 * v; }
+};
+template <> struct MfmaAcc<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row_of(int lk, int v) { return 4 * lk + v; }
+};
+
+constexpr int ST = SCHUR_TILE;       // 128
+constexpr int SP = ST + 2;           // padded LDS row
+constexpr int KC = 32;               // K columns staged per pass
+
+// big = 0: update after panel t inside its outer SB block, K = the panel's kb
+//          columns: the first tiles cover the rows below the panel and the
+//          columns up to the end of the outer block, the rest the remaining
+//          rows of the outer block and every column right of it;
+// big = 1: update of outer block t, K = its (up to SB) columns, everything
+//          right of and below it (including the contribution block).
 template <class T>
-__global__ __launch_bounds__(256) void k_schur(T *arena, const FrontDesc *__restrict__ fd,
-                                               TaskList tl, int t) {
-    __shared__ T As[SCHUR_TILE][FNB + 1];
-    __shared__ T Bs[FNB][SCHUR_TILE];
+__global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__restrict__ fd,
+                                                  TaskList tl, int t, int big) {
+    typedef typename MfmaAcc<T>::v4 v4;
+    __shared__ T smem[2 * KC * SP > 64 * (ST + 1) ? 2 * KC * SP : 64 * (ST + 1)];
+    T *As = smem;                    // As[k * SP + i]
+    T *Bs = smem + KC * SP;          // Bs[k * SP + j]
     int k = find_task(tl.prefix, tl.n, blockIdx.x);
     FrontDesc d = fd[tl.fronts[k]];
     int64_t tile = blockIdx.x - tl.prefix[k];
-    int k0 = t * FNB, kb = min(FNB, d.p - k0), k1 = k0 + kb, m = d.m;
-    int rest = m - k1;
-    int nt = (rest + SCHUR_TILE - 1) / SCHUR_TILE;
-    int ti = (int)(tile % nt), tj = (int)(tile / nt);
-    int r0 = k1 + ti * SCHUR_TILE, c0 = k1 + tj * SCHUR_TILE;
+    int m = d.m, kc0, kd, rlo, rhi, clo, chi;
+    if (!big) {
+        kc0 = t * FNB; kd = min(FNB, d.p - kc0);
+        int k1 = kc0 + kd, K1 = min(d.p, (kc0 / SB + 1) * SB);
+        int n0 = (K1 > k1) ? ((m - k1 + ST - 1) / ST) * ((K1 - k1 + ST - 1) / ST) : 0;
+        if (tile < n0) { rlo = k1; rhi = m; clo = k1; chi = K1; }
+        else { tile -= n0; rlo = k1; rhi = K1; clo = K1; chi = m; }
+    } else {
+        kc0 = t * SB; kd = min(SB, d.p - kc0); rlo = kc0 + kd; rhi = m; clo = rlo; chi = m;
+    }
+    int ntr = (rhi - rlo + ST - 1) / ST;
+    int ti = (int)(tile % ntr), tj = (int)(tile / ntr);
+    int r0 = rlo + ti * ST, c0 = clo + tj * ST;
     T *F = arena + d.off;
-    for (int e = threadIdx.x; e < SCHUR_TILE * FNB; e += blockDim.x) {
-        int i = e % SCHUR_TILE, kk = e / SCHUR_TILE;
-        int r = r0 + i;
-        As[i][kk] = (r < m && kk < kb) ? F[r + (int64_t)(k0 + kk) * m] : T(0);
-    }
-    for (int e = threadIdx.x; e < SCHUR_TILE * FNB; e += blockDim.x) {
-        int kk = e % FNB, j = e / FNB;
-        int c = c0 + j;
-        Bs[kk][j] = (c < m && kk < kb) ? F[(int64_t)(k0 + kk) + (int64_t)c * m] : T(0);
-    }
-    __syncthreads();
-    int tr = threadIdx.x % 16, tc = threadIdx.x / 16;
-    T acc[4][4];
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int wr = (w & 1) * 64, wc = (w >> 1) * 64;
+    int li = lane & 15, lk = lane >> 4;
+    v4 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; a++)
 #pragma unroll
-        for (int b = 0; b < 4; b++) acc[a][b] = T(0);
-    for (int kk = 0; kk < kb; kk++) {
-        T av[4], bv[4];
+        for (int b = 0; b < 4; b++) acc[a][b] = v4{0, 0, 0, 0};
+    for (int kc = 0; kc < kd; kc += KC) {
+        int kn = min(KC, kd - kc);
+        __syncthreads();
+        for (int e = threadIdx.x; e < ST * KC; e += blockDim.x) {
+            int i = e % ST, kk = e / ST, r = r0 + i;
+            As[kk * SP + i] = (r < rhi && kk < kn) ? F[r + (int64_t)(kc0 + kc + kk) * m] : T(0);
+        }
+        for (int e = threadIdx.x; e < ST * KC; e += blockDim.x) {
+            int kk = e % KC, j = e / KC, c = c0 + j;
+            Bs[kk * SP + j] = (c < chi && kk < kn) ? F[(int64_t)(kc0 + kc + kk) + (int64_t)c * m] : T(0);
+        }
+        __syncthreads();
+        int ksteps = (kn + 3) / 4;
+        for (int ks = 0; ks < ksteps; ks++) {
+            int kk = ks * 4 + lk;
+            T av[4], bv[4];
 #pragma unroll
-        for (int a = 0; a < 4; a++) av[a] = As[tr + 16 * a][kk];
+            for (int a = 0; a < 4; a++) av[a] = As[kk * SP + wr + a * 16 + li];
 #pragma unroll
-        for (int b = 0; b < 4; b++) bv[b] = Bs[kk][tc + 16 * b];
+            for (int b = 0; b < 4; b++) bv[b] = Bs[kk * SP + wc + b * 16 + li];
 #pragma unroll
-        for (int a = 0; a < 4; a++)
+            for (int a = 0; a < 4; a++)
 #pragma unroll
-            for (int b = 0; b < 4; b++) acc[a][b] += av[a] * bv[b];
-    }
-#pragma unroll
-    for (int b = 0; b < 4; b++) {
-        int c = c0 + tc + 16 * b;
-        if (c >= m) continue;
-#pragma unroll
-        for (int a = 0; a < 4; a++) {
-            int r = r0 + tr + 16 * a;
-            if (r < m) F[r + (int64_t)c * m] -= acc[a][b];
+                for (int b = 0; b < 4; b++) acc[a][b] = MfmaAcc<T>::mma(av[a], bv[b], acc[a][b]);
         }
     }
+    // write-back through LDS, one 64-column half of the tile at a time
+    T *Cs = smem;                    // Cs[col * (ST + 1) + row], col < 64
+    for (int half = 0; half < 2; half++) {
+        __syncthreads();
+        if ((w >> 1) == half) {
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int b = 0; b < 4; b++)
+#pragma unroll
+                    for (int v = 0; v < 4; v++) {
+                        int row = wr + a * 16 + MfmaAcc<T>::row_of(lk, v), col = b * 16 + li;
+                        Cs[col * (ST + 1) + row] = acc[a][b][v];
+                    }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < ST * 64; e += blockDim.x) {
+            int row = e % ST, col = e / ST;
+            int r = r0 + row, c = c0 + half * 64 + col;
+            if (r < rhi && c < chi) F[r + (int64_t)c * m] -= Cs[col * (ST + 1) + row];
+        }
+    }
+}
+
+// Once per factorisation, after the diagonal blocks are inverted: fold each
+// inverse into the off-diagonal panel of its block column,
+//   L~[rows below block t, t] = L[., t] Linv_tt,   U~[rows above, t] = U[., t] Uinv_tt,
+// so that a solve step needs only v_t (not Xinv_tt v_t) to update the other
+// rows, and the diagonal product runs in the same launch.  Work item: 16 rows
+// of one panel; the rows are staged in LDS (in place is then safe), the
+// inverse streams through LDS in 8-row slabs.
+constexpr int XR = 16, XS = 8;
+
+template <class T>
+__global__ __launch_bounds__(SB) void k_xform(T *arena, const FrontDesc *__restrict__ fd,
+                                              TaskList tl) {
+    __shared__ double a[XR][SB];
+    __shared__ double xs[XS][SB];
+    int k = find_task(tl.prefix, tl.n, blockIdx.x);
+    FrontDesc d = fd[tl.fronts[k]];
+    int64_t w = blockIdx.x - tl.prefix[k];
+    int m = d.m, nb = (d.p + SB - 1) / SB;
+    // locate (block t, side, chunk): per block first the L chunks, then the U chunks
+    int t = 0, side = 0, chunk = 0;
+    for (t = 0; t < nb; t++) {
+        int t0 = t * SB, tend = min(d.p, t0 + SB);
+        int nl = (m - tend + XR - 1) / XR, nu = (t0 + XR - 1) / XR;
+        if (w < nl) { side = 0; chunk = (int)w; break; }
+        w -= nl;
+        if (w < nu) { side = 1; chunk = (int)w; break; }
+        w -= nu;
+    }
+    int t0 = t * SB, st = min(SB, d.p - t0), tend = t0 + st;
+    int r0 = side == 0 ? tend + chunk * XR : chunk * XR;
+    int rlim = side == 0 ? m : t0;
+    int nr = min(XR, rlim - r0);
+    T *F = arena + d.off;
+    for (int e = threadIdx.x; e < XR * SB; e += blockDim.x) {
+        int r = e % XR, j = e / XR;
+        a[r][j] = (r < nr && j < st) ? (double)F[(r0 + r) + (int64_t)(t0 + j) * m] : 0.0;
+    }
+    int j = threadIdx.x;
+    double acc[XR];
+#pragma unroll
+    for (int r = 0; r < XR; r++) acc[r] = 0.0;
+    const T *X = F + t0 + (int64_t)t0 * m;          // the inverted diagonal block
+    for (int k0 = 0; k0 < st; k0 += XS) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < XS * SB; e += blockDim.x) {
+            int kk = e % XS, jj = e / XS, kr = k0 + kk;
+            double x = 0.0;
+            if (kr < st && jj < st) {
+                if (side == 0) x = (kr > jj) ? (double)X[kr + (int64_t)jj * m] : (kr == jj ? 1.0 : 0.0);
+                else x = (kr <= jj) ? (double)X[kr + (int64_t)jj * m] : 0.0;
+            }
+            xs[kk][jj] = x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < XS; kk++) {
+            double x = xs[kk][j];
+#pragma unroll
+            for (int r = 0; r < XR; r++) acc[r] += a[r][k0 + kk] * x;
+        }
+    }
+    if (j < st)
+#pragma unroll
+        for (int r = 0; r < XR; r++)
+            if (r < nr) F[(r0 + r) + (int64_t)(t0 + j) * m] = (T)acc[r];
 }
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace
+
+int64_t xform_items(int m, int p) {
+    int64_t n = 0;
+    for (int t0 = 0; t0 < p; t0 += SB) {
+        int tend = std::min(p, t0 + SB);
+        n += (m - tend + XR - 1) / XR + (t0 + XR - 1) / XR;
+    }
+    return n;
+}
 
 int64_t schur_tiles(int64_t rest) {
     int64_t nt = (rest + SCHUR_TILE - 1) / SCHUR_TILE;
@@ -493,27 +651,36 @@ void launch_trsm_u(T *arena, const FrontDesc *fd, const int32_t *ipiv, TaskList 
 
 template <class T>
 void launch_invert_diag(T *arena, const FrontDesc *fd, const int32_t *ipiv, int32_t *prow,
-                        TaskList tl, hipStream_t s) {
+                        TaskList tl, int mode, int fixed_blk, hipStream_t s) {
     if (tl.total == 0) return;
     hipLaunchKernelGGL(k_invert_diag<T>, dim3((unsigned)tl.total), dim3(256), 0, s, arena, fd, ipiv,
-                       prow, tl);
+                       prow, tl, mode, fixed_blk);
+    MBL_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_xform(T *arena, const FrontDesc *fd, TaskList tl, hipStream_t s) {
+    if (tl.total == 0) return;
+    hipLaunchKernelGGL(k_xform<T>, dim3((unsigned)tl.total), dim3(SB), 0, s, arena, fd, tl);
     MBL_CHECK_LAUNCH();
 }
 
 template <class T>
 void launch_trsm_l(T *arena, const FrontDesc *fd, TaskList tl, int t, hipStream_t s) {
     if (tl.total == 0) return;
-    hipLaunchKernelGGL(k_trsm_l<T>, dim3((unsigned)tl.total), dim3(TRSM_L_ROWS), 0, s, arena, fd,
+    hipLaunchKernelGGL(k_trsm_l<T>, dim3((unsigned)tl.total), dim3(256), 0, s, arena, fd,
                        tl, t);
     MBL_CHECK_LAUNCH();
 }
 
 template <class T>
-void launch_schur(T *arena, const FrontDesc *fd, TaskList tl, int t, hipStream_t s) {
+void launch_schur(T *arena, const FrontDesc *fd, TaskList tl, int t, bool big, hipStream_t s) {
     if (tl.total == 0) return;
-    hipLaunchKernelGGL(k_schur<T>, dim3((unsigned)tl.total), dim3(256), 0, s, arena, fd, tl, t);
+    hipLaunchKernelGGL(k_schur<T>, dim3((unsigned)tl.total), dim3(256), 0, s, arena, fd, tl, t,
+                       big ? 1 : 0);
     MBL_CHECK_LAUNCH();
 }
+
 
 #define MBL_INST_FRONT(T)                                                                       \
     template void launch_front_zero<T>(T *, int64_t, int64_t, hipStream_t);                    \
@@ -527,9 +694,10 @@ void launch_schur(T *arena, const FrontDesc *fd, TaskList tl, int t, hipStream_t
     template void launch_trsm_u<T>(T *, const FrontDesc *, const int32_t *, TaskList, int,      \
                                    hipStream_t);                                                \
     template void launch_trsm_l<T>(T *, const FrontDesc *, TaskList, int, hipStream_t);         \
+    template void launch_xform<T>(T *, const FrontDesc *, TaskList, hipStream_t);               \
     template void launch_invert_diag<T>(T *, const FrontDesc *, const int32_t *, int32_t *,      \
-                                        TaskList, hipStream_t);                                  \
-    template void launch_schur<T>(T *, const FrontDesc *, TaskList, int, hipStream_t);
+                                        TaskList, int, int, hipStream_t);                        \
+    template void launch_schur<T>(T *, const FrontDesc *, TaskList, int, bool, hipStream_t);
 
 MBL_INST_FRONT(float)
 MBL_INST_FRONT(double)

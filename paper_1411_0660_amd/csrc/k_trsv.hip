@@ -4,20 +4,20 @@
 //
 // The factor streams from HBM once per pass, shared by a block of up to 16
 // right-hand sides (vectors stay FP64 whatever the factor precision).  The
-// SB x SB diagonal blocks of L11 and U11 are stored inverted (k_front.hip), so
-// each diagonal step is a dense matrix-vector product.  Per tree level:
+// SB x SB diagonal blocks of L11 and U11 are stored inverted and folded into
+// the panels beside them (L~ = L Linv_tt below, U~ = U Uinv_tt above; see
+// k_front.hip), so one launch per solve block and tree level does both the
+// diagonal product and the update of the other rows, from the same input:
 //   forward (leaves to root), front f:
-//     v_f = P([b(pivots); 0] + children's updates)          (gather, row-parallel)
-//     for each solve block t:  v_t = Linv_tt v_t              (one workgroup per front)
-//                              rows below -= L[., t] v_t      (64-row work items)
-//     rows p..m-1 of v_f are then the update its parent gathers.
+//     V = P([b(pivots); 0] + children's updates)        (row-parallel gather)
+//     block t:  Y_t = Linv_tt V_t  and  V[rows below] -= L~[., t] V_t
+//     afterwards Y = L11^-1 P b and V[p:m] is the update the parent gathers.
 //   backward (root to leaves):
-//     v_f[p:m] = x(contribution rows); v_f[0:p] -= U12 v_f[p:m] (64 x 256 tiles,
-//     fixed-order sum); for each block t from the last: v_t = Uinv_tt v_t, rows
-//     above -= U[., t] v_t.
-// Update work items are 64 rows x SB columns: the four waves of a workgroup
-// take a quarter of the columns each and are summed through LDS, so the
-// column loop of a lane is 64 long and its loads are unrolled.
+//     V[p:m] = x(contribution rows); Y -= U12 V[p:m]   (64 x 256 tiles, fixed-order sum)
+//     block t from the last:  V_t = Uinv_tt Y_t  and  Y[rows above] -= U~[., t] Y_t
+//     afterwards V[0:p] = x of the pivots.
+// Work items are 64 rows x one SB block: the four waves of a workgroup take a
+// quarter of the columns each and are summed through LDS.
 #include <type_traits>
 
 #include "common.hpp"
@@ -67,46 +67,20 @@ __global__ __launch_bounds__(256) void k_fwd_gather(const FrontDesc *__restrict_
     for (int r = 0; r < nrhs; r++) vec[base + i + (int64_t)r * d.m] = val[r];
 }
 
-// v_t = Xinv_tt v_t in place, X = L (unit lower) or U (upper); one workgroup
-// of SB threads per front, one row per thread
-template <class T, int NR, bool LOWER>
-__global__ __launch_bounds__(SB) void k_diag_apply(const T *__restrict__ arena,
-                                                   const FrontDesc *__restrict__ fd, TaskList tl,
-                                                   int t, double *vec) {
-    __shared__ double in[SB][NR];
-    FrontDesc d = fd[tl.fronts[blockIdx.x]];
-    int m = d.m, t0 = t * SB, st = min(SB, d.p - t0);
-    double *v = vec + d.voff + t0;
-    for (int e = threadIdx.x; e < st * NR; e += blockDim.x) {
-        int j = e % st, r = e / st;
-        in[j][r] = v[j + (int64_t)r * m];
-    }
-    __syncthreads();
-    int i = threadIdx.x;
-    if (i >= st) return;
-    const T *B = arena + d.off + t0 + i + (int64_t)t0 * m;   // row i of the block
-    double acc[NR];
-#pragma unroll
-    for (int r = 0; r < NR; r++) acc[r] = LOWER ? in[i][r] : 0.0;
-    int j0 = LOWER ? 0 : i, j1 = LOWER ? i : st;
-#pragma unroll 8
-    for (int j = j0; j < j1; j++) {
-        double x = (double)B[(int64_t)j * m];
-#pragma unroll
-        for (int r = 0; r < NR; r++) acc[r] += x * in[j][r];
-    }
-#pragma unroll
-    for (int r = 0; r < NR; r++) v[i + (int64_t)r * m] = acc[r];
-}
-
-// dst rows -= M[rows, cols] * src, rows = a 64-row chunk, cols = one SB block;
-// lane = row, wave = quarter of the columns, sum over waves through LDS
-template <class T, int NR>
-__device__ __forceinline__ void chunk_update(const T *__restrict__ Mrow0, int64_t m, int ncols,
-                                             int nrows, const double (*src)[NR],
-                                             double (*red)[RW][NR], double *dst) {
+// out rows of one 64-row chunk from M[rows, SB block] times src (LDS):
+//   MODE 0: out -= M src            (panel update, in place)
+//   MODE 1: out  = src_i + sum_{j<i} M_ij src_j   (unit-lower inverse block)
+//   MODE 2: out  = sum_{j>=i} M_ij src_j           (upper inverse block)
+// lane = row, wave = quarter of the columns, sum over waves through LDS.
+template <class T, int NR, int MODE>
+__device__ __forceinline__ void chunk_apply(const T *__restrict__ Mrow0, int64_t m, int ncols,
+                                            int nrows, int rowoff, const double (*src)[NR],
+                                            double (*red)[RW][NR], double *out, int64_t ldo) {
     int lane = threadIdx.x % RW, w = threadIdx.x / RW;
     int j0 = w * CQ, j1 = min(j0 + CQ, ncols);
+    int i = rowoff + lane;                       // row index inside the diagonal block
+    if (MODE == 1) j1 = min(j1, i);
+    if (MODE == 2) j0 = max(j0, i);
     double acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) acc[r] = 0.0;
@@ -125,54 +99,55 @@ __device__ __forceinline__ void chunk_update(const T *__restrict__ Mrow0, int64_
     if (w == 0 && lane < nrows) {
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            double s = red[0][lane][r] + red[1][lane][r] + red[2][lane][r] + red[3][lane][r];
-            dst[lane + (int64_t)r * m] -= s;
+            double sum = red[0][lane][r] + red[1][lane][r] + red[2][lane][r] + red[3][lane][r];
+            double *o = out + lane + (int64_t)r * ldo;
+            if (MODE == 0) *o -= sum;
+            else if (MODE == 1) *o = src[i][r] + sum;
+            else *o = sum;
         }
     }
 }
 
-// forward: rows below block t -= L[., t] v_t
-template <class T, int NR>
-__global__ __launch_bounds__(SB) void k_fwd_update(const T *__restrict__ arena,
+// one solve block t of every listed front: the first ceil(st/64) items apply
+// the inverted diagonal block, the others update the remaining rows
+template <class T, int NR, bool FWD>
+__global__ __launch_bounds__(SB) void k_solve_step(const T *__restrict__ arena,
                                                    const FrontDesc *__restrict__ fd, TaskList tl,
-                                                   int t, double *vec) {
+                                                   int t, double *vec, double *yv) {
     __shared__ double src[SB][NR];
     __shared__ double red[4][RW][NR];
     int k = find_task(tl.prefix, tl.n, blockIdx.x);
     FrontDesc d = fd[tl.fronts[k]];
-    int chunk = (int)(blockIdx.x - tl.prefix[k]);
-    int m = d.m, t0 = t * SB, st = min(SB, d.p - t0), tend = t0 + st;
-    double *v = vec + d.voff;
+    int w = (int)(blockIdx.x - tl.prefix[k]);
+    int m = d.m, p = d.p, t0 = t * SB, st = min(SB, p - t0), tend = t0 + st;
+    int nA = (st + RW - 1) / RW;
+    double *V = vec + d.voff;          // ld m
+    double *Y = yv + d.yoff;           // ld p
+    const double *S = FWD ? V + t0 : Y + t0;
+    int64_t lds = FWD ? m : p;
     for (int e = threadIdx.x; e < st * NR; e += blockDim.x) {
         int j = e % st, r = e / st;
-        src[j][r] = v[t0 + j + (int64_t)r * m];
+        src[j][r] = S[j + (int64_t)r * lds];
     }
     __syncthreads();
-    int r0 = tend + chunk * RW;
-    chunk_update<T, NR>(arena + d.off + r0 + (int64_t)t0 * m, m, st, min(RW, m - r0), src, red,
-                        v + r0);
-}
-
-// backward: rows above block t -= U[., t] x_t
-template <class T, int NR>
-__global__ __launch_bounds__(SB) void k_bwd_update(const T *__restrict__ arena,
-                                                   const FrontDesc *__restrict__ fd, TaskList tl,
-                                                   int t, double *vec) {
-    __shared__ double src[SB][NR];
-    __shared__ double red[4][RW][NR];
-    int k = find_task(tl.prefix, tl.n, blockIdx.x);
-    FrontDesc d = fd[tl.fronts[k]];
-    int chunk = (int)(blockIdx.x - tl.prefix[k]);
-    int m = d.m, t0 = t * SB, st = min(SB, d.p - t0);
-    double *v = vec + d.voff;
-    for (int e = threadIdx.x; e < st * NR; e += blockDim.x) {
-        int j = e % st, r = e / st;
-        src[j][r] = v[t0 + j + (int64_t)r * m];
+    const T *F = arena + d.off;
+    if (w < nA) {
+        int i0 = w * RW;
+        const T *M = F + (t0 + i0) + (int64_t)t0 * m;
+        if (FWD) chunk_apply<T, NR, 1>(M, m, st, min(RW, st - i0), i0, src, red, Y + t0 + i0, p);
+        else chunk_apply<T, NR, 2>(M, m, st, min(RW, st - i0), i0, src, red, V + t0 + i0, m);
+    } else {
+        int c = w - nA;
+        if (FWD) {
+            int r0 = tend + c * RW;
+            chunk_apply<T, NR, 0>(F + r0 + (int64_t)t0 * m, m, st, min(RW, m - r0), 0, src, red,
+                                  V + r0, m);
+        } else {
+            int r0 = c * RW;
+            chunk_apply<T, NR, 0>(F + r0 + (int64_t)t0 * m, m, st, min(RW, t0 - r0), 0, src, red,
+                                  Y + r0, p);
+        }
     }
-    __syncthreads();
-    int r0 = chunk * RW;                                   // rows [0, t0) in 64-row chunks
-    chunk_update<T, NR>(arena + d.off + r0 + (int64_t)t0 * m, m, st, min(RW, t0 - r0), src, red,
-                        v + r0);
 }
 
 __global__ __launch_bounds__(256) void k_bwd_gather(const FrontDesc *__restrict__ fd,
@@ -238,19 +213,19 @@ __global__ __launch_bounds__(SB) void k_bwd_u12(const T *__restrict__ arena,
 
 template <int NR>
 __global__ __launch_bounds__(256) void k_bwd_u12_reduce(const FrontDesc *__restrict__ fd,
-                                                        TaskList tl, double *vec,
+                                                        TaskList tl, double *yv,
                                                         const double *__restrict__ part) {
     int k = find_task(tl.prefix, tl.n, blockIdx.x);
     FrontDesc d = fd[tl.fronts[k]];
     int row = (int)(blockIdx.x - tl.prefix[k]) * 256 + threadIdx.x;
     int m = d.m, p = d.p, ncc = (m - p + SB - 1) / SB;
     if (row >= p) return;
-    double *v = vec + d.voff;
+    double *y = yv + d.yoff;
 #pragma unroll
     for (int r = 0; r < NR; r++) {
         double s = 0.0;
         for (int q = 0; q < ncc; q++) s += part[d.poff + ((int64_t)q * MAXRHS + r) * p + row];
-        v[row + (int64_t)r * m] -= s;
+        y[row + (int64_t)r * p] -= s;
     }
 }
 
@@ -298,35 +273,17 @@ void launch_fwd_gather(const FrontDesc *fd, const int32_t *perm, const int32_t *
 }
 
 template <class T>
-void launch_diag_apply(const T *arena, const FrontDesc *fd, TaskList tl, int t, int nrhs,
-                       bool lower, double *vec, hipStream_t s) {
-    if (tl.n == 0) return;
-    rhs_dispatch(nrhs, [&](auto nr) {
-        constexpr int NR = decltype(nr)::value;
-        if (lower) k_diag_apply<T, NR, true><<<dim3(tl.n), dim3(SB), 0, s>>>(arena, fd, tl, t, vec);
-        else k_diag_apply<T, NR, false><<<dim3(tl.n), dim3(SB), 0, s>>>(arena, fd, tl, t, vec);
-    });
-    MBL_CHECK_LAUNCH();
-}
-
-template <class T>
-void launch_fwd_update(const T *arena, const FrontDesc *fd, TaskList tl, int t, int nrhs,
-                       double *vec, hipStream_t s) {
+void launch_solve_step(const T *arena, const FrontDesc *fd, TaskList tl, int t, int nrhs, bool fwd,
+                       double *vec, double *yv, hipStream_t s) {
     if (tl.total == 0) return;
     rhs_dispatch(nrhs, [&](auto nr) {
         constexpr int NR = decltype(nr)::value;
-        k_fwd_update<T, NR><<<dim3((unsigned)tl.total), dim3(SB), 0, s>>>(arena, fd, tl, t, vec);
-    });
-    MBL_CHECK_LAUNCH();
-}
-
-template <class T>
-void launch_bwd_update(const T *arena, const FrontDesc *fd, TaskList tl, int t, int nrhs,
-                       double *vec, hipStream_t s) {
-    if (tl.total == 0) return;
-    rhs_dispatch(nrhs, [&](auto nr) {
-        constexpr int NR = decltype(nr)::value;
-        k_bwd_update<T, NR><<<dim3((unsigned)tl.total), dim3(SB), 0, s>>>(arena, fd, tl, t, vec);
+        if (fwd)
+            k_solve_step<T, NR, true><<<dim3((unsigned)tl.total), dim3(SB), 0, s>>>(arena, fd, tl, t,
+                                                                                    vec, yv);
+        else
+            k_solve_step<T, NR, false><<<dim3((unsigned)tl.total), dim3(SB), 0, s>>>(arena, fd, tl,
+                                                                                     t, vec, yv);
     });
     MBL_CHECK_LAUNCH();
 }
@@ -350,12 +307,12 @@ void launch_bwd_u12(const T *arena, const FrontDesc *fd, TaskList tl, int nrhs, 
     MBL_CHECK_LAUNCH();
 }
 
-void launch_bwd_u12_reduce(const FrontDesc *fd, TaskList tl, int nrhs, double *vec,
+void launch_bwd_u12_reduce(const FrontDesc *fd, TaskList tl, int nrhs, double *yv,
                            const double *part, hipStream_t s) {
     if (tl.total == 0) return;
     rhs_dispatch(nrhs, [&](auto nr) {
         constexpr int NR = decltype(nr)::value;
-        k_bwd_u12_reduce<NR><<<dim3((unsigned)tl.total), dim3(256), 0, s>>>(fd, tl, vec, part);
+        k_bwd_u12_reduce<NR><<<dim3((unsigned)tl.total), dim3(256), 0, s>>>(fd, tl, yv, part);
     });
     MBL_CHECK_LAUNCH();
 }
@@ -370,14 +327,10 @@ void launch_bwd_scatter(const FrontDesc *fd, const int32_t *perm, TaskList tl, i
 }
 
 #define MBL_INST_TRSV(T)                                                                          \
-    template void launch_diag_apply<T>(const T *, const FrontDesc *, TaskList, int, int, bool,    \
-                                       double *, hipStream_t);                                    \
-    template void launch_fwd_update<T>(const T *, const FrontDesc *, TaskList, int, int,          \
-                                       double *, hipStream_t);                                    \
+    template void launch_solve_step<T>(const T *, const FrontDesc *, TaskList, int, int, bool,    \
+                                       double *, double *, hipStream_t);                          \
     template void launch_bwd_u12<T>(const T *, const FrontDesc *, TaskList, int, const double *,  \
-                                    double *, hipStream_t);                                       \
-    template void launch_bwd_update<T>(const T *, const FrontDesc *, TaskList, int, int,          \
-                                       double *, hipStream_t);
+                                    double *, hipStream_t);
 
 MBL_INST_TRSV(float)
 MBL_INST_TRSV(double)

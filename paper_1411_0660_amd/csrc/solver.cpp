@@ -174,6 +174,8 @@ void Context::ensure_symbolic(Plan &p) {
             voff += (int64_t)d.m * MAXRHS;
             d.poff = poff;
             poff += cdiv64(d.m - d.p, SB) * MAXRHS * (int64_t)d.p;
+            d.yoff = p.y_elems;
+            p.y_elems += (int64_t)d.p * MAXRHS;
             // original entries of H - sigma owned by this front
             const int32_t *cr = t.contrib.data() + F.cptr;
             auto local = [&](int32_t i) -> int32_t {
@@ -273,6 +275,9 @@ void Context::ensure_symbolic(Plan &p) {
         for (int f = 0; f < nf; f++)
             if (p.h_fd[f].p > 0) { all.push_back(f); nb.push_back(cdiv64(p.h_fd[f].p, SB)); }
         tb.add(p.inv, all, nb);
+        std::vector<int64_t> xi;
+        for (int f : all) xi.push_back(xform_items(p.h_fd[f].m, p.h_fd[f].p));
+        tb.add(p.xform, all, xi);
     }
     for (int l = 0; l < t.n_levels; l++) {
         LevelTasks &lv = p.levels[l];
@@ -321,11 +326,13 @@ void Context::ensure_symbolic(Plan &p) {
                 int k0 = st * FNB;
                 if (d.p <= k0) continue;
                 int kb = std::min(FNB, d.p - k0), k1 = k0 + kb;
+                int K1 = std::min(d.p, (k0 / SB + 1) * SB);
                 act.push_back(f);
                 o1.push_back(1);
                 tu.push_back(cdiv64(k0, TRSM_U_COLS) + cdiv64(d.m - k1, TRSM_U_COLS));
-                rb.push_back(cdiv64(d.m - k1, 256));
-                sh.push_back(schur_tiles(d.m - k1));
+                rb.push_back(cdiv64(d.m - k1, TRSM_L_ROWS));
+                sh.push_back((K1 > k1 ? cdiv64(d.m - k1, SCHUR_TILE) * cdiv64(K1 - k1, SCHUR_TILE) : 0) +
+                             cdiv64(K1 - k1, SCHUR_TILE) * cdiv64(d.m - K1, SCHUR_TILE));
             }
             StepTasks &S = lv.steps[st];
             tb.add(S.panel, act, o1);
@@ -334,9 +341,32 @@ void Context::ensure_symbolic(Plan &p) {
             tb.add(S.schur, act, sh);
             for (int f : act) {
                 const FrontDesc &d = p.h_fd[f];
-                double k0 = st * FNB, kb = std::min(FNB, d.p - st * FNB), rest = d.m - k0 - kb;
-                S.schur.flops += 2.0 * rest * rest * kb;
-                S.schur.elems += 2.0 * rest * rest + 2.0 * rest * kb;   // C read + write, A, B
+                double k0 = st * FNB, kb = std::min(FNB, d.p - st * FNB);
+                double K1 = std::min(d.p, (st * FNB / SB + 1) * SB);
+                double rows = d.m - k0 - kb, cols = K1 - k0 - kb, strip = d.m - K1;
+                S.schur.flops += 2.0 * (rows * cols + cols * strip) * kb;
+                S.schur.elems += 2.0 * (rows * cols + cols * strip) + (rows + cols + strip) * kb;
+            }
+        }
+        lv.outer.assign(maxsb, OuterTasks{});
+        for (int T = 0; T < maxsb; T++) {
+            std::vector<int32_t> act;
+            std::vector<int64_t> sh;
+            for (int f : fl) {
+                const FrontDesc &d = p.h_fd[f];
+                int K0 = T * SB;
+                if (d.p <= K0) continue;
+                int K1 = std::min(d.p, K0 + SB);
+                act.push_back(f);
+                sh.push_back(cdiv64(d.m - K1, SCHUR_TILE) * cdiv64(d.m - K1, SCHUR_TILE));
+            }
+            OuterTasks &O = lv.outer[T];
+            tb.add(O.schur, act, sh);
+            for (int f : act) {
+                const FrontDesc &d = p.h_fd[f];
+                double K0 = T * SB, kd = std::min(SB, d.p - T * SB), rest = d.m - K0 - kd;
+                O.schur.flops += 2.0 * rest * rest * kd;
+                O.schur.elems += 2.0 * rest * rest + 2.0 * rest * kd;
             }
         }
         {
@@ -344,31 +374,30 @@ void Context::ensure_symbolic(Plan &p) {
             for (int f : fl) gi.push_back(cdiv64(p.h_fd[f].m, 256));
             tb.add(lv.fgather, fl, gi);
         }
-        lv.diag.assign(maxsb, TaskList{});
-        lv.fupd.assign(maxsb, TaskList{});
-        lv.bupd.assign(maxsb, TaskList{});
+        lv.fstep.assign(maxsb, TaskList{});
+        lv.bstep.assign(maxsb, TaskList{});
         for (int st = 0; st < maxsb; st++) {
-            std::vector<int32_t> da, fa, ba;
-            std::vector<int64_t> di, fi, bi;
+            std::vector<int32_t> act;
+            std::vector<int64_t> fi, bi;
             for (int f : fl) {
                 const FrontDesc &d = p.h_fd[f];
                 int t0 = st * SB;
                 if (d.p <= t0) continue;
                 int tend = std::min(d.p, t0 + SB);
-                da.push_back(f); di.push_back(1);
-                if (d.m > tend) { fa.push_back(f); fi.push_back(cdiv64(d.m - tend, 64)); }
-                if (st >= 1) { ba.push_back(f); bi.push_back((int64_t)st * (SB / 64)); }
+                int64_t na = cdiv64(tend - t0, 64);
+                act.push_back(f);
+                fi.push_back(na + cdiv64(d.m - tend, 64));
+                bi.push_back(na + cdiv64(t0, 64));
             }
-            tb.add(lv.diag[st], da, di);
-            tb.add(lv.fupd[st], fa, fi);
-            tb.add(lv.bupd[st], ba, bi);
-            for (int f : da) {
+            tb.add(lv.fstep[st], act, fi);
+            tb.add(lv.bstep[st], act, bi);
+            for (int f : act) {
                 const FrontDesc &d = p.h_fd[f];
                 double t0 = st * SB, sw = std::min(SB, d.p - st * SB), tend = t0 + sw;
-                lv.diag[st].elems += 0.5 * sw * (sw + 1);
-                lv.diag[st].rows += sw;
-                if (d.m > tend) { lv.fupd[st].elems += (d.m - tend) * sw; lv.fupd[st].rows += d.m - tend; }
-                if (st >= 1) { lv.bupd[st].elems += t0 * sw; lv.bupd[st].rows += t0; }
+                lv.fstep[st].elems += 0.5 * sw * (sw + 1) + (d.m - tend) * sw;
+                lv.fstep[st].rows += 2.0 * sw + (d.m - tend);
+                lv.bstep[st].elems += 0.5 * sw * (sw + 1) + t0 * sw;
+                lv.bstep[st].rows += 2.0 * sw + t0;
             }
         }
     }
@@ -468,14 +497,22 @@ void Context::factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel, S
                             S.panel, (int)t, thresh, s);
             launch_trsm_u<T>(A, fd, f.ipiv.template ptr<int32_t>(), S.trsm_u, (int)t, s);
             launch_trsm_l<T>(A, fd, S.rows_below, (int)t, s);
-            bool pr = prof_on("schur") && S.schur.total > 0;
-            if (pr) prof_begin();
-            launch_schur<T>(A, fd, S.schur, (int)t, s);
-            if (pr) prof_end(S.schur.elems * sizeof(T), S.schur.flops);
+            launch_schur<T>(A, fd, S.schur, (int)t, false, s);
+            // end of an outer block (for every front whose block ends here or earlier)
+            int ob = (int)t / (SB / FNB);
+            bool last = ((int)t % (SB / FNB) == SB / FNB - 1) || t + 1 == lv.steps.size();
+            if (last && ob < (int)lv.outer.size()) {
+                OuterTasks &O = lv.outer[ob];
+                bool pr = prof_on("schur") && O.schur.total > 0;
+                if (pr) prof_begin();
+                launch_schur<T>(A, fd, O.schur, ob, true, s);
+                if (pr) prof_end(O.schur.elems * sizeof(T), O.schur.flops);
+            }
         }
     }
     launch_invert_diag<T>(A, fd, f.ipiv.template ptr<int32_t>(), f.prow.template ptr<int32_t>(),
-                          p.inv, s);
+                          p.inv, 3, -1, s);
+    launch_xform<T>(A, fd, p.xform, s);
     int32_t np = 0;
     d2h(&np, f.npert.template ptr<int32_t>(), 1, s);
     MBL_HIP(hipStreamSynchronize(s));
@@ -500,45 +537,31 @@ void Context::lu_apply(Plan &p, Factor<T> &f, int nrhs, const double *b, int64_t
     const T *A = f.arena.template ptr<T>();
     const FrontDesc *fd = p.d_fd.ptr<FrontDesc>();
     d_vec.ensure(sizeof(double) * std::max<int64_t>(1, p.vec_elems), &budget);
+    d_yv.ensure(sizeof(double) * std::max<int64_t>(1, p.y_elems), &budget);
     d_upart.ensure(sizeof(double) * std::max<int64_t>(1, p.part_elems), &budget);
     d_xnew.ensure(sizeof(double) * p.dim * MAXRHS, &budget);
-    double *vec = d_vec.ptr<double>();
+    double *vec = d_vec.ptr<double>(), *yv = d_yv.ptr<double>();
     double *part = d_upart.ptr<double>(), *xnew = d_xnew.ptr<double>();
     const int2 *isrc = reinterpret_cast<const int2 *>(p.d_inv_src.ptr<int32_t>());
+    auto step = [&](TaskList &tl, int t, bool fwd) {
+        const char *cls = fwd ? "fwd_update" : "bwd_update";
+        bool pr = prof_on(cls) && tl.total > 0;
+        if (pr) prof_begin();
+        launch_solve_step<T>(A, fd, tl, t, nrhs, fwd, vec, yv, s);
+        if (pr) prof_end(tl.elems * sizeof(T) + 16.0 * nrhs * tl.rows, 2.0 * nrhs * tl.elems);
+    };
     for (size_t l = 0; l < p.levels.size(); l++) {
         LevelTasks &lv = p.levels[l];
         launch_fwd_gather(fd, p.d_perm.ptr<int32_t>(), f.prow.template ptr<int32_t>(),
                           p.d_inv_ptr.ptr<int32_t>(), isrc, lv.fgather, nrhs, b, ldb, vec, s);
-        for (size_t t = 0; t < lv.diag.size(); t++) {
-            bool pd = prof_on("diag") && lv.diag[t].n > 0;
-            if (pd) prof_begin();
-            launch_diag_apply<T>(A, fd, lv.diag[t], (int)t, nrhs, true, vec, s);
-            if (pd) prof_end(lv.diag[t].elems * sizeof(T) + 16.0 * nrhs * lv.diag[t].rows, 0.0);
-            bool pu = prof_on("fwd_update") && lv.fupd[t].total > 0;
-            if (pu) prof_begin();
-            launch_fwd_update<T>(A, fd, lv.fupd[t], (int)t, nrhs, vec, s);
-            if (pu) prof_end(lv.fupd[t].elems * sizeof(T) + 16.0 * nrhs * lv.fupd[t].rows,
-                             2.0 * nrhs * lv.fupd[t].elems);
-        }
+        for (size_t t = 0; t < lv.fstep.size(); t++) step(lv.fstep[t], (int)t, true);
     }
     for (size_t l = p.levels.size(); l-- > 0;) {
         LevelTasks &lv = p.levels[l];
         launch_bwd_gather(fd, p.d_contrib.ptr<int32_t>(), lv.gather, nrhs, xnew, p.dim, vec, s);
         launch_bwd_u12<T>(A, fd, lv.u12, nrhs, vec, part, s);
-        launch_bwd_u12_reduce(fd, lv.u12red, nrhs, vec, part, s);
-        for (size_t t = lv.diag.size(); t-- > 0;) {
-            bool pd = prof_on("diag") && lv.diag[t].n > 0;
-            if (pd) prof_begin();
-            launch_diag_apply<T>(A, fd, lv.diag[t], (int)t, nrhs, false, vec, s);
-            if (pd) prof_end(lv.diag[t].elems * sizeof(T) + 16.0 * nrhs * lv.diag[t].rows, 0.0);
-            if (t >= 1) {
-                bool pu = prof_on("bwd_update") && lv.bupd[t].total > 0;
-                if (pu) prof_begin();
-                launch_bwd_update<T>(A, fd, lv.bupd[t], (int)t, nrhs, vec, s);
-                if (pu) prof_end(lv.bupd[t].elems * sizeof(T) + 16.0 * nrhs * lv.bupd[t].rows,
-                                 2.0 * nrhs * lv.bupd[t].elems);
-            }
-        }
+        launch_bwd_u12_reduce(fd, lv.u12red, nrhs, yv, part, s);
+        for (size_t t = lv.bstep.size(); t-- > 0;) step(lv.bstep[t], (int)t, false);
         launch_bwd_scatter(fd, p.d_perm.ptr<int32_t>(), lv.scatter, nrhs, vec, xnew, p.dim, x, ldx,
                            s);
     }

@@ -18,8 +18,12 @@
 
 namespace mbl {
 
-struct StepTasks {                    // one panel of the blocked LU
+struct StepTasks {                    // one 64-wide panel of the blocked LU
     TaskList panel, trsm_u, rows_below, schur;
+};
+
+struct OuterTasks {                   // one 256-wide outer block
+    TaskList schur;
 };
 
 struct LevelTasks {
@@ -29,8 +33,9 @@ struct LevelTasks {
     TaskList gather, scatter;          // row chunks
     std::vector<TaskList> ext;         // extend-add, one list per child slot
     std::vector<StepTasks> steps;
+    std::vector<OuterTasks> outer;
     // triangular solves, one list per SB-wide solve block
-    std::vector<TaskList> diag, fupd, bupd;
+    std::vector<TaskList> fstep, bstep;
     TaskList fgather;                  // forward right-hand sides, 256-row items
     TaskList u12, u12red;              // U12 x_c tiles and their reduction
     int64_t part_elems = 0;            // level scratch of the U12 partial products
@@ -47,6 +52,8 @@ struct Plan {
     int64_t arena_elems = 0, vec_elems = 0;
     std::vector<LevelTasks> levels;
     TaskList inv;                      // SB diagonal blocks of every front (inversion)
+    TaskList xform;                    // 16-row panels folded with the inverted blocks
+    int64_t y_elems = 0;               // forward-solution blocks (sum of p x 16)
     int64_t part_elems = 0;            // max over levels
     DevBuf d_fd, d_perm, d_contrib, d_relmap, d_child_ids, d_tfronts, d_tprefix;
     DevBuf d_efront, d_epos, d_esrc, d_inv_ptr, d_inv_src;
@@ -133,7 +140,7 @@ class Context {
     std::map<int, std::unique_ptr<Plan>> plans_;
     Factor<float> f32_;
     Factor<double> f64_;
-    DevBuf d_vec, d_upart, d_xnew, d_r, d_d, d_part, d_V, d_V2, d_W, d_small, d_tnpart;
+    DevBuf d_vec, d_yv, d_upart, d_xnew, d_r, d_d, d_part, d_V, d_V2, d_W, d_small, d_tnpart;
     template <class T> void factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel,
                                      SolveStats &st);
     template <class T> void lu_apply(Plan &p, Factor<T> &f, int nrhs, const double *b,
