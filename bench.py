@@ -2,13 +2,15 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--L 18] [--no-cpu]
 
-One step = one whole solve of one disorder realization (fields from the seed,
-Hamiltonian assembly, extremal energies, multifrontal LU of H - sigma, block
-Krylov-Schur on (H - sigma)^-1 with FP64-refined shifted solves, selection,
-r / S_1 / S_E); the per-L ordering and front tables are built during warm-up.
-Steps run over seeds 0..K-1 at h = 3, eps = 0.5, nev = 50 (the L = 18
-reference configuration; L = 20 with --L 20).  ``value`` counts the eigenpairs
-with ||H psi - E psi|| <= 1e-9 ||H|| per second of wall time.
+One step = one whole solve of one disorder realization and target (fields
+from the seed, Hamiltonian assembly, extremal energies, multifrontal LU of
+H - sigma, block Krylov-Schur on (H - sigma)^-1 with FP64-refined shifted
+solves, selection, r / S_1 / S_E); the per-L ordering and front tables are
+built during warm-up.  At L = 20 (the default) the steps walk the reference
+grid seed 0.., h in {2, 3, 4}, eps in {0.2, 0.5, 0.8} (first K of the 45
+solves); at L = 18 they are seeds 0..K-1 at h = 3, eps = 0.5.  nev = 50.
+``value`` counts eigenpairs with ||H psi - E psi|| <= 1e-9 ||H|| per second of
+wall time.
 
 Prints one JSON line (rank 0).  Besides the contract fields it carries
 ``latency_ms`` (p50 / p99 per solve), ``mixed`` (the FP32-LU + FP64-refinement
@@ -44,10 +46,18 @@ def percentile(xs, q):
     return xs[f] + (xs[c] - xs[f]) * (k - f)
 
 
-def run_steps(ctx, mbl, L, seeds, prec, nev, h, eps, tol=1e-9):
+def workload(L, steps):
+    """(seed, h, eps) of the timed steps."""
+    if L >= 20:
+        grid = [(s, h, e) for s in range(5) for h in (2.0, 3.0, 4.0) for e in (0.2, 0.5, 0.8)]
+        return [grid[i % len(grid)] for i in range(steps)]
+    return [(s, 3.0, 0.5) for s in range(steps)]
+
+
+def run_steps(ctx, mbl, L, cases, prec, nev, tol=1e-9):
     lat, conv = [], 0
     res = []
-    for s in seeds:
+    for (s, h, eps) in cases:
         t0 = time.perf_counter()
         g = ctx.mbl_solve(L, h, s, eps, nev, prec=prec, allow_notconv=True)
         lat.append(time.perf_counter() - t0)
@@ -103,13 +113,14 @@ def cpu_baseline(L, nev, budget_s=20.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--L", type=int, default=18)
+    ap.add_argument("--L", type=int, default=20)
+    ap.add_argument("--l18-steps", type=int, default=10)
     ap.add_argument("--nev", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--roofline-kernel", default="fwd_update")
+    ap.add_argument("--roofline-kernel", default="schur")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no collectives); use --gpus 1",
@@ -118,30 +129,30 @@ def main():
 
     import paper_1411_0660_amd as mbl
 
-    L, nev, h, eps = a.L, a.nev, 3.0, 0.5
+    L, nev = a.L, a.nev
     ctx = mbl.Context(0)
     info = ctx.mbl_symbolic(L)
-    warm = list(range(1000, 1000 + a.warmup))
-    seeds = list(range(a.steps))
-    run_steps(ctx, mbl, L, warm, mbl.MBL_FP64, nev, h, eps)
+    cases = workload(L, a.steps)
+    run_steps(ctx, mbl, L, [(1000 + i, 3.0, 0.5) for i in range(a.warmup)], mbl.MBL_FP64, nev)
 
     ctx.mbl_profile_enable(a.roofline_kernel)
     t0 = time.perf_counter()
-    lat, conv, res = run_steps(ctx, mbl, L, seeds, mbl.MBL_FP64, nev, h, eps)
+    lat, conv, res = run_steps(ctx, mbl, L, cases, mbl.MBL_FP64, nev)
     wall = time.perf_counter() - t0
     prof = ctx.mbl_profile_read()
     ctx.mbl_profile_enable(None)
 
+    desc = ("seed 0.., h in {2,3,4}, eps in {0.2,0.5,0.8} (first %d of 45)" % a.steps if L >= 20
+            else "h=3, eps=0.5, seeds 0..%d" % (a.steps - 1))
     out = {
         "metric": METRIC, "value": conv / wall, "unit": "eigenpairs/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * wall / a.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": (f"L={L} random-field Heisenberg chain, S^z=0 sector dim "
-                                f"{info['dim']}, J=1, h={h}, eps={eps}, nev={nev}, seeds "
-                                f"0..{a.steps - 1} (SplitMix64 fields), FP64 multifrontal LU"),
-                   "L": L, "dim": info["dim"], "nev": nev, "h": h, "eps": eps,
-                   "precision": "fp64"},
+                                f"{info['dim']}, J=1, nev={nev}, {desc}, SplitMix64 fields, "
+                                f"FP64 multifrontal LU"),
+                   "L": L, "dim": info["dim"], "nev": nev, "precision": "fp64"},
         "latency_ms": {"p50": 1e3 * percentile(lat, 0.5), "p99": 1e3 * percentile(lat, 0.99)},
         "converged": conv, "requested": nev * a.steps,
         "phases_s": {k: sum(r["t_phase"][i] for r in res) / len(res)
@@ -155,8 +166,10 @@ def main():
             ach = prof["flops"] / prof["seconds"] / 1e12
             out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
                                "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
-                               "kernel": "k_schur<double>", "launches": prof["launches"],
-                               "avg_launch_us": 1e6 * per_launch}
+                               "kernel": "k_schur<double> (outer-block K=256 updates)",
+                               "launches": prof["launches"],
+                               "avg_launch_us": 1e6 * per_launch,
+                               "flops_per_launch": prof["flops"] / prof["launches"]}
         else:
             ach = prof["bytes"] / prof["seconds"] / 1e9
             out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
@@ -165,7 +178,7 @@ def main():
                                "avg_launch_us": 1e6 * per_launch}
     if not a.no_mixed:
         t0 = time.perf_counter()
-        lat2, conv2, res2 = run_steps(ctx, mbl, L, seeds, mbl.MBL_FP32_IR64, nev, h, eps)
+        lat2, conv2, res2 = run_steps(ctx, mbl, L, cases, mbl.MBL_FP32_IR64, nev)
         wall2 = time.perf_counter() - t0
         out["mixed"] = {"value": conv2 / wall2, "ms_per_step": 1e3 * wall2 / a.steps,
                         "dtype": "fp32 LU + fp64 refinement",
@@ -176,10 +189,31 @@ def main():
                         "max_abs_eval_diff_vs_fp64": max(
                             float(max(abs(x - y) for x, y in zip(r1["evals"], r2["evals"])))
                             for r1, r2 in zip(res, res2))}
+    if L != 18 and a.l18_steps > 0:
+        info18 = ctx.mbl_symbolic(18)
+        cases18 = workload(18, a.l18_steps)
+        run_steps(ctx, mbl, 18, [(1000, 3.0, 0.5)], mbl.MBL_FP64, nev)
+        t0 = time.perf_counter()
+        lat3, conv3, _ = run_steps(ctx, mbl, 18, cases18, mbl.MBL_FP64, nev)
+        wall3 = time.perf_counter() - t0
+        out["L18"] = {"value": conv3 / wall3, "unit": "eigenpairs/s",
+                      "ms_per_step": 1e3 * wall3 / a.l18_steps, "dim": info18["dim"],
+                      "workload": "L=18, h=3, eps=0.5, nev=50, seeds 0..%d, FP64" % (a.l18_steps - 1),
+                      "latency_ms": {"p50": 1e3 * percentile(lat3, 0.5),
+                                     "p99": 1e3 * percentile(lat3, 0.99)}}
     ctx.close()
     if not a.no_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(L, nev)
+            if out["cpu_baseline"]["value"] is None and L > 18:
+                # the dense oracle does not fit at this L: time it at L = 18 and
+                # scale by the n^3 cost of the tridiagonalisation
+                b18 = cpu_baseline(18, nev)
+                n18, nL = math.comb(18, 9), math.comb(L, L // 2)
+                out["cpu_baseline"] = dict(b18, value=b18["value"] * (n18 / nL) ** 3,
+                                           sample=b18["sample"] + f"; scaled by (dim18/dim{L})^3 "
+                                           f"to L={L} (dense H at L={L} needs "
+                                           f"{8.0 * nL * nL / 1e9:.0f} GB)")
         except MemoryError:
             out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

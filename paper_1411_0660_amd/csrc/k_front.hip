@@ -426,8 +426,14 @@ template <> struct MfmaAcc<float> {
 };
 
 constexpr int ST = SCHUR_TILE;       // 128
-constexpr int SP = ST + 2;           // padded LDS row
-constexpr int KC = 32;               // K columns staged per pass
+constexpr int SP = ST + 8;           // LDS row of A and B: 4 k-rows read by a wave land on
+                                     // different bank quarters
+// K columns staged per pass (FP64 half as many, to keep the prefetch and the
+// 64 accumulators of a lane inside the register budget of two waves per SIMD)
+template <class T> struct SchurCfg {
+    static constexpr int KC = sizeof(T) == 8 ? 16 : 32;
+    static constexpr int PF = ST * KC / 256;   // elements of A (and of B) per thread
+};
 
 // big = 0: update after panel t inside its outer SB block, K = the panel's kb
 //          columns: the first tiles cover the rows below the panel and the
@@ -435,10 +441,13 @@ constexpr int KC = 32;               // K columns staged per pass
 //          rows of the outer block and every column right of it;
 // big = 1: update of outer block t, K = its (up to SB) columns, everything
 //          right of and below it (including the contribution block).
+// The next K chunk is fetched from HBM into registers while the current one
+// feeds the matrix cores from LDS.
 template <class T>
 __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__restrict__ fd,
                                                   TaskList tl, int t, int big) {
     typedef typename MfmaAcc<T>::v4 v4;
+    constexpr int KC = SchurCfg<T>::KC, PF = SchurCfg<T>::PF;
     __shared__ T smem[2 * KC * SP > 64 * (ST + 1) ? 2 * KC * SP : 64 * (ST + 1)];
     T *As = smem;                    // As[k * SP + i]
     T *Bs = smem + KC * SP;          // Bs[k * SP + j]
@@ -462,24 +471,40 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int wr = (w & 1) * 64, wc = (w >> 1) * 64;
     int li = lane & 15, lk = lane >> 4;
+    // global -> register prefetch of one K chunk: A rows i = e % ST (coalesced
+    // down the column), B rows k = e % KC (contiguous k of one column)
+    T pa[PF], pb[PF];
+    auto fetch = [&](int kc) {
+        int kn = min(KC, kd - kc);
+#pragma unroll
+        for (int q = 0; q < PF; q++) {
+            int e = threadIdx.x + q * 256;
+            int i = e % ST, kk = e / ST, r = r0 + i;
+            pa[q] = (r < rhi && kk < kn) ? F[r + (int64_t)(kc0 + kc + kk) * m] : T(0);
+            int kb2 = e % KC, j = e / KC, c = c0 + j;
+            pb[q] = (c < chi && kb2 < kn) ? F[(int64_t)(kc0 + kc + kb2) + (int64_t)c * m] : T(0);
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int q = 0; q < PF; q++) {
+            int e = threadIdx.x + q * 256;
+            As[(e / ST) * SP + (e % ST)] = pa[q];
+            Bs[(e % KC) * SP + (e / KC)] = pb[q];
+        }
+    };
     v4 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; a++)
 #pragma unroll
         for (int b = 0; b < 4; b++) acc[a][b] = v4{0, 0, 0, 0};
+    fetch(0);
     for (int kc = 0; kc < kd; kc += KC) {
-        int kn = min(KC, kd - kc);
         __syncthreads();
-        for (int e = threadIdx.x; e < ST * KC; e += blockDim.x) {
-            int i = e % ST, kk = e / ST, r = r0 + i;
-            As[kk * SP + i] = (r < rhi && kk < kn) ? F[r + (int64_t)(kc0 + kc + kk) * m] : T(0);
-        }
-        for (int e = threadIdx.x; e < ST * KC; e += blockDim.x) {
-            int kk = e % KC, j = e / KC, c = c0 + j;
-            Bs[kk * SP + j] = (c < chi && kk < kn) ? F[(int64_t)(kc0 + kc + kk) + (int64_t)c * m] : T(0);
-        }
+        stash();
         __syncthreads();
-        int ksteps = (kn + 3) / 4;
+        if (kc + KC < kd) fetch(kc + KC);
+        int ksteps = (min(KC, kd - kc) + 3) / 4;
         for (int ks = 0; ks < ksteps; ks++) {
             int kk = ks * 4 + lk;
             T av[4], bv[4];
