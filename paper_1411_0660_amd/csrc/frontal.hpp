@@ -36,6 +36,7 @@ struct FrontDesc {
 struct TaskList {
     const int32_t *fronts;   // front ids
     const int64_t *prefix;   // prefix[k] = first work item of fronts[k]; prefix[n] = total
+    const int2 *items;       // per work item: (front id, item index inside the front)
     int32_t n;
     int64_t total;
     double elems;            // factor entries the launch streams (algorithmic)

@@ -78,94 +78,142 @@ __global__ __launch_bounds__(BS) void k_residual(int64_t n, const int32_t *__res
     }
 }
 
-// C = A^T B: each block reduces a fixed contiguous row range into k*b partials
+// C = A^T B (A n x k, B n x b, column major).  The rows are cut into nparts
+// fixed contiguous ranges and the columns of A into chunks of TN_KC; block
+// (range, chunk) walks its range in LDS tiles of TN_ROWS rows.  A thread owns
+// one column of A and all b columns of B over one row group of the tile; the
+// row groups are combined in a fixed order at the end, so the partials (and
+// the fixed-order sum over ranges) are reproducible.
 constexpr int TN_ROWS = 32;
-constexpr int TN_MAXACC = 16;  // k*b <= 16 * BS
+constexpr int TN_KC = 128;
 
+template <int NB>
 __global__ __launch_bounds__(BS) void k_gemm_tn_part(int64_t n, int k, int b,
                                                      const double *__restrict__ A, int64_t lda,
                                                      const double *__restrict__ B, int64_t ldb,
                                                      double *__restrict__ partials,
                                                      int64_t rows_per_part) {
     extern __shared__ double sm[];
-    double *sA = sm;                   // [TN_ROWS][k]
-    double *sB = sm + TN_ROWS * k;     // [TN_ROWS][b]
+    const int c0 = blockIdx.y * TN_KC;
+    const int kc = min(TN_KC, k - c0);
+    const int lda_s = kc + 1;                 // odd stride: rows of a tile fall in different banks
+    double *sA = sm;                          // [TN_ROWS][kc + 1]
+    double *sB = sm + TN_ROWS * lda_s;        // [TN_ROWS][NB]
+    const int G = min(TN_ROWS, BS / kc);      // row groups
+    const int i = threadIdx.x % kc, g = threadIdx.x / kc;
+    const bool active = g < G;
     int64_t r0 = (int64_t)blockIdx.x * rows_per_part;
-    int64_t r1 = r0 + rows_per_part;
-    if (r1 > n) r1 = n;
-    int kb = k * b;
-    double acc[TN_MAXACC];
+    int64_t r1 = min(r0 + rows_per_part, n);
+    double acc[NB];
 #pragma unroll
-    for (int q = 0; q < TN_MAXACC; q++) acc[q] = 0.0;
+    for (int j = 0; j < NB; j++) acc[j] = 0.0;
     for (int64_t r = r0; r < r1; r += TN_ROWS) {
-        int nr = (int)((r1 - r) < TN_ROWS ? (r1 - r) : TN_ROWS);
-        for (int t = threadIdx.x; t < TN_ROWS * k; t += BS) {
-            int rr = t % TN_ROWS, i = t / TN_ROWS;
-            sA[rr * k + i] = (rr < nr) ? A[r + rr + (int64_t)i * lda] : 0.0;
+        int nr = (int)min((int64_t)TN_ROWS, r1 - r);
+        for (int t = threadIdx.x; t < TN_ROWS * kc; t += BS) {
+            int rr = t % TN_ROWS, c = t / TN_ROWS;
+            sA[rr * lda_s + c] = rr < nr ? A[r + rr + (int64_t)(c0 + c) * lda] : 0.0;
         }
-        for (int t = threadIdx.x; t < TN_ROWS * b; t += BS) {
+        for (int t = threadIdx.x; t < TN_ROWS * NB; t += BS) {
             int rr = t % TN_ROWS, j = t / TN_ROWS;
-            sB[rr * b + j] = (rr < nr) ? B[r + rr + (int64_t)j * ldb] : 0.0;
+            sB[rr * NB + j] = (rr < nr && j < b) ? B[r + rr + (int64_t)j * ldb] : 0.0;
         }
         __syncthreads();
+        if (active)
+            for (int rr = g; rr < nr; rr += G) {
+                double x = sA[rr * lda_s + i];
 #pragma unroll
-        for (int q = 0; q < TN_MAXACC; q++) {
-            int o = threadIdx.x + q * BS;
-            if (o < kb) {
-                int i = o % k, j = o / k;
-                double s = 0.0;
-                for (int rr = 0; rr < TN_ROWS; rr++) s += sA[rr * k + i] * sB[rr * b + j];
-                acc[q] += s;
+                for (int j = 0; j < NB; j++) acc[j] += x * sB[rr * NB + j];
             }
-        }
         __syncthreads();
     }
+    // combine the row groups: red[g][j][i]
+    double *red = sm;
+    if (active)
 #pragma unroll
-    for (int q = 0; q < TN_MAXACC; q++) {
-        int o = threadIdx.x + q * BS;
-        if (o < kb) partials[(int64_t)blockIdx.x * kb + o] = acc[q];
+        for (int j = 0; j < NB; j++) red[((int64_t)g * NB + j) * kc + i] = acc[j];
+    __syncthreads();
+    int kb = k * b;
+    for (int o = threadIdx.x; o < kc * b; o += BS) {
+        int ii = o % kc, j = o / kc;
+        double sum = 0.0;
+        for (int q = 0; q < G; q++) sum += red[((int64_t)q * NB + j) * kc + ii];
+        partials[(int64_t)blockIdx.x * kb + c0 + ii + (int64_t)j * k] = sum;
     }
 }
 
-__global__ void k_sum_parts(int kb, int nparts, const double *__restrict__ partials,
-                            double *__restrict__ C) {
-    int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= kb) return;
+// C[o] = sum over the ranges in order: SP_G groups of consecutive ranges per
+// output, combined in a fixed order
+constexpr int SP_G = 8;
+
+__global__ __launch_bounds__(64 * SP_G) void k_sum_parts(int kb, int nparts,
+                                                        const double *__restrict__ partials,
+                                                        double *__restrict__ C) {
+    __shared__ double red[SP_G][64];
+    int l = threadIdx.x % 64, g = threadIdx.x / 64;
+    int o = blockIdx.x * 64 + l;
+    int p0 = (int)((int64_t)nparts * g / SP_G), p1 = (int)((int64_t)nparts * (g + 1) / SP_G);
     double s = 0.0;
-    for (int p = 0; p < nparts; p++) s += partials[(int64_t)p * kb + o];
-    C[o] = s;
+    if (o < kb) {
+        const double *q = partials + o;
+#pragma unroll 8
+        for (int p = p0; p < p1; p++) s += q[(int64_t)p * kb];
+    }
+    red[g][l] = s;
+    __syncthreads();
+    if (g == 0 && o < kb) {
+        double t = red[0][l];
+#pragma unroll
+        for (int q = 1; q < SP_G; q++) t += red[q][l];
+        C[o] = t;
+    }
 }
 
-// C = beta C + alpha A Y for up to 16 output columns per launch
+// C = beta C + alpha A Y for up to 16 output columns per launch: 64 rows per
+// block, the k columns of A split over four waves and combined in order
 constexpr int NN_MAXB = 16;
+constexpr int NN_ROWS = 64;
+constexpr int NN_KG = BS / NN_ROWS;
 
+template <int NB>
 __global__ __launch_bounds__(BS) void k_gemm_nn(int64_t n, int k, int b, double alpha,
                                                 const double *__restrict__ A, int64_t lda,
                                                 const double *__restrict__ Y, int ldy, double beta,
                                                 double *__restrict__ C, int64_t ldc) {
-    extern __shared__ double sY[];    // [k][b]
-    for (int t = threadIdx.x; t < k * b; t += BS) {
-        int i = t % k, j = t / k;
-        sY[i * b + j] = Y[i + (int64_t)j * ldy];
+    extern __shared__ double sm[];
+    double *sY = sm;                                  // [k][NB]
+    double *red = sm + (int64_t)k * NB;               // [NN_KG][NN_ROWS][NB]
+    for (int t = threadIdx.x; t < k * NB; t += BS) {
+        int i = t / NB, j = t % NB;
+        sY[t] = j < b ? Y[i + (int64_t)j * ldy] : 0.0;
     }
     __syncthreads();
-    int64_t row = (int64_t)blockIdx.x * BS + threadIdx.x;
-    if (row >= n) return;
-    double acc[NN_MAXB];
+    int lane = threadIdx.x % NN_ROWS, g = threadIdx.x / NN_ROWS;
+    int64_t row = (int64_t)blockIdx.x * NN_ROWS + lane;
+    int i0 = k * g / NN_KG, i1 = k * (g + 1) / NN_KG;
+    double acc[NB];
 #pragma unroll
-    for (int j = 0; j < NN_MAXB; j++) acc[j] = 0.0;
-    for (int i = 0; i < k; i++) {
-        double a = A[row + (int64_t)i * lda];
+    for (int j = 0; j < NB; j++) acc[j] = 0.0;
+    if (row < n) {
+        const double *a = A + row;
+#pragma unroll 4
+        for (int i = i0; i < i1; i++) {
+            double x = a[(int64_t)i * lda];
 #pragma unroll
-        for (int j = 0; j < NN_MAXB; j++)
-            if (j < b) acc[j] += a * sY[i * b + j];
+            for (int j = 0; j < NB; j++) acc[j] += x * sY[i * NB + j];
+        }
     }
 #pragma unroll
-    for (int j = 0; j < NN_MAXB; j++)
-        if (j < b) {
-            double *c = C + row + (int64_t)j * ldc;
-            *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * acc[j];
-        }
+    for (int j = 0; j < NB; j++) red[(g * NN_ROWS + lane) * NB + j] = acc[j];
+    __syncthreads();
+    for (int t = threadIdx.x; t < NN_ROWS * b; t += BS) {
+        int l = t % NN_ROWS, j = t / NN_ROWS;
+        int64_t r = (int64_t)blockIdx.x * NN_ROWS + l;
+        if (r >= n) continue;
+        double sum = 0.0;
+        for (int q = 0; q < NN_KG; q++) sum += red[(q * NN_ROWS + l) * NB + j];
+        double *c = C + r + (int64_t)j * ldc;
+        *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * sum;
+    }
 }
 
 __global__ void k_gather(int64_t n, int nvec, const int32_t *__restrict__ idx,
@@ -272,7 +320,8 @@ void launch_residual(int64_t n, const int32_t *rowptr, const int32_t *col, const
 }
 
 int gemm_tn_parts(int64_t n) {
-    int64_t p = (n + 2047) / 2048;      // ~2048 rows per block
+    // ranges of at least 64 rows, at most 512 of them
+    int64_t p = (n + 63) / 64;
     if (p < 1) p = 1;
     if (p > 512) p = 512;
     return (int)p;
@@ -280,29 +329,48 @@ int gemm_tn_parts(int64_t n) {
 
 void launch_gemm_tn(int64_t n, int k, int b, const double *A, int64_t lda, const double *B,
                     int64_t ldb, double *C, double *partials, int nparts, hipStream_t s) {
-    MBL_REQUIRE(k * b <= TN_MAXACC * BS, MBL_EINVAL, "gemm_tn: k*b too large");
+    MBL_REQUIRE(b >= 0 && b <= NN_MAXB && k >= 0, MBL_EINVAL, "gemm_tn: b must be at most 16");
     if (k == 0 || b == 0) return;
     int64_t rpp = (n + nparts - 1) / nparts;
     rpp = (rpp + TN_ROWS - 1) / TN_ROWS * TN_ROWS;
-    size_t sh = sizeof(double) * TN_ROWS * (size_t)(k + b);
-    hipLaunchKernelGGL(k_gemm_tn_part, dim3(nparts), dim3(BS), sh, s, n, k, b, A, lda, B, ldb,
-                       partials, rpp);
+    int kc = std::min(k, TN_KC);
+    auto go = [&](auto nbc) {
+        constexpr int NB = decltype(nbc)::value;
+        int G = std::min(TN_ROWS, BS / kc);
+        size_t tile = sizeof(double) * TN_ROWS * ((size_t)kc + 1 + NB);
+        size_t red = sizeof(double) * (size_t)G * NB * kc;
+        size_t sh = std::max(tile, red);
+        k_gemm_tn_part<NB><<<dim3((unsigned)nparts, (unsigned)((k + TN_KC - 1) / TN_KC)), dim3(BS),
+                             sh, s>>>(n, k, b, A, lda, B, ldb, partials, rpp);
+    };
+    if (b <= 4) go(std::integral_constant<int, 4>{});
+    else if (b <= 8) go(std::integral_constant<int, 8>{});
+    else go(std::integral_constant<int, 16>{});
     MBL_CHECK_LAUNCH();
     int kb = k * b;
-    hipLaunchKernelGGL(k_sum_parts, dim3(grid_for(kb, 256)), dim3(256), 0, s, kb, nparts, partials,
-                       C);
+    k_sum_parts<<<dim3(grid_for(kb, 64)), dim3(64 * SP_G), 0, s>>>(kb, nparts, partials, C);
     MBL_CHECK_LAUNCH();
 }
 
 void launch_gemm_nn(int64_t n, int k, int b, double alpha, const double *A, int64_t lda,
                     const double *Y, int ldy, double beta, double *C, int64_t ldc, hipStream_t s) {
     if (n == 0 || b == 0) return;
+    constexpr int KN = 256;    // columns of A per launch (LDS for Y stays under 64 KB)
     for (int j0 = 0; j0 < b; j0 += NN_MAXB) {
         int bb = (b - j0) < NN_MAXB ? (b - j0) : NN_MAXB;
-        size_t sh = sizeof(double) * (size_t)k * bb;
-        MBL_REQUIRE(sh <= 64 * 1024, MBL_EINVAL, "gemm_nn: k too large");
-        hipLaunchKernelGGL(k_gemm_nn, dim3(grid_for(n, BS)), dim3(BS), sh, s, n, k, bb, alpha, A,
-                           lda, Y + (int64_t)j0 * ldy, ldy, beta, C + (int64_t)j0 * ldc, ldc);
+        auto go = [&](auto nbc) {
+            constexpr int NB = decltype(nbc)::value;
+            for (int k0 = 0; k0 < std::max(k, 1); k0 += KN) {
+                int kk = std::min(KN, k - k0);
+                size_t sh = sizeof(double) * ((size_t)kk * NB + (size_t)NN_KG * NN_ROWS * NB);
+                k_gemm_nn<NB><<<dim3(grid_for(n, NN_ROWS)), dim3(BS), sh, s>>>(
+                    n, kk, bb, alpha, A + (int64_t)k0 * lda, lda, Y + k0 + (int64_t)j0 * ldy, ldy,
+                    k0 == 0 ? beta : 1.0, C + (int64_t)j0 * ldc, ldc);
+            }
+        };
+        if (bb <= 4) go(std::integral_constant<int, 4>{});
+        else if (bb <= 8) go(std::integral_constant<int, 8>{});
+        else go(std::integral_constant<int, 16>{});
         MBL_CHECK_LAUNCH();
     }
 }

@@ -25,15 +25,6 @@
 namespace mbl {
 namespace {
 
-__device__ __forceinline__ int find_task(const int64_t *prefix, int n, int64_t w) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (prefix[mid] <= w) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 template <class T>
 __global__ void k_front_zero(T *a, int64_t lo, int64_t hi) {
     for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
@@ -60,9 +51,9 @@ template <class T>
 __global__ __launch_bounds__(256) void k_extend_add(T *arena, const FrontDesc *__restrict__ fd,
                                                     const int32_t *__restrict__ relmap,
                                                     TaskList tl) {
-    int k = find_task(tl.prefix, tl.n, blockIdx.x);
-    int ch = tl.fronts[k];
-    int j = (int)(blockIdx.x - tl.prefix[k]);
+    const int2 tk = tl.items[blockIdx.x];
+    int ch = tk.x;
+    int j = tk.y;
     FrontDesc c = fd[ch];
     FrontDesc P = fd[c.parent];
     const int32_t *map = relmap + c.mapoff;
@@ -148,9 +139,9 @@ __global__ __launch_bounds__(TRSM_U_COLS) void k_trsm_u(T *arena, const FrontDes
                                                         TaskList tl, int t) {
     __shared__ T Ls[FNB][FNB + 1];
     __shared__ int src[FNB];
-    int k = find_task(tl.prefix, tl.n, blockIdx.x);
-    FrontDesc d = fd[tl.fronts[k]];
-    int chunk = (int)(blockIdx.x - tl.prefix[k]);
+    const int2 tk = tl.items[blockIdx.x];
+    FrontDesc d = fd[tk.x];
+    int chunk = tk.y;
     int k0 = t * FNB, kb = min(FNB, d.p - k0), k1 = k0 + kb, m = d.m;
     int nleft = (k0 + TRSM_U_COLS - 1) / TRSM_U_COLS;
     T *F = arena + d.off;
@@ -206,9 +197,9 @@ __global__ __launch_bounds__(256) void k_invert_diag(T *arena, const FrontDesc *
                                                      int32_t *__restrict__ prow, TaskList tl,
                                                      int mode, int fixed_blk) {
     __shared__ double tmp[ISB][ISB + 1];
-    int k = find_task(tl.prefix, tl.n, blockIdx.x);
-    FrontDesc d = fd[tl.fronts[k]];
-    int blk = fixed_blk >= 0 ? fixed_blk : (int)(blockIdx.x - tl.prefix[k]);
+    const int2 tk = tl.items[blockIdx.x];
+    FrontDesc d = fd[tk.x];
+    int blk = fixed_blk >= 0 ? fixed_blk : tk.y;
     const bool doL = mode & 1, doU = mode & 2;
     int b0 = blk * SB, sz = min(SB, d.p - b0), m = d.m;
     T *F = arena + d.off + (int64_t)b0 * m + b0;     // block origin, leading dimension m
@@ -357,9 +348,9 @@ __global__ __launch_bounds__(256) void k_trsm_l(T *arena, const FrontDesc *__res
     __shared__ double Us[FNB][FNB + 1];
     __shared__ double Ui[FNB][FNB + 1];
     __shared__ double As[FNB][FNB + 1];     // As[k][i]: row i of the chunk, panel column k
-    int k = find_task(tl.prefix, tl.n, blockIdx.x);
-    FrontDesc d = fd[tl.fronts[k]];
-    int chunk = (int)(blockIdx.x - tl.prefix[k]);
+    const int2 tk = tl.items[blockIdx.x];
+    FrontDesc d = fd[tk.x];
+    int chunk = tk.y;
     int k0 = t * FNB, kb = min(FNB, d.p - k0), k1 = k0 + kb, m = d.m;
     int r0 = k1 + chunk * TRSM_L_ROWS, nr = min(TRSM_L_ROWS, m - r0);
     T *F = arena + d.off;
@@ -451,9 +442,9 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
     __shared__ T smem[2 * KC * SP > 64 * (ST + 1) ? 2 * KC * SP : 64 * (ST + 1)];
     T *As = smem;                    // As[k * SP + i]
     T *Bs = smem + KC * SP;          // Bs[k * SP + j]
-    int k = find_task(tl.prefix, tl.n, blockIdx.x);
-    FrontDesc d = fd[tl.fronts[k]];
-    int64_t tile = blockIdx.x - tl.prefix[k];
+    const int2 tk = tl.items[blockIdx.x];
+    FrontDesc d = fd[tk.x];
+    int64_t tile = tk.y;
     int m = d.m, kc0, kd, rlo, rhi, clo, chi;
     if (!big) {
         kc0 = t * FNB; kd = min(FNB, d.p - kc0);
@@ -556,9 +547,9 @@ __global__ __launch_bounds__(SB) void k_xform(T *arena, const FrontDesc *__restr
                                               TaskList tl) {
     __shared__ double a[XR][SB];
     __shared__ double xs[XS][SB];
-    int k = find_task(tl.prefix, tl.n, blockIdx.x);
-    FrontDesc d = fd[tl.fronts[k]];
-    int64_t w = blockIdx.x - tl.prefix[k];
+    const int2 tk = tl.items[blockIdx.x];
+    FrontDesc d = fd[tk.x];
+    int64_t w = tk.y;
     int m = d.m, nb = (d.p + SB - 1) / SB;
     // locate (block t, side, chunk): per block first the L chunks, then the U chunks
     int t = 0, side = 0, chunk = 0;

@@ -16,8 +16,9 @@
 //     V[p:m] = x(contribution rows); Y -= U12 V[p:m]   (64 x 256 tiles, fixed-order sum)
 //     block t from the last:  V_t = Uinv_tt Y_t  and  Y[rows above] -= U~[., t] Y_t
 //     afterwards V[0:p] = x of the pivots.
-// Work items are 64 rows x one SB block: the four waves of a workgroup take a
-// quarter of the columns each and are summed through LDS.
+// Work items are 64 rows x one SB block: the 8 or 16 waves of a workgroup
+// take an equal share of the columns each and are summed through LDS, which
+// keeps the dependent load chain of a lane short.
 #include <type_traits>
 
 #include "common.hpp"
@@ -28,19 +29,21 @@ namespace {
 
 constexpr int MAXRHS = 16;
 constexpr int RW = 64;          // rows per update work item (one per lane)
-constexpr int CQ = SB / 4;      // columns per wave
 
-__device__ __forceinline__ int find_task(const int64_t *prefix, int n, int64_t w) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (prefix[mid] <= w) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
+// column groups (waves) per 64-row work item: 16 for up to 8 right-hand sides,
+// 8 for 16 (LDS: the SB x NR source block plus CG x 64 x NR partial sums)
+template <int NR> struct StepCfg {
+    static constexpr int CG = NR <= 8 ? 16 : 8;
+    static constexpr int THREADS = 64 * CG;
+    static constexpr int CW = SB / CG;          // columns per wave
+    static constexpr int UNR = NR <= 8 ? 8 : 4; // column unroll (register budget)
+};
 
 // row-parallel gather of the forward right-hand side of every front
-// (including its children's updates and the row permutation of its pivots)
+// (including its children's updates and the row permutation of its pivots);
+// inv_src holds, per contribution, the element of the child's update row in
+// the solve vectors and the child's order (stride between right-hand sides)
+template <int NR>
 __global__ __launch_bounds__(256) void k_fwd_gather(const FrontDesc *__restrict__ fd,
                                                     const int32_t *__restrict__ perm,
                                                     const int32_t *__restrict__ prow,
@@ -48,104 +51,129 @@ __global__ __launch_bounds__(256) void k_fwd_gather(const FrontDesc *__restrict_
                                                     const int2 *__restrict__ inv_src, TaskList tl,
                                                     int nrhs, const double *__restrict__ b,
                                                     int64_t ldb, double *vec) {
-    int k = find_task(tl.prefix, tl.n, blockIdx.x);
-    FrontDesc d = fd[tl.fronts[k]];
-    int i = (int)(blockIdx.x - tl.prefix[k]) * 256 + threadIdx.x;
+    const int2 tk = tl.items[blockIdx.x];
+    FrontDesc d = fd[tk.x];
+    int i = tk.y * 256 + threadIdx.x;
     if (i >= d.m) return;
     int u = (i < d.p) ? prow[d.first + i] : i;        // row before the interchanges
-    double val[MAXRHS];
-    for (int r = 0; r < nrhs; r++)
-        val[r] = (u < d.p) ? b[perm[d.first + u] + (int64_t)r * ldb] : 0.0;
-    int64_t base = d.voff;                            // inverse relative map of this front
     int32_t a = inv_ptr[d.cptr_inv + u], e = inv_ptr[d.cptr_inv + u + 1];
-    for (int32_t q = a; q < e; q++) {
-        int2 s = inv_src[q];                          // (child front, row of its update)
-        FrontDesc c = fd[s.x];
-        const double *cu = vec + c.voff + c.p + s.y;
-        for (int r = 0; r < nrhs; r++) val[r] += cu[(int64_t)r * c.m];
+    double val[NR];
+    if (u < d.p) {
+        int32_t g = perm[d.first + u];
+#pragma unroll
+        for (int r = 0; r < NR; r++) val[r] = r < nrhs ? b[g + (int64_t)r * ldb] : 0.0;
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; r++) val[r] = 0.0;
     }
-    for (int r = 0; r < nrhs; r++) vec[base + i + (int64_t)r * d.m] = val[r];
+    for (int32_t q = a; q < e; q++) {
+        int2 sv = inv_src[q];
+        const double *cu = vec + sv.x;
+#pragma unroll
+        for (int r = 0; r < NR; r++) val[r] += cu[(int64_t)r * sv.y];
+    }
+    double *o = vec + d.voff + i;
+#pragma unroll
+    for (int r = 0; r < NR; r++) o[(int64_t)r * d.m] = val[r];
 }
 
-// out rows of one 64-row chunk from M[rows, SB block] times src (LDS):
-//   MODE 0: out -= M src            (panel update, in place)
-//   MODE 1: out  = src_i + sum_{j<i} M_ij src_j   (unit-lower inverse block)
-//   MODE 2: out  = sum_{j>=i} M_ij src_j           (upper inverse block)
-// lane = row, wave = quarter of the columns, sum over waves through LDS.
-template <class T, int NR, int MODE>
-__device__ __forceinline__ void chunk_apply(const T *__restrict__ Mrow0, int64_t m, int ncols,
-                                            int nrows, int rowoff, const double (*src)[NR],
-                                            double (*red)[RW][NR], double *out, int64_t ldo) {
-    int lane = threadIdx.x % RW, w = threadIdx.x / RW;
-    int j0 = w * CQ, j1 = min(j0 + CQ, ncols);
-    int i = rowoff + lane;                       // row index inside the diagonal block
-    if (MODE == 1) j1 = min(j1, i);
-    if (MODE == 2) j0 = max(j0, i);
+// One 64-row work item of solve block t: out rows from M[rows, SB block] and
+// the block's source values src (LDS):
+//   mode 0: out -= M src                            (panel update, in place)
+//   mode 1: out  = src_i + sum_{j<i} M_ij src_j     (unit-lower inverse block)
+//   mode 2: out  = sum_{j>=i} M_ij src_j            (upper inverse block)
+// lane = row, each wave an equal share of the columns, partial sums combined
+// in a fixed order through LDS.  The factor entries (and the rows updated in
+// place) are loaded before the source block is staged, so the two memory
+// round trips overlap.
+template <class T, int NR, bool FWD>
+__global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_solve_step(
+    const T *__restrict__ arena, const FrontDesc *__restrict__ fd, TaskList tl, int t,
+    double *vec, double *yv) {
+    constexpr int CG = StepCfg<NR>::CG, CW = StepCfg<NR>::CW;
+    __shared__ double src[SB][NR];
+    __shared__ double red[CG][RW][NR];
+    const int2 tk = tl.items[blockIdx.x];
+    const FrontDesc d = fd[tk.x];
+    const int w = tk.y;
+    const int m = d.m, p = d.p, t0 = t * SB, st = min(SB, p - t0), tend = t0 + st;
+    const int nA = (st + RW - 1) / RW;
+    double *V = vec + d.voff;          // ld m
+    double *Y = yv + d.yoff;           // ld p
+    int mode, r0, nrows, rowoff = 0;
+    double *out;
+    int64_t ldo;
+    if (w < nA) {                      // diagonal product
+        rowoff = w * RW;
+        r0 = t0 + rowoff;
+        nrows = min(RW, st - rowoff);
+        mode = FWD ? 1 : 2;
+        out = FWD ? Y + r0 : V + r0;
+        ldo = FWD ? p : m;
+    } else if (FWD) {                  // rows below the block
+        r0 = tend + (w - nA) * RW;
+        nrows = min(RW, m - r0);
+        mode = 0;
+        out = V + r0;
+        ldo = m;
+    } else {                           // pivot rows above the block
+        r0 = (w - nA) * RW;
+        nrows = min(RW, t0 - r0);
+        mode = 0;
+        out = Y + r0;
+        ldo = p;
+    }
+    const int lane = threadIdx.x % RW, wv = threadIdx.x / RW;
+    const int i = rowoff + lane;       // row inside the diagonal block (modes 1, 2)
+    int j0 = wv * CW, j1 = min(j0 + CW, st);
+    if (mode == 1) j1 = min(j1, i);
+    if (mode == 2) j0 = max(j0, i);
+    const bool rowok = lane < nrows;
+    double mv[CW];
+    {
+        const T *Mr = arena + d.off + r0 + lane + (int64_t)(t0 + wv * CW) * m;
+#pragma unroll
+        for (int q = 0; q < CW; q++) {
+            int j = wv * CW + q;
+            mv[q] = (rowok && j >= j0 && j < j1) ? (double)Mr[(int64_t)q * m] : 0.0;
+        }
+    }
+    double prev[NR];
+    if (mode == 0 && wv == 0 && rowok) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) prev[r] = out[lane + (int64_t)r * ldo];
+    }
+    {
+        const double *S = FWD ? V + t0 : Y + t0;
+        const int64_t lds = FWD ? m : p;
+        for (int e = threadIdx.x; e < SB * NR; e += blockDim.x) {
+            int j = e % SB, r = e / SB;
+            src[j][r] = j < st ? S[j + (int64_t)r * lds] : 0.0;
+        }
+    }
+    __syncthreads();
     double acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) acc[r] = 0.0;
-    if (lane < nrows) {
-        const T *Mr = Mrow0 + lane;
-#pragma unroll 8
-        for (int j = j0; j < j1; j++) {
-            double x = (double)Mr[(int64_t)j * m];
 #pragma unroll
-            for (int r = 0; r < NR; r++) acc[r] += x * src[j][r];
-        }
+    for (int q = 0; q < CW; q++) {
+        const double x = mv[q];
+#pragma unroll
+        for (int r = 0; r < NR; r++) acc[r] += x * src[wv * CW + q][r];
     }
 #pragma unroll
-    for (int r = 0; r < NR; r++) red[w][lane][r] = acc[r];
+    for (int r = 0; r < NR; r++) red[wv][lane][r] = acc[r];
     __syncthreads();
-    if (w == 0 && lane < nrows) {
+    if (wv == 0 && rowok) {
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            double sum = red[0][lane][r] + red[1][lane][r] + red[2][lane][r] + red[3][lane][r];
+            double sum = red[0][lane][r];
+#pragma unroll
+            for (int g = 1; g < CG; g++) sum += red[g][lane][r];
             double *o = out + lane + (int64_t)r * ldo;
-            if (MODE == 0) *o -= sum;
-            else if (MODE == 1) *o = src[i][r] + sum;
+            if (mode == 0) *o = prev[r] - sum;
+            else if (mode == 1) *o = src[i][r] + sum;
             else *o = sum;
-        }
-    }
-}
-
-// one solve block t of every listed front: the first ceil(st/64) items apply
-// the inverted diagonal block, the others update the remaining rows
-template <class T, int NR, bool FWD>
-__global__ __launch_bounds__(SB) void k_solve_step(const T *__restrict__ arena,
-                                                   const FrontDesc *__restrict__ fd, TaskList tl,
-                                                   int t, double *vec, double *yv) {
-    __shared__ double src[SB][NR];
-    __shared__ double red[4][RW][NR];
-    int k = find_task(tl.prefix, tl.n, blockIdx.x);
-    FrontDesc d = fd[tl.fronts[k]];
-    int w = (int)(blockIdx.x - tl.prefix[k]);
-    int m = d.m, p = d.p, t0 = t * SB, st = min(SB, p - t0), tend = t0 + st;
-    int nA = (st + RW - 1) / RW;
-    double *V = vec + d.voff;          // ld m
-    double *Y = yv + d.yoff;           // ld p
-    const double *S = FWD ? V + t0 : Y + t0;
-    int64_t lds = FWD ? m : p;
-    for (int e = threadIdx.x; e < st * NR; e += blockDim.x) {
-        int j = e % st, r = e / st;
-        src[j][r] = S[j + (int64_t)r * lds];
-    }
-    __syncthreads();
-    const T *F = arena + d.off;
-    if (w < nA) {
-        int i0 = w * RW;
-        const T *M = F + (t0 + i0) + (int64_t)t0 * m;
-        if (FWD) chunk_apply<T, NR, 1>(M, m, st, min(RW, st - i0), i0, src, red, Y + t0 + i0, p);
-        else chunk_apply<T, NR, 2>(M, m, st, min(RW, st - i0), i0, src, red, V + t0 + i0, m);
-    } else {
-        int c = w - nA;
-        if (FWD) {
-            int r0 = tend + c * RW;
-            chunk_apply<T, NR, 0>(F + r0 + (int64_t)t0 * m, m, st, min(RW, m - r0), 0, src, red,
-                                  V + r0, m);
-        } else {
-            int r0 = c * RW;
-            chunk_apply<T, NR, 0>(F + r0 + (int64_t)t0 * m, m, st, min(RW, t0 - r0), 0, src, red,
-                                  Y + r0, p);
         }
     }
 }
@@ -155,9 +183,9 @@ __global__ __launch_bounds__(256) void k_bwd_gather(const FrontDesc *__restrict_
                                                     TaskList tl, int nrhs,
                                                     const double *__restrict__ xnew, int64_t n,
                                                     double *vec) {
-    int k = find_task(tl.prefix, tl.n, blockIdx.x);
-    FrontDesc d = fd[tl.fronts[k]];
-    int i = (int)(blockIdx.x - tl.prefix[k]) * 256 + threadIdx.x;
+    const int2 tk = tl.items[blockIdx.x];
+    FrontDesc d = fd[tk.x];
+    int i = tk.y * 256 + threadIdx.x;
     int cc = d.m - d.p;
     if (i >= cc) return;
     int32_t g = contrib[d.cptr + i];
@@ -165,68 +193,79 @@ __global__ __launch_bounds__(256) void k_bwd_gather(const FrontDesc *__restrict_
     for (int r = 0; r < nrhs; r++) v[(int64_t)r * d.m] = xnew[g + (int64_t)r * n];
 }
 
-// partial U12 x_c over one 64-row x SB-column tile
+// partial U12 x_c over one 64-row x SB-column tile (factor entries loaded
+// before the source block is staged)
 template <class T, int NR>
-__global__ __launch_bounds__(SB) void k_bwd_u12(const T *__restrict__ arena,
-                                                const FrontDesc *__restrict__ fd, TaskList tl,
-                                                const double *__restrict__ vec,
-                                                double *__restrict__ part) {
+__global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_bwd_u12(
+    const T *__restrict__ arena, const FrontDesc *__restrict__ fd, TaskList tl,
+    const double *__restrict__ vec, double *__restrict__ part) {
+    constexpr int CG = StepCfg<NR>::CG, CW = StepCfg<NR>::CW;
     __shared__ double src[SB][NR];
-    __shared__ double red[4][RW][NR];
-    int k = find_task(tl.prefix, tl.n, blockIdx.x);
-    FrontDesc d = fd[tl.fronts[k]];
-    int w = (int)(blockIdx.x - tl.prefix[k]);
-    int m = d.m, p = d.p, c = m - p;
-    int nrc = (p + RW - 1) / RW;
-    int rc = w % nrc, cc = w / nrc;
-    int c0 = cc * SB, cw = min(SB, c - c0);
+    __shared__ double red[CG][RW][NR];
+    const int2 tk = tl.items[blockIdx.x];
+    const FrontDesc d = fd[tk.x];
+    const int w = tk.y;
+    const int m = d.m, p = d.p, c = m - p;
+    const int nrc = (p + RW - 1) / RW;
+    const int rc = w % nrc, cc = w / nrc;
+    const int c0 = cc * SB, cw = min(SB, c - c0);
+    const int lane = threadIdx.x % RW, wv = threadIdx.x / RW;
+    const int row = rc * RW + lane;
+    double mv[CW];
+    {
+        const T *U = arena + d.off + row + (int64_t)(p + c0 + wv * CW) * m;
+#pragma unroll
+        for (int q = 0; q < CW; q++)
+            mv[q] = (row < p && wv * CW + q < cw) ? (double)U[(int64_t)q * m] : 0.0;
+    }
     const double *v = vec + d.voff;
-    for (int e = threadIdx.x; e < cw * NR; e += blockDim.x) {
-        int j = e % cw, r = e / cw;
-        src[j][r] = v[p + c0 + j + (int64_t)r * m];
+    for (int e = threadIdx.x; e < SB * NR; e += blockDim.x) {
+        int j = e % SB, r = e / SB;
+        src[j][r] = j < cw ? v[p + c0 + j + (int64_t)r * m] : 0.0;
     }
     __syncthreads();
-    int lane = threadIdx.x % RW, wv = threadIdx.x / RW;
-    int row = rc * RW + lane;
-    int j0 = wv * CQ, j1 = min(j0 + CQ, cw);
     double acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; r++) acc[r] = 0.0;
-    if (row < p) {
-        const T *U = arena + d.off + row + (int64_t)(p + c0) * m;
-#pragma unroll 8
-        for (int j = j0; j < j1; j++) {
-            double x = (double)U[(int64_t)j * m];
 #pragma unroll
-            for (int r = 0; r < NR; r++) acc[r] += x * src[j][r];
-        }
+    for (int q = 0; q < CW; q++) {
+        const double x = mv[q];
+#pragma unroll
+        for (int r = 0; r < NR; r++) acc[r] += x * src[wv * CW + q][r];
     }
 #pragma unroll
     for (int r = 0; r < NR; r++) red[wv][lane][r] = acc[r];
     __syncthreads();
     if (wv == 0 && row < p)
 #pragma unroll
-        for (int r = 0; r < NR; r++)
-            part[d.poff + ((int64_t)cc * MAXRHS + r) * p + row] =
-                red[0][lane][r] + red[1][lane][r] + red[2][lane][r] + red[3][lane][r];
+        for (int r = 0; r < NR; r++) {
+            double sum = red[0][lane][r];
+#pragma unroll
+            for (int g = 1; g < CG; g++) sum += red[g][lane][r];
+            part[d.poff + ((int64_t)cc * MAXRHS + r) * p + row] = sum;
+        }
 }
 
 template <int NR>
 __global__ __launch_bounds__(256) void k_bwd_u12_reduce(const FrontDesc *__restrict__ fd,
                                                         TaskList tl, double *yv,
                                                         const double *__restrict__ part) {
-    int k = find_task(tl.prefix, tl.n, blockIdx.x);
-    FrontDesc d = fd[tl.fronts[k]];
-    int row = (int)(blockIdx.x - tl.prefix[k]) * 256 + threadIdx.x;
+    const int2 tk = tl.items[blockIdx.x];
+    FrontDesc d = fd[tk.x];
+    int row = tk.y * 256 + threadIdx.x;
     int m = d.m, p = d.p, ncc = (m - p + SB - 1) / SB;
     if (row >= p) return;
     double *y = yv + d.yoff;
+    double s[NR];
 #pragma unroll
-    for (int r = 0; r < NR; r++) {
-        double s = 0.0;
-        for (int q = 0; q < ncc; q++) s += part[d.poff + ((int64_t)q * MAXRHS + r) * p + row];
-        y[row + (int64_t)r * p] -= s;
-    }
+    for (int r = 0; r < NR; r++) s[r] = 0.0;
+    const double *pp = part + d.poff + row;
+#pragma unroll 2
+    for (int q = 0; q < ncc; q++)
+#pragma unroll
+        for (int r = 0; r < NR; r++) s[r] += pp[((int64_t)q * MAXRHS + r) * p];
+#pragma unroll
+    for (int r = 0; r < NR; r++) y[row + (int64_t)r * p] -= s[r];
 }
 
 __global__ __launch_bounds__(256) void k_bwd_scatter(const FrontDesc *__restrict__ fd,
@@ -234,9 +273,9 @@ __global__ __launch_bounds__(256) void k_bwd_scatter(const FrontDesc *__restrict
                                                      int nrhs, const double *__restrict__ vec,
                                                      double *xnew, int64_t n, double *xout,
                                                      int64_t ldx) {
-    int k = find_task(tl.prefix, tl.n, blockIdx.x);
-    FrontDesc d = fd[tl.fronts[k]];
-    int i = (int)(blockIdx.x - tl.prefix[k]) * 256 + threadIdx.x;
+    const int2 tk = tl.items[blockIdx.x];
+    FrontDesc d = fd[tk.x];
+    int i = tk.y * 256 + threadIdx.x;
     if (i >= d.p) return;
     int g = d.first + i;
     int32_t o = perm[g];
@@ -267,8 +306,12 @@ void launch_fwd_gather(const FrontDesc *fd, const int32_t *perm, const int32_t *
                        const int32_t *inv_ptr, const int2 *inv_src, TaskList tl, int nrhs,
                        const double *b, int64_t ldb, double *vec, hipStream_t s) {
     if (tl.total == 0) return;
-    hipLaunchKernelGGL(k_fwd_gather, dim3((unsigned)tl.total), dim3(256), 0, s, fd, perm, prow,
-                       inv_ptr, inv_src, tl, nrhs, b, ldb, vec);
+    rhs_dispatch(nrhs, [&](auto nr) {
+        constexpr int NR = decltype(nr)::value;
+        k_fwd_gather<NR><<<dim3((unsigned)tl.total), dim3(256), 0, s>>>(fd, perm, prow, inv_ptr,
+                                                                         inv_src, tl, nrhs, b, ldb,
+                                                                         vec);
+    });
     MBL_CHECK_LAUNCH();
 }
 
@@ -278,11 +321,12 @@ void launch_solve_step(const T *arena, const FrontDesc *fd, TaskList tl, int t, 
     if (tl.total == 0) return;
     rhs_dispatch(nrhs, [&](auto nr) {
         constexpr int NR = decltype(nr)::value;
+        constexpr int TH = StepCfg<NR>::THREADS;
         if (fwd)
-            k_solve_step<T, NR, true><<<dim3((unsigned)tl.total), dim3(SB), 0, s>>>(arena, fd, tl, t,
+            k_solve_step<T, NR, true><<<dim3((unsigned)tl.total), dim3(TH), 0, s>>>(arena, fd, tl, t,
                                                                                     vec, yv);
         else
-            k_solve_step<T, NR, false><<<dim3((unsigned)tl.total), dim3(SB), 0, s>>>(arena, fd, tl,
+            k_solve_step<T, NR, false><<<dim3((unsigned)tl.total), dim3(TH), 0, s>>>(arena, fd, tl,
                                                                                      t, vec, yv);
     });
     MBL_CHECK_LAUNCH();
@@ -302,7 +346,8 @@ void launch_bwd_u12(const T *arena, const FrontDesc *fd, TaskList tl, int nrhs, 
     if (tl.total == 0) return;
     rhs_dispatch(nrhs, [&](auto nr) {
         constexpr int NR = decltype(nr)::value;
-        k_bwd_u12<T, NR><<<dim3((unsigned)tl.total), dim3(SB), 0, s>>>(arena, fd, tl, vec, part);
+        k_bwd_u12<T, NR><<<dim3((unsigned)tl.total), dim3(StepCfg<NR>::THREADS), 0, s>>>(arena, fd,
+                                                                                      tl, vec, part);
     });
     MBL_CHECK_LAUNCH();
 }

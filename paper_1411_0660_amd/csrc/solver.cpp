@@ -38,19 +38,26 @@ int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct TaskBuilder {
     std::vector<int32_t> fr;
     std::vector<int64_t> pre;
+    std::vector<int2> its;
     std::vector<TaskList *> lists;
-    std::vector<std::pair<int64_t, int64_t>> offs;
+    struct Offs { int64_t fr, pre, its; };
+    std::vector<Offs> offs;
     void add(TaskList &tl, const std::vector<int32_t> &fronts, const std::vector<int64_t> &items) {
         tl.n = (int32_t)fronts.size();
-        int64_t fo = (int64_t)fr.size(), po = (int64_t)pre.size();
+        Offs o{(int64_t)fr.size(), (int64_t)pre.size(), (int64_t)its.size()};
         int64_t acc = 0;
         fr.insert(fr.end(), fronts.begin(), fronts.end());
-        for (int64_t it : items) { pre.push_back(acc); acc += it; }
+        for (size_t k = 0; k < items.size(); k++) {
+            pre.push_back(acc);
+            acc += items[k];
+            MBL_REQUIRE(items[k] < INT32_MAX, MBL_EINVAL, "task list: too many items per front");
+            for (int64_t j = 0; j < items[k]; j++) its.push_back(make_int2(fronts[k], (int)j));
+        }
         pre.push_back(acc);
         if (fronts.empty()) fr.push_back(0);    // keep pointers valid
         tl.total = acc;
         lists.push_back(&tl);
-        offs.push_back({fo, po});
+        offs.push_back(o);
     }
 };
 }  // namespace
@@ -216,7 +223,9 @@ void Context::ensure_symbolic(Plan &p) {
     // inverse relative map: for every front row, the (child, child row) pairs
     // whose update lands on it
     std::vector<int32_t> inv_ptr;
-    std::vector<int32_t> inv_src;   // pairs
+    std::vector<int32_t> inv_src;   // pairs (element of the child's update row in the solve
+                                    // vectors, the child's order = stride between right-hand sides)
+    MBL_REQUIRE(p.vec_elems < (int64_t)INT32_MAX, MBL_EINVAL, "solve vectors too long");
     {
         std::vector<std::vector<std::pair<int32_t, int32_t>>> rows;
         for (int f = 0; f < nf; f++) {
@@ -231,7 +240,12 @@ void Context::ensure_symbolic(Plan &p) {
             int32_t acc = (int32_t)(inv_src.size() / 2);
             for (int32_t i = 0; i < d.m; i++) {
                 inv_ptr.push_back(acc);
-                for (auto &pr : rows[i]) { inv_src.push_back(pr.first); inv_src.push_back(pr.second); acc++; }
+                for (auto &pr : rows[i]) {
+                    const FrontDesc &cd = p.h_fd[pr.first];
+                    inv_src.push_back((int32_t)(cd.voff + cd.p + pr.second));
+                    inv_src.push_back(cd.m);
+                    acc++;
+                }
             }
             inv_ptr.push_back(acc);
             MBL_REQUIRE(inv_ptr.size() < (size_t)INT32_MAX, MBL_EINVAL, "inverse map too long");
@@ -417,9 +431,13 @@ void Context::ensure_symbolic(Plan &p) {
     h2d(p.d_tfronts.ptr<int32_t>(), tb.fr.data(), tb.fr.size(), s);
     p.d_tprefix.alloc(sizeof(int64_t) * std::max<size_t>(1, tb.pre.size()), &budget);
     h2d(p.d_tprefix.ptr<int64_t>(), tb.pre.data(), tb.pre.size(), s);
+    if (tb.its.empty()) tb.its.push_back(make_int2(0, 0));
+    p.d_titems.alloc(sizeof(int2) * tb.its.size(), &budget);
+    h2d(p.d_titems.ptr<int2>(), tb.its.data(), tb.its.size(), s);
     for (size_t i = 0; i < tb.lists.size(); i++) {
-        tb.lists[i]->fronts = p.d_tfronts.ptr<int32_t>() + tb.offs[i].first;
-        tb.lists[i]->prefix = p.d_tprefix.ptr<int64_t>() + tb.offs[i].second;
+        tb.lists[i]->fronts = p.d_tfronts.ptr<int32_t>() + tb.offs[i].fr;
+        tb.lists[i]->prefix = p.d_tprefix.ptr<int64_t>() + tb.offs[i].pre;
+        tb.lists[i]->items = p.d_titems.ptr<int2>() + tb.offs[i].its;
     }
     p.d_inv_ptr.alloc(sizeof(int32_t) * std::max<size_t>(1, inv_ptr.size()), &budget);
     h2d(p.d_inv_ptr.ptr<int32_t>(), inv_ptr.data(), inv_ptr.size(), s);

@@ -55,7 +55,7 @@ struct Plan {
     TaskList xform;                    // 16-row panels folded with the inverted blocks
     int64_t y_elems = 0;               // forward-solution blocks (sum of p x 16)
     int64_t part_elems = 0;            // max over levels
-    DevBuf d_fd, d_perm, d_contrib, d_relmap, d_child_ids, d_tfronts, d_tprefix;
+    DevBuf d_fd, d_perm, d_contrib, d_relmap, d_child_ids, d_tfronts, d_tprefix, d_titems;
     DevBuf d_efront, d_epos, d_esrc, d_inv_ptr, d_inv_src;
 };
 
