@@ -282,6 +282,59 @@ __global__ void k_sub_scaled_cols(int64_t n, int ncol, const double *__restrict_
     if (i < n) Y[i + (int64_t)j * ldy] -= e[j] * X[i + (int64_t)j * ldx];
 }
 
+// Per-column dots against a stack of nb blocks (block i at V + i * bs, each
+// n x nrhs with ld n): part[(blk * nrhs + j) * nb + i] = sum over the block's
+// rows of V_i[r, j] W[r, j].  Wave shuffles then a fixed-order sum over the
+// four waves, so the partials are reproducible.
+constexpr int BD_MAX = 32;
+
+__global__ __launch_bounds__(BS) void k_bdot_part(int64_t n, int nb, int nrhs,
+                                                  const double *__restrict__ V, int64_t bs,
+                                                  const double *__restrict__ W,
+                                                  double *__restrict__ part) {
+    __shared__ double red[BS / 64][BD_MAX];
+    const int j = blockIdx.y;
+    double acc[BD_MAX];
+#pragma unroll
+    for (int i = 0; i < BD_MAX; i++) acc[i] = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x; r < n; r += (int64_t)gridDim.x * BS) {
+        const double w = W[r + (int64_t)j * n];
+        const double *v = V + r + (int64_t)j * n;
+#pragma unroll
+        for (int i = 0; i < BD_MAX; i++)
+            if (i < nb) acc[i] += v[(int64_t)i * bs] * w;
+    }
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+#pragma unroll
+    for (int i = 0; i < BD_MAX; i++) {
+        if (i >= nb) break;
+        double v = acc[i];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) red[wv][i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < nb) {
+        double t = red[0][threadIdx.x];
+        for (int q = 1; q < BS / 64; q++) t += red[q][threadIdx.x];
+        part[((int64_t)blockIdx.x * nrhs + j) * nb + threadIdx.x] = t;
+    }
+}
+
+// out[:, j] = beta out[:, j] + alpha sum_i coef[i + j nb] V_i[:, j]
+__global__ __launch_bounds__(BS) void k_bcomb(int64_t n, int nb, int nrhs,
+                                              const double *__restrict__ V, int64_t bs,
+                                              const double *__restrict__ coef, double alpha,
+                                              double beta, double *__restrict__ out) {
+    const int j = blockIdx.y;
+    const int64_t r = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (r >= n) return;
+    const double *v = V + r + (int64_t)j * n;
+    double s = 0.0;
+    for (int i = 0; i < nb; i++) s += coef[i + (int64_t)j * nb] * v[(int64_t)i * bs];
+    double *o = out + r + (int64_t)j * n;
+    *o = (beta == 0.0 ? 0.0 : beta * *o) + alpha * s;
+}
+
 }  // namespace
 
 void launch_coldot(int64_t n, int ncol, const double *A, int64_t lda, const double *B, int64_t ldb,
@@ -300,6 +353,26 @@ void launch_sub_scaled_cols(int64_t n, int ncol, const double *e, const double *
     if (ncol == 0 || n == 0) return;
     hipLaunchKernelGGL(k_sub_scaled_cols, dim3(grid_for(n, 256), ncol), dim3(256), 0, s, n, ncol, e,
                        X, ldx, Y, ldy);
+    MBL_CHECK_LAUNCH();
+}
+
+void launch_bdot(int64_t n, int nb, int nrhs, const double *V, int64_t bs, const double *W,
+                 double *out, double *partials, int nparts, hipStream_t s) {
+    MBL_REQUIRE(nb >= 0 && nb <= BD_MAX, MBL_EINVAL, "bdot: too many blocks");
+    if (nb == 0 || nrhs == 0) return;
+    k_bdot_part<<<dim3((unsigned)nparts, (unsigned)nrhs), dim3(BS), 0, s>>>(n, nb, nrhs, V, bs, W,
+                                                                            partials);
+    MBL_CHECK_LAUNCH();
+    int kb = nb * nrhs;
+    k_sum_parts<<<dim3(grid_for(kb, 64)), dim3(64 * SP_G), 0, s>>>(kb, nparts, partials, out);
+    MBL_CHECK_LAUNCH();
+}
+
+void launch_bcomb(int64_t n, int nb, int nrhs, const double *V, int64_t bs, const double *coef,
+                  double alpha, double beta, double *out, hipStream_t s) {
+    if (n == 0 || nrhs == 0) return;
+    k_bcomb<<<dim3(grid_for(n, BS), (unsigned)nrhs), dim3(BS), 0, s>>>(n, nb, nrhs, V, bs, coef,
+                                                                      alpha, beta, out);
     MBL_CHECK_LAUNCH();
 }
 

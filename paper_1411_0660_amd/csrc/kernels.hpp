@@ -43,6 +43,13 @@ void launch_copy(int64_t count, const double *x, double *y, hipStream_t s);
 void launch_axpy(int64_t count, double a, const double *x, double *y, hipStream_t s);
 void launch_coldot(int64_t n, int ncol, const double *A, int64_t lda, const double *B, int64_t ldb,
                    double *out, double *partials, int nparts, hipStream_t s);
+// per-column dots of W against nb stacked blocks (block i at V + i bs, n x nrhs,
+// ld n): out[i + j nb]; partials >= nparts * nb * nrhs, nb <= 32
+void launch_bdot(int64_t n, int nb, int nrhs, const double *V, int64_t bs, const double *W,
+                 double *out, double *partials, int nparts, hipStream_t s);
+// out[:, j] = beta out[:, j] + alpha sum_i coef[i + j nb] V_i[:, j]  (coef on the device)
+void launch_bcomb(int64_t n, int nb, int nrhs, const double *V, int64_t bs, const double *coef,
+                  double alpha, double beta, double *out, hipStream_t s);
 void launch_sub_scaled_cols(int64_t n, int ncol, const double *e, const double *X, int64_t ldx,
                             double *Y, int64_t ldy, hipStream_t s);
 

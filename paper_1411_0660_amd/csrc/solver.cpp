@@ -585,6 +585,140 @@ void Context::lu_apply(Plan &p, Factor<T> &f, int nrhs, const double *b, int64_t
     }
 }
 
+// Refinement for single-precision factors: each outer sweep forms the FP64
+// residual r = B - (H - sigma) X and solves (H - sigma) D = r by restarted
+// flexible GMRES in FP64, right-preconditioned by the FP32 LU (one Arnoldi
+// basis per right-hand side, classical Gram-Schmidt applied twice, Givens
+// rotations on the host), then X += D.  Unlike plain refinement, whose
+// contraction is |I - A M^-1| and stalls once kappa(A) u_32 is not small,
+// GMRES only needs the preconditioned spectrum to be clustered.
+template <class T>
+void Context::gmres_refine(Plan &p, Factor<T> &f, int nrhs, const double *B, double *X,
+                           double target, SolveStats &st) {
+    hipStream_t s = stream;
+    const int64_t n = p.dim;
+    constexpr int KM = 30;                   // Arnoldi steps per cycle (<= 31 blocks for bdot)
+    const double inner_tol = 1e-6;           // relative residual reduction per cycle
+    const int64_t bs = n * (int64_t)nrhs;    // stride between basis blocks
+    d_r.ensure(sizeof(double) * n * MAXRHS, &budget);
+    d_d.ensure(sizeof(double) * n * MAXRHS, &budget);
+    d_part.ensure(sizeof(double) * RES_PARTS * MAXRHS * 3, &budget);
+    d_gV.ensure(sizeof(double) * (size_t)bs * (KM + 1), &budget);
+    d_gZ.ensure(sizeof(double) * (size_t)bs * KM, &budget);
+    const int nparts = gemm_tn_parts(n);
+    d_gpart.ensure(sizeof(double) * (size_t)nparts * (KM + 1) * nrhs, &budget);
+    d_gcoef.ensure(sizeof(double) * (size_t)(KM + 1) * nrhs * 2, &budget);
+    double *r = d_r.ptr<double>(), *w = d_d.ptr<double>();
+    double *V = d_gV.ptr<double>(), *Z = d_gZ.ptr<double>();
+    double *gp = d_gpart.ptr<double>(), *co = d_gcoef.ptr<double>(), *co2 = co + (KM + 1) * nrhs;
+    std::vector<double> part((size_t)RES_PARTS * nrhs * 3);
+    std::vector<double> beta0(nrhs), hc((size_t)(KM + 1) * nrhs), hc2((size_t)(KM + 1) * nrhs);
+    std::vector<double> Hm((size_t)(KM + 1) * KM * nrhs), cs((size_t)KM * nrhs), sn((size_t)KM * nrhs);
+    std::vector<double> g((size_t)(KM + 1) * nrhs), y((size_t)KM * nrhs);
+    std::vector<int> kconv(nrhs);
+    std::vector<double> scal(nrhs), nn(nrhs);
+    auto Hat = [&](int i, int k, int j) -> double & { return Hm[((size_t)j * KM + k) * (KM + 1) + i]; };
+    double be = 1e300;
+    int sweeps = 0, inner_total = 0;
+    for (;; sweeps++) {
+        launch_residual(n, p.rowptr.ptr<int32_t>(), p.col.ptr<int32_t>(), d_diag.ptr<double>(),
+                        offv, f.sigma, nrhs, B, X, r, d_part.ptr<double>(), RES_PARTS, s);
+        d2h(part.data(), d_part.ptr<double>(), part.size(), s);
+        MBL_HIP(hipStreamSynchronize(s));
+        be = 0.0;
+        for (int v = 0; v < nrhs; v++) {
+            double sr = 0, sx = 0, sb = 0;
+            for (int q = 0; q < RES_PARTS; q++) {
+                const double *pp = &part[((size_t)q * nrhs + v) * 3];
+                sr += pp[0]; sx += pp[1]; sb += pp[2];
+            }
+            double den = anorm_ * std::sqrt(sx) + std::sqrt(sb);
+            be = std::max(be, den > 0 ? std::sqrt(sr) / den : 0.0);
+            beta0[v] = std::sqrt(sr);
+        }
+        if (debug_level() > 0)
+            std::fprintf(stderr, "[mbl] gmres-ir L=%d sweep=%d be=%.3e nrhs=%d inner=%d\n", p.L,
+                         sweeps, be, nrhs, inner_total);
+        if (be <= target || sweeps >= 6) break;
+        // V_0 = r / |r| per column
+        for (int v = 0; v < nrhs; v++) scal[v] = beta0[v] > 0 ? 1.0 / beta0[v] : 0.0;
+        h2d(co, scal.data(), (size_t)nrhs, s);
+        launch_bcomb(n, 1, nrhs, r, bs, co, 1.0, 0.0, V, s);
+        std::fill(Hm.begin(), Hm.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        for (int v = 0; v < nrhs; v++) { g[(size_t)v * (KM + 1)] = beta0[v]; kconv[v] = -1; }
+        int k = 0;
+        for (; k < KM; k++) {
+            double *Vk = V + (int64_t)k * bs, *Zk = Z + (int64_t)k * bs;
+            lu_apply<T>(p, f, nrhs, Vk, n, Zk, n);
+            launch_spmv(n, p.rowptr.ptr<int32_t>(), p.col.ptr<int32_t>(), d_diag.ptr<double>(), offv,
+                        f.sigma, nrhs, Zk, w, s);
+            for (int pass = 0; pass < 2; pass++) {
+                launch_bdot(n, k + 1, nrhs, V, bs, w, co, gp, nparts, s);
+                launch_bcomb(n, k + 1, nrhs, V, bs, co, -1.0, 1.0, w, s);
+                d2h(pass == 0 ? hc.data() : hc2.data(), co, (size_t)(k + 1) * nrhs, s);
+            }
+            launch_bdot(n, 1, nrhs, w, bs, w, co2, gp, nparts, s);
+            d2h(nn.data(), co2, (size_t)nrhs, s);
+            MBL_HIP(hipStreamSynchronize(s));
+            bool all = true;
+            for (int v = 0; v < nrhs; v++) {
+                double hn = std::sqrt(std::max(0.0, nn[v]));
+                for (int i = 0; i <= k; i++)
+                    Hat(i, k, v) = hc[(size_t)v * (k + 1) + i] + hc2[(size_t)v * (k + 1) + i];
+                Hat(k + 1, k, v) = hn;
+                scal[v] = hn > 1e-300 ? 1.0 / hn : 0.0;   // scaling of the next basis vector
+                if (kconv[v] >= 0) continue;
+                // apply the previous rotations of this column, then a new one
+                for (int i = 0; i < k; i++) {
+                    double a = Hat(i, k, v), b2 = Hat(i + 1, k, v);
+                    Hat(i, k, v) = cs[(size_t)v * KM + i] * a + sn[(size_t)v * KM + i] * b2;
+                    Hat(i + 1, k, v) = -sn[(size_t)v * KM + i] * a + cs[(size_t)v * KM + i] * b2;
+                }
+                double a = Hat(k, k, v), b2 = Hat(k + 1, k, v);
+                double rr = std::hypot(a, b2);
+                double c = rr > 0 ? a / rr : 1.0, sgn = rr > 0 ? b2 / rr : 0.0;
+                cs[(size_t)v * KM + k] = c;
+                sn[(size_t)v * KM + k] = sgn;
+                Hat(k, k, v) = rr;
+                Hat(k + 1, k, v) = 0.0;
+                double gk = g[(size_t)v * (KM + 1) + k];
+                g[(size_t)v * (KM + 1) + k] = c * gk;
+                g[(size_t)v * (KM + 1) + k + 1] = -sgn * gk;
+                if (std::fabs(g[(size_t)v * (KM + 1) + k + 1]) <= inner_tol * beta0[v] || hn <= 1e-300)
+                    kconv[v] = k + 1;
+                else
+                    all = false;
+            }
+            inner_total++;
+            if (all || k + 1 == KM) { k++; break; }
+            h2d(co, scal.data(), (size_t)nrhs, s);
+            launch_bcomb(n, 1, nrhs, w, bs, co, 1.0, 0.0, V + (int64_t)(k + 1) * bs, s);
+        }
+        // least-squares solutions (upper triangular) and D = Z y, X += D
+        std::fill(y.begin(), y.end(), 0.0);
+        for (int v = 0; v < nrhs; v++) {
+            int kv = kconv[v] >= 0 ? kconv[v] : k;
+            for (int i = kv - 1; i >= 0; i--) {
+                double acc = g[(size_t)v * (KM + 1) + i];
+                for (int q = i + 1; q < kv; q++) acc -= Hat(i, q, v) * y[(size_t)v * k + q];
+                y[(size_t)v * k + i] = Hat(i, i, v) != 0.0 ? acc / Hat(i, i, v) : 0.0;
+            }
+        }
+        h2d(co, y.data(), (size_t)k * nrhs, s);
+        launch_bcomb(n, k, nrhs, Z, bs, co, 1.0, 1.0, X, s);
+    }
+    st.backward_error = be;
+    st.ir_iters = std::max(st.ir_iters, sweeps);
+    st.gmres_inner += inner_total;
+    if (be > 1e-10) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "shifted solve: backward error %.3e after %d GMRES sweeps",
+                      be, sweeps);
+        throw Error(MBL_ENUMERIC, msg);
+    }
+}
+
 template <class T>
 void Context::refine(Plan &p, Factor<T> &f, int nrhs, const double *B, double *X,
                      SolveStats &st) {
@@ -597,6 +731,7 @@ void Context::refine(Plan &p, Factor<T> &f, int nrhs, const double *B, double *X
     lu_apply<T>(p, f, nrhs, B, n, X, n);
     std::vector<double> part((size_t)RES_PARTS * nrhs * 3);
     const double target = 1e-13;
+
     double prev = 1e300;
     int it = 0;
     for (;; it++) {
@@ -620,6 +755,13 @@ void Context::refine(Plan &p, Factor<T> &f, int nrhs, const double *B, double *X
             std::fprintf(stderr, "[mbl] refine L=%d prec=%s it=%d be=%.3e nrhs=%d npert=%d\n", p.L,
                          sizeof(T) == 4 ? "fp32" : "fp64", it, be, nrhs, st.n_perturbed);
         if (be <= target || it >= 12) break;
+        if (sizeof(T) == 4 && it >= 1 && be > 0.25 * prev) {
+            // single-precision factors contracting slowly (kappa u_32 not small):
+            // continue from the current X with GMRES-based refinement
+            st.ir_iters = std::max(st.ir_iters, it);
+            gmres_refine<T>(p, f, nrhs, B, X, target, st);
+            return;
+        }
         if (be > 0.5 * prev && it >= 3) break;    // stagnation
         prev = be;
         lu_apply<T>(p, f, nrhs, r, n, dd, n);
@@ -637,6 +779,7 @@ void Context::refine(Plan &p, Factor<T> &f, int nrhs, const double *B, double *X
 void Context::shift_solve(Plan &p, int prec, int nrhs, const double *B, double *X,
                           SolveStats &st) {
     double t0 = wall_seconds();
+    st.gmres_inner = 0;
     for (int c = 0; c < nrhs; c += MAXRHS) {
         int nb = std::min(MAXRHS, nrhs - c);
         if (prec == MBL_FP32_IR64) refine<float>(p, f32_, nb, B + (int64_t)c * p.dim, X + (int64_t)c * p.dim, st);
@@ -923,6 +1066,14 @@ void solve_problem(Context &ctx, const mbl_problem &pr, mbl_result &res) {
     auto op = [&](const double *X, double *Y, int nb) {
         try {
             ctx.shift_solve(p, prec, nb, X, Y, st);
+            if (prec == MBL_FP32_IR64 && st.gmres_inner > 8) {
+                // the FP32 factor needs many GMRES steps per solve here (kappa u_32
+                // near one): this result stands, later solves use an FP64 factor
+                prec = MBL_FP64;
+                fell_back = true;
+                SolveStats s2;
+                ctx.factor(p, prec, sigma_f, anorm, s2);
+            }
         } catch (const Error &e) {
             if (e.code != MBL_ENUMERIC || prec != MBL_FP32_IR64) throw;
             // FP32 refinement did not reach the target: refactor in FP64

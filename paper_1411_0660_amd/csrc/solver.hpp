@@ -73,6 +73,7 @@ struct SolveStats {
     double backward_error = 0.0;
     double t_factor = 0.0, t_solve = 0.0;
     int n_rhs = 0;
+    int gmres_inner = 0;               // GMRES iterations of the latest shifted solve
 };
 
 class Context {
@@ -141,10 +142,13 @@ class Context {
     Factor<float> f32_;
     Factor<double> f64_;
     DevBuf d_vec, d_yv, d_upart, d_xnew, d_r, d_d, d_part, d_V, d_V2, d_W, d_small, d_tnpart;
+    DevBuf d_gV, d_gZ, d_gpart, d_gcoef;   // GMRES refinement: bases, partials, coefficients
     template <class T> void factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel,
                                      SolveStats &st);
     template <class T> void lu_apply(Plan &p, Factor<T> &f, int nrhs, const double *b,
                                      int64_t ldb, double *x, int64_t ldx);
+    template <class T> void gmres_refine(Plan &p, Factor<T> &f, int nrhs, const double *B,
+                                         double *X, double target, SolveStats &st);
     template <class T> void refine(Plan &p, Factor<T> &f, int nrhs, const double *B, double *X,
                                    SolveStats &st);
 };
