@@ -32,8 +32,17 @@ sys.path.insert(0, HERE)
 
 METRIC = "converged interior eigenpairs/sec (resid≤1e-9) at L=18/20; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of the outer Schur update per launch at L = 20 from rocprofv3 PMC
+# counters (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain copy
+# of known size); valid only for the kernel source it was measured on
+SCHUR_SRC = os.path.join(HERE, "paper_1411_0660_amd", "csrc", "k_front.hip")
+SCHUR_TRAFFIC = {"sha256": None, "bytes_per_launch": None}
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def percentile(xs, q):
@@ -44,6 +53,29 @@ def percentile(xs, q):
     f = math.floor(k)
     c = min(f + 1, len(xs) - 1)
     return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def schur_traffic():
+    import hashlib
+    if SCHUR_TRAFFIC["sha256"] is None:
+        return None
+    with open(SCHUR_SRC, "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest() != SCHUR_TRAFFIC["sha256"]:
+            return None
+    return SCHUR_TRAFFIC["bytes_per_launch"]
+
+
+def copy_probe(nbytes, reps=5):
+    """A plain device-to-device copy of nbytes (torch), the reference that
+    scales the PMC byte counters."""
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": 4 * n, "reps": reps}), flush=True)
 
 
 def workload(L, steps):
@@ -121,7 +153,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--roofline-kernel", default="schur")
+    ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
     a = ap.parse_args()
+    if a.copy_probe > 0:
+        copy_probe(a.copy_probe)
+        return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no collectives); use --gpus 1",
               file=sys.stderr)
@@ -133,7 +169,9 @@ def main():
     ctx = mbl.Context(0)
     info = ctx.mbl_symbolic(L)
     cases = workload(L, a.steps)
+    log(f"L={L} symbolic done ({info['seconds']:.2f} s); warm-up")
     run_steps(ctx, mbl, L, [(1000 + i, 3.0, 0.5) for i in range(a.warmup)], mbl.MBL_FP64, nev)
+    log("timed FP64 steps")
 
     ctx.mbl_profile_enable(a.roofline_kernel)
     t0 = time.perf_counter()
@@ -165,8 +203,9 @@ def main():
         if a.roofline_kernel == "schur":
             ach = prof["flops"] / prof["seconds"] / 1e12
             out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
-                               "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
-                               "kernel": "k_schur<double> (outer-block K=256 updates)",
+                               "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
+                               "traffic": schur_traffic() if L == 20 else None,
+                               "kernel": "k_schur<double, 1> (outer-block K=256 updates)",
                                "launches": prof["launches"],
                                "avg_launch_us": 1e6 * per_launch,
                                "flops_per_launch": prof["flops"] / prof["launches"]}
@@ -176,7 +215,9 @@ def main():
                                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
                                "kernel": a.roofline_kernel, "launches": prof["launches"],
                                "avg_launch_us": 1e6 * per_launch}
+    log(f"FP64: {out['value']:.2f} eigenpairs/s, {out['ms_per_step']:.0f} ms/step")
     if not a.no_mixed:
+        log("mixed-precision steps")
         t0 = time.perf_counter()
         lat2, conv2, res2 = run_steps(ctx, mbl, L, cases, mbl.MBL_FP32_IR64, nev)
         wall2 = time.perf_counter() - t0
@@ -190,6 +231,7 @@ def main():
                             float(max(abs(x - y) for x, y in zip(r1["evals"], r2["evals"])))
                             for r1, r2 in zip(res, res2))}
     if L != 18 and a.l18_steps > 0:
+        log("L=18 steps")
         info18 = ctx.mbl_symbolic(18)
         cases18 = workload(18, a.l18_steps)
         run_steps(ctx, mbl, 18, [(1000, 3.0, 0.5)], mbl.MBL_FP64, nev)
@@ -203,6 +245,7 @@ def main():
                                      "p99": 1e3 * percentile(lat3, 0.99)}}
     ctx.close()
     if not a.no_cpu:
+        log("cpu baseline (oracle)")
         try:
             out["cpu_baseline"] = cpu_baseline(L, nev)
             if out["cpu_baseline"]["value"] is None and L > 18:

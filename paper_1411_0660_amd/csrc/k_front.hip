@@ -426,17 +426,17 @@ template <class T> struct SchurCfg {
     static constexpr int PF = ST * KC / 256;   // elements of A (and of B) per thread
 };
 
-// big = 0: update after panel t inside its outer SB block, K = the panel's kb
+// BIG = 0: update after panel t inside its outer SB block, K = the panel's kb
 //          columns: the first tiles cover the rows below the panel and the
 //          columns up to the end of the outer block, the rest the remaining
 //          rows of the outer block and every column right of it;
-// big = 1: update of outer block t, K = its (up to SB) columns, everything
+// BIG = 1: update of outer block t, K = its (up to SB) columns, everything
 //          right of and below it (including the contribution block).
 // The next K chunk is fetched from HBM into registers while the current one
 // feeds the matrix cores from LDS.
-template <class T>
+template <class T, int BIG>
 __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__restrict__ fd,
-                                                  TaskList tl, int t, int big) {
+                                                  TaskList tl, int t) {
     typedef typename MfmaAcc<T>::v4 v4;
     constexpr int KC = SchurCfg<T>::KC, PF = SchurCfg<T>::PF;
     __shared__ T smem[2 * KC * SP > 64 * (ST + 1) ? 2 * KC * SP : 64 * (ST + 1)];
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
     FrontDesc d = fd[tk.x];
     int64_t tile = tk.y;
     int m = d.m, kc0, kd, rlo, rhi, clo, chi;
-    if (!big) {
+    if (!BIG) {
         kc0 = t * FNB; kd = min(FNB, d.p - kc0);
         int k1 = kc0 + kd, K1 = min(d.p, (kc0 / SB + 1) * SB);
         int n0 = (K1 > k1) ? ((m - k1 + ST - 1) / ST) * ((K1 - k1 + ST - 1) / ST) : 0;
@@ -692,8 +692,8 @@ void launch_trsm_l(T *arena, const FrontDesc *fd, TaskList tl, int t, hipStream_
 template <class T>
 void launch_schur(T *arena, const FrontDesc *fd, TaskList tl, int t, bool big, hipStream_t s) {
     if (tl.total == 0) return;
-    hipLaunchKernelGGL(k_schur<T>, dim3((unsigned)tl.total), dim3(256), 0, s, arena, fd, tl, t,
-                       big ? 1 : 0);
+    if (big) k_schur<T, 1><<<dim3((unsigned)tl.total), dim3(256), 0, s>>>(arena, fd, tl, t);
+    else k_schur<T, 0><<<dim3((unsigned)tl.total), dim3(256), 0, s>>>(arena, fd, tl, t);
     MBL_CHECK_LAUNCH();
 }
 
