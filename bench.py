@@ -36,7 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # counters (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain copy
 # of known size); valid only for the kernel source it was measured on
 SCHUR_SRC = os.path.join(HERE, "paper_1411_0660_amd", "csrc", "k_front.hip")
-SCHUR_TRAFFIC = {"sha256": None, "bytes_per_launch": None}
+SCHUR_TRAFFIC = {"sha256": "0f99162245ee12288a685d505f03c642f724fa211589c3afe68238028a8131f0",
+                 "bytes_per_launch": 1.859028e+10}
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
@@ -208,7 +209,8 @@ def main():
                                "kernel": "k_schur<double, 1> (outer-block K=256 updates)",
                                "launches": prof["launches"],
                                "avg_launch_us": 1e6 * per_launch,
-                               "flops_per_launch": prof["flops"] / prof["launches"]}
+                               "flops_per_launch": prof["flops"] / prof["launches"],
+                               "algorithmic_bytes_per_launch": prof["bytes"] / prof["launches"]}
         else:
             ach = prof["bytes"] / prof["seconds"] / 1e9
             out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
