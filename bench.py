@@ -79,6 +79,74 @@ def copy_probe(nbytes, reps=5):
     print(json.dumps({"copy_probe_bytes": 4 * n, "reps": reps}), flush=True)
 
 
+def splitmix_uniforms(seed, count):
+    """u in [0, 1) from SplitMix64 (the generator of the disorder fields)."""
+    M = (1 << 64) - 1
+    x, out = seed & M, []
+    for _ in range(count):
+        x = (x + 0x9E3779B97F4A7C15) & M
+        z = x
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        z ^= z >> 31
+        out.append((z >> 11) * 2.0 ** -53)
+    return out
+
+
+def serve_stream(n, seed=0):
+    """Requests of the served workload: L uniform in {10, 12, 14, 16},
+    h ~ U[0.5, 5], eps ~ U[0.05, 0.95], nev = 20, seed = request index."""
+    u = splitmix_uniforms(seed ^ 0x5EED, 3 * n)
+    return [((10, 12, 14, 16)[min(3, int(4 * u[3 * i]))], 0.5 + 4.5 * u[3 * i + 1],
+             i, 0.05 + 0.9 * u[3 * i + 2]) for i in range(n)]
+
+
+def run_served(mbl, reqs, prec, rate, slots, nev=20):
+    """Submit reqs at Poisson arrival times (rate per second; 0 = all at once)
+    to a fresh serving context; returns throughput and latency figures."""
+    import threading
+    ctx = mbl.Context(0)
+    ctx.mbl_serve_start(slots)
+    for L in sorted({r[0] for r in reqs}):          # plans built before the clock starts
+        ctx.mbl_footprint(L, prec, nev)
+    gaps = [0.0] * len(reqs)
+    if rate > 0:
+        gaps = [-math.log(1.0 - u) / rate for u in splitmix_uniforms(12345, len(reqs))]
+    tickets, outs = [], [None] * len(reqs)
+    done_evt = threading.Event()
+
+    def collect():
+        for i in range(len(reqs)):
+            while i >= len(tickets):
+                time.sleep(0.0005)
+            outs[i] = ctx.mbl_wait(tickets[i])
+        done_evt.set()
+
+    th = threading.Thread(target=collect)
+    t0 = time.perf_counter()
+    th.start()
+    t_next = t0
+    for (L, h, s, e), g in zip(reqs, gaps):
+        t_next += g
+        dt = t_next - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(ctx.mbl_submit(L, h, s, e, nev, prec=prec))
+    done_evt.wait()
+    wall = time.perf_counter() - t0
+    th.join()
+    st = ctx.mbl_serve_stats()
+    ctx.close()
+    ok = [o for o in outs if o["status"] == 0]
+    lat = [o["t_done"] - o["t_submit"] for o in outs]
+    conv = sum(int(sum(1 for r in o["resid"] if r <= 1e-9)) for o in ok)
+    return {"requests": len(reqs), "ok": len(ok), "wall_s": wall,
+            "requests_per_s": len(reqs) / wall, "eigenpairs_per_s": conv / wall,
+            "latency_ms": {"p50": 1e3 * percentile(lat, 0.5), "p99": 1e3 * percentile(lat, 0.99)},
+            "fallbacks": sum(o["fallback"] for o in ok), "max_running": st["max_running"],
+            "bypasses": st["bypasses"]}, outs
+
+
 def workload(L, steps):
     """(seed, h, eps) of the timed steps."""
     if L >= 20:
@@ -155,6 +223,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--roofline-kernel", default="schur")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run a device copy of this many bytes")
+    ap.add_argument("--serve-requests", type=int, default=1024)
+    ap.add_argument("--serve-slots", type=int, default=4)
     a = ap.parse_args()
     if a.copy_probe > 0:
         copy_probe(a.copy_probe)
@@ -163,6 +233,8 @@ def main():
         print("bench.py: this build runs on one GPU only (no collectives); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+
+    import numpy as np
 
     import paper_1411_0660_amd as mbl
 
@@ -246,6 +318,24 @@ def main():
                       "latency_ms": {"p50": 1e3 * percentile(lat3, 0.5),
                                      "p99": 1e3 * percentile(lat3, 0.99)}}
     ctx.close()
+    if a.serve_requests > 0:
+        log("served stream: closed-loop capacity")
+        reqs = serve_stream(a.serve_requests)
+        cap, _ = run_served(mbl, reqs[:min(256, len(reqs))], mbl.MBL_FP32_IR64, 0.0, a.serve_slots)
+        rate = 0.8 * cap["requests_per_s"]
+        log(f"served stream: {len(reqs)} requests at {rate:.1f}/s, FP32+refinement")
+        mixed, outs32 = run_served(mbl, reqs, mbl.MBL_FP32_IR64, rate, a.serve_slots)
+        log("served stream: FP64")
+        plain, outs64 = run_served(mbl, reqs, mbl.MBL_FP64, rate, a.serve_slots)
+        err = [float(np.abs(o32["evals"] - o64["evals"]).max() / o64["hnorm"])
+               for o32, o64 in zip(outs32, outs64) if o32["status"] == 0 and o64["status"] == 0]
+        out["served"] = {
+            "workload": (f"{len(reqs)} requests, L uniform in {{10,12,14,16}}, h ~ U[0.5,5], "
+                         f"eps ~ U[0.05,0.95], nev=20, Poisson arrivals at 0.8 x the closed-loop "
+                         f"capacity of the mixed path, {a.serve_slots} slots, footprint admission"),
+            "arrival_rate_per_s": rate, "closed_loop_capacity_per_s": cap["requests_per_s"],
+            "fp32_refined": mixed, "fp64": plain,
+            "max_eval_err_fp32_vs_fp64_over_hnorm": max(err) if err else None}
     if not a.no_cpu:
         log("cpu baseline (oracle)")
         try:

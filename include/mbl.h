@@ -108,6 +108,8 @@ typedef struct {
     double t_phase[8];     /* seconds: 0 assemble, 1 extremal, 2 symbolic, 3 factor,
                               4 Krylov (solves + orthogonalisation), 5 observables,
                               6 total, 7 of which shifted solves */
+    double t_submit, t_start, t_done; /* requests (mbl_submit): seconds since the server
+                              started at submission, admission and completion */
 } mbl_result;
 
 /* Statistics of the per-L symbolic analysis (fill-reducing nested dissection,
@@ -202,12 +204,44 @@ int mbl_profile_enable(mbl_ctx *ctx, const char *kernel_class);
 /* Synchronises the stream and returns the counters. */
 int mbl_profile_read(mbl_ctx *ctx, mbl_kernel_profile *out);
 
-/* ---- serving: requests of mixed sizes admitted as device memory frees up -- */
-/* The problem and result structs (and the buffers they point to) must stay
- * valid until mbl_wait returns for the ticket. */
+/* ---- serving: continuous batching of solve requests ----------------------
+ * The paper's workload is many independent solves (disorder realizations x
+ * energy targets, "Numerical method" section).  Requests of mixed sizes are
+ * taken in arrival order and admitted to one of `slots` solver slots (each its
+ * own HIP stream and host thread, so their work overlaps on the device) when a
+ * slot is idle and the device bytes all slots hold, plus the request's
+ * predicted footprint (mbl_footprint; an FP32 request also counts the FP64
+ * factor of its fallback), fit `budget_bytes`.  A request that does not fit
+ * lets later ones pass, at most 2 x slots times.  The per-L plans are built
+ * once by the context and shared.  A request's arithmetic does not depend on
+ * its slot or on the other requests: its result is the same alone and in the
+ * mix (bitwise, given the same device).  Requests whose footprint exceeds the
+ * budget complete with MBL_ENOMEM. */
+typedef struct {
+    int slots;
+    size_t budget_bytes;
+    size_t held_bytes;          /* bytes the slots may hold now (largest admitted each) */
+    int64_t submitted, admitted, completed;
+    int64_t running, queued;    /* now */
+    int64_t max_running;        /* largest number of requests on the device at once */
+    int64_t bypasses;           /* admissions ahead of an earlier request */
+    int64_t trims;              /* idle slots that gave their buffers back */
+} mbl_serve_info;
+
+/* Start the server with `slots` (1..16; 0 = 4) slots and a budget (0 = the
+ * context's budget).  Optional: mbl_submit starts it with the defaults.
+ * MBL_EBUSY if it is already running. */
+int mbl_serve_start(mbl_ctx *ctx, int slots, size_t budget_bytes);
+/* Queue one request; `prob` is copied, but prob->fields (if set), `res` and the
+ * buffers it points to must stay valid until mbl_wait returns for the ticket.
+ * Errors of the solve itself are reported by mbl_wait's status. */
 int mbl_submit(mbl_ctx *ctx, const mbl_problem *prob, mbl_result *res, uint64_t *ticket);
+/* done = 1 once the result is written. MBL_ENOTFOUND for unknown tickets. */
 int mbl_poll(mbl_ctx *ctx, uint64_t ticket, int *done);
+/* Block until the request completes; *status = its mbl status.  The ticket is
+ * released. */
 int mbl_wait(mbl_ctx *ctx, uint64_t ticket, int *status);
+int mbl_serve_stats(mbl_ctx *ctx, mbl_serve_info *out);
 
 #ifdef __cplusplus
 }

@@ -29,7 +29,8 @@ EXPORTS = ("mbl_create", "mbl_destroy", "mbl_strerror", "mbl_last_error", "mbl_p
            "mbl_sector_dim", "mbl_fields", "mbl_basis", "mbl_rank", "mbl_hamiltonian",
            "mbl_spmv", "mbl_extremal", "mbl_symbolic", "mbl_ordering", "mbl_shift_solve",
            "mbl_observables", "mbl_observables_extra", "mbl_solve", "mbl_footprint",
-           "mbl_submit", "mbl_poll", "mbl_wait", "mbl_profile_enable", "mbl_profile_read")
+           "mbl_serve_start", "mbl_submit", "mbl_poll", "mbl_wait", "mbl_serve_stats",
+           "mbl_profile_enable", "mbl_profile_read")
 
 _d = ctypes.c_double
 _pd = ctypes.POINTER(ctypes.c_double)
@@ -50,7 +51,8 @@ class mbl_result(ctypes.Structure):
                 ("max_resid", _d), ("nconv", ctypes.c_int), ("n_restarts", ctypes.c_int),
                 ("n_opapply", ctypes.c_int), ("ir_iters_max", ctypes.c_int),
                 ("n_perturbed", ctypes.c_int), ("fallback", ctypes.c_int),
-                ("t_phase", _d * 8)]
+                ("t_phase", _d * 8),
+                ("t_submit", _d), ("t_start", _d), ("t_done", _d)]
 
 
 class mbl_symbolic_info(ctypes.Structure):
@@ -61,6 +63,13 @@ class mbl_symbolic_info(ctypes.Structure):
 
 class mbl_kernel_profile(ctypes.Structure):
     _fields_ = [("launches", _i64), ("seconds", _d), ("bytes", _d), ("flops", _d)]
+
+
+class mbl_serve_info(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int), ("budget_bytes", ctypes.c_size_t),
+                ("held_bytes", ctypes.c_size_t), ("submitted", _i64), ("admitted", _i64),
+                ("completed", _i64), ("running", _i64), ("queued", _i64), ("max_running", _i64),
+                ("bypasses", _i64), ("trims", _i64)]
 
 
 class mbl_solve_info(ctypes.Structure):
@@ -107,6 +116,8 @@ def lib() -> ctypes.CDLL:
     L.mbl_solve.argtypes = [vp, ctypes.POINTER(mbl_problem), ctypes.POINTER(mbl_result)]
     L.mbl_footprint.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                 ctypes.POINTER(ctypes.c_size_t)]
+    L.mbl_serve_start.argtypes = [vp, ctypes.c_int, ctypes.c_size_t]
+    L.mbl_serve_stats.argtypes = [vp, ctypes.POINTER(mbl_serve_info)]
     L.mbl_submit.argtypes = [vp, ctypes.POINTER(mbl_problem), ctypes.POINTER(mbl_result),
                              ctypes.POINTER(ctypes.c_uint64)]
     L.mbl_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
@@ -149,6 +160,7 @@ class Context:
     """A libmbl context on one HIP device (``mbl_create`` / ``mbl_destroy``)."""
 
     def __init__(self, device: int = 0, hbm_budget: int = 0, stream=None):
+        self._pending = {}          # ticket -> buffers the library writes into
         self._h = ctypes.c_void_p()
         s = ctypes.c_void_p(stream) if stream else None
         _check(lib().mbl_create(device, hbm_budget, s, ctypes.byref(self._h)), "mbl_create")
@@ -259,10 +271,8 @@ class Context:
         return s2, fl, df, kl[:max(nev - 1, 0)]
 
     # -- whole path
-    def mbl_solve(self, L: int, h: float, seed: int, eps: float, nev: int, *, J: float = 1.0,
-                  prec: int = MBL_FP64, fields=None, sigma: float = math.nan, tol: float = 0.0,
-                  vectors: bool = False, extra: bool = False, block: int = 0, ncv: int = 0,
-                  entanglement: bool = True, allow_notconv: bool = False) -> dict:
+    def _prepare(self, L, h, seed, eps, nev, J, prec, fields, sigma, tol, vectors, extra, block,
+                 ncv, entanglement):
         pr = mbl_problem()
         lib().mbl_problem_init(ctypes.byref(pr))
         pr.L, pr.J, pr.h, pr.seed, pr.eps, pr.sigma, pr.nev = L, J, h, seed, eps, sigma, nev
@@ -273,21 +283,24 @@ class Context:
             pr.fields = _pd_of(f)
         pr.flags = MBL_WANT_OBS | (MBL_WANT_VECTORS if vectors else 0) | \
             (MBL_WANT_OBS_EXTRA if extra else 0)
-        n = mbl_sector_dim(L)
-        bufs = dict(evals=np.zeros(nev), resid=np.zeros(nev), r=np.zeros(max(nev - 2, 1)),
-                    s1=np.zeros(nev))
+        n = mbl_sector_dim(L) if 2 <= L <= MBL_L_MAX and L % 2 == 0 else 1
+        nb = max(nev, 1)
+        bufs = dict(evals=np.zeros(nb), resid=np.zeros(nb), r=np.zeros(max(nev - 2, 1)),
+                    s1=np.zeros(nb))
         if entanglement:
-            bufs["se"] = np.zeros(nev)
+            bufs["se"] = np.zeros(nb)
         if vectors:
-            bufs["evecs"] = np.zeros((nev, n))
+            bufs["evecs"] = np.zeros((nb, n))
         if extra:
-            bufs.update(s2=np.zeros(nev), fluct=np.zeros(nev), dynfrac=np.zeros(nev),
+            bufs.update(s2=np.zeros(nb), fluct=np.zeros(nb), dynfrac=np.zeros(nb),
                         kl=np.zeros(max(nev - 1, 1)))
         res = mbl_result()
         for k, v in bufs.items():
             setattr(res, k, _pd_of(v))
-        code = lib().mbl_solve(self._h, ctypes.byref(pr), ctypes.byref(res))
-        _check(code, "mbl_solve", allow=(MBL_ENOTCONV,) if allow_notconv else ())
+        return pr, res, bufs, f
+
+    @staticmethod
+    def _collect(res, bufs, nev, vectors):
         out = {k: v for k, v in bufs.items()}
         out["r"] = out["r"][:max(nev - 2, 0)]
         if "kl" in out:
@@ -295,11 +308,58 @@ class Context:
         if vectors:
             out["evecs"] = out["evecs"].T.copy()      # dim x nev
         for k in ("emin", "emax", "sigma", "hnorm", "r_mean", "max_resid", "nconv", "n_restarts",
-                  "n_opapply", "ir_iters_max", "n_perturbed", "fallback"):
+                  "n_opapply", "ir_iters_max", "n_perturbed", "fallback", "t_submit", "t_start",
+                  "t_done"):
             out[k] = getattr(res, k)
         out["t_phase"] = list(res.t_phase)
+        return out
+
+    def mbl_solve(self, L: int, h: float, seed: int, eps: float, nev: int, *, J: float = 1.0,
+                  prec: int = MBL_FP64, fields=None, sigma: float = math.nan, tol: float = 0.0,
+                  vectors: bool = False, extra: bool = False, block: int = 0, ncv: int = 0,
+                  entanglement: bool = True, allow_notconv: bool = False) -> dict:
+        pr, res, bufs, _f = self._prepare(L, h, seed, eps, nev, J, prec, fields, sigma, tol,
+                                          vectors, extra, block, ncv, entanglement)
+        code = lib().mbl_solve(self._h, ctypes.byref(pr), ctypes.byref(res))
+        _check(code, "mbl_solve", allow=(MBL_ENOTCONV,) if allow_notconv else ())
+        out = self._collect(res, bufs, nev, vectors)
         out["status"] = code
         return out
+
+    # -- serving (continuous batching)
+    def mbl_serve_start(self, slots: int = 0, budget_bytes: int = 0):
+        _check(lib().mbl_serve_start(self._h, slots, budget_bytes), "mbl_serve_start")
+
+    def mbl_submit(self, L: int, h: float, seed: int, eps: float, nev: int, *, J: float = 1.0,
+                   prec: int = MBL_FP64, fields=None, sigma: float = math.nan, tol: float = 0.0,
+                   vectors: bool = False, extra: bool = False, block: int = 0, ncv: int = 0,
+                   entanglement: bool = True) -> int:
+        pr, res, bufs, f = self._prepare(L, h, seed, eps, nev, J, prec, fields, sigma, tol,
+                                         vectors, extra, block, ncv, entanglement)
+        t = ctypes.c_uint64()
+        _check(lib().mbl_submit(self._h, ctypes.byref(pr), ctypes.byref(res), ctypes.byref(t)),
+               "mbl_submit")
+        self._pending[t.value] = (pr, res, bufs, f, nev, vectors)
+        return t.value
+
+    def mbl_poll(self, ticket: int) -> bool:
+        done = ctypes.c_int()
+        _check(lib().mbl_poll(self._h, ticket, ctypes.byref(done)), "mbl_poll")
+        return bool(done.value)
+
+    def mbl_wait(self, ticket: int) -> dict:
+        """Result dict of the request (as mbl_solve) plus ``status``."""
+        st = ctypes.c_int()
+        _check(lib().mbl_wait(self._h, ticket, ctypes.byref(st)), "mbl_wait")
+        pr, res, bufs, f, nev, vectors = self._pending.pop(ticket)
+        out = self._collect(res, bufs, nev, vectors)
+        out["status"] = st.value
+        return out
+
+    def mbl_serve_stats(self) -> dict:
+        i = mbl_serve_info()
+        _check(lib().mbl_serve_stats(self._h, ctypes.byref(i)), "mbl_serve_stats")
+        return {k: getattr(i, k) for k, _ in i._fields_}
 
     def mbl_profile_enable(self, kernel_class: str | None):
         _check(lib().mbl_profile_enable(self._h, kernel_class.encode() if kernel_class else None),

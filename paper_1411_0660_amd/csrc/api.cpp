@@ -19,6 +19,7 @@ void set_last_error(const std::string &msg) { g_last_error = msg; }
 struct mbl_ctx {
     mbl::Context *c;
     mbl::Server *srv;
+    std::mutex srv_mu;
 };
 
 using namespace mbl;
@@ -398,12 +399,35 @@ int mbl_profile_read(mbl_ctx *ctx, mbl_kernel_profile *out) {
     });
 }
 
+int mbl_serve_start(mbl_ctx *ctx, int slots, size_t budget_bytes) {
+    if (!ctx || slots < 0 || slots > 16) return MBL_EINVAL;
+    return guarded([&] {
+        std::lock_guard<std::mutex> lk(ctx->srv_mu);
+        MBL_REQUIRE(!ctx->srv, MBL_EBUSY, "server already running");
+        MBL_HIP(hipSetDevice(ctx->c->device));
+        ctx->srv = new Server(ctx->c, slots ? slots : 4,
+                              budget_bytes ? budget_bytes : ctx->c->budget.limit);
+    });
+}
+
 int mbl_submit(mbl_ctx *ctx, const mbl_problem *prob, mbl_result *res, uint64_t *ticket) {
     if (!ctx || !prob || !res || !ticket) return MBL_EINVAL;
     return guarded([&] {
-        if (!ctx->srv) ctx->srv = new Server(ctx->c);
+        {
+            std::lock_guard<std::mutex> lk(ctx->srv_mu);
+            if (!ctx->srv) {
+                MBL_HIP(hipSetDevice(ctx->c->device));
+                ctx->srv = new Server(ctx->c, 4, ctx->c->budget.limit);
+            }
+        }
         *ticket = ctx->srv->submit(*prob, res);
     });
+}
+
+int mbl_serve_stats(mbl_ctx *ctx, mbl_serve_info *out) {
+    if (!ctx || !out) return MBL_EINVAL;
+    if (!ctx->srv) return MBL_ENOTFOUND;
+    return guarded([&] { ctx->srv->info(out); });
 }
 
 int mbl_poll(mbl_ctx *ctx, uint64_t ticket, int *done) {

@@ -89,6 +89,36 @@ class DevBuf {
     Budget *b_ = nullptr;
 };
 
+// Page-locked host memory (hipHostMalloc), grow-only, for asynchronous
+// device-to-host copies of small results.
+class PinnedBuf {
+  public:
+    PinnedBuf() = default;
+    PinnedBuf(const PinnedBuf &) = delete;
+    PinnedBuf &operator=(const PinnedBuf &) = delete;
+    ~PinnedBuf() { reset(); }
+    void ensure(size_t bytes) {
+        if (bytes <= n_) return;
+        reset();
+        void *p = nullptr;
+        hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+        if (e != hipSuccess)
+            throw Error(MBL_ENOMEM, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+        p_ = p;
+        n_ = bytes;
+    }
+    void reset() {
+        if (p_) (void)hipHostFree(p_);
+        p_ = nullptr;
+        n_ = 0;
+    }
+    template <class T> T *ptr() const { return static_cast<T *>(p_); }
+
+  private:
+    void *p_ = nullptr;
+    size_t n_ = 0;
+};
+
 template <class T>
 inline void h2d(T *dst, const T *src, size_t n, hipStream_t s) {
     if (n) MBL_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, s));

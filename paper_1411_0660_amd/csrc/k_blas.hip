@@ -335,6 +335,42 @@ __global__ __launch_bounds__(BS) void k_bcomb(int64_t n, int nb, int nrhs,
     *o = (beta == 0.0 ? 0.0 : beta * *o) + alpha * s;
 }
 
+// Cholesky G = R^T R of a small b x b Gram matrix (b <= 16) and R^-1, by one
+// lane (a few hundred flops, kept on the device so the Krylov expansion needs
+// no host round trip): R (upper, column-major, zeros below) to Rout, R^-1 to
+// Rinv; *flag = 1 if a pivot fell below rel_tiny * max diag (it is then
+// floored there, so the factor stays finite).
+__global__ void k_small_chol(int b, const double *__restrict__ G, double *__restrict__ Rout,
+                             double *__restrict__ Rinv, int *__restrict__ flag, double rel_tiny) {
+    __shared__ double R[16 * 16], Ri[16 * 16];
+    if (threadIdx.x != 0) return;
+    double dmax = 0.0;
+    for (int i = 0; i < b; i++) dmax = fmax(dmax, G[i * b + i]);
+    int fl = 0;
+    for (int q = 0; q < b * b; q++) { R[q] = 0.0; Ri[q] = 0.0; }
+    for (int j = 0; j < b; j++)
+        for (int i = 0; i <= j; i++) {
+            double sum = G[j * b + i];
+            for (int k = 0; k < i; k++) sum -= R[i * b + k] * R[j * b + k];
+            if (i == j) {
+                if (sum <= rel_tiny * dmax) { fl = 1; sum = fmax(sum, rel_tiny * dmax + 1e-300); }
+                R[j * b + j] = sqrt(sum);
+            } else {
+                R[j * b + i] = sum / R[i * b + i];
+            }
+        }
+    for (int j = 0; j < b; j++) {
+        Ri[j * b + j] = 1.0 / R[j * b + j];
+        for (int i = j - 1; i >= 0; i--) {
+            double sum = 0.0;
+            for (int k = i + 1; k <= j; k++) sum += R[k * b + i] * Ri[j * b + k];
+            Ri[j * b + i] = -sum / R[i * b + i];
+        }
+    }
+    for (int q = 0; q < b * b; q++) { Rout[q] = R[q]; Rinv[q] = Ri[q]; }
+    *flag = fl;
+}
+
 }  // namespace
 
 void launch_coldot(int64_t n, int ncol, const double *A, int64_t lda, const double *B, int64_t ldb,
@@ -353,6 +389,13 @@ void launch_sub_scaled_cols(int64_t n, int ncol, const double *e, const double *
     if (ncol == 0 || n == 0) return;
     hipLaunchKernelGGL(k_sub_scaled_cols, dim3(grid_for(n, 256), ncol), dim3(256), 0, s, n, ncol, e,
                        X, ldx, Y, ldy);
+    MBL_CHECK_LAUNCH();
+}
+
+void launch_small_chol(int b, const double *G, double *R, double *Rinv, int *flag,
+                       double rel_tiny, hipStream_t s) {
+    MBL_REQUIRE(b >= 1 && b <= 16, MBL_EINVAL, "small_chol: b must be 1..16");
+    k_small_chol<<<dim3(1), dim3(64), 0, s>>>(b, G, R, Rinv, flag, rel_tiny);
     MBL_CHECK_LAUNCH();
 }
 

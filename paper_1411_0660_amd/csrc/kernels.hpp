@@ -43,6 +43,10 @@ void launch_copy(int64_t count, const double *x, double *y, hipStream_t s);
 void launch_axpy(int64_t count, double a, const double *x, double *y, hipStream_t s);
 void launch_coldot(int64_t n, int ncol, const double *A, int64_t lda, const double *B, int64_t ldb,
                    double *out, double *partials, int nparts, hipStream_t s);
+// G = R^T R (b x b, b <= 16): R and R^-1 (upper, column-major) on the device;
+// *flag = 1 if a pivot fell below rel_tiny * max diag
+void launch_small_chol(int b, const double *G, double *R, double *Rinv, int *flag,
+                       double rel_tiny, hipStream_t s);
 // per-column dots of W against nb stacked blocks (block i at V + i bs, n x nrhs,
 // ld n): out[i + j nb]; partials >= nparts * nb * nrhs, nb <= 32
 void launch_bdot(int64_t n, int nb, int nrhs, const double *V, int64_t bs, const double *W,

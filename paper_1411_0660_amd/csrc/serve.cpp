@@ -1,5 +1,15 @@
-// serve.cpp -- request queue: requests are taken in arrival order by a worker
-// thread and run through the same path as mbl_solve.
+// serve.cpp -- continuous batching of solve requests.
+//
+// Requests wait in arrival order.  A dispatcher thread sizes each one (the
+// per-L plan and symbolic analysis are built once, by the owning context, and
+// shared read-only by the slots) and admits it to an idle slot when the bytes
+// all slots may hold -- their grow-only work buffers, counted at the largest
+// footprint each slot has run -- plus its own footprint fit the budget.  A
+// request that does not fit lets later ones pass, at most 2 x slots times, and
+// idle slots give back their buffers when that makes it fit.  Each slot solves
+// on its own stream in its own thread, so requests overlap on the device; the
+// arithmetic of a request does not depend on the slot or on what else runs, so
+// its result is the same alone and in the mix.
 #include "serve.hpp"
 
 #include <algorithm>
@@ -8,19 +18,33 @@ namespace mbl {
 
 size_t footprint_bytes(const Plan &p, int prec, int nev, int block) {
     size_t n = (size_t)p.dim;
-    size_t es = (prec == MBL_FP32_IR64) ? 4 : 8;
-    int b = block > 0 ? block : 8;
-    size_t cols = (size_t)std::max(2 * nev + 2 * b, nev + nev / 2 + 3 * b) + 2 * b;
+    int b = block > 0 ? std::min(block, 16) : (n >= 10000 ? 8 : (n >= 600 ? 4 : 1));
+    int nw = (int)std::min<size_t>(n, (size_t)nev + 2 + nev / 16);
+    size_t cols = (size_t)std::max(2 * nw + 2 * b, nw + std::max(8, nw / 2) + 3 * b) + 2 * b;
+    cols = std::min(cols, n + 16);
     size_t bytes = 0;
-    bytes += es * (size_t)p.arena_elems + 4 * n;           // fronts + pivots
-    if (prec == MBL_FP32_IR64) bytes += 0;                  // FP64 fallback is allocated on demand
-    bytes += 8 * (size_t)p.vec_elems + 8 * n * 16 * 3;      // solve vectors, x_new, r, d
-    bytes += 8 * n * cols * 2 + 8 * n * b;                  // Krylov bases + work block
-    bytes += 8 * n * (size_t)nev * 4;                       // Ritz vectors, H psi, sorted copy, blocks
+    bytes += 8 * (size_t)p.arena_elems + 12 * n;            // FP64 fronts, pivots, row maps
+    if (prec == MBL_FP32_IR64) bytes += 4 * (size_t)p.arena_elems + 12 * n;   // FP32 factor
+    bytes += 8 * (size_t)p.vec_elems * 2 + 8 * n * 16 * 4; // solve vectors, x_new, r, d
+    bytes += 8 * (size_t)p.part_elems;                      // U12 partial products
+    bytes += 8 * n * cols * 2 + 8 * n * 16;                 // Krylov bases + work block
+    if (prec == MBL_FP32_IR64) bytes += 8 * n * 16 * 62;    // GMRES bases (30 + 31 blocks)
+    bytes += 8 * n * (size_t)(nw + 8) * 4;                  // Ritz vectors, H psi, copies
     return bytes;
 }
 
-Server::Server(Context *ctx) : ctx_(ctx) { worker_ = std::thread([this] { loop(); }); }
+Server::Server(Context *owner, int slots, size_t budget) : owner_(owner), budget_(budget) {
+    t0_ = wall_seconds();
+    stats_.slots = slots;
+    stats_.budget_bytes = budget;
+    for (int i = 0; i < slots; i++) {
+        std::unique_ptr<Slot> sl(new Slot);
+        sl->ctx.reset(new Context(*owner, budget));
+        slots_.push_back(std::move(sl));
+    }
+    for (int i = 0; i < slots; i++) slots_[i]->th = std::thread([this, i] { worker(i); });
+    dispatcher_ = std::thread([this] { dispatcher(); });
+}
 
 Server::~Server() {
     {
@@ -28,18 +52,25 @@ Server::~Server() {
         stop_ = true;
     }
     cv_.notify_all();
-    if (worker_.joinable()) worker_.join();
+    for (auto &sl : slots_) sl->cv.notify_all();
+    if (dispatcher_.joinable()) dispatcher_.join();
+    for (auto &sl : slots_)
+        if (sl->th.joinable()) sl->th.join();
+    std::lock_guard<std::mutex> lk(mu_);
+    for (uint64_t t : queue_) finish_locked(t, MBL_EBUSY);   // never started
+    queue_.clear();
 }
 
 uint64_t Server::submit(const mbl_problem &prob, mbl_result *res) {
     std::lock_guard<std::mutex> lk(mu_);
     uint64_t t = next_++;
-    Req r;
+    Req &r = reqs_[t];
     r.prob = prob;
     r.res = res;
-    reqs_[t] = r;
+    r.t_submit = wall_seconds() - t0_;
     queue_.push_back(t);
-    cv_.notify_one();
+    stats_.submitted++;
+    cv_.notify_all();
     return t;
 }
 
@@ -53,46 +84,173 @@ int Server::poll(uint64_t ticket, int *done) {
 
 int Server::wait(uint64_t ticket, int *status) {
     std::unique_lock<std::mutex> lk(mu_);
-    auto it = reqs_.find(ticket);
-    if (it == reqs_.end()) return MBL_ENOTFOUND;
+    if (reqs_.find(ticket) == reqs_.end()) return MBL_ENOTFOUND;
     done_cv_.wait(lk, [&] { return reqs_[ticket].done; });
     if (status) *status = reqs_[ticket].status;
     reqs_.erase(ticket);
     return MBL_OK;
 }
 
-void Server::loop() {
-    for (;;) {
-        uint64_t t;
-        mbl_problem prob;
-        mbl_result *res;
-        {
-            std::unique_lock<std::mutex> lk(mu_);
-            cv_.wait(lk, [&] { return stop_ || !queue_.empty(); });
-            if (stop_ && queue_.empty()) return;
-            t = queue_.front();
-            queue_.pop_front();
-            prob = reqs_[t].prob;
-            res = reqs_[t].res;
+void Server::info(mbl_serve_info *out) {
+    std::lock_guard<std::mutex> lk(mu_);
+    *out = stats_;
+    out->running = running_;
+    out->queued = (int64_t)queue_.size();
+    size_t held = 0;
+    for (auto &sl : slots_) held += sl->held;
+    out->held_bytes = held;
+}
+
+void Server::finish_locked(uint64_t t, int status) {
+    Req &r = reqs_[t];
+    r.status = status;
+    r.done = true;
+    r.t_done = wall_seconds() - t0_;
+    if (r.res) {
+        r.res->t_submit = r.t_submit;
+        r.res->t_start = r.t_start;
+        r.res->t_done = r.t_done;
+    }
+    stats_.completed++;
+    done_cv_.notify_all();
+}
+
+bool Server::admit_locked() {
+    bool any = false;
+    const int nslots = (int)slots_.size();
+    std::vector<uint64_t> skipped;
+    for (auto it = queue_.begin(); it != queue_.end();) {
+        uint64_t t = *it;
+        Req &r = reqs_[t];
+        if (!r.sized) break;                      // arrival order: size first
+        if (r.fp > budget_) {                     // can never fit
+            it = queue_.erase(it);
+            finish_locked(t, MBL_ENOMEM);
+            continue;
         }
+        size_t total = 0, busy_held = 0;
+        for (auto &sl : slots_) {
+            total += sl->held;
+            if (sl->busy) busy_held += sl->held;
+        }
+        int best = -1;
+        size_t best_growth = 0;
+        for (int s = 0; s < nslots; s++) {
+            Slot &sl = *slots_[s];
+            if (sl.busy) continue;
+            size_t grown = std::max(sl.held, r.fp);
+            if (total - sl.held + grown > budget_) continue;
+            size_t growth = grown - sl.held;
+            if (best < 0 || growth < best_growth) { best = s; best_growth = growth; }
+        }
+        if (best < 0 && busy_held + r.fp <= budget_) {
+            // idle slots give their buffers back until the request fits
+            for (int s = 0; s < nslots && best < 0; s++) {
+                Slot &sl = *slots_[s];
+                if (sl.busy || sl.held == 0) continue;
+                {
+                    std::lock_guard<std::recursive_mutex> g(sl.ctx->mu);
+                    sl.ctx->trim();
+                }
+                total -= sl.held;
+                sl.held = 0;
+                stats_.trims++;
+                if (total + r.fp <= budget_) best = s;
+            }
+        }
+        if (best < 0) {
+            skipped.push_back(t);
+            if (r.bypassed >= 2 * nslots) break;  // stop letting later requests pass
+            ++it;
+            continue;
+        }
+        Slot &sl = *slots_[best];
+        sl.held = std::max(sl.held, r.fp);
+        sl.busy = true;
+        sl.ticket = t;
+        r.t_start = wall_seconds() - t0_;
+        running_++;
+        stats_.admitted++;
+        stats_.max_running = std::max<int64_t>(stats_.max_running, running_);
+        for (uint64_t u : skipped) {
+            reqs_[u].bypassed++;
+            stats_.bypasses++;
+        }
+        it = queue_.erase(it);
+        sl.cv.notify_one();
+        any = true;
+    }
+    return any;
+}
+
+void Server::dispatcher() {
+    (void)hipSetDevice(owner_->device);
+    std::unique_lock<std::mutex> lk(mu_);
+    while (!stop_) {
+        // size the first request that has no footprint yet (plans are built
+        // by the owning context, outside the queue lock)
+        uint64_t t = 0;
+        for (uint64_t u : queue_)
+            if (!reqs_[u].sized) { t = u; break; }
+        if (t) {
+            mbl_problem prob = reqs_[t].prob;
+            lk.unlock();
+            int code = MBL_OK;
+            size_t fp = 0;
+            try {
+                MBL_REQUIRE(prob.L >= 2 && prob.L <= MBL_L_MAX && prob.L % 2 == 0, MBL_EINVAL,
+                            "L must be even with 2 <= L <= 22");
+                std::lock_guard<std::recursive_mutex> g(owner_->mu);
+                Plan &p = owner_->plan(prob.L);
+                owner_->ensure_symbolic(p);
+                fp = footprint_bytes(p, prob.prec, prob.nev > 0 ? prob.nev : 1, prob.block);
+            } catch (const Error &e) {
+                code = e.code;
+            } catch (const std::exception &) {
+                code = MBL_EDEVICE;
+            }
+            lk.lock();
+            if (code != MBL_OK) {
+                queue_.erase(std::find(queue_.begin(), queue_.end(), t));
+                finish_locked(t, code);
+            } else {
+                reqs_[t].fp = fp;
+                reqs_[t].sized = true;
+            }
+            admit_locked();
+            continue;
+        }
+        if (!admit_locked()) cv_.wait(lk);
+    }
+}
+
+void Server::worker(int s) {
+    (void)hipSetDevice(owner_->device);
+    Slot &sl = *slots_[s];
+    std::unique_lock<std::mutex> lk(mu_);
+    for (;;) {
+        sl.cv.wait(lk, [&] { return stop_ || sl.busy; });
+        if (!sl.busy) return;                     // stopping, nothing assigned
+        uint64_t t = sl.ticket;
+        mbl_problem prob = reqs_[t].prob;
+        mbl_result *res = reqs_[t].res;
+        lk.unlock();
         int st = MBL_OK;
         try {
-            std::lock_guard<std::recursive_mutex> g(ctx_->mu);
-            MBL_HIP(hipSetDevice(ctx_->device));
-            solve_problem(*ctx_, prob, *res);
+            std::lock_guard<std::recursive_mutex> g(sl.ctx->mu);
+            solve_problem(*sl.ctx, prob, *res);
         } catch (const Error &e) {
-            set_last_error(e.what());
             st = e.code;
-        } catch (const std::exception &e) {
-            set_last_error(e.what());
+        } catch (const std::bad_alloc &) {
+            st = MBL_ENOMEM;
+        } catch (const std::exception &) {
             st = MBL_EDEVICE;
         }
-        {
-            std::lock_guard<std::mutex> lk(mu_);
-            reqs_[t].status = st;
-            reqs_[t].done = true;
-        }
-        done_cv_.notify_all();
+        lk.lock();
+        sl.busy = false;
+        running_--;
+        finish_locked(t, st);
+        cv_.notify_all();
     }
 }
 

@@ -1,5 +1,5 @@
 // smalleig.cpp -- eigenpairs of the small dense symmetric projected matrix of
-// the Krylov method (order ~ 100).  All eigenvalues by Sturm bisection on the
+// the Krylov method (order ~ 100).  All eigenvalues by implicit QR on the
 // Householder tridiagonal form; eigenvectors only for the selected values, by
 // inverse iteration on the tridiagonal (with Gram-Schmidt inside clusters) and
 // back-transformation.
@@ -33,11 +33,13 @@ void tridiag(int m, std::vector<double> &a, std::vector<double> &d, std::vector<
         e[c] = beta;
         v[0] = 1.0;
         for (int i = 1; i < mm; i++) { col[c + 1 + i] *= sc; v[i] = col[c + 1 + i]; }
-        for (int i = 0; i < mm; i++) {
-            double s = 0.0;
-            for (int j = 0; j < mm; j++) s += a[(size_t)(c + 1 + j) * m + (c + 1 + i)] * v[j];
-            p[i] = t * s;
+        std::fill(p.begin(), p.begin() + mm, 0.0);
+        for (int j = 0; j < mm; j++) {             // p = t A v, column by column
+            const double *aj = &a[(size_t)(c + 1 + j) * m + (c + 1)];
+            const double vj = v[j];
+            for (int i = 0; i < mm; i++) p[i] += aj[i] * vj;
         }
+        for (int i = 0; i < mm; i++) p[i] *= t;
         double pv = 0.0;
         for (int i = 0; i < mm; i++) pv += p[i] * v[i];
         double K = 0.5 * t * pv;
@@ -50,17 +52,48 @@ void tridiag(int m, std::vector<double> &a, std::vector<double> &d, std::vector<
     if (m >= 2) e[m - 2] = a[(size_t)(m - 2) * m + (m - 1)];
 }
 
-int sturm(int m, const double *d, const double *e2, double x, double pivmin) {
-    int cnt = 0;
-    double q = d[0] - x;
-    if (std::fabs(q) < pivmin) q = -pivmin;
-    if (q < 0) cnt++;
-    for (int i = 1; i < m; i++) {
-        q = d[i] - x - e2[i - 1] / q;
-        if (std::fabs(q) < pivmin) q = -pivmin;
-        if (q < 0) cnt++;
+// All eigenvalues of the symmetric tridiagonal (d, e) by implicit QR steps with
+// the Wilkinson shift (a bulge chased down each unreduced block), ascending.
+// Deflation when |e_i| <= u (|d_i| + |d_i+1|).
+void tri_qr_values(int m, const double *d0, const double *e0, std::vector<double> &w) {
+    std::vector<double> a(d0, d0 + m), b(e0, e0 + std::max(m - 1, 0));
+    const double u = std::numeric_limits<double>::epsilon();
+    int hi = m - 1, iters = 0;
+    while (hi > 0 && iters < 60 * m) {
+        if (std::fabs(b[hi - 1]) <= u * (std::fabs(a[hi - 1]) + std::fabs(a[hi])) ||
+            b[hi - 1] == 0.0) {
+            b[hi - 1] = 0.0;
+            hi--;
+            continue;
+        }
+        int lo = hi - 1;
+        while (lo > 0 && std::fabs(b[lo - 1]) > u * (std::fabs(a[lo - 1]) + std::fabs(a[lo])))
+            lo--;
+        if (lo > 0) b[lo - 1] = 0.0;
+        // Wilkinson shift: eigenvalue of the trailing 2 x 2 nearer a[hi]
+        double dd = 0.5 * (a[hi - 1] - a[hi]), bb = b[hi - 1];
+        double den = dd + (dd >= 0.0 ? 1.0 : -1.0) * std::hypot(dd, bb);
+        double mu = a[hi] - (den != 0.0 ? bb * bb / den : 0.0);
+        double x = a[lo] - mu, z = b[lo];
+        for (int k = lo; k < hi; k++) {
+            double r = std::hypot(x, z);
+            double c = 1.0, s = 0.0;
+            if (r != 0.0) { c = x / r; s = -z / r; }
+            if (k > lo) b[k - 1] = r;
+            double ak = a[k], bk = b[k], ak1 = a[k + 1];
+            a[k] = c * c * ak - 2.0 * c * s * bk + s * s * ak1;
+            b[k] = c * s * ak + (c * c - s * s) * bk - c * s * ak1;
+            a[k + 1] = s * s * ak + 2.0 * c * s * bk + c * c * ak1;
+            if (k + 1 < hi) {
+                z = -s * b[k + 1];
+                b[k + 1] *= c;
+                x = b[k];
+            }
+        }
+        iters++;
     }
-    return cnt;
+    w = a;
+    std::sort(w.begin(), w.end());
 }
 
 // (T - lam) x = b by Gaussian elimination with partial pivoting (tridiagonal)
@@ -99,41 +132,46 @@ void tri_shift_solve(int m, const double *d, const double *e, double lam, double
 
 }  // namespace
 
-void sym_eig_select(int m, const double *A, std::vector<double> &w, const std::vector<int> &sel,
-                    std::vector<double> &Y) {
+void sym_eig_values(int m, const double *A, SymEigWork &wk, std::vector<double> &w) {
+    wk.m = m;
     w.assign(m, 0.0);
-    Y.assign((size_t)m * sel.size(), 0.0);
     if (m == 0) return;
     if (m == 1) {
         w[0] = A[0];
-        for (size_t j = 0; j < sel.size(); j++) Y[j] = 1.0;
+        wk.d.assign(1, A[0]);
+        wk.e.assign(1, 0.0);
+        wk.tmax = std::fabs(A[0]);
         return;
     }
-    std::vector<double> a(A, A + (size_t)m * m), d, e, tau;
+    wk.a.assign(A, A + (size_t)m * m);
+    std::vector<double> &a = wk.a;
     for (int j = 0; j < m; j++)          // symmetrise
         for (int i = j + 1; i < m; i++) {
             double s = 0.5 * (a[(size_t)j * m + i] + a[(size_t)i * m + j]);
             a[(size_t)j * m + i] = a[(size_t)i * m + j] = s;
         }
-    tridiag(m, a, d, e, tau);
-    std::vector<double> e2(m);
-    double tmax = 0.0, lo = 1e300, hi = -1e300;
+    tridiag(m, a, wk.d, wk.e, wk.tau);
+    const std::vector<double> &d = wk.d, &e = wk.e;
+    double tmax = 0.0;
     for (int i = 0; i < m; i++) {
         double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(e[i]) : 0.0);
-        lo = std::min(lo, d[i] - r);
-        hi = std::max(hi, d[i] + r);
         tmax = std::max(tmax, std::fabs(d[i]) + r);
-        if (i + 1 < m) e2[i] = e[i] * e[i];
     }
-    double pivmin = std::numeric_limits<double>::min() + 1e-30 * tmax * tmax;
-    for (int idx = 0; idx < m; idx++) {
-        double a0 = lo, b0 = hi;
-        for (int it = 0; it < 200 && b0 - a0 > 2e-16 * std::max(tmax, 1e-300); it++) {
-            double mid = 0.5 * (a0 + b0);
-            if (sturm(m, d.data(), e2.data(), mid, pivmin) > idx) b0 = mid; else a0 = mid;
-        }
-        w[idx] = 0.5 * (a0 + b0);
+    wk.tmax = tmax;
+    tri_qr_values(m, d.data(), e.data(), w);
+}
+
+void sym_eig_vectors(const SymEigWork &wk, const std::vector<double> &w,
+                     const std::vector<int> &sel, std::vector<double> &Y) {
+    const int m = wk.m;
+    Y.assign((size_t)m * sel.size(), 0.0);
+    if (m == 0) return;
+    if (m == 1) {
+        for (size_t j = 0; j < sel.size(); j++) Y[j] = 1.0;
+        return;
     }
+    const std::vector<double> &d = wk.d, &e = wk.e, &a = wk.a, &tau = wk.tau;
+    const double tmax = wk.tmax;
     // eigenvectors of T for the selected values, ascending order of value
     std::vector<int> order(sel.size());
     for (size_t j = 0; j < sel.size(); j++) order[j] = (int)j;
@@ -150,7 +188,7 @@ void sym_eig_select(int m, const double *A, std::vector<double> &w, const std::v
             st ^= st << 13; st ^= st >> 7; st ^= st << 17;
             x[i] = (double)(st >> 11) * (1.0 / 9007199254740992.0) - 0.5;
         }
-        for (int it = 0; it < 4; it++) {
+        for (int it = 0; it < 3; it++) {
             tri_shift_solve(m, d.data(), e.data(), lam, tiny, x);
             for (int o : done) {
                 if (std::fabs(w[sel[o]] - lam) > ortol) continue;
@@ -179,6 +217,13 @@ void sym_eig_select(int m, const double *A, std::vector<double> &w, const std::v
             for (int i = c + 2; i < m; i++) x[i] -= dot * col[i];
         }
     }
+}
+
+void sym_eig_select(int m, const double *A, std::vector<double> &w, const std::vector<int> &sel,
+                    std::vector<double> &Y) {
+    SymEigWork wk;
+    sym_eig_values(m, A, wk, w);
+    sym_eig_vectors(wk, w, sel, Y);
 }
 
 bool cholesky_upper(int b, const double *G, std::vector<double> &R, double rel_tiny) {

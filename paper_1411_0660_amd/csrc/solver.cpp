@@ -62,7 +62,8 @@ struct TaskBuilder {
 };
 }  // namespace
 
-Context::Context(int dev, size_t budget_bytes, hipStream_t s) : device(dev) {
+Context::Context(int dev, size_t budget_bytes, hipStream_t s)
+    : device(dev), plans_(std::make_shared<PlanCache>()) {
     MBL_HIP(hipSetDevice(dev));
     if (s) { stream = s; own_stream = false; }
     else { MBL_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking)); own_stream = true; }
@@ -71,10 +72,33 @@ Context::Context(int dev, size_t budget_bytes, hipStream_t s) : device(dev) {
     budget.limit = budget_bytes ? budget_bytes : (size_t)(0.92 * (double)fr);
 }
 
+Context::Context(const Context &owner, size_t budget_bytes)
+    : device(owner.device), plans_(owner.plans_), owns_plans_(false) {
+    MBL_HIP(hipSetDevice(device));
+    MBL_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+    own_stream = true;
+    budget.limit = budget_bytes;
+}
+
+void Context::trim() {
+    MBL_HIP(hipStreamSynchronize(stream));
+    for (DevBuf *b : {&f32_.arena, &f32_.ipiv, &f32_.prow, &f32_.npert, &f64_.arena, &f64_.ipiv,
+                      &f64_.prow, &f64_.npert, &d_vec, &d_yv, &d_upart, &d_xnew, &d_r, &d_d,
+                      &d_part, &d_V, &d_V2, &d_W, &d_small, &d_tnpart, &d_gV, &d_gZ, &d_gpart,
+                      &d_gcoef, &d_psi, &d_psi2, &d_hpsi, &d_e, &d_cpart, &d_obs, &d_r_out,
+                      &d_se})
+        b->reset();
+    f32_.valid = false;
+    f64_.valid = false;
+}
+
 Context::~Context() {
     (void)hipStreamSynchronize(stream);
     for (auto &e : prof.pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
-    plans_.clear();
+    if (owns_plans_) {
+        std::lock_guard<std::recursive_mutex> lk(plans_->mu);
+        plans_->plans.clear();
+    }
     if (own_stream) (void)hipStreamDestroy(stream);
 }
 
@@ -109,8 +133,10 @@ void Context::prof_collect() {
 }
 
 Plan &Context::plan(int L) {
-    auto it = plans_.find(L);
-    if (it != plans_.end()) return *it->second;
+    std::lock_guard<std::recursive_mutex> lk(plans_->mu);
+    auto it = plans_->plans.find(L);
+    if (it != plans_->plans.end()) return *it->second;
+    MBL_REQUIRE(owns_plans_, MBL_EINVAL, "plan for this L not prepared by the owning context");
     std::unique_ptr<Plan> p(new Plan);
     p->L = L;
     p->dim = binom(L, L / 2);
@@ -133,12 +159,14 @@ Plan &Context::plan(int L) {
     d2h(p->h_col.data(), p->col.ptr<int32_t>(), p->nnz, stream);
     MBL_HIP(hipStreamSynchronize(stream));
     Plan &ref = *p;
-    plans_[L] = std::move(p);
+    plans_->plans[L] = std::move(p);
     return ref;
 }
 
 void Context::ensure_symbolic(Plan &p) {
+    std::lock_guard<std::recursive_mutex> lk(plans_->mu);
     if (p.have_symbolic) return;
+    MBL_REQUIRE(owns_plans_, MBL_EINVAL, "symbolic analysis not prepared by the owning context");
     Pattern A;
     A.n = p.dim;
     A.rowptr = p.h_rowptr;
@@ -451,6 +479,7 @@ void Context::ensure_symbolic(Plan &p) {
     h2d(p.d_epos.ptr<int32_t>(), epos.data(), epos.size(), s);
     h2d(p.d_esrc.ptr<int32_t>(), esrc.data(), esrc.size(), s);
     MBL_HIP(hipStreamSynchronize(s));
+    MBL_HIP(hipStreamSynchronize(s));   // uploads complete before other streams read them
     p.have_symbolic = true;
 }
 
@@ -855,12 +884,84 @@ Context::KSOut Context::krylov_schur(int64_t n, int b, int ncv, int nkeep, int n
         return ok;
     };
 
+    // Blocks of more than one vector expand without host round trips: the
+    // Cholesky factors are computed on the device, the projection coefficients
+    // and R factors are copied to page-locked memory asynchronously, and the
+    // projected matrix is assembled once per restart cycle.
+    const bool async = (b > 1);
+    struct Stage { int cur; size_t h1, h2, r1, r2; };
+    std::vector<Stage> stages;
+    const size_t stage_max = (size_t)(cols / b + 1) * (2 * (size_t)cols * b + 2 * (size_t)b * b);
+    double *smG = sm + (size_t)cols * std::max(cols, b), *smR = smG + b * b, *smRi = smR + b * b;
+    int *dflag = reinterpret_cast<int *>(smRi + b * b);
+    if (async) h_stage.ensure(sizeof(double) * stage_max + sizeof(int) * 2 * (cols / b + 1));
+    double *hp = h_stage.ptr<double>();
+    int *hflag = async ? reinterpret_cast<int *>(hp + stage_max) : nullptr;
+    size_t hoff = 0;
+    auto stage_block = [&](int c0, double *blk, double *dst) {
+        Stage stg{c0, 0, 0, 0, 0};
+        const int k = (int)stages.size();
+        for (int pass = 0; pass < 2; pass++) {             // CGS2 against V[:, 0:c0]
+            launch_gemm_tn(n, c0, b, V, n, blk, n, sm, tnp, nparts, s);
+            launch_gemm_nn(n, c0, b, -1.0, V, n, sm, c0, 1.0, blk, n, s);
+            (pass ? stg.h2 : stg.h1) = hoff;
+            MBL_HIP(hipMemcpyAsync(hp + hoff, sm, sizeof(double) * c0 * b,
+                                   hipMemcpyDeviceToHost, s));
+            hoff += (size_t)c0 * b;
+        }
+        double *from = blk, *to = dst;                      // Cholesky QR, twice
+        for (int pass = 0; pass < 2; pass++) {
+            launch_gemm_tn(n, b, b, from, n, from, n, smG, tnp, nparts, s);
+            launch_small_chol(b, smG, smR, smRi, dflag + pass, 1e-24, s);
+            (pass ? stg.r2 : stg.r1) = hoff;
+            MBL_HIP(hipMemcpyAsync(hp + hoff, smR, sizeof(double) * b * b, hipMemcpyDeviceToHost,
+                                   s));
+            hoff += (size_t)b * b;
+            launch_gemm_nn(n, b, b, 1.0, from, n, smRi, b, 0.0, to, n, s);
+            std::swap(from, to);
+        }
+        launch_copy(n * b, from, dst, s);                   // from == blk after two passes
+        MBL_HIP(hipMemcpyAsync(hflag + 2 * k, dflag, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+        stages.push_back(stg);
+    };
+    auto assemble_stages = [&]() {
+        MBL_HIP(hipStreamSynchronize(s));
+        for (size_t k = 0; k < stages.size(); k++) {
+            const Stage &stg = stages[k];
+            if (hflag[2 * k] || hflag[2 * k + 1]) throw Error(MBL_ENUMERIC, "block Krylov breakdown");
+            const int c0 = stg.cur;
+            for (int j = 0; j < b; j++)
+                for (int i = 0; i < c0; i++) {
+                    double v = hp[stg.h1 + (size_t)j * c0 + i] + hp[stg.h2 + (size_t)j * c0 + i];
+                    Tat(i, c0 - b + j) = v;
+                    Tat(c0 - b + j, i) = v;
+                }
+            const double *R1 = hp + stg.r1, *R2 = hp + stg.r2;   // R = R2 R1
+            for (int j = 0; j < b; j++)
+                for (int i = 0; i < b; i++) {
+                    double acc = 0.0;
+                    for (int q = 0; q < b; q++) acc += R2[(size_t)q * b + i] * R1[(size_t)j * b + q];
+                    Tat(c0 + i, c0 - b + j) = acc;
+                    Tat(c0 - b + j, c0 + i) = acc;
+                }
+        }
+        stages.clear();
+        hoff = 0;
+    };
+
     KSOut res;
     std::vector<double> R, hsum;
     launch_fill_start(n, b, seed, W, s);
     if (!cholqr(W, V, R)) throw Error(MBL_ENUMERIC, "start block is rank deficient");
     int cur = b;
     for (int restart = 0;; restart++) {
+        while (async && cur < cols) {
+            op(V + (int64_t)(cur - b) * n, W, b);
+            res.napply += b;
+            stage_block(cur, W, V + (int64_t)cur * n);
+            cur += b;
+        }
+        if (async) assemble_stages();
         while (cur < cols) {
             // expand the block [cur - b, cur) into [cur, cur + b)
             op(V + (int64_t)(cur - b) * n, W, b);
@@ -901,8 +1002,9 @@ Context::KSOut Context::krylov_schur(int64_t n, int b, int ncv, int nkeep, int n
             for (int i = 0; i < m; i++) Tm[(size_t)j * m + i] = Tat(i, j);
             for (int i = 0; i < b; i++) C[(size_t)j * b + i] = Tat(m + i, j);
         }
-        std::vector<double> wall, w, Y, dummy;
-        sym_eig_select(m, Tm.data(), wall, std::vector<int>(), dummy);
+        std::vector<double> wall, Y;
+        SymEigWork ew;
+        sym_eig_values(m, Tm.data(), ew, wall);
         res.tmin = wall.front();
         res.tmax = wall.back();
         std::vector<int> order(m);
@@ -918,7 +1020,8 @@ Context::KSOut Context::krylov_schur(int64_t n, int b, int ncv, int nkeep, int n
             }
         }
         std::vector<int> sel(order.begin(), order.begin() + nkeep);
-        sym_eig_select(m, Tm.data(), w, sel, Y);
+        sym_eig_vectors(ew, wall, sel, Y);
+        const std::vector<double> &w = wall;
         res.theta.assign(nkeep, 0.0);
         res.rho.assign(nkeep, 0.0);
         std::vector<double> CY((size_t)b * nkeep, 0.0);
@@ -968,7 +1071,7 @@ namespace mbl {
 
 void Context::extremal(Plan &p, double &emin, double &emax, int &napply) {
     int64_t n = p.dim;
-    int b = n >= 2000 ? 4 : 1;
+    int b = n >= 128 ? 4 : 1;
     int ncv = 64, nkeep = 16, nwant = 2;
     if (ncv >= n) { b = 1; ncv = (int)n; nkeep = std::max(1, (int)n - 1); nwant = std::min(2, nkeep); }
     d_psi.ensure(sizeof(double) * n * nwant, &budget);

@@ -76,9 +76,19 @@ struct SolveStats {
     int gmres_inner = 0;               // GMRES iterations of the latest shifted solve
 };
 
+// Per-L plans (basis, CSR pattern, symbolic analysis, task lists): read-only
+// once built, shared by the contexts of one device (the serving slots).  Only
+// the owning context builds plans, so their memory is charged to its budget.
+struct PlanCache {
+    std::recursive_mutex mu;
+    std::map<int, std::unique_ptr<Plan>> plans;
+};
+
 class Context {
   public:
     Context(int device, size_t budget, hipStream_t stream);
+    // a context on the same device that reads the plans of `owner`
+    Context(const Context &owner, size_t budget);
     ~Context();
 
     int device;
@@ -89,6 +99,8 @@ class Context {
 
     Plan &plan(int L);                 // basis + CSR on the device (cached)
     void ensure_symbolic(Plan &p);     // ordering + front tables (cached)
+    // free the per-request work buffers (factors, solve vectors, Krylov bases)
+    void trim();
 
     // realization state: fields + diagonal of H on the device
     void set_realization(Plan &p, double J, const double *fields_host, double h, uint64_t seed,
@@ -138,11 +150,13 @@ class Context {
     double hnorm_ = 1.0;
 
   private:
-    std::map<int, std::unique_ptr<Plan>> plans_;
+    std::shared_ptr<PlanCache> plans_;
+    bool owns_plans_ = true;
     Factor<float> f32_;
     Factor<double> f64_;
     DevBuf d_vec, d_yv, d_upart, d_xnew, d_r, d_d, d_part, d_V, d_V2, d_W, d_small, d_tnpart;
     DevBuf d_gV, d_gZ, d_gpart, d_gcoef;   // GMRES refinement: bases, partials, coefficients
+    PinnedBuf h_stage;                     // Krylov coefficients copied back asynchronously
     template <class T> void factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel,
                                      SolveStats &st);
     template <class T> void lu_apply(Plan &p, Factor<T> &f, int nrhs, const double *b,

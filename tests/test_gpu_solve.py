@@ -77,12 +77,31 @@ def test_solve_fp32_refined_vs_oracle(ctx, L, h, seed, eps, nev):
     compare(g, o, o["hnorm"], nev)
 
 
+def nearest_set_ok(g, allw, sigma, nev, hn):
+    """Every returned level is an eigenvalue, and the set is a set of nev levels
+    nearest sigma; where the nev-th and (nev+1)-th distances tie within
+    1e-10 ||H||, either choice is one."""
+    Eg = np.sort(g["evals"])
+    assert np.all([np.abs(allw - e).min() <= EIG_TOL * hn for e in Eg])
+    d = np.sort(np.abs(allw - sigma))
+    assert np.abs(Eg - sigma).max() <= d[nev - 1] + EIG_TOL * hn
+    return True
+
+
 @pytest.mark.parametrize("L,nev", [(2, 1), (2, 2), (4, 6), (4, 3), (6, 20)])
 def test_tiny_sectors_full_space(ctx, L, nev):
     say("tiny", L, nev)
-    o = oracle.solve(L, 2.0, 3, 0.5, nev)
+    o = oracle.solve(L, 2.0, 3, 0.5, nev, full_spectrum=True)
     g = ctx.mbl_solve(L, 2.0, 3, 0.5, nev)
-    compare(g, o, o["hnorm"], nev)
+    hn = o["hnorm"]
+    d = np.sort(np.abs(o["spectrum"] - o["sigma"]))
+    if nev < d.size and d[nev] - d[nev - 1] <= EIG_TOL * hn:
+        # the window boundary is a tie (L = 2 at eps = 0.5: the two levels are
+        # symmetric about -J/2, and sigma is their midpoint)
+        assert nearest_set_ok(g, o["spectrum"], o["sigma"], nev, hn)
+        assert g["max_resid"] <= RES_TOL
+    else:
+        compare(g, o, hn, nev)
 
 
 def test_J0_diagonal_limit(ctx):
