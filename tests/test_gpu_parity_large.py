@@ -77,19 +77,31 @@ def test_golden_parity(ctx, path):
         rmask = np.minimum(gaps[:-1], gaps[1:]) >= GAP_MIN * hn
         d = np.abs(g["r"] - np.array(t["r"]))[rmask]
         assert d.max(initial=0.0) <= OBS_TOL, (t["eps"], "r", d.max())
-        # KL(p_n | p_n+1) = sum p ln(p/q) is gated where it is well conditioned:
-        # a componentwise vector error delta moves it by about
-        # sum_i p_i 2 delta / |phi_i| (first order in delta / phi_i); with
-        # delta = 1e-13 that estimate must stay below 1e-8
+        # KL(p_n | p_n+1) = sum p ln(p/q) is ill-conditioned where components of
+        # the neighbour are tiny (strongly localized states).  Its first-order
+        # error for a componentwise vector error delta (Davis-Kahan: residual /
+        # gap to the other levels) is est = sum_i p_i min(1, 2 delta / |phi_i|)
+        # + sum_i |ln(p_i / q_i)| min(p_i, 2 delta |psi_i|); the gate is
+        # 1e-7 + 10 est, on pairs separated from their neighbours
         Z = g["evecs"]
+        Eg = g["evals"]
         kmask = sep[:-1] & sep[1:]
+        ktol = np.full(nev - 1, 1e-7)
         for k in range(nev - 1):
-            p_, phi = Z[:, k] ** 2, np.abs(Z[:, k + 1])
-            nz = phi > 0
-            cond = np.sum(p_[nz] * np.minimum(1.0, 2e-13 / phi[nz])) + p_[~nz].sum()
-            kmask[k] &= cond <= 1e-8
-        d = np.abs(g["kl"] - np.array(t["kl"]))[kmask]
-        assert d.max(initial=0.0) <= 1e-7, (t["eps"], "kl", d.max())
+            gaps_k = [abs(Eg[k + 1] - Eg[k])]
+            if k > 0:
+                gaps_k.append(abs(Eg[k] - Eg[k - 1]))
+            if k + 2 < nev:
+                gaps_k.append(abs(Eg[k + 2] - Eg[k + 1]))
+            delta = max(g["resid"][k], g["resid"][k + 1]) * hn / min(gaps_k) + 1e-14
+            psi, phi = np.abs(Z[:, k]), np.abs(Z[:, k + 1])
+            p_, q_ = psi ** 2, phi ** 2
+            nz = (phi > 0) & (psi > 0)
+            est = np.sum(p_[phi > 0] * np.minimum(1.0, 2 * delta / phi[phi > 0]))
+            est += np.sum(np.abs(np.log(p_[nz] / q_[nz])) * np.minimum(p_[nz], 2 * delta * psi[nz]))
+            ktol[k] += 10.0 * est
+        d = np.abs(g["kl"] - np.array(t["kl"]))
+        assert np.all(d[kmask] <= ktol[kmask]), (t["eps"], "kl", (d - ktol)[kmask].max())
 
 
 # (L, h, seed, eps, vectors whose S_E the oracle recomputes)
