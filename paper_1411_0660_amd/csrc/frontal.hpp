@@ -15,6 +15,7 @@ constexpr int FNB = 64;
 // Diagonal block of the triangular solves (a multiple of FNB); these blocks of
 // L11 and U11 are stored inverted after the factorisation.
 constexpr int SB = 4 * FNB;
+constexpr int SSB = 2 * SB;         // solve block: two factorization blocks merged
 
 struct FrontDesc {
     int64_t off;      // first element of the dense m x m front (column-major) in the arena
@@ -73,8 +74,16 @@ template <class T>
 void launch_trsm_l(T *arena, const FrontDesc *fd, TaskList tl, int t, hipStream_t s);
 // inner (panel t, K = 64, inside its outer block) or outer-block (block t,
 // K = 256, everything right of and below it) trailing update
+// kind 0: inner update after panel t; 1: outer update of block t; 2 and 3: the
+// two products that merge the factorization blocks 2t and 2t + 1 into solve
+// block t (rows below, then rows above; see k_merge_tri)
 template <class T>
-void launch_schur(T *arena, const FrontDesc *fd, TaskList tl, int t, bool big, hipStream_t s);
+void launch_schur(T *arena, const FrontDesc *fd, TaskList tl, int t, int kind, hipStream_t s);
+// in-place triangular products that complete the inverse of each merged
+// solve block (work items: 16-column chunks, see k_merge_tri)
+template <class T>
+void launch_merge_tri(T *arena, const FrontDesc *fd, TaskList tl, hipStream_t s);
+int merge_tri_items(int p);
 
 
 // tile sizes used by the work-item counts of the task lists

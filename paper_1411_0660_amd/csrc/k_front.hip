@@ -431,7 +431,12 @@ template <class T> struct SchurCfg {
 //          columns up to the end of the outer block, the rest the remaining
 //          rows of the outer block and every column right of it;
 // BIG = 1: update of outer block t, K = its (up to SB) columns, everything
-//          right of and below it (including the contribution block).
+//          right of and below it (including the contribution block);
+// BIG = 2, 3: merge of the inverted, folded blocks b1 = [a, a + SB) and
+//          b2 = [a + SB, e) (a = t SSB) into one solve block: with the folded
+//          panels L~ = L Linv and U~ = U Uinv, the rows below e need
+//          L~[., b1] -= L~[., b2] L~[b2, b1]   (BIG = 2: K = b2),
+//          the rows above a need U~[., b2] -= U~[., b1] U~[b1, b2]  (BIG = 3: K = b1).
 // The next K chunk is fetched from HBM into registers while the current one
 // feeds the matrix cores from LDS.
 template <class T, int BIG>
@@ -452,8 +457,12 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
         int n0 = (K1 > k1) ? ((m - k1 + ST - 1) / ST) * ((K1 - k1 + ST - 1) / ST) : 0;
         if (tile < n0) { rlo = k1; rhi = m; clo = k1; chi = K1; }
         else { tile -= n0; rlo = k1; rhi = K1; clo = K1; chi = m; }
-    } else {
+    } else if (BIG == 1) {
         kc0 = t * SB; kd = min(SB, d.p - kc0); rlo = kc0 + kd; rhi = m; clo = rlo; chi = m;
+    } else {
+        int a = t * SSB, e = min(d.p, a + SSB);
+        if (BIG == 2) { kc0 = a + SB; kd = e - kc0; rlo = e; rhi = m; clo = a; chi = a + SB; }
+        else { kc0 = a; kd = SB; rlo = 0; rhi = a; clo = a + SB; chi = e; }
     }
     int ntr = (rhi - rlo + ST - 1) / ST;
     int ti = (int)(tile % ntr), tj = (int)(tile / ntr);
@@ -530,6 +539,76 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
             int r = r0 + row, c = c0 + half * 64 + col;
             if (r < rhi && c < chi) F[r + (int64_t)c * m] -= Cs[col * (ST + 1) + row];
         }
+    }
+}
+
+// Completes the inverse of every merged solve block [a, e) (a = t SSB) once
+// the two products of k_schur<., 2 / 3> have run:
+//   lower: Linv = [[I1, 0], [X, I2]],  X = -I2 L~[b2, b1]   (I2 unit lower)
+//   upper: Uinv = [[J1, Y], [0, J2]],  Y = -J1 U~[b1, b2]   (J1 upper)
+// computed in place over the folded blocks L~[b2, b1] and U~[b1, b2].  Work
+// item: 16 columns of one side of one pair (per pair the lower-side chunks
+// first, then the upper-side ones); the columns are staged in LDS, then
+// thread i forms row i from row i of the triangular factor.
+constexpr int MT_COLS = 16;
+
+template <class T>
+__global__ __launch_bounds__(256) void k_merge_tri(T *arena, const FrontDesc *__restrict__ fd,
+                                                  TaskList tl) {
+    __shared__ double vs[MT_COLS][SB + 1];
+    const int2 tk = tl.items[blockIdx.x];
+    const FrontDesc d = fd[tk.x];
+    const int m = d.m;
+    int w = tk.y, a = 0, n2 = 0;
+    for (a = 0; a + SB < d.p; a += SSB) {            // locate the pair and side
+        n2 = min(d.p, a + SSB) - a - SB;
+        int nl = SB / MT_COLS, nu = (n2 + MT_COLS - 1) / MT_COLS;
+        if (w < nl + nu) break;
+        w -= nl + nu;
+    }
+    if (a + SB >= d.p) return;                       // not reached for valid items
+    const int b2 = a + SB;
+    T *F = arena + d.off;
+    const int i = threadIdx.x;
+    if (w < SB / MT_COLS) {
+        // lower side: X[:, j] = -(v + sum_{k<i} I2[i][k] v[k]), v = L~[b2 + ., a + j]
+        const int j0 = w * MT_COLS;
+        for (int e = threadIdx.x; e < MT_COLS * SB; e += 256) {
+            int c = e / SB, r = e % SB;
+            vs[c][r] = r < n2 ? (double)F[(b2 + r) + (int64_t)(a + j0 + c) * m] : 0.0;
+        }
+        __syncthreads();
+        if (i < n2) {
+            double acc[MT_COLS];
+#pragma unroll
+            for (int c = 0; c < MT_COLS; c++) acc[c] = vs[c][i];
+            for (int k = 0; k < i; k++) {
+                double coef = (double)F[(b2 + i) + (int64_t)(b2 + k) * m];
+#pragma unroll
+                for (int c = 0; c < MT_COLS; c++) acc[c] += coef * vs[c][k];
+            }
+#pragma unroll
+            for (int c = 0; c < MT_COLS; c++) F[(b2 + i) + (int64_t)(a + j0 + c) * m] = (T)(-acc[c]);
+        }
+    } else {
+        // upper side: Y[:, j] = -sum_{k>=i} J1[i][k] v[k], v = U~[a + ., b2 + j]
+        const int j0 = (w - SB / MT_COLS) * MT_COLS, nc = min(MT_COLS, n2 - j0);
+        for (int e = threadIdx.x; e < MT_COLS * SB; e += 256) {
+            int c = e / SB, r = e % SB;
+            vs[c][r] = c < nc ? (double)F[(a + r) + (int64_t)(b2 + j0 + c) * m] : 0.0;
+        }
+        __syncthreads();
+        double acc[MT_COLS];
+#pragma unroll
+        for (int c = 0; c < MT_COLS; c++) acc[c] = 0.0;
+        for (int k = i; k < SB; k++) {
+            double coef = (double)F[(a + i) + (int64_t)(a + k) * m];
+#pragma unroll
+            for (int c = 0; c < MT_COLS; c++) acc[c] += coef * vs[c][k];
+        }
+#pragma unroll
+        for (int c = 0; c < MT_COLS; c++)
+            if (c < nc) F[(a + i) + (int64_t)(b2 + j0 + c) * m] = (T)(-acc[c]);
     }
 }
 
@@ -690,11 +769,32 @@ void launch_trsm_l(T *arena, const FrontDesc *fd, TaskList tl, int t, hipStream_
 }
 
 template <class T>
-void launch_schur(T *arena, const FrontDesc *fd, TaskList tl, int t, bool big, hipStream_t s) {
+void launch_schur(T *arena, const FrontDesc *fd, TaskList tl, int t, int kind, hipStream_t s) {
     if (tl.total == 0) return;
-    if (big) k_schur<T, 1><<<dim3((unsigned)tl.total), dim3(256), 0, s>>>(arena, fd, tl, t);
-    else k_schur<T, 0><<<dim3((unsigned)tl.total), dim3(256), 0, s>>>(arena, fd, tl, t);
+    const dim3 g((unsigned)tl.total), b(256);
+    switch (kind) {
+        case 0: k_schur<T, 0><<<g, b, 0, s>>>(arena, fd, tl, t); break;
+        case 1: k_schur<T, 1><<<g, b, 0, s>>>(arena, fd, tl, t); break;
+        case 2: k_schur<T, 2><<<g, b, 0, s>>>(arena, fd, tl, t); break;
+        default: k_schur<T, 3><<<g, b, 0, s>>>(arena, fd, tl, t); break;
+    }
     MBL_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_merge_tri(T *arena, const FrontDesc *fd, TaskList tl, hipStream_t s) {
+    if (tl.total == 0) return;
+    k_merge_tri<T><<<dim3((unsigned)tl.total), dim3(256), 0, s>>>(arena, fd, tl);
+    MBL_CHECK_LAUNCH();
+}
+
+int merge_tri_items(int p) {
+    int n = 0;
+    for (int a = 0; a + SB < p; a += SSB) {
+        int n2 = std::min(p, a + SSB) - a - SB;
+        n += SB / MT_COLS + (n2 + MT_COLS - 1) / MT_COLS;
+    }
+    return n;
 }
 
 
@@ -713,7 +813,8 @@ void launch_schur(T *arena, const FrontDesc *fd, TaskList tl, int t, bool big, h
     template void launch_xform<T>(T *, const FrontDesc *, TaskList, hipStream_t);               \
     template void launch_invert_diag<T>(T *, const FrontDesc *, const int32_t *, int32_t *,      \
                                         TaskList, int, int, hipStream_t);                        \
-    template void launch_schur<T>(T *, const FrontDesc *, TaskList, int, bool, hipStream_t);
+    template void launch_schur<T>(T *, const FrontDesc *, TaskList, int, int, hipStream_t);     \
+    template void launch_merge_tri<T>(T *, const FrontDesc *, TaskList, hipStream_t);
 
 MBL_INST_FRONT(float)
 MBL_INST_FRONT(double)

@@ -4,10 +4,11 @@
 //
 // The factor streams from HBM once per pass, shared by a block of up to 16
 // right-hand sides (vectors stay FP64 whatever the factor precision).  The
-// SB x SB diagonal blocks of L11 and U11 are stored inverted and folded into
-// the panels beside them (L~ = L Linv_tt below, U~ = U Uinv_tt above; see
-// k_front.hip), so one launch per solve block and tree level does both the
-// diagonal product and the update of the other rows, from the same input:
+// SSB x SSB diagonal blocks of L11 and U11 (two factorization blocks) are
+// stored inverted and folded into the panels beside them (L~ = L Linv_tt
+// below, U~ = U Uinv_tt above; see k_front.hip), so one launch per solve
+// block and tree level does both the diagonal product and the update of the
+// other rows, from the same input:
 //   forward (leaves to root), front f:
 //     V = P([b(pivots); 0] + children's updates)        (row-parallel gather)
 //     block t:  Y_t = Linv_tt V_t  and  V[rows below] -= L~[., t] V_t
@@ -16,7 +17,7 @@
 //     V[p:m] = x(contribution rows); Y -= U12 V[p:m]   (64 x 256 tiles, fixed-order sum)
 //     block t from the last:  V_t = Uinv_tt Y_t  and  Y[rows above] -= U~[., t] Y_t
 //     afterwards V[0:p] = x of the pivots.
-// Work items are 64 rows x one SB block: the 8 or 16 waves of a workgroup
+// Work items are 64 rows x one SSB block: the 8 or 16 waves of a workgroup
 // take an equal share of the columns each and are summed through LDS, which
 // keeps the dependent load chain of a lane short.
 #include <type_traits>
@@ -31,12 +32,12 @@ constexpr int MAXRHS = 16;
 constexpr int RW = 64;          // rows per update work item (one per lane)
 
 // column groups (waves) per 64-row work item: 16 for up to 8 right-hand sides,
-// 8 for 16 (LDS: the SB x NR source block plus CG x 64 x NR partial sums)
+// 8 for 16 (LDS: the SSB x NR source block plus CG x 64 x NR partial sums)
 template <int NR> struct StepCfg {
     static constexpr int CG = NR <= 8 ? 16 : 8;
     static constexpr int THREADS = 64 * CG;
-    static constexpr int CW = SB / CG;          // columns per wave
-    static constexpr int UNR = NR <= 8 ? 8 : 4; // column unroll (register budget)
+    static constexpr int CW = SSB / CG;         // columns per wave (solve steps)
+    static constexpr int CWU = SB / CG;         // columns per wave (U12 tiles)
 };
 
 // row-parallel gather of the forward right-hand side of every front
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(256) void k_fwd_gather(const FrontDesc *__restrict_
     for (int r = 0; r < NR; r++) o[(int64_t)r * d.m] = val[r];
 }
 
-// One 64-row work item of solve block t: out rows from M[rows, SB block] and
+// One 64-row work item of solve block t: out rows from M[rows, SSB block] and
 // the block's source values src (LDS):
 //   mode 0: out -= M src                            (panel update, in place)
 //   mode 1: out  = src_i + sum_{j<i} M_ij src_j     (unit-lower inverse block)
@@ -91,12 +92,13 @@ __global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_solve_step(
     const T *__restrict__ arena, const FrontDesc *__restrict__ fd, TaskList tl, int t,
     double *vec, double *yv) {
     constexpr int CG = StepCfg<NR>::CG, CW = StepCfg<NR>::CW;
-    __shared__ double src[SB][NR];
-    __shared__ double red[CG][RW][NR];
+    constexpr int HG = CG / 2;                       // partial sums: two phases of CG / 2
+    __shared__ double src[SSB][NR];
+    __shared__ double red[HG][RW][NR];
     const int2 tk = tl.items[blockIdx.x];
     const FrontDesc d = fd[tk.x];
     const int w = tk.y;
-    const int m = d.m, p = d.p, t0 = t * SB, st = min(SB, p - t0), tend = t0 + st;
+    const int m = d.m, p = d.p, t0 = t * SSB, st = min(SSB, p - t0), tend = t0 + st;
     const int nA = (st + RW - 1) / RW;
     double *V = vec + d.voff;          // ld m
     double *Y = yv + d.yoff;           // ld p
@@ -146,8 +148,8 @@ __global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_solve_step(
     {
         const double *S = FWD ? V + t0 : Y + t0;
         const int64_t lds = FWD ? m : p;
-        for (int e = threadIdx.x; e < SB * NR; e += blockDim.x) {
-            int j = e % SB, r = e / SB;
+        for (int e = threadIdx.x; e < SSB * NR; e += blockDim.x) {
+            int j = e % SSB, r = e / SSB;
             src[j][r] = j < st ? S[j + (int64_t)r * lds] : 0.0;
         }
     }
@@ -161,15 +163,23 @@ __global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_solve_step(
 #pragma unroll
         for (int r = 0; r < NR; r++) acc[r] += x * src[wv * CW + q][r];
     }
+    // fixed-order sum over the waves: g + HG into g, then g = 0 .. HG-1
+    if (wv >= HG) {
 #pragma unroll
-    for (int r = 0; r < NR; r++) red[wv][lane][r] = acc[r];
+        for (int r = 0; r < NR; r++) red[wv - HG][lane][r] = acc[r];
+    }
+    __syncthreads();
+    if (wv < HG) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) red[wv][lane][r] += acc[r];
+    }
     __syncthreads();
     if (wv == 0 && rowok) {
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             double sum = red[0][lane][r];
 #pragma unroll
-            for (int g = 1; g < CG; g++) sum += red[g][lane][r];
+            for (int g = 1; g < HG; g++) sum += red[g][lane][r];
             double *o = out + lane + (int64_t)r * ldo;
             if (mode == 0) *o = prev[r] - sum;
             else if (mode == 1) *o = src[i][r] + sum;
@@ -199,9 +209,9 @@ template <class T, int NR>
 __global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_bwd_u12(
     const T *__restrict__ arena, const FrontDesc *__restrict__ fd, TaskList tl,
     const double *__restrict__ vec, double *__restrict__ part) {
-    constexpr int CG = StepCfg<NR>::CG, CW = StepCfg<NR>::CW;
+    constexpr int CG = StepCfg<NR>::CG, CW = StepCfg<NR>::CWU, HG = CG / 2;
     __shared__ double src[SB][NR];
-    __shared__ double red[CG][RW][NR];
+    __shared__ double red[HG][RW][NR];
     const int2 tk = tl.items[blockIdx.x];
     const FrontDesc d = fd[tk.x];
     const int w = tk.y;
@@ -233,15 +243,22 @@ __global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_bwd_u12(
 #pragma unroll
         for (int r = 0; r < NR; r++) acc[r] += x * src[wv * CW + q][r];
     }
+    if (wv >= HG) {
 #pragma unroll
-    for (int r = 0; r < NR; r++) red[wv][lane][r] = acc[r];
+        for (int r = 0; r < NR; r++) red[wv - HG][lane][r] = acc[r];
+    }
+    __syncthreads();
+    if (wv < HG) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) red[wv][lane][r] += acc[r];
+    }
     __syncthreads();
     if (wv == 0 && row < p)
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             double sum = red[0][lane][r];
 #pragma unroll
-            for (int g = 1; g < CG; g++) sum += red[g][lane][r];
+            for (int g = 1; g < HG; g++) sum += red[g][lane][r];
             part[d.poff + ((int64_t)cc * MAXRHS + r) * p + row] = sum;
         }
 }

@@ -320,6 +320,29 @@ void Context::ensure_symbolic(Plan &p) {
         std::vector<int64_t> xi;
         for (int f : all) xi.push_back(xform_items(p.h_fd[f].m, p.h_fd[f].p));
         tb.add(p.xform, all, xi);
+        // merging factorization blocks 2t, 2t + 1 into solve block t
+        int maxpairs = 0;
+        for (int f : all) maxpairs = std::max<int>(maxpairs, (int)cdiv64(p.h_fd[f].p, SSB));
+        p.fold_lo.assign(maxpairs, TaskList{});
+        p.fold_up.assign(maxpairs, TaskList{});
+        for (int tp = 0; tp < maxpairs; tp++) {
+            std::vector<int32_t> flo, fup;
+            std::vector<int64_t> nlo, nup;
+            for (int f : all) {
+                const FrontDesc &d = p.h_fd[f];
+                int a = tp * SSB, e = std::min(d.p, a + SSB);
+                if (e <= a + SB) continue;           // no second block to merge
+                if (d.m > e) { flo.push_back(f); nlo.push_back(cdiv64(d.m - e, SCHUR_TILE) * cdiv64(SB, SCHUR_TILE)); }
+                if (a > 0) { fup.push_back(f); nup.push_back(cdiv64(a, SCHUR_TILE) * cdiv64(e - a - SB, SCHUR_TILE)); }
+            }
+            tb.add(p.fold_lo[tp], flo, nlo);
+            tb.add(p.fold_up[tp], fup, nup);
+        }
+        std::vector<int32_t> mf;
+        std::vector<int64_t> mi;
+        for (int f : all)
+            if (p.h_fd[f].p > SB) { mf.push_back(f); mi.push_back(merge_tri_items(p.h_fd[f].p)); }
+        tb.add(p.merge, mf, mi);
     }
     for (int l = 0; l < t.n_levels; l++) {
         LevelTasks &lv = p.levels[l];
@@ -416,16 +439,17 @@ void Context::ensure_symbolic(Plan &p) {
             for (int f : fl) gi.push_back(cdiv64(p.h_fd[f].m, 256));
             tb.add(lv.fgather, fl, gi);
         }
-        lv.fstep.assign(maxsb, TaskList{});
-        lv.bstep.assign(maxsb, TaskList{});
-        for (int st = 0; st < maxsb; st++) {
+        const int maxssb = (int)cdiv64((int64_t)maxsb * SB, SSB);   // solve blocks of SSB columns
+        lv.fstep.assign(maxssb, TaskList{});
+        lv.bstep.assign(maxssb, TaskList{});
+        for (int st = 0; st < maxssb; st++) {
             std::vector<int32_t> act;
             std::vector<int64_t> fi, bi;
             for (int f : fl) {
                 const FrontDesc &d = p.h_fd[f];
-                int t0 = st * SB;
+                int t0 = st * SSB;
                 if (d.p <= t0) continue;
-                int tend = std::min(d.p, t0 + SB);
+                int tend = std::min(d.p, t0 + SSB);
                 int64_t na = cdiv64(tend - t0, 64);
                 act.push_back(f);
                 fi.push_back(na + cdiv64(d.m - tend, 64));
@@ -435,7 +459,7 @@ void Context::ensure_symbolic(Plan &p) {
             tb.add(lv.bstep[st], act, bi);
             for (int f : act) {
                 const FrontDesc &d = p.h_fd[f];
-                double t0 = st * SB, sw = std::min(SB, d.p - st * SB), tend = t0 + sw;
+                double t0 = st * SSB, sw = std::min(SSB, d.p - st * SSB), tend = t0 + sw;
                 lv.fstep[st].elems += 0.5 * sw * (sw + 1) + (d.m - tend) * sw;
                 lv.fstep[st].rows += 2.0 * sw + (d.m - tend);
                 lv.bstep[st].elems += 0.5 * sw * (sw + 1) + t0 * sw;
@@ -544,7 +568,7 @@ void Context::factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel, S
                             S.panel, (int)t, thresh, s);
             launch_trsm_u<T>(A, fd, f.ipiv.template ptr<int32_t>(), S.trsm_u, (int)t, s);
             launch_trsm_l<T>(A, fd, S.rows_below, (int)t, s);
-            launch_schur<T>(A, fd, S.schur, (int)t, false, s);
+            launch_schur<T>(A, fd, S.schur, (int)t, 0, s);
             // end of an outer block (for every front whose block ends here or earlier)
             int ob = (int)t / (SB / FNB);
             bool last = ((int)t % (SB / FNB) == SB / FNB - 1) || t + 1 == lv.steps.size();
@@ -552,7 +576,7 @@ void Context::factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel, S
                 OuterTasks &O = lv.outer[ob];
                 bool pr = prof_on("schur") && O.schur.total > 0;
                 if (pr) prof_begin();
-                launch_schur<T>(A, fd, O.schur, ob, true, s);
+                launch_schur<T>(A, fd, O.schur, ob, 1, s);
                 if (pr) prof_end(O.schur.elems * sizeof(T), O.schur.flops);
             }
         }
@@ -560,6 +584,11 @@ void Context::factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel, S
     launch_invert_diag<T>(A, fd, f.ipiv.template ptr<int32_t>(), f.prow.template ptr<int32_t>(),
                           p.inv, 3, -1, s);
     launch_xform<T>(A, fd, p.xform, s);
+    for (size_t tp = 0; tp < p.fold_lo.size(); tp++) {
+        launch_schur<T>(A, fd, p.fold_lo[tp], (int)tp, 2, s);
+        launch_schur<T>(A, fd, p.fold_up[tp], (int)tp, 3, s);
+    }
+    launch_merge_tri<T>(A, fd, p.merge, s);
     int32_t np = 0;
     d2h(&np, f.npert.template ptr<int32_t>(), 1, s);
     MBL_HIP(hipStreamSynchronize(s));

@@ -53,6 +53,8 @@ struct Plan {
     std::vector<LevelTasks> levels;
     TaskList inv;                      // SB diagonal blocks of every front (inversion)
     TaskList xform;                    // 16-row panels folded with the inverted blocks
+    std::vector<TaskList> fold_lo, fold_up;   // per merged solve block: the two products
+    TaskList merge;                    // in-place triangular products of the merge
     int64_t y_elems = 0;               // forward-solution blocks (sum of p x 16)
     int64_t part_elems = 0;            // max over levels
     DevBuf d_fd, d_perm, d_contrib, d_relmap, d_child_ids, d_tfronts, d_tprefix, d_titems;
