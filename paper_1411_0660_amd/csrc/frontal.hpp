@@ -123,6 +123,13 @@ void launch_bwd_u12(const T *arena, const FrontDesc *fd, TaskList tl, int nrhs,
                     const double *vec, double *part, hipStream_t s);
 void launch_bwd_u12_reduce(const FrontDesc *fd, TaskList tl, int nrhs, double *yv,
                            const double *part, hipStream_t s);
+// forward contribution rows: V[p:m] -= L~21 V[0:p] (tiles into part, then the
+// reduction into the solve vectors)
+template <class T>
+void launch_fwd_l21(const T *arena, const FrontDesc *fd, TaskList tl, int nrhs, const double *vec,
+                    double *part, hipStream_t s);
+void launch_fwd_l21_reduce(const FrontDesc *fd, TaskList tl, int nrhs, double *vec,
+                           const double *part, hipStream_t s);
 // x_new[first..] = v_f[0:p] and x_out[perm[first..]] = v_f[0:p]
 void launch_bwd_scatter(const FrontDesc *fd, const int32_t *perm, TaskList tl, int nrhs,
                         const double *vec, double *xnew, int64_t n, double *xout, int64_t ldx,

@@ -112,9 +112,9 @@ __global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_solve_step(
         mode = FWD ? 1 : 2;
         out = FWD ? Y + r0 : V + r0;
         ldo = FWD ? p : m;
-    } else if (FWD) {                  // rows below the block
-        r0 = tend + (w - nA) * RW;
-        nrows = min(RW, m - r0);
+    } else if (FWD) {                  // pivot rows below the block (the contribution
+        r0 = tend + (w - nA) * RW;     // rows are updated once per level by k_fwd_l21)
+        nrows = min(RW, p - r0);
         mode = 0;
         out = V + r0;
         ldo = m;
@@ -201,6 +201,92 @@ __global__ __launch_bounds__(256) void k_bwd_gather(const FrontDesc *__restrict_
     int32_t g = contrib[d.cptr + i];
     double *v = vec + d.voff + d.p + i;
     for (int r = 0; r < nrhs; r++) v[(int64_t)r * d.m] = xnew[g + (int64_t)r * n];
+}
+
+// Contribution rows of the forward pass: once every solve block of a front
+// is done, V[0:p] holds the source values of all blocks (a block's rows are
+// not touched after its own step), so V[p:m] -= L~21 V[0:p] in one pass with
+// the folded panel L~21 = L[p:m, 0:p] (per block times its inverse): tiles of
+// 64 contribution rows x SB pivot columns into partial sums, then a
+// fixed-order reduction over the column chunks (k_fwd_l21_reduce).
+template <class T, int NR>
+__global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_fwd_l21(
+    const T *__restrict__ arena, const FrontDesc *__restrict__ fd, TaskList tl,
+    const double *__restrict__ vec, double *__restrict__ part) {
+    constexpr int CG = StepCfg<NR>::CG, CW = StepCfg<NR>::CWU, HG = CG / 2;
+    __shared__ double src[SB][NR];
+    __shared__ double red[HG][RW][NR];
+    const int2 tk = tl.items[blockIdx.x];
+    const FrontDesc d = fd[tk.x];
+    const int w = tk.y;
+    const int m = d.m, p = d.p, c = m - p;
+    const int nrc = (c + RW - 1) / RW;
+    const int rc = w % nrc, cc = w / nrc;
+    const int c0 = cc * SB, cw = min(SB, p - c0);
+    const int lane = threadIdx.x % RW, wv = threadIdx.x / RW;
+    const int row = rc * RW + lane;                  // contribution row
+    double mv[CW];
+    {
+        const T *Lp = arena + d.off + p + row + (int64_t)(c0 + wv * CW) * m;
+#pragma unroll
+        for (int q = 0; q < CW; q++)
+            mv[q] = (row < c && wv * CW + q < cw) ? (double)Lp[(int64_t)q * m] : 0.0;
+    }
+    const double *v = vec + d.voff;
+    for (int e = threadIdx.x; e < SB * NR; e += blockDim.x) {
+        int j = e % SB, r = e / SB;
+        src[j][r] = j < cw ? v[c0 + j + (int64_t)r * m] : 0.0;
+    }
+    __syncthreads();
+    double acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) acc[r] = 0.0;
+#pragma unroll
+    for (int q = 0; q < CW; q++) {
+        const double x = mv[q];
+#pragma unroll
+        for (int r = 0; r < NR; r++) acc[r] += x * src[wv * CW + q][r];
+    }
+    if (wv >= HG) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) red[wv - HG][lane][r] = acc[r];
+    }
+    __syncthreads();
+    if (wv < HG) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) red[wv][lane][r] += acc[r];
+    }
+    __syncthreads();
+    if (wv == 0 && row < c)
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            double sum = red[0][lane][r];
+#pragma unroll
+            for (int g = 1; g < HG; g++) sum += red[g][lane][r];
+            part[d.poff + ((int64_t)cc * MAXRHS + r) * c + row] = sum;
+        }
+}
+
+template <int NR>
+__global__ __launch_bounds__(256) void k_fwd_l21_reduce(const FrontDesc *__restrict__ fd,
+                                                        TaskList tl, double *vec,
+                                                        const double *__restrict__ part) {
+    const int2 tk = tl.items[blockIdx.x];
+    FrontDesc d = fd[tk.x];
+    int row = tk.y * 256 + threadIdx.x;
+    int m = d.m, p = d.p, c = m - p, ncc = (p + SB - 1) / SB;
+    if (row >= c) return;
+    double s[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) s[r] = 0.0;
+    const double *pp = part + d.poff + row;
+#pragma unroll 2
+    for (int q = 0; q < ncc; q++)
+#pragma unroll
+        for (int r = 0; r < NR; r++) s[r] += pp[((int64_t)q * MAXRHS + r) * c];
+    double *o = vec + d.voff + p + row;
+#pragma unroll
+    for (int r = 0; r < NR; r++) o[(int64_t)r * m] -= s[r];
 }
 
 // partial U12 x_c over one 64-row x SB-column tile (factor entries loaded
@@ -369,6 +455,28 @@ void launch_bwd_u12(const T *arena, const FrontDesc *fd, TaskList tl, int nrhs, 
     MBL_CHECK_LAUNCH();
 }
 
+template <class T>
+void launch_fwd_l21(const T *arena, const FrontDesc *fd, TaskList tl, int nrhs, const double *vec,
+                    double *part, hipStream_t s) {
+    if (tl.total == 0) return;
+    rhs_dispatch(nrhs, [&](auto nr) {
+        constexpr int NR = decltype(nr)::value;
+        k_fwd_l21<T, NR><<<dim3((unsigned)tl.total), dim3(StepCfg<NR>::THREADS), 0, s>>>(arena, fd,
+                                                                                      tl, vec, part);
+    });
+    MBL_CHECK_LAUNCH();
+}
+
+void launch_fwd_l21_reduce(const FrontDesc *fd, TaskList tl, int nrhs, double *vec,
+                           const double *part, hipStream_t s) {
+    if (tl.total == 0) return;
+    rhs_dispatch(nrhs, [&](auto nr) {
+        constexpr int NR = decltype(nr)::value;
+        k_fwd_l21_reduce<NR><<<dim3((unsigned)tl.total), dim3(256), 0, s>>>(fd, tl, vec, part);
+    });
+    MBL_CHECK_LAUNCH();
+}
+
 void launch_bwd_u12_reduce(const FrontDesc *fd, TaskList tl, int nrhs, double *yv,
                            const double *part, hipStream_t s) {
     if (tl.total == 0) return;
@@ -392,6 +500,8 @@ void launch_bwd_scatter(const FrontDesc *fd, const int32_t *perm, TaskList tl, i
     template void launch_solve_step<T>(const T *, const FrontDesc *, TaskList, int, int, bool,    \
                                        double *, double *, hipStream_t);                          \
     template void launch_bwd_u12<T>(const T *, const FrontDesc *, TaskList, int, const double *,  \
+                                    double *, hipStream_t);                                        \
+    template void launch_fwd_l21<T>(const T *, const FrontDesc *, TaskList, int, const double *,  \
                                     double *, hipStream_t);
 
 MBL_INST_TRSV(float)

@@ -18,7 +18,7 @@ namespace mbl {
 
 size_t footprint_bytes(const Plan &p, int prec, int nev, int block) {
     size_t n = (size_t)p.dim;
-    int b = block > 0 ? std::min(block, 16) : (n >= 10000 ? 8 : (n >= 600 ? 4 : 1));
+    int b = block > 0 ? std::min(block, 16) : default_block((int64_t)n);
     int nw = (int)std::min<size_t>(n, (size_t)nev + 2 + nev / 16);
     size_t cols = (size_t)std::max(2 * nw + 2 * b, nw + std::max(8, nw / 2) + 3 * b) + 2 * b;
     cols = std::min(cols, n + 16);

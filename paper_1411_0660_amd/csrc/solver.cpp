@@ -208,7 +208,9 @@ void Context::ensure_symbolic(Plan &p) {
             off += (int64_t)d.m * d.m;
             voff += (int64_t)d.m * MAXRHS;
             d.poff = poff;
-            poff += cdiv64(d.m - d.p, SB) * MAXRHS * (int64_t)d.p;
+            poff += std::max(cdiv64(d.m - d.p, SB) * (int64_t)d.p,    // U12 (backward) or
+                             cdiv64(d.p, SB) * (int64_t)(d.m - d.p))    // L21 (forward) partials
+                    * MAXRHS;
             d.yoff = p.y_elems;
             p.y_elems += (int64_t)d.p * MAXRHS;
             // original entries of H - sigma owned by this front
@@ -348,8 +350,8 @@ void Context::ensure_symbolic(Plan &p) {
         LevelTasks &lv = p.levels[l];
         const std::vector<int32_t> &fl = bylev[l];
         std::vector<int64_t> one(fl.size(), 1), g, sc;
-        std::vector<int32_t> ut, ur;
-        std::vector<int64_t> uti, uri;
+        std::vector<int32_t> ut, ur, lt, lr;
+        std::vector<int64_t> uti, uri, lti, lri;
         int maxch = 0, maxsteps = 0, maxsb = 0;
         for (int f : fl) {
             const FrontDesc &d = p.h_fd[f];
@@ -360,6 +362,12 @@ void Context::ensure_symbolic(Plan &p) {
                 uri.push_back(cdiv64(d.p, SB));
                 if (d.m > d.p) { ut.push_back(f); uti.push_back(cdiv64(d.p, 64) * cdiv64(d.m - d.p, SB)); }
                 uri.back() = cdiv64(d.p, 256);
+                if (d.m > d.p) {
+                    lt.push_back(f);
+                    lti.push_back(cdiv64(d.m - d.p, 64) * cdiv64(d.p, SB));
+                    lr.push_back(f);
+                    lri.push_back(cdiv64(d.m - d.p, 256));
+                }
             }
             maxch = std::max(maxch, d.nchild);
             maxsteps = std::max<int>(maxsteps, (int)cdiv64(d.p, FNB));
@@ -370,6 +378,8 @@ void Context::ensure_symbolic(Plan &p) {
         tb.add(lv.scatter, fl, sc);
         tb.add(lv.u12, ut, uti);
         tb.add(lv.u12red, ur, uri);
+        tb.add(lv.l21, lt, lti);
+        tb.add(lv.l21red, lr, lri);
         lv.ext.assign(maxch, TaskList{});
         for (int s = 0; s < maxch; s++) {
             std::vector<int32_t> ch;
@@ -452,7 +462,7 @@ void Context::ensure_symbolic(Plan &p) {
                 int tend = std::min(d.p, t0 + SSB);
                 int64_t na = cdiv64(tend - t0, 64);
                 act.push_back(f);
-                fi.push_back(na + cdiv64(d.m - tend, 64));
+                fi.push_back(na + cdiv64(d.p - tend, 64));
                 bi.push_back(na + cdiv64(t0, 64));
             }
             tb.add(lv.fstep[st], act, fi);
@@ -460,8 +470,8 @@ void Context::ensure_symbolic(Plan &p) {
             for (int f : act) {
                 const FrontDesc &d = p.h_fd[f];
                 double t0 = st * SSB, sw = std::min(SSB, d.p - st * SSB), tend = t0 + sw;
-                lv.fstep[st].elems += 0.5 * sw * (sw + 1) + (d.m - tend) * sw;
-                lv.fstep[st].rows += 2.0 * sw + (d.m - tend);
+                lv.fstep[st].elems += 0.5 * sw * (sw + 1) + (d.p - tend) * sw;
+                lv.fstep[st].rows += 2.0 * sw + (d.p - tend);
                 lv.bstep[st].elems += 0.5 * sw * (sw + 1) + t0 * sw;
                 lv.bstep[st].rows += 2.0 * sw + t0;
             }
@@ -631,6 +641,8 @@ void Context::lu_apply(Plan &p, Factor<T> &f, int nrhs, const double *b, int64_t
         launch_fwd_gather(fd, p.d_perm.ptr<int32_t>(), f.prow.template ptr<int32_t>(),
                           p.d_inv_ptr.ptr<int32_t>(), isrc, lv.fgather, nrhs, b, ldb, vec, s);
         for (size_t t = 0; t < lv.fstep.size(); t++) step(lv.fstep[t], (int)t, true);
+        launch_fwd_l21<T>(A, fd, lv.l21, nrhs, vec, part, s);
+        launch_fwd_l21_reduce(fd, lv.l21red, nrhs, vec, part, s);
     }
     for (size_t l = p.levels.size(); l-- > 0;) {
         LevelTasks &lv = p.levels[l];
@@ -1183,7 +1195,7 @@ void solve_problem(Context &ctx, const mbl_problem &pr, mbl_result &res) {
     t0 = wall_seconds();
     int nev = pr.nev;
     int nw = (int)std::min<int64_t>(n, nev + 2 + nev / 16);
-    int b = pr.block > 0 ? std::min(pr.block, 16) : (n >= 10000 ? 8 : (n >= 600 ? 4 : 1));
+    int b = pr.block > 0 ? std::min(pr.block, 16) : default_block((int64_t)n);
     int nkeep = round_up(nw + std::max(8, nw / 2), b);
     int ncv = pr.ncv > 0 ? round_up(pr.ncv, b) : round_up(std::max(2 * nw + 2 * b, nkeep + 3 * b), b);
     if (ncv + b > n) {               // small sector: a full-space basis, vector at a time

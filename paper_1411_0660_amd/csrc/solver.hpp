@@ -38,6 +38,7 @@ struct LevelTasks {
     std::vector<TaskList> fstep, bstep;
     TaskList fgather;                  // forward right-hand sides, 256-row items
     TaskList u12, u12red;              // U12 x_c tiles and their reduction
+    TaskList l21, l21red;              // forward contribution rows: tiles and reduction
     int64_t part_elems = 0;            // level scratch of the U12 partial products
 };
 
@@ -168,6 +169,11 @@ class Context {
     template <class T> void refine(Plan &p, Factor<T> &f, int nrhs, const double *B, double *X,
                                    SolveStats &st);
 };
+
+// Block size of the shift-invert Krylov iteration (right-hand sides per pass
+// through the factors) when the problem does not set one: 8 from sector
+// dimension 1e5 (L = 20), 4 from 600, single vectors below.
+inline int default_block(int64_t n) { return n >= 100000 ? 8 : (n >= 600 ? 4 : 1); }
 
 void solve_problem(Context &ctx, const mbl_problem &prob, mbl_result &res);
 
