@@ -444,9 +444,9 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
                                                   TaskList tl, int t) {
     typedef typename MfmaAcc<T>::v4 v4;
     constexpr int KC = SchurCfg<T>::KC, PF = SchurCfg<T>::PF;
-    __shared__ T smem[2 * KC * SP > 64 * (ST + 1) ? 2 * KC * SP : 64 * (ST + 1)];
-    T *As = smem;                    // As[k * SP + i]
-    T *Bs = smem + KC * SP;          // Bs[k * SP + j]
+    // two LDS buffers of the A and B chunks: the next chunk is stashed into the
+    // idle one right after the current one is consumed (one barrier per chunk)
+    __shared__ T smem[4 * KC * SP > 64 * (ST + 1) ? 4 * KC * SP : 64 * (ST + 1)];
     const int2 tk = tl.items[blockIdx.x];
     FrontDesc d = fd[tk.x];
     int64_t tile = tk.y;
@@ -485,7 +485,8 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
             pb[q] = (c < chi && kb2 < kn) ? F[(int64_t)(kc0 + kc + kb2) + (int64_t)c * m] : T(0);
         }
     };
-    auto stash = [&]() {
+    auto stash = [&](int buf) {
+        T *As = smem + buf * 2 * KC * SP, *Bs = As + KC * SP;
 #pragma unroll
         for (int q = 0; q < PF; q++) {
             int e = threadIdx.x + q * 256;
@@ -499,11 +500,12 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
 #pragma unroll
         for (int b = 0; b < 4; b++) acc[a][b] = v4{0, 0, 0, 0};
     fetch(0);
-    for (int kc = 0; kc < kd; kc += KC) {
-        __syncthreads();
-        stash();
-        __syncthreads();
-        if (kc + KC < kd) fetch(kc + KC);
+    stash(0);
+    __syncthreads();
+    for (int kc = 0, buf = 0; kc < kd; kc += KC, buf ^= 1) {
+        const T *As = smem + buf * 2 * KC * SP, *Bs = As + KC * SP;
+        const bool more = kc + KC < kd;
+        if (more) fetch(kc + KC);
         int ksteps = (min(KC, kd - kc) + 3) / 4;
         for (int ks = 0; ks < ksteps; ks++) {
             int kk = ks * 4 + lk;
@@ -517,6 +519,8 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
 #pragma unroll
                 for (int b = 0; b < 4; b++) acc[a][b] = MfmaAcc<T>::mma(av[a], bv[b], acc[a][b]);
         }
+        if (more) stash(buf ^ 1);
+        __syncthreads();
     }
     // write-back through LDS, one 64-column half of the tile at a time
     T *Cs = smem;                    // Cs[col * (ST + 1) + row], col < 64
