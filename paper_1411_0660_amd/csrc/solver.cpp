@@ -70,6 +70,7 @@ Context::Context(int dev, size_t budget_bytes, hipStream_t s)
     size_t fr = 0, tot = 0;
     MBL_HIP(hipMemGetInfo(&fr, &tot));
     budget.limit = budget_bytes ? budget_bytes : (size_t)(0.92 * (double)fr);
+    use_graphs_ = std::getenv("MBL_NO_GRAPH") == nullptr;
 }
 
 Context::Context(const Context &owner, size_t budget_bytes)
@@ -78,10 +79,12 @@ Context::Context(const Context &owner, size_t budget_bytes)
     MBL_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
     own_stream = true;
     budget.limit = budget_bytes;
+    use_graphs_ = std::getenv("MBL_NO_GRAPH") == nullptr;
 }
 
 void Context::trim() {
     MBL_HIP(hipStreamSynchronize(stream));
+    clear_graphs();
     for (DevBuf *b : {&f32_.arena, &f32_.ipiv, &f32_.prow, &f32_.npert, &f64_.arena, &f64_.ipiv,
                       &f64_.prow, &f64_.npert, &d_vec, &d_yv, &d_upart, &d_xnew, &d_r, &d_d,
                       &d_part, &d_V, &d_V2, &d_W, &d_small, &d_tnpart, &d_gV, &d_gZ, &d_gpart,
@@ -94,6 +97,7 @@ void Context::trim() {
 
 Context::~Context() {
     (void)hipStreamSynchronize(stream);
+    clear_graphs();
     for (auto &e : prof.pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     if (owns_plans_) {
         std::lock_guard<std::recursive_mutex> lk(plans_->mu);
@@ -619,6 +623,57 @@ void Context::factor(Plan &p, int prec, double sigma, double anorm, SolveStats &
 template <class T>
 void Context::lu_apply(Plan &p, Factor<T> &f, int nrhs, const double *b, int64_t ldb, double *x,
                        int64_t ldx) {
+    const int64_t n = p.dim;
+    if (!use_graphs_ || !prof.cls.empty() || ldb != n || ldx != n) {
+        lu_apply_seq<T>(p, f, nrhs, b, ldb, x, ldx);
+        return;
+    }
+    // The launch sequence of one application is the same every time for a
+    // given plan, factor, right-hand-side count and work buffers: it is
+    // captured once as a graph between fixed staging vectors and replayed.
+    d_vec.ensure(sizeof(double) * std::max<int64_t>(1, p.vec_elems), &budget);
+    d_yv.ensure(sizeof(double) * std::max<int64_t>(1, p.y_elems), &budget);
+    d_upart.ensure(sizeof(double) * std::max<int64_t>(1, p.part_elems), &budget);
+    d_xnew.ensure(sizeof(double) * n * MAXRHS, &budget);
+    d_gin.ensure(sizeof(double) * n * MAXRHS, &budget);
+    d_gout.ensure(sizeof(double) * n * MAXRHS, &budget);
+    GraphKey key{p.L, (int)sizeof(T), nrhs,
+                 {f.arena.template ptr<void>(), f.prow.template ptr<void>(), d_vec.ptr<void>(),
+                  d_yv.ptr<void>(),
+                  d_upart.ptr<void>(), d_xnew.ptr<void>(), d_gin.ptr<void>(), d_gout.ptr<void>()}};
+    auto it = graphs_.find(key);
+    if (it == graphs_.end()) {
+        if (graphs_.size() >= 32) clear_graphs();
+        hipGraph_t g = nullptr;
+        MBL_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        try {
+            lu_apply_seq<T>(p, f, nrhs, d_gin.ptr<double>(), n, d_gout.ptr<double>(), n);
+        } catch (...) {
+            hipGraph_t dead = nullptr;
+            (void)hipStreamEndCapture(stream, &dead);
+            if (dead) (void)hipGraphDestroy(dead);
+            throw;
+        }
+        MBL_HIP(hipStreamEndCapture(stream, &g));
+        hipGraphExec_t ex = nullptr;
+        hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        MBL_HIP(e);
+        it = graphs_.emplace(key, ex).first;
+    }
+    launch_copy(n * nrhs, b, d_gin.ptr<double>(), stream);
+    MBL_HIP(hipGraphLaunch(it->second, stream));
+    launch_copy(n * nrhs, d_gout.ptr<double>(), x, stream);
+}
+
+void Context::clear_graphs() {
+    for (auto &kv : graphs_) (void)hipGraphExecDestroy(kv.second);
+    graphs_.clear();
+}
+
+template <class T>
+void Context::lu_apply_seq(Plan &p, Factor<T> &f, int nrhs, const double *b, int64_t ldb,
+                           double *x, int64_t ldx) {
     hipStream_t s = stream;
     const T *A = f.arena.template ptr<T>();
     const FrontDesc *fd = p.d_fd.ptr<FrontDesc>();

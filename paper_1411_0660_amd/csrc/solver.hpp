@@ -162,6 +162,25 @@ class Context {
     PinnedBuf h_stage;                     // Krylov coefficients copied back asynchronously
     template <class T> void factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel,
                                      SolveStats &st);
+    template <class T> void lu_apply_seq(Plan &p, Factor<T> &f, int nrhs, const double *b,
+                                         int64_t ldb, double *x, int64_t ldx);
+    // captured launch sequences of lu_apply (see lu_apply)
+    struct GraphKey {
+        int L, tsize, nrhs;
+        const void *bufs[8];
+        bool operator<(const GraphKey &o) const {
+            if (L != o.L) return L < o.L;
+            if (tsize != o.tsize) return tsize < o.tsize;
+            if (nrhs != o.nrhs) return nrhs < o.nrhs;
+            for (int i = 0; i < 8; i++)
+                if (bufs[i] != o.bufs[i]) return bufs[i] < o.bufs[i];
+            return false;
+        }
+    };
+    std::map<GraphKey, hipGraphExec_t> graphs_;
+    bool use_graphs_ = true;
+    DevBuf d_gin, d_gout;              // staging vectors of the captured sequences
+    void clear_graphs();
     template <class T> void lu_apply(Plan &p, Factor<T> &f, int nrhs, const double *b,
                                      int64_t ldb, double *x, int64_t ldx);
     template <class T> void gmres_refine(Plan &p, Factor<T> &f, int nrhs, const double *B,
@@ -172,8 +191,8 @@ class Context {
 
 // Block size of the shift-invert Krylov iteration (right-hand sides per pass
 // through the factors) when the problem does not set one: 8 from sector
-// dimension 1e5 (L = 20), 4 from 600, single vectors below.
-inline int default_block(int64_t n) { return n >= 100000 ? 8 : (n >= 600 ? 4 : 1); }
+// dimension 1e5 (L = 20), 4 from 128 (L = 10), single vectors below.
+inline int default_block(int64_t n) { return n >= 100000 ? 8 : (n >= 128 ? 4 : 1); }
 
 void solve_problem(Context &ctx, const mbl_problem &prob, mbl_result &res);
 

@@ -154,3 +154,30 @@ def test_bitwise_reproducible(ctx):
     a = ctx.mbl_solve(12, 3.0, 11, 0.5, 20)
     b = ctx.mbl_solve(12, 3.0, 11, 0.5, 20)
     assert np.array_equal(a["evals"], b["evals"]) and np.array_equal(a["se"], b["se"])
+
+
+def test_graph_replays_match_eager(ctx):
+    """The triangular-solve sequence runs as a captured graph, replayed for
+    every application (with the refinement's own kernels and host
+    synchronizations between the replays); each result must equal the eager
+    launch sequence bitwise."""
+    import os
+    cases = [(8, 2.0, 1, 0.5, 10, mbl.MBL_FP64), (12, 3.0, 2, 0.3, 20, mbl.MBL_FP64),
+             (14, 1.0, 3, 0.7, 30, mbl.MBL_FP64), (12, 3.0, 2, 0.3, 20, mbl.MBL_FP32_IR64),
+             (12, 3.0, 2, 0.3, 20, mbl.MBL_FP64)]
+    outs = [ctx.mbl_solve(L, h, s, e, nev, prec=p) for (L, h, s, e, nev, p) in cases]
+    f = oracle.fields(14, 3.0, 2)
+    rhs = [np.random.default_rng(k).standard_normal((3432, k)) for k in (1, 5, 16)]
+    xs = [ctx.mbl_shift_solve(14, 1.0, f, 0.31, b)[0] for b in rhs]
+    os.environ["MBL_NO_GRAPH"] = "1"
+    try:
+        eager = mbl.Context(0)
+    finally:
+        del os.environ["MBL_NO_GRAPH"]
+    with eager:
+        for (L, h, s, e, nev, p), g in zip(cases, outs):
+            a = eager.mbl_solve(L, h, s, e, nev, prec=p)
+            for k in ("evals", "resid", "s1", "se", "r"):
+                assert np.array_equal(g[k], a[k]), (L, p, k)
+        for b, x in zip(rhs, xs):
+            assert np.array_equal(eager.mbl_shift_solve(14, 1.0, f, 0.31, b)[0], x)
