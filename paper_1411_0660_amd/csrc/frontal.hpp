@@ -66,12 +66,13 @@ void launch_extend_add(T *arena, const FrontDesc *fd, const int32_t *relmap, Tas
 // step t of the blocked partial LU on every listed front
 template <class T>
 void launch_panel(T *arena, const FrontDesc *fd, int32_t *ipiv, int32_t *nperturbed, TaskList tl,
-                  int t, double thresh, hipStream_t s);
+                  int t, double thresh, double *uinv, hipStream_t s);
 template <class T>
 void launch_trsm_u(T *arena, const FrontDesc *fd, const int32_t *ipiv, TaskList tl, int t,
                    hipStream_t s);
 template <class T>
-void launch_trsm_l(T *arena, const FrontDesc *fd, TaskList tl, int t, hipStream_t s);
+void launch_trsm_l(T *arena, const FrontDesc *fd, TaskList tl, int t, const double *uinv,
+                   hipStream_t s);
 // inner (panel t, K = 64, inside its outer block) or outer-block (block t,
 // K = 256, everything right of and below it) trailing update
 // kind 0: inner update after panel t; 1: outer update of block t; 2 and 3: the

@@ -64,69 +64,110 @@ __global__ __launch_bounds__(256) void k_extend_add(T *arena, const FrontDesc *_
 }
 
 // LU with partial pivoting of the kb x kb diagonal block of panel t (one
-// workgroup per front, block in LDS)
+// workgroup per front, block in LDS), plus U_tt^-1 for the L-column solves of
+// the rows below (stored once per front in uinv, FNB x FNB column major,
+// identity beyond kb).  The multipliers of column j are used as D[i][j] /
+// pivot_j in the updates and the column is scaled at the end (the scaling of
+// a row commutes with the later interchanges).  Thread (column c = tid % 64,
+// row group g = tid / 64) updates rows i = g (mod 4) of its column.
 template <class T>
 __global__ __launch_bounds__(256) void k_panel(T *arena, const FrontDesc *__restrict__ fd,
                                                int32_t *__restrict__ ipiv,
                                                int32_t *__restrict__ nperturbed, TaskList tl,
-                                               int t, double thresh) {
+                                               int t, double thresh, double *__restrict__ uinv) {
+    constexpr int H = FNB / 2;
     __shared__ T D[FNB][FNB + 1];
+    __shared__ double Ui[FNB][FNB + 1];
+    __shared__ double Tm[H][H + 1];
     __shared__ int piv[FNB];
-    FrontDesc d = fd[tl.fronts[blockIdx.x]];
-    int k0 = t * FNB;
-    int kb = min(FNB, d.p - k0);
-    int m = d.m;
+    __shared__ T rpv[FNB];
+    const int f = tl.fronts[blockIdx.x];
+    const FrontDesc d = fd[f];
+    const int k0 = t * FNB, kb = min(FNB, d.p - k0), m = d.m;
     T *F = arena + d.off;
-    for (int e = threadIdx.x; e < FNB * FNB; e += blockDim.x) {
-        int i = e % FNB, j = e / FNB;
-        D[i][j] = (i < kb && j < kb) ? F[(int64_t)(k0 + i) + (int64_t)(k0 + j) * m] : T(0);
-    }
+    const int c = threadIdx.x % FNB, g = threadIdx.x / FNB;
+    for (int i = g; i < FNB; i += 4)
+        D[i][c] = (i < kb && c < kb) ? F[(int64_t)(k0 + i) + (int64_t)(k0 + c) * m] : T(0);
     __syncthreads();
     const T th = (T)thresh;
     for (int j = 0; j < kb; j++) {
-        if (threadIdx.x < 64) {           // wave 0: argmax |D[i][j]|, i in [j, kb)
-            int i = threadIdx.x;
-            T v = (i >= j && i < kb) ? fabs(D[i][j]) : T(-1);
-            int idx = i;
+        if (g == 0) {
+            // pivot: argmax over rows i >= j of |D[i][j]| (lane = row), first on ties
+            T v = (c >= j && c < kb) ? fabs(D[c][j]) : T(-1);
+            int idx = c;
             for (int off = 32; off > 0; off >>= 1) {
                 T ov = __shfl_xor(v, off);
                 int oi = __shfl_xor(idx, off);
                 if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
             }
-            if (threadIdx.x == 0) piv[j] = idx;
+            const int r = idx;
+            if (r != j && c < kb) {                  // interchange rows j and r of column c
+                T x = D[j][c];
+                D[j][c] = D[r][c];
+                D[r][c] = x;
+            }
+            if (c == 0) piv[j] = r;
         }
         __syncthreads();
-        int r = piv[j];
-        if (r != j)
-            for (int c = threadIdx.x; c < kb; c += blockDim.x) {
-                T a = D[j][c];
-                D[j][c] = D[r][c];
-                D[r][c] = a;
-            }
-        __syncthreads();
         T pv = D[j][j];
-        bool pert = fabs(pv) < th;
+        const bool pert = fabs(pv) < th;
         if (pert) pv = (pv >= T(0)) ? th : -th;
+        const T rp = T(1) / pv;
+        if (c > j && c < kb) {                       // trailing update of column c
+            const T ujc = D[j][c];
+            for (int i = j + 1 + g; i < kb; i += 4) D[i][c] -= (D[i][j] * rp) * ujc;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             D[j][j] = pv;
+            rpv[j] = rp;
             if (pert) atomicAdd(nperturbed, 1);
         }
-        T rp = T(1) / pv;
-        for (int i = j + 1 + threadIdx.x; i < kb; i += blockDim.x) D[i][j] *= rp;
-        __syncthreads();
-        int w = kb - j - 1;
-        for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
-            int i = j + 1 + e % w, c = j + 1 + e / w;
-            D[i][c] -= D[i][j] * D[j][c];
+    }
+    __syncthreads();
+    if (c < kb)
+        for (int i = c + 1 + g; i < kb; i += 4) D[i][c] *= rpv[c];      // column c of L
+    for (int i = g; i < FNB; i += 4)
+        if (i >= kb && i == c) D[i][c] = T(1);                           // identity padding
+    __syncthreads();
+    if (c < kb)
+        for (int i = g; i < kb; i += 4) F[(int64_t)(k0 + i) + (int64_t)(k0 + c) * m] = D[i][c];
+    if (g == 0 && c < kb) ipiv[d.first + k0 + c] = piv[c];
+    // U^-1 by 32 x 32 blocks: the two diagonal inverses (one column per lane of
+    // waves 0 and 1), then Ui12 = -Ui11 (U12 Ui22)
+    if (g < 2 && c < H) {
+        const int o = g * H;                         // block origin
+        double x[H];
+#pragma unroll
+        for (int i = H - 1; i >= 0; i--) {
+            double sum = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+            for (int q = i + 1; q < H; q++) sum -= (double)D[o + i][o + q] * x[q];
+            x[i] = (i <= c) ? sum / (double)D[o + i][o + i] : 0.0;
         }
-        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < H; i++) {
+            Ui[o + i][o + c] = x[i];
+            Ui[(1 - g) * H + i][o + c] = 0.0;        // the block below (g = 0) / left of U22 rows
+        }
     }
-    for (int e = threadIdx.x; e < kb * kb; e += blockDim.x) {
-        int i = e % kb, j = e / kb;
-        F[(int64_t)(k0 + i) + (int64_t)(k0 + j) * m] = D[i][j];
+    __syncthreads();
+    for (int e = threadIdx.x; e < H * H; e += 256) {             // Tm = U12 Ui22
+        int i = e % H, jj = e / H;
+        double acc = 0.0;
+        for (int q = 0; q <= jj; q++) acc += (double)D[i][H + q] * Ui[H + q][H + jj];
+        Tm[i][jj] = acc;
     }
-    for (int j = threadIdx.x; j < kb; j += blockDim.x) ipiv[d.first + k0 + j] = piv[j];
+    __syncthreads();
+    for (int e = threadIdx.x; e < H * H; e += 256) {             // Ui12 = -Ui11 Tm
+        int i = e % H, jj = e / H;
+        double acc = 0.0;
+        for (int q = i; q < H; q++) acc += Ui[i][q] * Tm[q][jj];
+        Ui[i][H + jj] = -acc;
+    }
+    __syncthreads();
+    double *u = uinv + (int64_t)f * FNB * FNB;
+    for (int e = threadIdx.x; e < FNB * FNB; e += 256) u[e] = Ui[e % FNB][e / FNB];
 }
 
 // Row interchanges of panel t applied to every column outside the panel (so
@@ -339,13 +380,12 @@ __global__ __launch_bounds__(256) void k_invert_diag(T *arena, const FrontDesc *
     }
 }
 
-// L21 of panel t: every row below the panel times U_tt^-1.  Each workgroup
-// inverts U_tt in LDS (one column per lane of wave 0) and multiplies its 64
-// rows by the inverse.
+// L21 of panel t: every row below the panel times U_tt^-1 (computed once per
+// front by k_panel); each workgroup multiplies its 64 rows by the inverse.
 template <class T>
 __global__ __launch_bounds__(256) void k_trsm_l(T *arena, const FrontDesc *__restrict__ fd,
-                                                TaskList tl, int t) {
-    __shared__ double Us[FNB][FNB + 1];
+                                                TaskList tl, int t,
+                                                const double *__restrict__ uinv) {
     __shared__ double Ui[FNB][FNB + 1];
     __shared__ double As[FNB][FNB + 1];     // As[k][i]: row i of the chunk, panel column k
     const int2 tk = tl.items[blockIdx.x];
@@ -354,26 +394,11 @@ __global__ __launch_bounds__(256) void k_trsm_l(T *arena, const FrontDesc *__res
     int k0 = t * FNB, kb = min(FNB, d.p - k0), k1 = k0 + kb, m = d.m;
     int r0 = k1 + chunk * TRSM_L_ROWS, nr = min(TRSM_L_ROWS, m - r0);
     T *F = arena + d.off;
+    const double *u = uinv + (int64_t)tk.x * FNB * FNB;
     for (int e = threadIdx.x; e < FNB * FNB; e += blockDim.x) {
         int i = e % FNB, j = e / FNB;
-        bool in = i < kb && j < kb;
-        Us[i][j] = (in && i <= j) ? (double)F[(int64_t)(k0 + i) + (int64_t)(k0 + j) * m]
-                                  : (i == j ? 1.0 : 0.0);
+        Ui[i][j] = u[e];
         As[j][i] = (i < nr && j < kb) ? (double)F[(int64_t)(r0 + i) + (int64_t)(k0 + j) * m] : 0.0;
-    }
-    __syncthreads();
-    if (threadIdx.x < FNB) {                 // column j of U_tt^-1 by back substitution
-        int j = threadIdx.x;
-        double x[FNB];
-#pragma unroll
-        for (int i = FNB - 1; i >= 0; i--) {
-            double v = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-            for (int q = i + 1; q < FNB; q++) v -= Us[i][q] * x[q];
-            x[i] = (i <= j) ? v / Us[i][i] : 0.0;
-        }
-#pragma unroll
-        for (int i = 0; i < FNB; i++) Ui[i][j] = x[i];
     }
     __syncthreads();
     int i = threadIdx.x % TRSM_L_ROWS, jb = (threadIdx.x / TRSM_L_ROWS) * 16;
@@ -732,10 +757,9 @@ void launch_extend_add(T *arena, const FrontDesc *fd, const int32_t *relmap, Tas
 
 template <class T>
 void launch_panel(T *arena, const FrontDesc *fd, int32_t *ipiv, int32_t *nperturbed, TaskList tl,
-                  int t, double thresh, hipStream_t s) {
+                  int t, double thresh, double *uinv, hipStream_t s) {
     if (tl.n == 0) return;
-    hipLaunchKernelGGL(k_panel<T>, dim3(tl.n), dim3(256), 0, s, arena, fd, ipiv, nperturbed, tl, t,
-                       thresh);
+    k_panel<T><<<dim3(tl.n), dim3(256), 0, s>>>(arena, fd, ipiv, nperturbed, tl, t, thresh, uinv);
     MBL_CHECK_LAUNCH();
 }
 
@@ -765,10 +789,10 @@ void launch_xform(T *arena, const FrontDesc *fd, TaskList tl, hipStream_t s) {
 }
 
 template <class T>
-void launch_trsm_l(T *arena, const FrontDesc *fd, TaskList tl, int t, hipStream_t s) {
+void launch_trsm_l(T *arena, const FrontDesc *fd, TaskList tl, int t, const double *uinv,
+                   hipStream_t s) {
     if (tl.total == 0) return;
-    hipLaunchKernelGGL(k_trsm_l<T>, dim3((unsigned)tl.total), dim3(256), 0, s, arena, fd,
-                       tl, t);
+    k_trsm_l<T><<<dim3((unsigned)tl.total), dim3(256), 0, s>>>(arena, fd, tl, t, uinv);
     MBL_CHECK_LAUNCH();
 }
 
@@ -810,10 +834,11 @@ int merge_tri_items(int p) {
     template void launch_extend_add<T>(T *, const FrontDesc *, const int32_t *, TaskList,       \
                                        hipStream_t);                                            \
     template void launch_panel<T>(T *, const FrontDesc *, int32_t *, int32_t *, TaskList, int,  \
-                                  double, hipStream_t);                                         \
+                                  double, double *, hipStream_t);                               \
     template void launch_trsm_u<T>(T *, const FrontDesc *, const int32_t *, TaskList, int,      \
                                    hipStream_t);                                                \
-    template void launch_trsm_l<T>(T *, const FrontDesc *, TaskList, int, hipStream_t);         \
+    template void launch_trsm_l<T>(T *, const FrontDesc *, TaskList, int, const double *,       \
+                                   hipStream_t);                                                \
     template void launch_xform<T>(T *, const FrontDesc *, TaskList, hipStream_t);               \
     template void launch_invert_diag<T>(T *, const FrontDesc *, const int32_t *, int32_t *,      \
                                         TaskList, int, int, hipStream_t);                        \

@@ -91,8 +91,11 @@ void Context::trim() {
                       &d_gcoef, &d_psi, &d_psi2, &d_hpsi, &d_e, &d_cpart, &d_obs, &d_r_out,
                       &d_se})
         b->reset();
+    for (DevBuf *b : {&f32_.uinv, &f64_.uinv}) b->reset();
     f32_.valid = false;
     f64_.valid = false;
+    f32_.L = -1;                       // buffers freed: the next factorization reallocates
+    f64_.L = -1;
 }
 
 Context::~Context() {
@@ -561,6 +564,7 @@ void Context::factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel, S
         f.ipiv.alloc(sizeof(int32_t) * std::max<int64_t>(1, p.dim), &budget);
         f.prow.alloc(sizeof(int32_t) * std::max<int64_t>(1, p.dim), &budget);
         f.npert.alloc(sizeof(int32_t), &budget);
+        f.uinv.alloc(sizeof(double) * FNB * FNB * std::max<size_t>(1, p.h_fd.size()), &budget);
         f.L = p.L;
     }
     f.valid = false;
@@ -579,9 +583,9 @@ void Context::factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel, S
         for (size_t t = 0; t < lv.steps.size(); t++) {
             StepTasks &S = lv.steps[t];
             launch_panel<T>(A, fd, f.ipiv.template ptr<int32_t>(), f.npert.template ptr<int32_t>(),
-                            S.panel, (int)t, thresh, s);
+                            S.panel, (int)t, thresh, f.uinv.template ptr<double>(), s);
             launch_trsm_u<T>(A, fd, f.ipiv.template ptr<int32_t>(), S.trsm_u, (int)t, s);
-            launch_trsm_l<T>(A, fd, S.rows_below, (int)t, s);
+            launch_trsm_l<T>(A, fd, S.rows_below, (int)t, f.uinv.template ptr<double>(), s);
             launch_schur<T>(A, fd, S.schur, (int)t, 0, s);
             // end of an outer block (for every front whose block ends here or earlier)
             int ob = (int)t / (SB / FNB);

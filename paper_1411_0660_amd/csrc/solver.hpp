@@ -66,6 +66,7 @@ template <class T>
 struct Factor {
     int L = -1;
     DevBuf arena, ipiv, prow, npert;
+    DevBuf uinv;                       // per front: U_tt^-1 of the current panel (FNB x FNB)
     bool valid = false;
     double sigma = 0.0;
 };
