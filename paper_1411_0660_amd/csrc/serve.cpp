@@ -23,8 +23,9 @@ size_t footprint_bytes(const Plan &p, int prec, int nev, int block) {
     size_t cols = (size_t)std::max(2 * nw + 2 * b, nw + std::max(8, nw / 2) + 3 * b) + 2 * b;
     cols = std::min(cols, n + 16);
     size_t bytes = 0;
-    bytes += 8 * (size_t)p.arena_elems + 12 * n;            // FP64 fronts, pivots, row maps
-    if (prec == MBL_FP32_IR64) bytes += 4 * (size_t)p.arena_elems + 12 * n;   // FP32 factor
+    const size_t panel_inv = 8 * (size_t)FNB * FNB * std::max<size_t>(1, p.h_fd.size());
+    bytes += 8 * (size_t)p.arena_elems + 12 * n + panel_inv;     // FP64 fronts, pivots, row maps
+    if (prec == MBL_FP32_IR64) bytes += 4 * (size_t)p.arena_elems + 12 * n + panel_inv;  // FP32
     bytes += 8 * (size_t)p.vec_elems * 2 + 8 * n * 16 * 6; // solve vectors, x_new, r, d, staging
     bytes += 8 * (size_t)p.part_elems;                      // U12 partial products
     bytes += 8 * n * cols * 2 + 8 * n * 16;                 // Krylov bases + work block

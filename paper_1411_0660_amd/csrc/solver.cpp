@@ -559,6 +559,10 @@ template <class T>
 void Context::factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel, SolveStats &st) {
     hipStream_t s = stream;
     if (f.L != p.L) {
+        // invalid until every buffer is in place: an allocation that throws
+        // part way must not leave buffers of another size behind a valid L
+        f.L = -1;
+        f.valid = false;
         f.arena.reset();
         f.arena.alloc(sizeof(T) * p.arena_elems, &budget);
         f.ipiv.alloc(sizeof(int32_t) * std::max<int64_t>(1, p.dim), &budget);

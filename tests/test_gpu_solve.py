@@ -181,3 +181,31 @@ def test_graph_replays_match_eager(ctx):
                 assert np.array_equal(g[k], a[k]), (L, p, k)
         for b, x in zip(rhs, xs):
             assert np.array_equal(eager.mbl_shift_solve(14, 1.0, f, 0.31, b)[0], x)
+
+
+def test_factor_reallocated_after_failed_allocation():
+    """A factorization whose allocation runs out of budget leaves the factor
+    marked invalid, so a later solve of another size reallocates every factor
+    buffer (instead of reusing buffers of the failed size)."""
+    with mbl.Context(0) as probe:
+        fp8 = probe.mbl_footprint(8, mbl.MBL_FP64, 10)
+        fp14 = probe.mbl_footprint(14, mbl.MBL_FP64, 10)
+    for frac in (0.35, 0.5, 0.65, 0.8):
+        budget = int(fp8 * 2 + frac * fp14)
+        with mbl.Context(0, hbm_budget=budget) as c:
+            try:
+                c.mbl_footprint(14, mbl.MBL_FP64, 10)      # plans of both sizes in place
+                first = c.mbl_solve(8, 2.0, 4, 0.5, 10)
+            except mbl.MblError as e:
+                assert e.code == mbl.MBL_ENOMEM
+                continue
+            try:
+                c.mbl_solve(14, 2.0, 4, 0.5, 10)
+                continue                                    # fits: try a smaller budget
+            except mbl.MblError as e:
+                assert e.code == mbl.MBL_ENOMEM
+            again = c.mbl_solve(8, 2.0, 4, 0.5, 10)
+            assert np.array_equal(first["evals"], again["evals"])
+            assert np.array_equal(first["se"], again["se"])
+            return
+    pytest.skip("no budget between the L = 8 and L = 14 footprints on this device")
