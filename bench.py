@@ -56,13 +56,20 @@ def percentile(xs, q):
     return xs[f] + (xs[c] - xs[f]) * (k - f)
 
 
-def schur_traffic():
+def schur_source_sha():
+    """sha256 of the Schur kernel's source: from its MFMA helpers to the end of
+    k_schur (the counters stay valid while this text is unchanged)."""
     import hashlib
-    if SCHUR_TRAFFIC["sha256"] is None:
+    with open(SCHUR_SRC) as fh:
+        src = fh.read()
+    a = src.index("template <class T> struct MfmaAcc;")
+    b = src.index("\n}\n", src.index("void k_schur(", a)) + 3
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
+def schur_traffic():
+    if SCHUR_TRAFFIC["sha256"] is None or schur_source_sha() != SCHUR_TRAFFIC["sha256"]:
         return None
-    with open(SCHUR_SRC, "rb") as fh:
-        if hashlib.sha256(fh.read()).hexdigest() != SCHUR_TRAFFIC["sha256"]:
-            return None
     return SCHUR_TRAFFIC["bytes_per_launch"]
 
 
