@@ -192,7 +192,8 @@ int mbl_footprint(mbl_ctx *ctx, int L, int prec, int nev, int block, size_t *byt
  * stream, plus the algorithmic bytes and flops of the timed launches (what the
  * method must move or compute, not what the hardware counters report).
  * Classes: "schur" (trailing update of the frontal LU), "fwd_update",
- * "bwd_update", "diag" (diagonal-block products of the solves), "spmv". */
+ * "bwd_update" (diagonal-block products of the solves), "l21" and "u12" (the
+ * off-diagonal block products L21 y and U12 x of the solves), "spmv". */
 typedef struct {
     int64_t launches;      /* launches timed since mbl_profile_enable */
     double seconds;        /* sum of their durations */

@@ -442,13 +442,20 @@ template <> struct MfmaAcc<float> {
 };
 
 constexpr int ST = SCHUR_TILE;       // 128
-constexpr int SP = ST + 8;           // LDS row of A and B: 4 k-rows read by a wave land on
-                                     // different bank quarters
-// K columns staged per pass (FP64 half as many, to keep the prefetch and the
-// 64 accumulators of a lane inside the register budget of two waves per SIMD)
+// K columns staged per pass (FP64 half as many, to keep the prefetch, the two
+// operand sets and the 64 accumulators of a lane inside the register budget of
+// two waves per SIMD)
 template <class T> struct SchurCfg {
     static constexpr int KC = sizeof(T) == 8 ? 16 : 32;
     static constexpr int PF = ST * KC / 256;   // elements of A (and of B) per thread
+    // LDS layouts (64 banks of 4 bytes): A as [k][row] with rows padded to 144
+    // elements, so the four k-rows one operand read touches sit half the banks
+    // apart (FP64) or a quarter apart (FP32); B as [column][k], as it lies in
+    // the front, with an odd row length, so the 16 columns one read touches and
+    // the k-runs one stash writes fall on distinct banks
+    static constexpr int SPA = ST + 16;
+    static constexpr int SPB = KC + 1;
+    static constexpr int ABUF = KC * SPA, BBUF = ST * SPB;
 };
 
 // BIG = 0: update after panel t inside its outer SB block, K = the panel's kb
@@ -469,9 +476,11 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
                                                   TaskList tl, int t) {
     typedef typename MfmaAcc<T>::v4 v4;
     constexpr int KC = SchurCfg<T>::KC, PF = SchurCfg<T>::PF;
-    // two LDS buffers of the A and B chunks: the next chunk is stashed into the
-    // idle one right after the current one is consumed (one barrier per chunk)
-    __shared__ T smem[4 * KC * SP > 64 * (ST + 1) ? 4 * KC * SP : 64 * (ST + 1)];
+    constexpr int SPA = SchurCfg<T>::SPA, SPB = SchurCfg<T>::SPB;
+    constexpr int STAGE = SchurCfg<T>::ABUF + SchurCfg<T>::BBUF;
+    // two LDS stages of the A and B chunks: the next chunk is stashed into the
+    // idle one while the current one is consumed (one barrier per chunk)
+    __shared__ T smem[2 * STAGE];
     const int2 tk = tl.items[blockIdx.x];
     FrontDesc d = fd[tk.x];
     int64_t tile = tk.y;
@@ -497,77 +506,108 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
     int wr = (w & 1) * 64, wc = (w >> 1) * 64;
     int li = lane & 15, lk = lane >> 4;
     // global -> register prefetch of one K chunk: A rows i = e % ST (coalesced
-    // down the column), B rows k = e % KC (contiguous k of one column)
+    // down the column), B k = e % KC (contiguous k of one column).  Each load
+    // is a per-chunk uniform base plus one 32-bit per-lane offset.
+    const int tid = threadIdx.x;
+    const uint32_t aoff = (uint32_t)((tid % ST) + (tid / ST) * m) * (uint32_t)sizeof(T);
+    const uint32_t boff = (uint32_t)((tid % KC) + (tid / KC) * m) * (uint32_t)sizeof(T);
+    const bool rok = r0 + tid % ST < rhi;
     T pa[PF], pb[PF];
     auto fetch = [&](int kc) {
-        int kn = min(KC, kd - kc);
+        const int kn = min(KC, kd - kc);
+        const char *Ab = reinterpret_cast<const char *>(F + r0 + (int64_t)(kc0 + kc) * m);
+        const char *Bb = reinterpret_cast<const char *>(F + (kc0 + kc) + (int64_t)c0 * m);
 #pragma unroll
         for (int q = 0; q < PF; q++) {
-            int e = threadIdx.x + q * 256;
-            int i = e % ST, kk = e / ST, r = r0 + i;
-            pa[q] = (r < rhi && kk < kn) ? F[r + (int64_t)(kc0 + kc + kk) * m] : T(0);
-            int kb2 = e % KC, j = e / KC, c = c0 + j;
-            pb[q] = (c < chi && kb2 < kn) ? F[(int64_t)(kc0 + kc + kb2) + (int64_t)c * m] : T(0);
+            const int kk = tid / ST + q * (256 / ST), j = tid / KC + q * (256 / KC);
+            pa[q] = (rok && kk < kn)
+                        ? *reinterpret_cast<const T *>(Ab + (int64_t)q * (256 / ST) * m * sizeof(T) + aoff)
+                        : T(0);
+            pb[q] = (c0 + j < chi && tid % KC < kn)
+                        ? *reinterpret_cast<const T *>(Bb + (int64_t)q * (256 / KC) * m * sizeof(T) + boff)
+                        : T(0);
         }
     };
     auto stash = [&](int buf) {
-        T *As = smem + buf * 2 * KC * SP, *Bs = As + KC * SP;
+        T *As = smem + buf * STAGE, *Bs = As + SchurCfg<T>::ABUF;
 #pragma unroll
         for (int q = 0; q < PF; q++) {
-            int e = threadIdx.x + q * 256;
-            As[(e / ST) * SP + (e % ST)] = pa[q];
-            Bs[(e % KC) * SP + (e / KC)] = pb[q];
+            int e = tid + q * 256;
+            As[(e / ST) * SPA + (e % ST)] = -pa[q];
+            Bs[(e / KC) * SPB + (e % KC)] = pb[q];
         }
     };
+    // operands of one 4-deep k-step: A rows wr + 16 a + li, B columns
+    // wc + 16 b + li, k = 4 ks + lk
+    auto operands = [&](int buf, int ks, T (&av)[4], T (&bv)[4]) {
+        const T *As = smem + buf * STAGE, *Bs = As + SchurCfg<T>::ABUF;
+        const int kk = ks * 4 + lk;
+#pragma unroll
+        for (int a = 0; a < 4; a++) av[a] = As[kk * SPA + wr + a * 16 + li];
+#pragma unroll
+        for (int b = 0; b < 4; b++) bv[b] = Bs[(wc + b * 16 + li) * SPB + kk];
+    };
+    // The accumulators start from the C tile itself and the A operand is
+    // stashed negated, so the matrix cores leave C - A B in registers: the
+    // tile is read once at the start (while the first chunk is in flight) and
+    // only written at the end.  Lane (li, lk) holds rows
+    // wr + 16 a + row_of(lk, v) and columns wc + 16 b + li.
     v4 acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; a++)
-#pragma unroll
-        for (int b = 0; b < 4; b++) acc[a][b] = v4{0, 0, 0, 0};
     fetch(0);
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+        const int c = c0 + wc + b * 16 + li;
+        const T *Fc = F + (int64_t)min(c, chi - 1) * m;
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int r = r0 + wr + a * 16 + MfmaAcc<T>::row_of(lk, v);
+                acc[a][b][v] = (r < rhi && c < chi) ? Fc[r] : T(0);
+            }
+    }
+    auto mma = [&](const T (&av)[4], const T (&bv)[4]) {
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int b = 0; b < 4; b++) acc[a][b] = MfmaAcc<T>::mma(av[a], bv[b], acc[a][b]);
+    };
     stash(0);
     __syncthreads();
+    if (KC < kd) fetch(KC);
+    // Per chunk: the first operands are read, then the next chunk (in flight
+    // since the previous one) is stashed into the idle stage and the one after
+    // it fetched, while the reads land; inside the chunk the operands of
+    // k-step ks + 1 are read while the matrix cores work on k-step ks.
+    // A partial last chunk runs all KC / 4 k-steps: its missing k are zeros.
     for (int kc = 0, buf = 0; kc < kd; kc += KC, buf ^= 1) {
-        const T *As = smem + buf * 2 * KC * SP, *Bs = As + KC * SP;
-        const bool more = kc + KC < kd;
-        if (more) fetch(kc + KC);
-        int ksteps = (min(KC, kd - kc) + 3) / 4;
-        for (int ks = 0; ks < ksteps; ks++) {
-            int kk = ks * 4 + lk;
-            T av[4], bv[4];
-#pragma unroll
-            for (int a = 0; a < 4; a++) av[a] = As[kk * SP + wr + a * 16 + li];
-#pragma unroll
-            for (int b = 0; b < 4; b++) bv[b] = Bs[kk * SP + wc + b * 16 + li];
-#pragma unroll
-            for (int a = 0; a < 4; a++)
-#pragma unroll
-                for (int b = 0; b < 4; b++) acc[a][b] = MfmaAcc<T>::mma(av[a], bv[b], acc[a][b]);
+        T av0[4], bv0[4], av1[4], bv1[4];
+        operands(buf, 0, av0, bv0);
+        if (kc + KC < kd) {
+            stash(buf ^ 1);
+            if (kc + 2 * KC < kd) fetch(kc + 2 * KC);
         }
-        if (more) stash(buf ^ 1);
+#pragma unroll
+        for (int ks = 0; ks < KC / 4; ks += 2) {
+            operands(buf, ks + 1, av1, bv1);
+            mma(av0, bv0);
+            if (ks + 2 < KC / 4) operands(buf, ks + 2, av0, bv0);
+            mma(av1, bv1);
+        }
         __syncthreads();
     }
-    // write-back through LDS, one 64-column half of the tile at a time
-    T *Cs = smem;                    // Cs[col * (ST + 1) + row], col < 64
-    for (int half = 0; half < 2; half++) {
-        __syncthreads();
-        if ((w >> 1) == half) {
 #pragma unroll
-            for (int a = 0; a < 4; a++)
+    for (int b = 0; b < 4; b++) {
+        const int c = c0 + wc + b * 16 + li;
+        if (c >= chi) continue;
+        T *Fc = F + (int64_t)c * m;
 #pragma unroll
-                for (int b = 0; b < 4; b++)
+        for (int a = 0; a < 4; a++)
 #pragma unroll
-                    for (int v = 0; v < 4; v++) {
-                        int row = wr + a * 16 + MfmaAcc<T>::row_of(lk, v), col = b * 16 + li;
-                        Cs[col * (ST + 1) + row] = acc[a][b][v];
-                    }
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < ST * 64; e += blockDim.x) {
-            int row = e % ST, col = e / ST;
-            int r = r0 + row, c = c0 + half * 64 + col;
-            if (r < rhi && c < chi) F[r + (int64_t)c * m] -= Cs[col * (ST + 1) + row];
-        }
+            for (int v = 0; v < 4; v++) {
+                const int r = r0 + wr + a * 16 + MfmaAcc<T>::row_of(lk, v);
+                if (r < rhi) Fc[r] = acc[a][b][v];
+            }
     }
 }
 

@@ -387,6 +387,13 @@ void Context::ensure_symbolic(Plan &p) {
         tb.add(lv.u12red, ur, uri);
         tb.add(lv.l21, lt, lti);
         tb.add(lv.l21red, lr, lri);
+        for (int f : ut) {        // each streams its p x (m - p) block once
+            const FrontDesc &d = p.h_fd[f];
+            lv.u12.elems += (double)d.p * (d.m - d.p);
+            lv.u12.rows += d.m;
+            lv.l21.elems += (double)d.p * (d.m - d.p);
+            lv.l21.rows += d.m;
+        }
         lv.ext.assign(maxch, TaskList{});
         for (int s = 0; s < maxch; s++) {
             std::vector<int32_t> ch;
@@ -704,13 +711,19 @@ void Context::lu_apply_seq(Plan &p, Factor<T> &f, int nrhs, const double *b, int
         launch_fwd_gather(fd, p.d_perm.ptr<int32_t>(), f.prow.template ptr<int32_t>(),
                           p.d_inv_ptr.ptr<int32_t>(), isrc, lv.fgather, nrhs, b, ldb, vec, s);
         for (size_t t = 0; t < lv.fstep.size(); t++) step(lv.fstep[t], (int)t, true);
+        bool pr = prof_on("l21") && lv.l21.total > 0;
+        if (pr) prof_begin();
         launch_fwd_l21<T>(A, fd, lv.l21, nrhs, vec, part, s);
+        if (pr) prof_end(lv.l21.elems * sizeof(T) + 8.0 * nrhs * lv.l21.rows, 2.0 * nrhs * lv.l21.elems);
         launch_fwd_l21_reduce(fd, lv.l21red, nrhs, vec, part, s);
     }
     for (size_t l = p.levels.size(); l-- > 0;) {
         LevelTasks &lv = p.levels[l];
         launch_bwd_gather(fd, p.d_contrib.ptr<int32_t>(), lv.gather, nrhs, xnew, p.dim, vec, s);
+        bool pr = prof_on("u12") && lv.u12.total > 0;
+        if (pr) prof_begin();
         launch_bwd_u12<T>(A, fd, lv.u12, nrhs, vec, part, s);
+        if (pr) prof_end(lv.u12.elems * sizeof(T) + 8.0 * nrhs * lv.u12.rows, 2.0 * nrhs * lv.u12.elems);
         launch_bwd_u12_reduce(fd, lv.u12red, nrhs, yv, part, s);
         for (size_t t = lv.bstep.size(); t-- > 0;) step(lv.bstep[t], (int)t, false);
         launch_bwd_scatter(fd, p.d_perm.ptr<int32_t>(), lv.scatter, nrhs, vec, xnew, p.dim, x, ldx,
