@@ -73,9 +73,10 @@ void launch_trsm_u(T *arena, const FrontDesc *fd, const int32_t *ipiv, TaskList 
 template <class T>
 void launch_trsm_l(T *arena, const FrontDesc *fd, TaskList tl, int t, const double *uinv,
                    hipStream_t s);
-// inner (panel t, K = 64, inside its outer block) or outer-block (block t,
-// K = 256, everything right of and below it) trailing update
-// kind 0: inner update after panel t; 1: outer update of block t; 2 and 3: the
+// inner (panel t, K = 64, inside its outer block) or outer-block trailing
+// update; kind 0: inner update after panel t; 1: trailing update after outer
+// block t (even t: K = block t; odd t: K = blocks t - 1 and t); 5: after even
+// block t, block t's update of the strips of block t + 1 only; 2 and 3: the
 // two products that merge the factorization blocks 2t and 2t + 1 into solve
 // block t (rows below, then rows above; see k_merge_tri)
 template <class T>

@@ -462,8 +462,12 @@ template <class T> struct SchurCfg {
 //          columns: the first tiles cover the rows below the panel and the
 //          columns up to the end of the outer block, the rest the remaining
 //          rows of the outer block and every column right of it;
-// BIG = 1: update of outer block t, K = its (up to SB) columns, everything
-//          right of and below it (including the contribution block);
+// BIG = 1: trailing update (everything right of and below, including the
+//          contribution block) after outer block t: for even t, K = block t's
+//          (up to SB) columns; for odd t, K = blocks t - 1 and t together;
+// BIG = 5: after even outer block t whose successor exists, K = block t's SB
+//          columns applied only to the strips block t + 1 = [K1, K2) reads:
+//          rows [K1, m) x columns [K1, K2), then rows [K1, K2) x columns [K2, m);
 // BIG = 2, 3: merge of the inverted, folded blocks b1 = [a, a + SB) and
 //          b2 = [a + SB, e) (a = t SSB) into one solve block: with the folded
 //          panels L~ = L Linv and U~ = U Uinv, the rows below e need
@@ -492,7 +496,15 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
         if (tile < n0) { rlo = k1; rhi = m; clo = k1; chi = K1; }
         else { tile -= n0; rlo = k1; rhi = K1; clo = K1; chi = m; }
     } else if (BIG == 1) {
-        kc0 = t * SB; kd = min(SB, d.p - kc0); rlo = kc0 + kd; rhi = m; clo = rlo; chi = m;
+        kc0 = (t & 1) ? (t - 1) * SB : t * SB;
+        kd = min((t & 1) ? 2 * SB : SB, d.p - kc0);
+        rlo = kc0 + kd; rhi = m; clo = rlo; chi = m;
+    } else if (BIG == 5) {
+        kc0 = t * SB; kd = SB;
+        const int K1 = kc0 + SB, K2 = min(d.p, K1 + SB);
+        const int64_t n1 = (int64_t)((m - K1 + ST - 1) / ST) * ((K2 - K1 + ST - 1) / ST);
+        if (tile < n1) { rlo = K1; rhi = m; clo = K1; chi = K2; }
+        else { tile -= n1; rlo = K1; rhi = K2; clo = K2; chi = m; }
     } else {
         int a = t * SSB, e = min(d.p, a + SSB);
         if (BIG == 2) { kc0 = a + SB; kd = e - kc0; rlo = e; rhi = m; clo = a; chi = a + SB; }
@@ -844,7 +856,8 @@ void launch_schur(T *arena, const FrontDesc *fd, TaskList tl, int t, int kind, h
         case 0: k_schur<T, 0><<<g, b, 0, s>>>(arena, fd, tl, t); break;
         case 1: k_schur<T, 1><<<g, b, 0, s>>>(arena, fd, tl, t); break;
         case 2: k_schur<T, 2><<<g, b, 0, s>>>(arena, fd, tl, t); break;
-        default: k_schur<T, 3><<<g, b, 0, s>>>(arena, fd, tl, t); break;
+        case 3: k_schur<T, 3><<<g, b, 0, s>>>(arena, fd, tl, t); break;
+        default: k_schur<T, 5><<<g, b, 0, s>>>(arena, fd, tl, t); break;
     }
     MBL_CHECK_LAUNCH();
 }

@@ -439,23 +439,39 @@ void Context::ensure_symbolic(Plan &p) {
         }
         lv.outer.assign(maxsb, OuterTasks{});
         for (int T = 0; T < maxsb; T++) {
-            std::vector<int32_t> act;
-            std::vector<int64_t> sh;
+            std::vector<int32_t> act, sact;
+            std::vector<int64_t> sh, ss;
             for (int f : fl) {
                 const FrontDesc &d = p.h_fd[f];
                 int K0 = T * SB;
                 if (d.p <= K0) continue;
                 int K1 = std::min(d.p, K0 + SB);
+                if (T % 2 == 0 && d.p > K1) {         // successor exists: strips only
+                    int K2 = std::min(d.p, K1 + SB);
+                    sact.push_back(f);
+                    ss.push_back(cdiv64(d.m - K1, SCHUR_TILE) * cdiv64(K2 - K1, SCHUR_TILE) +
+                                 cdiv64(K2 - K1, SCHUR_TILE) * cdiv64(d.m - K2, SCHUR_TILE));
+                    continue;
+                }
                 act.push_back(f);
                 sh.push_back(cdiv64(d.m - K1, SCHUR_TILE) * cdiv64(d.m - K1, SCHUR_TILE));
             }
             OuterTasks &O = lv.outer[T];
             tb.add(O.schur, act, sh);
+            tb.add(O.strip, sact, ss);
             for (int f : act) {
                 const FrontDesc &d = p.h_fd[f];
-                double K0 = T * SB, kd = std::min(SB, d.p - T * SB), rest = d.m - K0 - kd;
+                double K0 = (T % 2 ? T - 1 : T) * SB, kd = std::min(d.p - K0, (T % 2 ? 2.0 : 1.0) * SB);
+                double rest = d.m - K0 - kd;
                 O.schur.flops += 2.0 * rest * rest * kd;
                 O.schur.elems += 2.0 * rest * rest + 2.0 * rest * kd;
+            }
+            for (int f : sact) {
+                const FrontDesc &d = p.h_fd[f];
+                double K1 = (T + 1.0) * SB, K2 = std::min<double>(d.p, K1 + SB), w = K2 - K1;
+                double area = (d.m - K1) * w + w * (d.m - K2);
+                O.strip.flops += 2.0 * area * SB;
+                O.strip.elems += 2.0 * area + SB * (2.0 * d.m - K1 - K2 + 2.0 * w);
             }
         }
         {
@@ -603,6 +619,7 @@ void Context::factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel, S
             bool last = ((int)t % (SB / FNB) == SB / FNB - 1) || t + 1 == lv.steps.size();
             if (last && ob < (int)lv.outer.size()) {
                 OuterTasks &O = lv.outer[ob];
+                launch_schur<T>(A, fd, O.strip, ob, 5, s);
                 bool pr = prof_on("schur") && O.schur.total > 0;
                 if (pr) prof_begin();
                 launch_schur<T>(A, fd, O.schur, ob, 1, s);

@@ -22,8 +22,12 @@ struct StepTasks {                    // one 64-wide panel of the blocked LU
     TaskList panel, trsm_u, rows_below, schur;
 };
 
+// Outer blocks are applied in pairs: after an even block t whose successor
+// exists, only the strips block t + 1 reads are updated (strip); after odd
+// block t + 1 the trailing matrix takes both blocks at once (schur, K = 2 SB).
+// A front whose last block is even takes that block alone (schur, K = SB).
 struct OuterTasks {                   // one 256-wide outer block
-    TaskList schur;
+    TaskList schur, strip;
 };
 
 struct LevelTasks {
