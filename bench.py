@@ -36,8 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # counters (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain copy
 # of known size); valid only for the kernel source it was measured on
 SCHUR_SRC = os.path.join(HERE, "paper_1411_0660_amd", "csrc", "k_front.hip")
-SCHUR_TRAFFIC = {"sha256": "5db1e7891f0a93edd3e0dd144d1cde33b5d8b32c9f7daf2aed345837478e009c",
-                 "bytes_per_launch": 1.858927e+10}
+SCHUR_TRAFFIC = {"sha256": "5532735567361259b5400b7174c280634f007990d162bd189e3658e5b8f8e01c",
+                 "bytes_per_launch": 2.447973e+10}
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
@@ -285,7 +285,7 @@ def main():
             out["roofline"] = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
                                "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
                                "traffic": schur_traffic() if L == 20 else None,
-                               "kernel": "k_schur<double, 1> (outer-block K=256 updates)",
+                               "kernel": "k_schur<double, 1> (outer-block trailing updates, K=512 per pair of blocks)",
                                "launches": prof["launches"],
                                "avg_launch_us": 1e6 * per_launch,
                                "flops_per_launch": prof["flops"] / prof["launches"],

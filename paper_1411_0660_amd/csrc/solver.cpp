@@ -656,7 +656,10 @@ template <class T>
 void Context::lu_apply(Plan &p, Factor<T> &f, int nrhs, const double *b, int64_t ldb, double *x,
                        int64_t ldx) {
     const int64_t n = p.dim;
-    if (!use_graphs_ || !prof.cls.empty() || ldb != n || ldx != n) {
+    // timing a class of the solve launches needs events between them: eager
+    const bool timed = prof_on("fwd_update") || prof_on("bwd_update") || prof_on("l21") ||
+                       prof_on("u12");
+    if (!use_graphs_ || timed || ldb != n || ldx != n) {
         lu_apply_seq<T>(p, f, nrhs, b, ldb, x, ldx);
         return;
     }
