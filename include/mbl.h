@@ -205,6 +205,52 @@ int mbl_profile_enable(mbl_ctx *ctx, const char *kernel_class);
 /* Synchronises the stream and returns the counters. */
 int mbl_profile_read(mbl_ctx *ctx, mbl_kernel_profile *out);
 
+/* ---- energy sweep of one realization, disorder averages ------------------
+ * The paper's protocol ("Numerical method" section): for each disorder
+ * realization the extremal energies are computed once and then the eigenpairs
+ * nearest every target of an energy-density grid (eps = 0.05, 0.1, ..., 0.95);
+ * observables are first averaged over the eigenstates of one realization (one
+ * bin per realization and target, since eigenstates of one sample are
+ * correlated) and then over realizations, with the standard error taken over
+ * the bins.  sigma_E, the standard deviation of the entanglement entropy, is
+ * the quantity the entanglement discussion of the paper follows across the
+ * transition. */
+#define MBL_NBIN 10
+enum {
+    MBL_BIN_R = 0,      /* mean of the finite gap ratios r_n (item (i)) */
+    MBL_BIN_S1 = 1,     /* mean participation entropy S_1 */
+    MBL_BIN_S2 = 2,     /* mean participation entropy S_2 */
+    MBL_BIN_SE = 3,     /* mean half-chain entanglement entropy S_E */
+    MBL_BIN_SE2 = 4,    /* mean of S_E^2 (for sigma_E) */
+    MBL_BIN_FLUCT = 5,  /* mean bipartite fluctuation F */
+    MBL_BIN_DYNFRAC = 6,/* mean dynamical spin fraction f */
+    MBL_BIN_KL = 7,     /* mean of the finite KL divergences of neighbours (NaN if none) */
+    MBL_BIN_EDENS = 8,  /* mean energy density (E - E_min) / (E_max - E_min) of the states */
+    MBL_BIN_NCONV = 9   /* converged pairs */
+};
+/* Solves the realization of `base` (L, J, h, seed or fields, nev, prec, tol,
+ * block, ncv, max_restarts; base->eps, base->sigma and MBL_WANT_VECTORS are
+ * ignored) at each eps[k], k < n_eps, reusing its fields, H, the symbolic
+ * analysis and E_min / E_max (computed once, by the first target), and writes
+ * that target's bin to bins[k * MBL_NBIN + q] (host, n_eps * MBL_NBIN doubles;
+ * NaN where a target failed) and its mbl status to status[k] (host, n_eps
+ * ints; MBL_ENOTCONV bins come from the partial results).  Each target's
+ * arithmetic is that of mbl_solve with the same problem, so its results are
+ * identical to a separate call.  Returns MBL_OK, the status of the first target
+ * that did not converge (the others are still solved), or an argument or device
+ * error (then later targets keep MBL_EBUSY: not attempted). */
+int mbl_sweep(mbl_ctx *ctx, const mbl_problem *base, const double *eps, int n_eps,
+              double *bins, int *status);
+/* Disorder average of one target's bins over n_real realizations
+ * (bins[i * MBL_NBIN + q], host): mean[q] over the realizations whose bin q is
+ * finite, sem[q] = sqrt(sum_i (b_i - mean)^2 / (k (k - 1))) over those k bins
+ * (NaN for k < 2), and, if sigma_e is not NULL, *sigma_e = the standard
+ * deviation of S_E over all eigenstates of all realizations (each realization
+ * weighted equally), sqrt(max(0, mean[SE2] - mean[SE]^2)).  Host arithmetic
+ * only; mean and sem are MBL_NBIN doubles. */
+int mbl_disorder_average(const double *bins, int n_real, double *mean, double *sem,
+                         double *sigma_e);
+
 /* ---- serving: continuous batching of solve requests ----------------------
  * The paper's workload is many independent solves (disorder realizations x
  * energy targets, "Numerical method" section).  Requests of mixed sizes are

@@ -309,3 +309,56 @@ def solve_targets(L: int, h: float, seed: int, eps_list, nev: int, J: float = 1.
             out["evecs"] = np.ascontiguousarray(Zt)
         outs.append(out)
     return outs
+
+
+# ---- the sweep protocol ("Numerical method" section): per-realization bins,
+# then averages over realizations with the standard error over the bins
+
+BIN_NAMES = ("r", "s1", "s2", "se", "se2", "fluct", "dynfrac", "kl", "edens", "nconv")
+
+
+def _finite_mean(values) -> float:
+    vals = [float(v) for v in values if math.isfinite(float(v))]
+    return sum(vals) / len(vals) if vals else math.nan
+
+
+def realization_bins(out: dict, nconv: int | None = None) -> np.ndarray:
+    """One realization's bin for one target: each observable averaged over the
+    nev eigenstates of that realization (the paper bins over the eigenstates
+    of a sample because they are correlated).  r and KL average their finite
+    values; edens is the mean of (E - E_min) / (E_max - E_min)."""
+    nev = len(out["evals"])
+    w = out["emax"] - out["emin"]
+    b = np.full(len(BIN_NAMES), math.nan)
+    b[0] = _finite_mean(out["r"]) if nev >= 3 else math.nan
+    b[1] = _finite_mean(out["s1"])
+    b[2] = _finite_mean(out["s2"])
+    b[3] = _finite_mean(out["se"])
+    b[4] = sum(float(x) * float(x) for x in out["se"]) / nev
+    b[5] = _finite_mean(out["fluct"])
+    b[6] = _finite_mean(out["dynfrac"])
+    b[7] = _finite_mean(out["kl"]) if nev >= 2 else math.nan
+    b[8] = sum(((float(E) - out["emin"]) / w if w > 0 else 0.0) for E in out["evals"]) / nev
+    b[9] = float(nev if nconv is None else nconv)
+    return b
+
+
+def disorder_average(bins) -> dict:
+    """Mean over realizations of each bin (finite bins only), the standard
+    error over those bins, sqrt(sum (b - mean)^2 / (k (k - 1))), and sigma_E,
+    the standard deviation of S_E over all eigenstates of all realizations:
+    sqrt(<S_E^2> - <S_E>^2) with each realization weighted equally."""
+    B = np.asarray(bins, dtype=np.float64).reshape(-1, len(BIN_NAMES))
+    mean = np.full(B.shape[1], math.nan)
+    sem = np.full(B.shape[1], math.nan)
+    for q in range(B.shape[1]):
+        col = [float(x) for x in B[:, q] if math.isfinite(float(x))]
+        k = len(col)
+        if k == 0:
+            continue
+        m = sum(col) / k
+        mean[q] = m
+        if k >= 2:
+            sem[q] = math.sqrt(sum((x - m) ** 2 for x in col) / (k * (k - 1)))
+    sig = math.sqrt(max(0.0, mean[4] - mean[3] * mean[3]))
+    return {"mean": mean, "sem": sem, "sigma_e": sig}

@@ -22,6 +22,8 @@ MBL_OK, MBL_EINVAL, MBL_ENOMEM, MBL_ENOTCONV = 0, -1, -2, -3
 MBL_ENUMERIC, MBL_EDEVICE, MBL_EBUSY, MBL_ENOTFOUND = -4, -5, -6, -7
 MBL_FP64, MBL_FP32_IR64 = 0, 1
 MBL_WANT_VECTORS, MBL_WANT_OBS, MBL_WANT_OBS_EXTRA = 1, 2, 4
+MBL_NBIN = 10
+BIN_NAMES = ("r", "s1", "s2", "se", "se2", "fluct", "dynfrac", "kl", "edens", "nconv")
 MBL_L_MAX = 22
 
 # every symbol include/mbl.h declares
@@ -30,7 +32,7 @@ EXPORTS = ("mbl_create", "mbl_destroy", "mbl_strerror", "mbl_last_error", "mbl_p
            "mbl_spmv", "mbl_extremal", "mbl_symbolic", "mbl_ordering", "mbl_shift_solve",
            "mbl_observables", "mbl_observables_extra", "mbl_solve", "mbl_footprint",
            "mbl_serve_start", "mbl_submit", "mbl_poll", "mbl_wait", "mbl_serve_stats",
-           "mbl_profile_enable", "mbl_profile_read")
+           "mbl_profile_enable", "mbl_profile_read", "mbl_sweep", "mbl_disorder_average")
 
 _d = ctypes.c_double
 _pd = ctypes.POINTER(ctypes.c_double)
@@ -124,6 +126,9 @@ def lib() -> ctypes.CDLL:
     L.mbl_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
     L.mbl_profile_enable.argtypes = [vp, ctypes.c_char_p]
     L.mbl_profile_read.argtypes = [vp, ctypes.POINTER(mbl_kernel_profile)]
+    L.mbl_sweep.argtypes = [vp, ctypes.POINTER(mbl_problem), _pd, ctypes.c_int, _pd,
+                            ctypes.POINTER(ctypes.c_int)]
+    L.mbl_disorder_average.argtypes = [_pd, ctypes.c_int, _pd, _pd, _pd]
     _lib = L
     return L
 
@@ -148,6 +153,16 @@ def _pd_of(a):
 # ------------------------------------------------------------------ functions
 def mbl_sector_dim(L: int) -> int:
     return int(lib().mbl_sector_dim(L))
+
+
+def mbl_disorder_average(bins) -> dict:
+    """Mean and standard error over realizations of one target's bins
+    (n_real x MBL_NBIN), and sigma_E; host arithmetic in the library."""
+    b = np.ascontiguousarray(bins, dtype=np.float64).reshape(-1, MBL_NBIN)
+    mean, sem, sig = np.zeros(MBL_NBIN), np.zeros(MBL_NBIN), ctypes.c_double(0.0)
+    _check(lib().mbl_disorder_average(_pd_of(b), b.shape[0], _pd_of(mean), _pd_of(sem),
+                                      ctypes.byref(sig)), "mbl_disorder_average")
+    return {"mean": mean, "sem": sem, "sigma_e": sig.value}
 
 
 def mbl_fields(L: int, h: float, seed: int) -> np.ndarray:
@@ -325,6 +340,22 @@ class Context:
         out = self._collect(res, bufs, nev, vectors)
         out["status"] = code
         return out
+
+    def mbl_sweep(self, L: int, h: float, seed: int, eps, nev: int, *, J: float = 1.0,
+                  prec: int = MBL_FP64, fields=None, tol: float = 0.0, block: int = 0,
+                  ncv: int = 0) -> dict:
+        """One realization at every target of `eps`: bins (n_eps x MBL_NBIN,
+        columns BIN_NAMES) and per-target status."""
+        e = np.ascontiguousarray(eps, dtype=np.float64).ravel()
+        pr, _res, _bufs, f = self._prepare(L, h, seed, float(e[0]) if e.size else 0.5, nev, J, prec,
+                                           fields, math.nan, tol, False, True, block, ncv, True)
+        bins = np.zeros((max(e.size, 1), MBL_NBIN))
+        status = (ctypes.c_int * max(e.size, 1))()
+        code = lib().mbl_sweep(self._h, ctypes.byref(pr), _pd_of(e), int(e.size), _pd_of(bins),
+                               status)
+        _check(code, "mbl_sweep", allow=(MBL_ENOTCONV, MBL_ENUMERIC))
+        return {"bins": bins[:e.size], "status": np.array(status[:e.size], dtype=np.int32),
+                "code": code, "fields": f}
 
     # -- serving (continuous batching)
     def mbl_serve_start(self, slots: int = 0, budget_bytes: int = 0):

@@ -361,6 +361,104 @@ int mbl_solve(mbl_ctx *ctx, const mbl_problem *prob, mbl_result *res) {
     });
 }
 
+namespace {
+// One realization's bin for one target: averages over its nev eigenstates
+// (the per-sample binning of the "Numerical method" section).
+void realization_bins(const mbl_result &r, int nev, const std::vector<double> &E,
+                      const std::vector<double> &rv, const std::vector<double> &s1,
+                      const std::vector<double> &s2, const std::vector<double> &se,
+                      const std::vector<double> &fl, const std::vector<double> &df,
+                      const std::vector<double> &kl, double *bin) {
+    auto mean = [](const std::vector<double> &v, size_t count) {
+        double sum = 0.0;
+        size_t k = 0;
+        for (size_t j = 0; j < count; j++)
+            if (std::isfinite(v[j])) { sum += v[j]; k++; }
+        return k ? sum / (double)k : NAN;
+    };
+    const size_t n = (size_t)nev;
+    bin[MBL_BIN_R] = nev >= 3 ? mean(rv, n - 2) : NAN;
+    bin[MBL_BIN_S1] = mean(s1, n);
+    bin[MBL_BIN_S2] = mean(s2, n);
+    bin[MBL_BIN_SE] = mean(se, n);
+    double q = 0.0;
+    for (size_t j = 0; j < n; j++) q += se[j] * se[j];
+    bin[MBL_BIN_SE2] = q / (double)n;
+    bin[MBL_BIN_FLUCT] = mean(fl, n);
+    bin[MBL_BIN_DYNFRAC] = mean(df, n);
+    bin[MBL_BIN_KL] = nev >= 2 ? mean(kl, n - 1) : NAN;
+    double w = r.emax - r.emin, ed = 0.0;
+    for (size_t j = 0; j < n; j++) ed += w > 0 ? (E[j] - r.emin) / w : 0.0;
+    bin[MBL_BIN_EDENS] = ed / (double)n;
+    bin[MBL_BIN_NCONV] = (double)r.nconv;
+}
+}  // namespace
+
+int mbl_sweep(mbl_ctx *ctx, const mbl_problem *base, const double *eps, int n_eps,
+              double *bins, int *status) {
+    if (!ctx || !base || !eps || !bins || !status || n_eps < 1) return MBL_EINVAL;
+    for (int k = 0; k < n_eps; k++)
+        if (!(eps[k] >= 0.0 && eps[k] <= 1.0)) return MBL_EINVAL;
+    for (int k = 0; k < n_eps; k++) status[k] = MBL_EBUSY;   // not reached yet
+    for (int k = 0; k < n_eps * MBL_NBIN; k++) bins[k] = NAN;
+    const int nev = base->nev;
+    if (nev < 1 || nev > 256) return MBL_EINVAL;
+    std::vector<double> E(nev), rv(std::max(1, nev - 2)), s1(nev), s2(nev), se(nev), fl(nev),
+        df(nev), kl(std::max(1, nev - 1)), rs(nev);
+    double ext[2] = {0.0, 0.0};
+    bool have_ext = false;
+    int first_err = MBL_OK;
+    for (int k = 0; k < n_eps; k++) {
+        mbl_problem pr = *base;
+        pr.eps = eps[k];
+        pr.sigma = NAN;
+        pr.flags = (base->flags | MBL_WANT_OBS | MBL_WANT_OBS_EXTRA) & ~MBL_WANT_VECTORS;
+        mbl_result res;
+        std::memset(&res, 0, sizeof res);
+        res.evals = E.data(); res.resid = rs.data(); res.r = rv.data(); res.s1 = s1.data();
+        res.se = se.data(); res.s2 = s2.data(); res.fluct = fl.data(); res.dynfrac = df.data();
+        res.kl = kl.data();
+        int code = guarded([&] {
+            std::lock_guard<std::recursive_mutex> lk(ctx->c->mu);
+            MBL_HIP(hipSetDevice(ctx->c->device));
+            solve_problem(*ctx->c, pr, res, have_ext ? ext : nullptr);
+        });
+        status[k] = code;
+        if (code == MBL_OK || code == MBL_ENOTCONV) {
+            if (!have_ext) { ext[0] = res.emin; ext[1] = res.emax; have_ext = true; }
+            realization_bins(res, nev, E, rv, s1, s2, se, fl, df, kl, bins + (size_t)k * MBL_NBIN);
+        }
+        if (code != MBL_OK && first_err == MBL_OK) first_err = code;
+        if (code != MBL_OK && code != MBL_ENOTCONV && code != MBL_ENUMERIC) return code;
+    }
+    return first_err;
+}
+
+int mbl_disorder_average(const double *bins, int n_real, double *mean, double *sem,
+                         double *sigma_e) {
+    if (!bins || n_real < 1 || !mean || !sem) return MBL_EINVAL;
+    for (int q = 0; q < MBL_NBIN; q++) {
+        double sum = 0.0;
+        int k = 0;
+        for (int i = 0; i < n_real; i++) {
+            double b = bins[(size_t)i * MBL_NBIN + q];
+            if (std::isfinite(b)) { sum += b; k++; }
+        }
+        double m = k ? sum / k : NAN, ss = 0.0;
+        for (int i = 0; i < n_real; i++) {
+            double b = bins[(size_t)i * MBL_NBIN + q];
+            if (std::isfinite(b)) ss += (b - m) * (b - m);
+        }
+        mean[q] = m;
+        sem[q] = k >= 2 ? std::sqrt(ss / ((double)k * (k - 1))) : NAN;
+    }
+    if (sigma_e) {
+        double v = mean[MBL_BIN_SE2] - mean[MBL_BIN_SE] * mean[MBL_BIN_SE];
+        *sigma_e = std::sqrt(std::max(0.0, v));
+    }
+    return MBL_OK;
+}
+
 int mbl_footprint(mbl_ctx *ctx, int L, int prec, int nev, int block, size_t *bytes) {
     if (!ctx || !bytes) return MBL_EINVAL;
     return guarded([&] {

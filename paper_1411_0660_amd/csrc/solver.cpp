@@ -1239,7 +1239,7 @@ namespace {
 int round_up(int a, int b) { return (a + b - 1) / b * b; }
 }
 
-void solve_problem(Context &ctx, const mbl_problem &pr, mbl_result &res) {
+void solve_problem(Context &ctx, const mbl_problem &pr, mbl_result &res, const double *extremal) {
     MBL_REQUIRE(pr.L >= 2 && pr.L <= MBL_L_MAX && pr.L % 2 == 0, MBL_EINVAL,
                 "L must be even with 2 <= L <= 22");
     int64_t n = binom(pr.L, pr.L / 2);
@@ -1260,7 +1260,8 @@ void solve_problem(Context &ctx, const mbl_problem &pr, mbl_result &res) {
     t0 = wall_seconds();
     double emin = 0, emax = 0;
     int nap = 0;
-    ctx.extremal(p, emin, emax, nap);
+    if (extremal) { emin = extremal[0]; emax = extremal[1]; }
+    else ctx.extremal(p, emin, emax, nap);
     double hnorm = std::max(std::fabs(emin), std::fabs(emax));
     if (hnorm == 0.0) hnorm = 1.0;
     ctx.hnorm_ = hnorm;

@@ -199,6 +199,9 @@ class Context {
 // dimension 1e5 (L = 20), 4 from 128 (L = 10), single vectors below.
 inline int default_block(int64_t n) { return n >= 100000 ? 8 : (n >= 128 ? 4 : 1); }
 
-void solve_problem(Context &ctx, const mbl_problem &prob, mbl_result &res);
+// extremal: optional {E_min, E_max} of this realization, computed earlier
+// (energy sweeps reuse them); nullptr computes them.
+void solve_problem(Context &ctx, const mbl_problem &prob, mbl_result &res,
+                   const double *extremal = nullptr);
 
 }  // namespace mbl

@@ -7,6 +7,7 @@ import re
 import subprocess
 
 import numpy as np
+import pytest
 
 import oracle
 import paper_1411_0660_amd as mbl
@@ -57,3 +58,19 @@ def test_problem_init_defaults():
     mbl.lib().mbl_problem_init(ctypes.byref(p))
     assert p.J == 1.0 and math.isnan(p.sigma) and p.prec == mbl.MBL_FP64
     assert p.flags & mbl.MBL_WANT_OBS
+
+
+def test_disorder_average_matches_oracle():
+    # host arithmetic of the library (no device work) against the oracle's
+    rng = np.random.default_rng(5)
+    B = rng.normal(size=(7, mbl.MBL_NBIN))
+    B[:, 4] = B[:, 3] ** 2 + rng.uniform(0.1, 1.0, size=7)
+    B[2, 0] = math.nan
+    B[5, 7] = math.inf
+    got = mbl.mbl_disorder_average(B)
+    ref = oracle.disorder_average(B)
+    assert np.allclose(got["mean"], ref["mean"], rtol=1e-14, atol=0, equal_nan=True)
+    assert np.allclose(got["sem"], ref["sem"], rtol=1e-13, atol=0, equal_nan=True)
+    assert got["sigma_e"] == pytest.approx(ref["sigma_e"], rel=1e-13)
+    with pytest.raises(mbl.MblError):
+        mbl.mbl_disorder_average(np.zeros((0, mbl.MBL_NBIN)))

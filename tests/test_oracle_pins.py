@@ -384,3 +384,52 @@ def test_residual_and_rayleigh_helpers():
     H = oracle.dense_H(L, 1.0, out["fields"])
     x = np.random.default_rng(0).standard_normal(H.shape[0])
     assert np.abs(oracle.apply_H(L, 1.0, out["fields"], x) - H @ x).max() < 1e-12
+
+
+def _fake_target(evals, emin, emax, r, s1, s2, se, fluct, dynfrac, kl):
+    return dict(evals=np.array(evals, float), emin=emin, emax=emax, r=np.array(r, float),
+                s1=np.array(s1, float), s2=np.array(s2, float), se=np.array(se, float),
+                fluct=np.array(fluct, float), dynfrac=np.array(dynfrac, float),
+                kl=np.array(kl, float))
+
+
+def test_realization_bins_hand_example():
+    # averages over the eigenstates of one sample ("Numerical method" section):
+    # r and KL average only their finite values; energy density (E - Emin)/(Emax - Emin)
+    out = _fake_target([-1.0, 0.0, 1.0], -2.0, 2.0, [0.4],
+                       [1.0, 2.0, 3.0], [0.5, 1.0, 1.5], [1.0, 2.0, 4.0], [0.1, 0.2, 0.3],
+                       [0.9, 0.6, 0.3], [math.inf, 1.0])
+    b = oracle.realization_bins(out)
+    assert b[0] == pytest.approx(0.4)
+    assert b[1] == pytest.approx(2.0) and b[2] == pytest.approx(1.0)
+    assert b[3] == pytest.approx(7.0 / 3.0)
+    assert b[4] == pytest.approx(21.0 / 3.0)               # (1 + 4 + 16) / 3
+    assert b[5] == pytest.approx(0.2) and b[6] == pytest.approx(0.6)
+    assert b[7] == pytest.approx(1.0)                      # the infinite KL is left out
+    assert b[8] == pytest.approx(0.5)                      # (0.25 + 0.5 + 0.75) / 3
+    assert b[9] == 3
+    out4 = _fake_target([-1.0, 0.0, 0.5, 1.0], -2.0, 2.0, [0.5, math.nan], [0] * 4, [0] * 4,
+                        [0] * 4, [0] * 4, [0] * 4, [0] * 3)
+    assert oracle.realization_bins(out4)[0] == pytest.approx(0.5)   # a NaN ratio is skipped
+
+
+def test_disorder_average_hand_example():
+    # two samples with S_E = {1, 3} and {3, 5}: pooled states {1, 3, 3, 5} have
+    # mean 3 and variance 2, so sigma_E = sqrt(2); r bins 1..4 -> SEM sqrt(5/12)
+    t1 = _fake_target([0.0, 1.0], 0.0, 1.0, [], [0, 0], [0, 0], [1.0, 3.0], [0, 0], [0, 0], [0.0])
+    t2 = _fake_target([0.0, 1.0], 0.0, 1.0, [], [0, 0], [0, 0], [3.0, 5.0], [0, 0], [0, 0], [0.0])
+    B = np.array([oracle.realization_bins(t1), oracle.realization_bins(t2)])
+    avg = oracle.disorder_average(B)
+    assert avg["mean"][3] == pytest.approx(3.0)
+    assert avg["sigma_e"] == pytest.approx(math.sqrt(2.0))
+    assert avg["sem"][3] == pytest.approx(1.0)             # bins 2 and 4: sqrt(2 / 2)
+    assert math.isnan(avg["mean"][0])                      # nev = 2: no gap ratio
+    R = np.zeros((4, len(oracle.BIN_NAMES)))
+    R[:, 0] = [1.0, 2.0, 3.0, 4.0]
+    R[2, 1] = math.nan                                     # a missing bin is skipped
+    avg = oracle.disorder_average(R)
+    assert avg["mean"][0] == pytest.approx(2.5)
+    assert avg["sem"][0] == pytest.approx(math.sqrt(5.0 / 12.0))
+    assert avg["mean"][1] == 0.0 and avg["sem"][1] == 0.0
+    one = oracle.disorder_average(R[:1])
+    assert math.isnan(one["sem"][0])                       # one sample: no error bar
