@@ -448,14 +448,21 @@ constexpr int ST = SCHUR_TILE;       // 128
 template <class T> struct SchurCfg {
     static constexpr int KC = sizeof(T) == 8 ? 16 : 32;
     static constexpr int PF = ST * KC / 256;   // elements of A (and of B) per thread
-    // LDS layouts (64 banks of 4 bytes): A as [k][row] with rows padded to 144
+    // LDS layouts (64 banks of 4 bytes).  A as [k][row], rows padded to 144
     // elements, so the four k-rows one operand read touches sit half the banks
-    // apart (FP64) or a quarter apart (FP32); B as [column][k], as it lies in
-    // the front, with an odd row length, so the 16 columns one read touches and
-    // the k-runs one stash writes fall on distinct banks
+    // apart (FP64) or a quarter apart (FP32).  B as [column][k], as it lies in
+    // the front: FP64 unpadded, the 16-byte k-pairs of column c stored at pair
+    // slot (k / 2) xor ((c / 2) mod 8), so the 16 columns one operand read
+    // touches fall on distinct banks and each 1 KB run of 8 columns can be
+    // filled by one direct global-to-LDS load per wave; FP32 with an odd row
+    // length (33) for the same effect.
+    static constexpr bool SWZ = sizeof(T) == 8;
     static constexpr int SPA = ST + 16;
-    static constexpr int SPB = KC + 1;
+    static constexpr int SPB = SWZ ? KC : KC + 1;
     static constexpr int ABUF = KC * SPA, BBUF = ST * SPB;
+    static __device__ __forceinline__ int bpos(int c, int k) {
+        return SWZ ? c * SPB + ((((k >> 1) ^ ((c >> 1) & 7))) << 1) + (k & 1) : c * SPB + k;
+    }
 };
 
 // BIG = 0: update after panel t inside its outer SB block, K = the panel's kb
@@ -545,60 +552,75 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
 #pragma unroll
         for (int q = 0; q < PF; q++) {
             int e = tid + q * 256;
-            As[(e / ST) * SPA + (e % ST)] = -pa[q];
-            Bs[(e / KC) * SPB + (e % KC)] = pb[q];
+            As[(e / ST) * SPA + (e % ST)] = pa[q];
+            Bs[SchurCfg<T>::bpos(e / KC, e % KC)] = pb[q];
         }
     };
-    // operands of one 4-deep k-step: A rows wr + 16 a + li, B columns
-    // wc + 16 b + li, k = 4 ks + lk
+    // Interior FP64 tiles fill full chunks with direct global-to-LDS loads
+    // (16 bytes per lane, lane l at byte 16 l of the wave's 1 KB run): A one
+    // k-row of 128 rows per instruction, B 8 columns per instruction with the
+    // k-pair slots swizzled as above.  No registers and no stash.
+    auto issue = [&](int kc, int buf) {
+        T *As = smem + buf * STAGE, *Bs = As + SchurCfg<T>::ABUF;
+#pragma unroll
+        for (int i = 0; i < KC / 4; i++) {
+            const int k = w + 4 * i;
+            const T *src = F + r0 + 2 * lane + (int64_t)(kc0 + kc + k) * m;
+            __builtin_amdgcn_global_load_lds((const void *)src,
+                                             (__attribute__((address_space(3))) void *)(As + k * SPA),
+                                             16, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < ST / 32; i++) {
+            const int ib = w + 4 * i, c = ib * 8 + (lane >> 3), slot = lane & 7;
+            const int kp = slot ^ ((c >> 1) & 7);
+            const T *src = F + (kc0 + kc + 2 * kp) + (int64_t)(c0 + c) * m;
+            __builtin_amdgcn_global_load_lds((const void *)src,
+                                             (__attribute__((address_space(3))) void *)(Bs + ib * 8 * SPB),
+                                             16, 0, 0);
+        }
+    };
+    // operands of one 4-deep k-step: A rows wr + 16 a + li (negated: the tile
+    // computes C - A B), B columns wc + 16 b + li, k = 4 ks + lk
     auto operands = [&](int buf, int ks, T (&av)[4], T (&bv)[4]) {
         const T *As = smem + buf * STAGE, *Bs = As + SchurCfg<T>::ABUF;
         const int kk = ks * 4 + lk;
 #pragma unroll
-        for (int a = 0; a < 4; a++) av[a] = As[kk * SPA + wr + a * 16 + li];
+        for (int a = 0; a < 4; a++) av[a] = -As[kk * SPA + wr + a * 16 + li];
 #pragma unroll
-        for (int b = 0; b < 4; b++) bv[b] = Bs[(wc + b * 16 + li) * SPB + kk];
+        for (int b = 0; b < 4; b++) bv[b] = Bs[SchurCfg<T>::bpos(wc + b * 16 + li, kk)];
     };
-    // The accumulators start from the C tile itself and the A operand is
-    // stashed negated, so the matrix cores leave C - A B in registers: the
-    // tile is read once at the start (while the first chunk is in flight) and
-    // only written at the end.  Lane (li, lk) holds rows
-    // wr + 16 a + row_of(lk, v) and columns wc + 16 b + li.
+    // The accumulators start from the C tile itself and A enters negated, so
+    // the matrix cores leave C - A B in registers: the tile is read once at
+    // the start (while the first chunk is in flight) and only written at the
+    // end.  Lane (li, lk) holds rows wr + 16 a + row_of(lk, v) and columns
+    // wc + 16 b + li.
     v4 acc[4][4];
-    fetch(0);
+    auto load_c = [&]() {
 #pragma unroll
-    for (int b = 0; b < 4; b++) {
-        const int c = c0 + wc + b * 16 + li;
-        const T *Fc = F + (int64_t)min(c, chi - 1) * m;
+        for (int b = 0; b < 4; b++) {
+            const int c = c0 + wc + b * 16 + li;
+            const T *Fc = F + (int64_t)min(c, chi - 1) * m;
 #pragma unroll
-        for (int a = 0; a < 4; a++)
+            for (int a = 0; a < 4; a++)
 #pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const int r = r0 + wr + a * 16 + MfmaAcc<T>::row_of(lk, v);
-                acc[a][b][v] = (r < rhi && c < chi) ? Fc[r] : T(0);
-            }
-    }
+                for (int v = 0; v < 4; v++) {
+                    const int r = r0 + wr + a * 16 + MfmaAcc<T>::row_of(lk, v);
+                    acc[a][b][v] = (r < rhi && c < chi) ? Fc[r] : T(0);
+                }
+        }
+    };
     auto mma = [&](const T (&av)[4], const T (&bv)[4]) {
 #pragma unroll
         for (int a = 0; a < 4; a++)
 #pragma unroll
             for (int b = 0; b < 4; b++) acc[a][b] = MfmaAcc<T>::mma(av[a], bv[b], acc[a][b]);
     };
-    stash(0);
-    __syncthreads();
-    if (KC < kd) fetch(KC);
-    // Per chunk: the first operands are read, then the next chunk (in flight
-    // since the previous one) is stashed into the idle stage and the one after
-    // it fetched, while the reads land; inside the chunk the operands of
-    // k-step ks + 1 are read while the matrix cores work on k-step ks.
-    // A partial last chunk runs all KC / 4 k-steps: its missing k are zeros.
-    for (int kc = 0, buf = 0; kc < kd; kc += KC, buf ^= 1) {
+    // all KC / 4 k-steps of the chunk in `buf` (a partial chunk's missing k are
+    // zeros), the operands of k-step ks + 1 read while k-step ks runs
+    auto steps = [&](int buf) {
         T av0[4], bv0[4], av1[4], bv1[4];
         operands(buf, 0, av0, bv0);
-        if (kc + KC < kd) {
-            stash(buf ^ 1);
-            if (kc + 2 * KC < kd) fetch(kc + 2 * KC);
-        }
 #pragma unroll
         for (int ks = 0; ks < KC / 4; ks += 2) {
             operands(buf, ks + 1, av1, bv1);
@@ -606,7 +628,51 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
             if (ks + 2 < KC / 4) operands(buf, ks + 2, av0, bv0);
             mma(av1, bv1);
         }
+    };
+    const bool dma = SchurCfg<T>::SWZ && r0 + ST <= rhi && c0 + ST <= chi;
+    if (dma) {
+        const int nfull = kd / KC;
+        if (nfull > 0) issue(0, 0);
+        load_c();
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
+        for (int c = 0; c < nfull; c++) {
+            if (c + 1 < nfull) issue((c + 1) * KC, (c + 1) & 1);
+            steps(c & 1);
+            __builtin_amdgcn_s_waitcnt(0);       // the next chunk's direct loads
+            __syncthreads();
+        }
+        if (nfull * KC < kd) {                   // partial last chunk: masked loads
+            fetch(nfull * KC);
+            stash(nfull & 1);
+            __syncthreads();
+            steps(nfull & 1);
+        }
+    } else {
+        fetch(0);
+        load_c();
+        stash(0);
+        __syncthreads();
+        if (KC < kd) fetch(KC);
+        // Per chunk: the first operands are read, then the next chunk (in
+        // flight since the previous one) is stashed into the idle stage and
+        // the one after it fetched, while the reads land.
+        for (int kc = 0, buf = 0; kc < kd; kc += KC, buf ^= 1) {
+            T av0[4], bv0[4], av1[4], bv1[4];
+            operands(buf, 0, av0, bv0);
+            if (kc + KC < kd) {
+                stash(buf ^ 1);
+                if (kc + 2 * KC < kd) fetch(kc + 2 * KC);
+            }
+#pragma unroll
+            for (int ks = 0; ks < KC / 4; ks += 2) {
+                operands(buf, ks + 1, av1, bv1);
+                mma(av0, bv0);
+                if (ks + 2 < KC / 4) operands(buf, ks + 2, av0, bv0);
+                mma(av1, bv1);
+            }
+            __syncthreads();
+        }
     }
 #pragma unroll
     for (int b = 0; b < 4; b++) {
