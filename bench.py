@@ -36,8 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # counters (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain copy
 # of known size); valid only for the kernel source it was measured on
 SCHUR_SRC = os.path.join(HERE, "paper_1411_0660_amd", "csrc", "k_front.hip")
-SCHUR_TRAFFIC = {"sha256": "5532735567361259b5400b7174c280634f007990d162bd189e3658e5b8f8e01c",
-                 "bytes_per_launch": 2.447973e+10}
+SCHUR_TRAFFIC = {"sha256": "ede0f1f2f41d2d9cad8c0ac0a8a9dea22d45e3c22d89728905e183cb227fe4f0",
+                 "bytes_per_launch": 2.508754e+10}
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
