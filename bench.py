@@ -233,6 +233,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=1024)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--sweep-realizations", type=int, default=2)
+    ap.add_argument("--l19-steps", type=int, default=5)
     a = ap.parse_args()
     if a.copy_probe > 0:
         copy_probe(a.copy_probe)
@@ -325,6 +326,21 @@ def main():
                       "workload": "L=18, h=3, eps=0.5, nev=50, seeds 0..%d, FP64" % (a.l18_steps - 1),
                       "latency_ms": {"p50": 1e3 * percentile(lat3, 0.5),
                                      "p99": 1e3 * percentile(lat3, 0.99)}}
+    if a.l19_steps > 0:
+        # the paper's largest odd chain, S^z = +1/2 sector
+        log("L=19 steps")
+        info19 = ctx.mbl_symbolic(19)
+        run_steps(ctx, mbl, 19, [(1000, 3.0, 0.5)], mbl.MBL_FP64, nev)
+        t0 = time.perf_counter()
+        lat5, conv5, _ = run_steps(ctx, mbl, 19, [(s, 3.0, 0.5) for s in range(a.l19_steps)],
+                                   mbl.MBL_FP64, nev)
+        wall5 = time.perf_counter() - t0
+        out["L19"] = {"value": conv5 / wall5, "unit": "eigenpairs/s",
+                      "ms_per_step": 1e3 * wall5 / a.l19_steps, "dim": info19["dim"],
+                      "workload": "L=19 (S^z=1/2 sector), h=3, eps=0.5, nev=50, seeds 0..%d, FP64"
+                                  % (a.l19_steps - 1),
+                      "latency_ms": {"p50": 1e3 * percentile(lat5, 0.5),
+                                     "p99": 1e3 * percentile(lat5, 0.99)}}
     if a.sweep_realizations > 0:
         # the paper's protocol: per realization the full eps grid 0.05..0.95,
         # bins over each realization's eigenstates, averages over realizations

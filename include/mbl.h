@@ -5,7 +5,9 @@
  *     H = J sum_{i=1..L} S_i . S_{i+1} + sum_i h_i S^z_i ,   S_{L+1} = S_1,
  *
  * (Eq. (1) of Luitz, Laflorencie, Alet, "Many-body localization edge in the
- * random-field Heisenberg chain", 2014), restricted to the S^z = 0 sector.
+ * random-field Heisenberg chain", 2014), restricted to the S^z = 0 sector for
+ * even L and to the S^z = +1/2 sector for odd L (the paper's odd sizes; the
+ * smallest |S^z| an odd chain has).
  * For one disorder realization (L, h, seed) and an energy-density target eps
  * it computes the nev eigenpairs nearest sigma = E_min + eps (E_max - E_min)
  * with a sparse LU of (H - sigma) driving a Krylov method on (H - sigma)^-1,
@@ -17,9 +19,11 @@
  *     else crosses the ABI on failure (no exceptions).  mbl_strerror() names a
  *     code; mbl_last_error() gives a message for the last failure on the
  *     calling thread.
- *   - Basis order: the S^z = 0 sector is the set of L-bit words with L/2 bits
- *     set, in ascending integer order; bit i is site i+1, bit set = spin up.
- *     Every vector of length dim = C(L, L/2) is in this order.
+ *   - Basis order: the sector is the set of L-bit words with nup = (L + 1) / 2
+ *     bits set (integer division: L/2 for even L), in ascending integer
+ *     order; bit i is site i+1, bit set = spin up.  Every vector of length
+ *     dim = C(L, nup) is in this order.  The half chain A of the observables is
+ *     sites 1..L/2 (integer division: the low L/2 bits).
  *   - Fields: h_i = h (2 u_i - 1), u_i = (z_i >> 11) 2^-53 where z_i is the
  *     i-th output of SplitMix64 (Steele, Lea, Flood 2014) started from state
  *     = seed (uniform distribution on [-h, h], the sentence after Eq. (1)).
@@ -44,7 +48,7 @@ extern "C" {
 
 /* ---- status codes -------------------------------------------------------- */
 #define MBL_OK        0
-#define MBL_EINVAL   -1   /* bad argument: odd or out-of-range L, nev > dim, eps not in [0,1], NULL */
+#define MBL_EINVAL   -1   /* bad argument: L out of range, nev > dim, eps not in [0,1], NULL */
 #define MBL_ENOMEM   -2   /* device allocation failed or footprint above the context budget */
 #define MBL_ENOTCONV -3   /* fewer than nev pairs reached the tolerance; partial results are valid */
 #define MBL_ENUMERIC -4   /* shifted solve could not be refined to the target backward error */
@@ -52,7 +56,7 @@ extern "C" {
 #define MBL_EBUSY    -6   /* request queue full */
 #define MBL_ENOTFOUND -7  /* unknown ticket */
 
-#define MBL_L_MAX 22      /* largest even L with a 32-bit sector word and int32 indices */
+#define MBL_L_MAX 22      /* largest L with a 32-bit sector word and int32 indices */
 
 /* ---- precision of the sparse LU ------------------------------------------ */
 typedef enum {
@@ -67,7 +71,7 @@ typedef enum {
 
 /* One shift-invert eigenproblem (section "Numerical method"). */
 typedef struct {
-    int L;                 /* even, 2 <= L <= MBL_L_MAX */
+    int L;                 /* 2 <= L <= MBL_L_MAX; odd L: the S^z = +1/2 sector */
     double J;              /* exchange coupling (1.0 in the paper's model); 0 allowed */
     double h;              /* disorder strength: h_i uniform in [-h, h] */
     uint64_t seed;         /* SplitMix64 seed of the fields */
@@ -145,7 +149,7 @@ const char *mbl_last_error(void);
 void mbl_problem_init(mbl_problem *p);   /* defaults: J = 1, sigma = NaN, prec FP64, MBL_WANT_OBS */
 
 /* ---- single steps (parity hooks; each runs the same kernels as mbl_solve) -- */
-int64_t mbl_sector_dim(int L);                                  /* C(L, L/2), or -1 */
+int64_t mbl_sector_dim(int L);                        /* C(L, (L + 1) / 2), or -1 out of range */
 int mbl_fields(int L, double h, uint64_t seed, double *out_host); /* SplitMix64 fields */
 /* Sector words in basis order, enumerated on the device. */
 int mbl_basis(mbl_ctx *ctx, int L, uint32_t *out_host);

@@ -112,12 +112,18 @@ def fields(L: int, h: float, seed: int) -> np.ndarray:
     return out
 
 
+def sector_nup(L: int) -> int:
+    """Up spins of the sector: L/2 (S^z = 0) for even L, (L+1)/2 (S^z = +1/2,
+    the smallest |S^z| of an odd chain) for odd L."""
+    return (L + 1) // 2
+
+
 def sector_dim(L: int, nup: int | None = None) -> int:
-    return math.comb(L, L // 2 if nup is None else nup)
+    return math.comb(L, sector_nup(L) if nup is None else nup)
 
 
 def basis(L: int, nup: int | None = None) -> np.ndarray:
-    nup = L // 2 if nup is None else nup
+    nup = sector_nup(L) if nup is None else nup
     out = np.zeros(sector_dim(L, nup), dtype=np.uint32)
     n = lib().orc_sector_basis(L, nup, _pu(out))
     assert n == out.size

@@ -30,7 +30,8 @@
  *     "Dynamical spin fraction").
  *
  * Conventions (readings where the paper is silent):
- *   - basis: all L-bit words with popcount L/2, ascending; bit i <-> site i+1,
+ *   - basis: all L-bit words with popcount (L+1)/2 (integer division: L/2,
+ *     the S^z = 0 sector, for even L; S^z = +1/2 for odd L), ascending; bit i <-> site i+1,
  *     bit set = spin up;
  *   - fields: SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) from state = seed,
  *     u = (z >> 11) * 2^-53, h_i = h (2u - 1), one draw per site in site order;

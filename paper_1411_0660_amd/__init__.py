@@ -298,7 +298,7 @@ class Context:
             pr.fields = _pd_of(f)
         pr.flags = MBL_WANT_OBS | (MBL_WANT_VECTORS if vectors else 0) | \
             (MBL_WANT_OBS_EXTRA if extra else 0)
-        n = mbl_sector_dim(L) if 2 <= L <= MBL_L_MAX and L % 2 == 0 else 1
+        n = mbl_sector_dim(L) if 2 <= L <= MBL_L_MAX else 1
         nb = max(nev, 1)
         bufs = dict(evals=np.zeros(nb), resid=np.zeros(nb), r=np.zeros(max(nev - 2, 1)),
                     s1=np.zeros(nb))

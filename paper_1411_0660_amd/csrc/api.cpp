@@ -44,8 +44,7 @@ int guarded(F &&f) {
 }
 
 void check_L(int L) {
-    MBL_REQUIRE(L >= 2 && L <= MBL_L_MAX && L % 2 == 0, MBL_EINVAL,
-                "L must be even with 2 <= L <= 22");
+    MBL_REQUIRE(L >= 2 && L <= MBL_L_MAX, MBL_EINVAL, "L must satisfy 2 <= L <= 22");
 }
 
 }  // namespace
@@ -106,8 +105,8 @@ int mbl_destroy(mbl_ctx *ctx) {
 }
 
 int64_t mbl_sector_dim(int L) {
-    if (L < 2 || L > MBL_L_MAX || L % 2) return -1;
-    return binom(L, L / 2);
+    if (L < 2 || L > MBL_L_MAX) return -1;
+    return binom(L, sector_nup(L));
 }
 
 int mbl_fields(int L, double h, uint64_t seed, double *out_host) {

@@ -131,6 +131,10 @@ inline void d2h(T *dst, const T *src, size_t n, hipStream_t s) {
 double wall_seconds();
 int debug_level();   // MBL_DEBUG environment variable (0 = quiet)
 
+// Up spins of the sector: L / 2 (S^z = 0) for even L, (L + 1) / 2
+// (S^z = +1/2) for odd L.
+inline int sector_nup(int L) { return (L + 1) / 2; }
+
 inline int64_t binom(int n, int k) {
     if (k < 0 || k > n) return 0;
     int64_t r = 1;

@@ -211,14 +211,14 @@ void launch_fields(int L, double h, uint64_t seed, double *out, hipStream_t s) {
 void launch_basis(int L, int64_t dim, uint32_t *basis, hipStream_t s) {
     ensure_binom();
     if (dim == 0) return;
-    hipLaunchKernelGGL(k_basis, dim3(grid_for(dim, 256)), dim3(256), 0, s, L, L / 2, dim, basis);
+    hipLaunchKernelGGL(k_basis, dim3(grid_for(dim, 256)), dim3(256), 0, s, L, sector_nup(L), dim, basis);
     MBL_CHECK_LAUNCH();
 }
 
 void launch_rank(int L, const uint32_t *words, int64_t count, int64_t *ranks, hipStream_t s) {
     ensure_binom();
     if (count == 0) return;
-    hipLaunchKernelGGL(k_rank, dim3(grid_for(count, 256)), dim3(256), 0, s, L, L / 2, words,
+    hipLaunchKernelGGL(k_rank, dim3(grid_for(count, 256)), dim3(256), 0, s, L, sector_nup(L), words,
                        count, ranks);
     MBL_CHECK_LAUNCH();
 }
@@ -247,7 +247,7 @@ void launch_row_ptr(int L, int64_t dim, const uint32_t *basis, int32_t *rowptr, 
 void launch_fill_csr(int L, int64_t dim, const uint32_t *basis, const int32_t *rowptr,
                      int32_t *col, hipStream_t s) {
     ensure_binom();
-    hipLaunchKernelGGL(k_fill_csr, dim3(grid_for(dim, 256)), dim3(256), 0, s, L, L / 2, dim,
+    hipLaunchKernelGGL(k_fill_csr, dim3(grid_for(dim, 256)), dim3(256), 0, s, L, sector_nup(L), dim,
                        basis, rowptr, col);
     MBL_CHECK_LAUNCH();
 }

@@ -44,7 +44,9 @@ __device__ __forceinline__ int sub_rank(uint32_t w) {
     return r;
 }
 
-// destination of each sector state in the concatenated blocks (row a, col b, row-major)
+// destination of each sector state in the concatenated blocks (row a, col b,
+// row-major): block k holds the states with k up spins in A (the low la =
+// L / 2 bits b), C(L - la, nup - k) rows a by C(la, k) columns b
 __global__ void k_block_index(int L, int64_t dim, const uint32_t *basis, const int64_t *blockoff,
                               int32_t *dst) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -94,22 +96,30 @@ __device__ int sturm_count(int n, const double *d, const double *e2, double x, d
 }
 
 // one workgroup per (vector, block): entropy contribution of block k of vector v
-__global__ __launch_bounds__(SEB) void k_se_block(int la, int nvec, int64_t dim,
+// (rows a: the nup - k up spins of B among L - la sites; columns b: the k up
+// spins of A; square for even L, one site more on the B side for odd L)
+__global__ __launch_bounds__(SEB) void k_se_block(int L, int nup, int nvec, int64_t dim,
                                                   const int64_t *blockoff, const double *norms2,
                                                   const double *M,
                                                   double *scratch, int64_t scratch_stride,
                                                   double *part) {
     __shared__ double sh[SEB];
     __shared__ double dd[512], ee[512], e2[512], vv[512], pp[512];
+    const int la = L / 2, lb = L - la;
     int v = blockIdx.x / (la + 1), k = blockIdx.x % (la + 1);
     int d = (int)o_binom[la][k];
-    const double *Mk = M + (int64_t)v * dim + blockoff[k];   // d x d, row a, col b
+    int nr = (nup - k >= 0 && nup - k <= lb) ? (int)o_binom[lb][nup - k] : 0;
+    if (nr == 0 || d == 0) {                      // no state of the sector in this block
+        if (threadIdx.x == 0) part[blockIdx.x] = 0.0;
+        return;
+    }
+    const double *Mk = M + (int64_t)v * dim + blockoff[k];   // nr x d, row a, col b
     double *G = scratch + (int64_t)blockIdx.x * scratch_stride;  // d x d column-major
-    // Gram G = Mk^T Mk
+    // Gram G = Mk^T Mk (the reduced density matrix of A on this block)
     for (int e = threadIdx.x; e < d * d; e += SEB) {
         int i = e % d, j = e / d;
         double s = 0.0;
-        for (int a = 0; a < d; a++) s += Mk[(int64_t)a * d + i] * Mk[(int64_t)a * d + j];
+        for (int a = 0; a < nr; a++) s += Mk[(int64_t)a * d + i] * Mk[(int64_t)a * d + j];
         G[e] = s;
     }
     __syncthreads();
@@ -284,14 +294,15 @@ void ObsWork::prepare(int L_, const uint32_t *basis, int64_t dim_, int nvec_max,
     L = L_;
     dim = dim_;
     nvmax = nvec_max;
-    int la = L / 2;
+    const int la = L / 2, lb = L - la, nup = sector_nup(L);
     std::vector<int64_t> off(la + 2, 0);
     int64_t maxd = 0;
     for (int k = 0; k <= la; k++) {
-        int64_t d = binom(la, k);
-        off[k + 1] = off[k] + d * d;
+        int64_t d = binom(la, k), nr = (nup - k >= 0 && nup - k <= lb) ? binom(lb, nup - k) : 0;
+        off[k + 1] = off[k] + nr * d;
         maxd = std::max(maxd, d);
     }
+    MBL_REQUIRE(off[la + 1] == dim_, MBL_EINVAL, "entanglement blocks do not cover the sector");
     maxd_ = maxd;
     d_blockoff.alloc(sizeof(int64_t) * (la + 2), bud);
     h2d(d_blockoff.ptr<int64_t>(), off.data(), off.size(), s);
@@ -313,7 +324,7 @@ void ObsWork::entanglement(const double *psi, int64_t ldpsi, int nvec, const dou
                        d_dst.ptr<int32_t>(), psi, ldpsi, d_M.ptr<double>());
     MBL_CHECK_LAUNCH();
     MBL_REQUIRE(maxd_ <= 512, MBL_EINVAL, "entanglement: subsystem block above 512");
-    hipLaunchKernelGGL(k_se_block, dim3(nvec * (la + 1)), dim3(SEB), 0, s, la, nvec, dim,
+    hipLaunchKernelGGL(k_se_block, dim3(nvec * (la + 1)), dim3(SEB), 0, s, L, sector_nup(L), nvec, dim,
                        d_blockoff.ptr<int64_t>(), norms2, d_M.ptr<double>(), d_scratch.ptr<double>(),
                        (int64_t)(maxd_ * maxd_), d_part.ptr<double>());
     MBL_CHECK_LAUNCH();

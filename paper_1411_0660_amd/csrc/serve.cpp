@@ -199,8 +199,8 @@ void Server::dispatcher() {
             int code = MBL_OK;
             size_t fp = 0;
             try {
-                MBL_REQUIRE(prob.L >= 2 && prob.L <= MBL_L_MAX && prob.L % 2 == 0, MBL_EINVAL,
-                            "L must be even with 2 <= L <= 22");
+                MBL_REQUIRE(prob.L >= 2 && prob.L <= MBL_L_MAX, MBL_EINVAL,
+                            "L must satisfy 2 <= L <= 22");
                 std::lock_guard<std::recursive_mutex> g(owner_->mu);
                 Plan &p = owner_->plan(prob.L);
                 owner_->ensure_symbolic(p);

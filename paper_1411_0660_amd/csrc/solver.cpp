@@ -146,7 +146,7 @@ Plan &Context::plan(int L) {
     MBL_REQUIRE(owns_plans_, MBL_EINVAL, "plan for this L not prepared by the owning context");
     std::unique_ptr<Plan> p(new Plan);
     p->L = L;
-    p->dim = binom(L, L / 2);
+    p->dim = binom(L, sector_nup(L));
     int64_t n = p->dim;
     p->basis.alloc(sizeof(uint32_t) * n, &budget);
     launch_basis(L, n, p->basis.ptr<uint32_t>(), stream);
@@ -1240,9 +1240,8 @@ int round_up(int a, int b) { return (a + b - 1) / b * b; }
 }
 
 void solve_problem(Context &ctx, const mbl_problem &pr, mbl_result &res, const double *extremal) {
-    MBL_REQUIRE(pr.L >= 2 && pr.L <= MBL_L_MAX && pr.L % 2 == 0, MBL_EINVAL,
-                "L must be even with 2 <= L <= 22");
-    int64_t n = binom(pr.L, pr.L / 2);
+    MBL_REQUIRE(pr.L >= 2 && pr.L <= MBL_L_MAX, MBL_EINVAL, "L must satisfy 2 <= L <= 22");
+    int64_t n = binom(pr.L, sector_nup(pr.L));
     MBL_REQUIRE(pr.nev >= 1 && pr.nev <= n, MBL_EINVAL, "nev must satisfy 1 <= nev <= dim");
     MBL_REQUIRE(std::isfinite(pr.sigma) || (pr.eps >= 0.0 && pr.eps <= 1.0), MBL_EINVAL,
                 "eps must lie in [0, 1]");

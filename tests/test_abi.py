@@ -42,7 +42,8 @@ def test_library_is_gfx950_code_object():
 def test_sector_dim_and_errors():
     assert mbl.mbl_sector_dim(22) == 705432
     assert mbl.mbl_sector_dim(20) == 184756
-    assert mbl.mbl_sector_dim(3) == -1 and mbl.mbl_sector_dim(24) == -1
+    assert mbl.mbl_sector_dim(19) == 92378 and mbl.mbl_sector_dim(3) == 3   # S^z = +1/2
+    assert mbl.mbl_sector_dim(1) == -1 and mbl.mbl_sector_dim(24) == -1
     assert mbl.lib().mbl_strerror(mbl.MBL_EINVAL) == b"invalid argument"
 
 

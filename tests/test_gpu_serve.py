@@ -88,7 +88,7 @@ def test_errors_and_late_arrivals():
     with mbl.Context(0) as c:
         fp10 = c.mbl_footprint(10, mbl.MBL_FP64, 10)
         c.mbl_serve_start(2, fp10 * 3)
-        bad = c.mbl_submit(11, 1.0, 0, 0.5, 10)                 # odd L
+        bad = c.mbl_submit(1, 1.0, 0, 0.5, 10)                  # L below 2
         big = c.mbl_submit(16, 1.0, 0, 0.5, 10)                 # above the budget
         first = [c.mbl_submit(10, 2.0, s, 0.5, 10) for s in range(3)]
         time.sleep(0.01)

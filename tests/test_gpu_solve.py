@@ -141,7 +141,7 @@ def test_extra_observables_vs_oracle(ctx):
     assert np.abs(g["kl"] - o["kl"])[ksep].max() <= 1e-7
 
 
-@pytest.mark.parametrize("bad", [dict(L=11), dict(L=24), dict(nev=0), dict(nev=253), dict(eps=1.5)])
+@pytest.mark.parametrize("bad", [dict(L=1), dict(L=24), dict(nev=0), dict(nev=253), dict(eps=1.5)])
 def test_invalid_arguments(ctx, bad):
     args = dict(L=8, h=1.0, seed=0, eps=0.5, nev=5)
     args.update(bad)

@@ -86,4 +86,4 @@ def test_sweep_errors():
         with pytest.raises(mbl.MblError):
             c.mbl_sweep(10, 1.0, 0, [0.5, 1.5], 10)
         with pytest.raises(mbl.MblError):
-            c.mbl_sweep(11, 1.0, 0, [0.5], 10)
+            c.mbl_sweep(23, 1.0, 0, [0.5], 10)

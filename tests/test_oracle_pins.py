@@ -433,3 +433,69 @@ def test_disorder_average_hand_example():
     assert avg["mean"][1] == 0.0 and avg["sem"][1] == 0.0
     one = oracle.disorder_average(R[:1])
     assert math.isnan(one["sem"][0])                       # one sample: no error bar
+
+
+# ------------------------------------------- odd L: the S^z = +1/2 sector
+
+@pytest.mark.parametrize("L", [3, 5, 7, 9, 11, 13, 15])
+def test_odd_sector_dimension_and_order(L):
+    b = oracle.basis(L)
+    nup = (L + 1) // 2
+    assert oracle.sector_nup(L) == nup
+    assert b.size == math.comb(L, nup)
+    assert np.all(np.diff(b.astype(np.int64)) > 0)
+    assert all(bin(int(s)).count("1") == nup for s in b[:: max(1, b.size // 97)])
+
+
+def test_odd_sector_dimensions_of_the_paper_sizes():
+    # the paper's odd chains 15, 17, 19 (and 21): C(L, (L+1)/2)
+    assert [oracle.sector_dim(L) for L in (15, 17, 19, 21)] == [6435, 24310, 92378, 352716]
+
+
+@pytest.mark.parametrize("L", [3, 5, 7, 9])
+def test_odd_sector_block_equals_bruteforce(L):
+    f = oracle.fields(L, 2.0, 13)
+    Hf = _full_H(L, 1.0, f)
+    assert np.abs(Hf.imag).max() < 1e-14
+    Hf = Hf.real
+    b = oracle.basis(L)
+    Hs = oracle.dense_H(L, 1.0, f, b)
+    assert np.abs(Hf[np.ix_(b, b)] - Hs).max() < 1e-14
+    # the block is S^z = +1/2: <S^z_tot> = 1/2 on every basis state
+    assert all(bin(int(s)).count("1") - L / 2 == 0.5 for s in b)
+    wf = np.linalg.eigvalsh(Hf)
+    for lam in oracle.eigvalsh(Hs):
+        assert np.min(np.abs(wf - lam)) < 1e-12
+
+
+@pytest.mark.parametrize("L", [5, 7, 9, 11])
+@pytest.mark.parametrize("J", [1.0, 0.6])
+def test_odd_trace_closed_form(L, J):
+    # S^z = 1/2 on a ring of odd L: a bond is parallel with probability
+    # (L-1)/(2L), so each bond contributes -J/(4L) on average; site i is up in
+    # a fraction (L+1)/(2L) of the states, so sum_i h_i <S^z_i> = sum h / (2L)
+    f = oracle.fields(L, 2.5, 100 + L)
+    H = oracle.dense_H(L, J, f)
+    dim = math.comb(L, (L + 1) // 2)
+    tr = -J * dim / 4 + dim * np.sum(f) / (2 * L)
+    assert abs(np.trace(H) - tr) < 1e-10 * dim
+    assert abs(oracle.eigvalsh(H).sum() - tr) < 1e-9 * dim
+
+
+def test_odd_entanglement_vs_numpy_svd():
+    # A = sites 1..(L-1)/2 (low bits), B one site larger: rectangular blocks
+    L = 9
+    out = oracle.solve(L, 1.0, 4, 0.5, 4)
+    b = oracle.basis(L)
+    la = L // 2
+    for j in range(4):
+        M = np.zeros((2 ** (L - la), 2 ** la))
+        for k, s in enumerate(b):
+            M[int(s) >> la, int(s) & (2 ** la - 1)] = out["evecs"][k, j]
+        sv = np.linalg.svd(M, compute_uv=False) ** 2
+        sv = sv[sv > 0]
+        assert abs(-np.sum(sv * np.log(sv)) - out["se"][j]) < 1e-11
+        # S^z_A fluctuation: sites 1..la, B carries the extra half
+        p = out["evecs"][:, j] ** 2
+        sza = np.array([bin(int(s) & (2 ** la - 1)).count("1") - la / 2 for s in b])
+        assert abs(p @ sza ** 2 - (p @ sza) ** 2 - out["fluct"][j]) < 1e-12
