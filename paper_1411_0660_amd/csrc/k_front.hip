@@ -63,6 +63,27 @@ __global__ __launch_bounds__(256) void k_extend_add(T *arena, const FrontDesc *_
     for (int i = threadIdx.x; i < cc; i += blockDim.x) dst[map[i]] += src[i];
 }
 
+// max of v over the 64 lanes of a wave by DPP lane moves (quad swaps, row
+// mirrors, row broadcasts): a few cycles per step instead of an LDS round
+// trip; the result is valid in lane 63.  Lanes a row mask leaves out keep
+// their own value.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_step_max(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
+    const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
+    return fmax(v, __hiloint2double(hi2, lo2));
+}
+__device__ __forceinline__ double wave_max(double v) {
+    v = dpp_step_max<0xB1, 0xF>(v);     // quad_perm [1, 0, 3, 2]
+    v = dpp_step_max<0x4E, 0xF>(v);     // quad_perm [2, 3, 0, 1]
+    v = dpp_step_max<0x141, 0xF>(v);    // row_half_mirror
+    v = dpp_step_max<0x140, 0xF>(v);    // row_mirror: every lane of a row holds its max
+    v = dpp_step_max<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
+    v = dpp_step_max<0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // LU with partial pivoting of the kb x kb diagonal block of panel t (one
 // workgroup per front, block in LDS), plus U_tt^-1 for the L-column solves of
 // the rows below (stored once per front in uinv, FNB x FNB column major,
@@ -92,15 +113,12 @@ __global__ __launch_bounds__(256) void k_panel(T *arena, const FrontDesc *__rest
     const T th = (T)thresh;
     for (int j = 0; j < kb; j++) {
         if (g == 0) {
-            // pivot: argmax over rows i >= j of |D[i][j]| (lane = row), first on ties
-            T v = (c >= j && c < kb) ? fabs(D[c][j]) : T(-1);
-            int idx = c;
-            for (int off = 32; off > 0; off >>= 1) {
-                T ov = __shfl_xor(v, off);
-                int oi = __shfl_xor(idx, off);
-                if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-            }
-            const int r = idx;
+            // pivot: argmax over rows i >= j of |D[i][j]| (lane = row), first on
+            // ties: the wave maximum, then the lowest lane holding it
+            const double v = (c >= j && c < kb) ? (double)fabs(D[c][j]) : -1.0;
+            const double mx = __shfl(wave_max(v), 63);
+            const uint64_t hit = __ballot(v == mx);
+            const int r = __ffsll((unsigned long long)hit) - 1;
             if (r != j && c < kb) {                  // interchange rows j and r of column c
                 T x = D[j][c];
                 D[j][c] = D[r][c];
@@ -763,16 +781,20 @@ __global__ __launch_bounds__(256) void k_merge_tri(T *arena, const FrontDesc *__
 // inverse into the off-diagonal panel of its block column,
 //   L~[rows below block t, t] = L[., t] Linv_tt,   U~[rows above, t] = U[., t] Uinv_tt,
 // so that a solve step needs only v_t (not Xinv_tt v_t) to update the other
-// rows, and the diagonal product runs in the same launch.  Work item: 16 rows
-// of one panel; the rows are staged in LDS (in place is then safe), the
-// inverse streams through LDS in 8-row slabs.
-constexpr int XR = 16, XS = 8;
+// rows, and the diagonal product runs in the same launch.  Work item: XR = 64
+// rows of one panel times the (unit lower or upper) inverse, on the matrix
+// cores: wave w owns output columns 64 w .. 64 w + 63 (4 x 4 MFMA 16x16x4
+// blocks), K in chunks of XK through LDS.  In place is safe: a workgroup
+// reads all of its rows before it writes any, and no other workgroup touches
+// them.
+constexpr int XR = 64, XK = 8, XAP = XR + 16, XBP = SB + 16;
 
 template <class T>
-__global__ __launch_bounds__(SB) void k_xform(T *arena, const FrontDesc *__restrict__ fd,
+__global__ __launch_bounds__(256) void k_xform(T *arena, const FrontDesc *__restrict__ fd,
                                               TaskList tl) {
-    __shared__ double a[XR][SB];
-    __shared__ double xs[XS][SB];
+    typedef typename MfmaAcc<T>::v4 v4;
+    __shared__ T As[2][XK][XAP];     // A chunk: k-row, panel row
+    __shared__ T Bs[2][XK][XBP];     // inverse chunk: k-row, column
     const int2 tk = tl.items[blockIdx.x];
     FrontDesc d = fd[tk.x];
     int64_t w = tk.y;
@@ -787,43 +809,84 @@ __global__ __launch_bounds__(SB) void k_xform(T *arena, const FrontDesc *__restr
         if (w < nu) { side = 1; chunk = (int)w; break; }
         w -= nu;
     }
-    int t0 = t * SB, st = min(SB, d.p - t0), tend = t0 + st;
-    int r0 = side == 0 ? tend + chunk * XR : chunk * XR;
-    int rlim = side == 0 ? m : t0;
-    int nr = min(XR, rlim - r0);
+    const int t0 = t * SB, st = min(SB, d.p - t0), tend = t0 + st;
+    const int r0 = side == 0 ? tend + chunk * XR : chunk * XR;
+    const int rlim = side == 0 ? m : t0;
+    const int nr = min(XR, rlim - r0);
     T *F = arena + d.off;
-    for (int e = threadIdx.x; e < XR * SB; e += blockDim.x) {
-        int r = e % XR, j = e / XR;
-        a[r][j] = (r < nr && j < st) ? (double)F[(r0 + r) + (int64_t)(t0 + j) * m] : 0.0;
-    }
-    int j = threadIdx.x;
-    double acc[XR];
-#pragma unroll
-    for (int r = 0; r < XR; r++) acc[r] = 0.0;
     const T *X = F + t0 + (int64_t)t0 * m;          // the inverted diagonal block
-    for (int k0 = 0; k0 < st; k0 += XS) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < XS * SB; e += blockDim.x) {
-            int kk = e % XS, jj = e / XS, kr = k0 + kk;
-            double x = 0.0;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4, wc = wv * 64;
+    // staging of one K chunk: A 64 x XK (2 per thread), X XK x 256 (8 per thread)
+    T pa[XR * XK / 256], pb[XK * SB / 256];
+    auto fetch = [&](int kc) {
+#pragma unroll
+        for (int q = 0; q < XR * XK / 256; q++) {
+            const int e = tid + q * 256, i = e % XR, k = e / XR, kk = kc + k;
+            pa[q] = (i < nr && kk < st) ? F[(r0 + i) + (int64_t)(t0 + kk) * m] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < XK * SB / 256; q++) {
+            const int e = tid + q * 256, k = e % XK, jj = e / XK, kr = kc + k;
+            T x = T(0);
             if (kr < st && jj < st) {
-                if (side == 0) x = (kr > jj) ? (double)X[kr + (int64_t)jj * m] : (kr == jj ? 1.0 : 0.0);
-                else x = (kr <= jj) ? (double)X[kr + (int64_t)jj * m] : 0.0;
+                if (side == 0) x = (kr > jj) ? X[kr + (int64_t)jj * m] : (kr == jj ? T(1) : T(0));
+                else x = (kr <= jj) ? X[kr + (int64_t)jj * m] : T(0);
             }
-            xs[kk][jj] = x;
+            pb[q] = x;
         }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < XR * XK / 256; q++) {
+            const int e = tid + q * 256;
+            As[buf][e / XR][e % XR] = pa[q];
+        }
+#pragma unroll
+        for (int q = 0; q < XK * SB / 256; q++) {
+            const int e = tid + q * 256;
+            Bs[buf][e % XK][e / XK] = pb[q];
+        }
+    };
+    v4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+        for (int b = 0; b < 4; b++) acc[a][b] = v4{0, 0, 0, 0};
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int kc = 0, buf = 0; kc < st; kc += XK, buf ^= 1) {
+        if (kc + XK < st) fetch(kc + XK);
+#pragma unroll
+        for (int ks = 0; ks < XK / 4; ks++) {
+            const int kk = ks * 4 + lk;
+            T av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; a++) av[a] = As[buf][kk][a * 16 + li];
+#pragma unroll
+            for (int b = 0; b < 4; b++) bv[b] = Bs[buf][kk][wc + b * 16 + li];
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int b = 0; b < 4; b++) acc[a][b] = MfmaAcc<T>::mma(av[a], bv[b], acc[a][b]);
+        }
+        if (kc + XK < st) stash(buf ^ 1);
         __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < XS; kk++) {
-            double x = xs[kk][j];
-#pragma unroll
-            for (int r = 0; r < XR; r++) acc[r] += a[r][k0 + kk] * x;
-        }
     }
-    if (j < st)
 #pragma unroll
-        for (int r = 0; r < XR; r++)
-            if (r < nr) F[(r0 + r) + (int64_t)(t0 + j) * m] = (T)acc[r];
+    for (int b = 0; b < 4; b++) {
+        const int c = wc + b * 16 + li;
+        if (c >= st) continue;
+        T *Fc = F + (int64_t)(t0 + c) * m + r0;
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int r = a * 16 + MfmaAcc<T>::row_of(lk, v);
+                if (r < nr) Fc[r] = acc[a][b][v];
+            }
+    }
 }
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
@@ -902,7 +965,7 @@ void launch_invert_diag(T *arena, const FrontDesc *fd, const int32_t *ipiv, int3
 template <class T>
 void launch_xform(T *arena, const FrontDesc *fd, TaskList tl, hipStream_t s) {
     if (tl.total == 0) return;
-    hipLaunchKernelGGL(k_xform<T>, dim3((unsigned)tl.total), dim3(SB), 0, s, arena, fd, tl);
+    hipLaunchKernelGGL(k_xform<T>, dim3((unsigned)tl.total), dim3(256), 0, s, arena, fd, tl);
     MBL_CHECK_LAUNCH();
 }
 
