@@ -280,6 +280,19 @@ def main():
                                             "krylov", "observables", "total", "solves"])},
         "symbolic": {k: info[k] for k in ("n_fronts", "max_front", "nnz_factor", "flops_factor")},
     }
+    # whole-solve bound from the algorithmic work: the LU flops at the FP64
+    # matrix peak plus, per pass through the factors, nnz(L+U) 8-byte entries
+    # and 16 bytes per right-hand side and row at the HBM peak
+    passes = sum(r["n_passes"] for r in res) / len(res)
+    pass_rhs = sum(r["n_pass_rhs"] for r in res) / len(res)
+    t_lu = info["flops_factor"] / (FP64_PEAK_TFLOPS * 1e12)
+    t_sv = (passes * info["nnz_factor"] * 8.0 + pass_rhs * 16.0 * info["dim"]) / (HBM_PEAK_GBS * 1e9)
+    out["solve_roofline"] = {"lu_bound_ms": 1e3 * t_lu, "solves_bound_ms": 1e3 * t_sv,
+                             "bound_ms": 1e3 * (t_lu + t_sv), "measured_ms": out["ms_per_step"],
+                             "frac": 1e3 * (t_lu + t_sv) / out["ms_per_step"],
+                             "passes_per_solve": passes, "rhs_per_solve": pass_rhs,
+                             "measured_factor_ms": 1e3 * out["phases_s"]["factor"],
+                             "measured_solves_ms": 1e3 * out["phases_s"]["solves"]}
     if prof["launches"] > 0 and prof["seconds"] > 0:
         per_launch = prof["seconds"] / prof["launches"]
         if a.roofline_kernel == "schur":

@@ -106,6 +106,9 @@ typedef struct {
     int nconv;             /* pairs that met tol (== nev on success) */
     int n_restarts;        /* Krylov restarts */
     int n_opapply;         /* right-hand sides pushed through the shifted solve */
+    int n_passes;          /* passes through the LU factors (forward and backward sweep of a
+                              block of right-hand sides), refinement included */
+    int n_pass_rhs;        /* right-hand sides those passes carried in total */
     int ir_iters_max;      /* largest number of refinement sweeps of one solve */
     int n_perturbed;       /* pivots replaced by the static-pivot threshold */
     int fallback;          /* 0 none; 1 FP32 refinement stalled -> FP64 LU used */

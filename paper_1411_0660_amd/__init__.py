@@ -51,7 +51,8 @@ class mbl_result(ctypes.Structure):
                 ("se", _pd), ("s2", _pd), ("fluct", _pd), ("dynfrac", _pd), ("kl", _pd),
                 ("emin", _d), ("emax", _d), ("sigma", _d), ("hnorm", _d), ("r_mean", _d),
                 ("max_resid", _d), ("nconv", ctypes.c_int), ("n_restarts", ctypes.c_int),
-                ("n_opapply", ctypes.c_int), ("ir_iters_max", ctypes.c_int),
+                ("n_opapply", ctypes.c_int), ("n_passes", ctypes.c_int),
+                ("n_pass_rhs", ctypes.c_int), ("ir_iters_max", ctypes.c_int),
                 ("n_perturbed", ctypes.c_int), ("fallback", ctypes.c_int),
                 ("t_phase", _d * 8),
                 ("t_submit", _d), ("t_start", _d), ("t_done", _d)]
@@ -323,7 +324,7 @@ class Context:
         if vectors:
             out["evecs"] = out["evecs"].T.copy()      # dim x nev
         for k in ("emin", "emax", "sigma", "hnorm", "r_mean", "max_resid", "nconv", "n_restarts",
-                  "n_opapply", "ir_iters_max", "n_perturbed", "fallback", "t_submit", "t_start",
+                  "n_opapply", "n_passes", "n_pass_rhs", "ir_iters_max", "n_perturbed", "fallback", "t_submit", "t_start",
                   "t_done"):
             out[k] = getattr(res, k)
         out["t_phase"] = list(res.t_phase)

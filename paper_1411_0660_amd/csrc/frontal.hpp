@@ -16,6 +16,13 @@ constexpr int FNB = 64;
 // L11 and U11 are stored inverted after the factorisation.
 constexpr int SB = 4 * FNB;
 constexpr int SSB = 2 * SB;         // solve block: two factorization blocks merged
+// Rows of one work item of a solve step (k_solve_step): 64 / STEP_RW adjacent
+// columns per wave load, so small steps still spread over many workgroups.
+#ifndef MBL_STEP_RW
+#define MBL_STEP_RW 32
+#endif
+constexpr int STEP_RW = MBL_STEP_RW;
+static_assert(STEP_RW == 16 || STEP_RW == 32 || STEP_RW == 64, "rows per solve-step item");
 
 struct FrontDesc {
     int64_t off;      // first element of the dense m x m front (column-major) in the arena

@@ -17,9 +17,10 @@
 //     V[p:m] = x(contribution rows); Y -= U12 V[p:m]   (64 x 256 tiles, fixed-order sum)
 //     block t from the last:  V_t = Uinv_tt Y_t  and  Y[rows above] -= U~[., t] Y_t
 //     afterwards V[0:p] = x of the pivots.
-// Work items are 64 rows x one SSB block: the 8 or 16 waves of a workgroup
-// take an equal share of the columns each and are summed through LDS, which
-// keeps the dependent load chain of a lane short.
+// Work items of a step are STEP_RW rows x one SSB block (the off-diagonal
+// products: 64 rows x SB columns): the 8 or 16 waves of a workgroup take an
+// equal share of the columns each and are summed through LDS, which keeps the
+// dependent load chain of a lane short.
 #include <type_traits>
 
 #include "common.hpp"
@@ -78,72 +79,76 @@ __global__ __launch_bounds__(256) void k_fwd_gather(const FrontDesc *__restrict_
     for (int r = 0; r < NR; r++) o[(int64_t)r * d.m] = val[r];
 }
 
-// One 64-row work item of solve block t: out rows from M[rows, SSB block] and
-// the block's source values src (LDS):
+// One work item of solve block t: STEP_RW rows, out rows from M[rows, SSB
+// block] and the block's source values src (LDS):
 //   mode 0: out -= M src                            (panel update, in place)
 //   mode 1: out  = src_i + sum_{j<i} M_ij src_j     (unit-lower inverse block)
 //   mode 2: out  = sum_{j>=i} M_ij src_j            (upper inverse block)
-// lane = row, each wave an equal share of the columns, partial sums combined
-// in a fixed order through LDS.  The factor entries (and the rows updated in
-// place) are loaded before the source block is staged, so the two memory
-// round trips overlap.
+// Each wave takes an equal share of the columns; inside a wave, lane % STEP_RW
+// is the row and lane / STEP_RW one of 64 / STEP_RW interleaved column slices,
+// so one load brings 64 / STEP_RW adjacent column segments of STEP_RW rows.
+// The slices are summed by a butterfly over the wave and the waves in a fixed
+// order through LDS.  The factor entries (and the rows updated in place) are
+// loaded before the source block is staged, so the two memory round trips
+// overlap.
 template <class T, int NR, bool FWD>
 __global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_solve_step(
     const T *__restrict__ arena, const FrontDesc *__restrict__ fd, TaskList tl, int t,
     double *vec, double *yv) {
     constexpr int CG = StepCfg<NR>::CG, CW = StepCfg<NR>::CW;
     constexpr int HG = CG / 2;                       // partial sums: two phases of CG / 2
+    constexpr int R = STEP_RW, LS = 64 / R, CQ = CW / LS;
+    static_assert(CW % LS == 0, "columns per wave split over the slices");
     __shared__ double src[SSB][NR];
-    __shared__ double red[HG][RW][NR];
+    __shared__ double red[HG][R][NR];
     const int2 tk = tl.items[blockIdx.x];
     const FrontDesc d = fd[tk.x];
     const int w = tk.y;
     const int m = d.m, p = d.p, t0 = t * SSB, st = min(SSB, p - t0), tend = t0 + st;
-    const int nA = (st + RW - 1) / RW;
+    const int nA = (st + R - 1) / R;
     double *V = vec + d.voff;          // ld m
     double *Y = yv + d.yoff;           // ld p
     int mode, r0, nrows, rowoff = 0;
     double *out;
     int64_t ldo;
     if (w < nA) {                      // diagonal product
-        rowoff = w * RW;
+        rowoff = w * R;
         r0 = t0 + rowoff;
-        nrows = min(RW, st - rowoff);
+        nrows = min(R, st - rowoff);
         mode = FWD ? 1 : 2;
         out = FWD ? Y + r0 : V + r0;
         ldo = FWD ? p : m;
     } else if (FWD) {                  // pivot rows below the block (the contribution
-        r0 = tend + (w - nA) * RW;     // rows are updated once per level by k_fwd_l21)
-        nrows = min(RW, p - r0);
+        r0 = tend + (w - nA) * R;      // rows are updated once per level by k_fwd_l21)
+        nrows = min(R, p - r0);
         mode = 0;
         out = V + r0;
         ldo = m;
     } else {                           // pivot rows above the block
-        r0 = (w - nA) * RW;
-        nrows = min(RW, t0 - r0);
+        r0 = (w - nA) * R;
+        nrows = min(R, t0 - r0);
         mode = 0;
         out = Y + r0;
         ldo = p;
     }
-    const int lane = threadIdx.x % RW, wv = threadIdx.x / RW;
-    const int i = rowoff + lane;       // row inside the diagonal block (modes 1, 2)
-    int j0 = wv * CW, j1 = min(j0 + CW, st);
-    if (mode == 1) j1 = min(j1, i);
-    if (mode == 2) j0 = max(j0, i);
-    const bool rowok = lane < nrows;
-    double mv[CW];
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+    const int rl = lane % R, sl = lane / R;
+    const int i = rowoff + rl;         // row inside the diagonal block (modes 1, 2)
+    const bool rowok = rl < nrows;
+    double mv[CQ];
     {
-        const T *Mr = arena + d.off + r0 + lane + (int64_t)(t0 + wv * CW) * m;
+        const T *Mr = arena + d.off + r0 + rl + (int64_t)(t0 + wv * CW + sl) * m;
 #pragma unroll
-        for (int q = 0; q < CW; q++) {
-            int j = wv * CW + q;
-            mv[q] = (rowok && j >= j0 && j < j1) ? (double)Mr[(int64_t)q * m] : 0.0;
+        for (int q = 0; q < CQ; q++) {
+            const int j = wv * CW + q * LS + sl;
+            const bool ok = rowok && j < st && (mode == 0 || (mode == 1 ? j < i : j >= i));
+            mv[q] = ok ? (double)Mr[(int64_t)q * LS * m] : 0.0;
         }
     }
     double prev[NR];
-    if (mode == 0 && wv == 0 && rowok) {
+    if (mode == 0 && wv == 0 && sl == 0 && rowok) {
 #pragma unroll
-        for (int r = 0; r < NR; r++) prev[r] = out[lane + (int64_t)r * ldo];
+        for (int r = 0; r < NR; r++) prev[r] = out[rl + (int64_t)r * ldo];
     }
     {
         const double *S = FWD ? V + t0 : Y + t0;
@@ -158,29 +163,35 @@ __global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_solve_step(
 #pragma unroll
     for (int r = 0; r < NR; r++) acc[r] = 0.0;
 #pragma unroll
-    for (int q = 0; q < CW; q++) {
+    for (int q = 0; q < CQ; q++) {
         const double x = mv[q];
 #pragma unroll
-        for (int r = 0; r < NR; r++) acc[r] += x * src[wv * CW + q][r];
+        for (int r = 0; r < NR; r++) acc[r] += x * src[wv * CW + q * LS + sl][r];
+    }
+    // slices of a row: butterfly (every lane of the row ends with the same sum)
+#pragma unroll
+    for (int off = 32; off >= R; off >>= 1) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) acc[r] += __shfl_xor(acc[r], off);
     }
     // fixed-order sum over the waves: g + HG into g, then g = 0 .. HG-1
-    if (wv >= HG) {
+    if (wv >= HG && sl == 0) {
 #pragma unroll
-        for (int r = 0; r < NR; r++) red[wv - HG][lane][r] = acc[r];
+        for (int r = 0; r < NR; r++) red[wv - HG][rl][r] = acc[r];
     }
     __syncthreads();
-    if (wv < HG) {
+    if (wv < HG && sl == 0) {
 #pragma unroll
-        for (int r = 0; r < NR; r++) red[wv][lane][r] += acc[r];
+        for (int r = 0; r < NR; r++) red[wv][rl][r] += acc[r];
     }
     __syncthreads();
-    if (wv == 0 && rowok) {
+    if (wv == 0 && sl == 0 && rowok) {
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            double sum = red[0][lane][r];
+            double sum = red[0][rl][r];
 #pragma unroll
-            for (int g = 1; g < HG; g++) sum += red[g][lane][r];
-            double *o = out + lane + (int64_t)r * ldo;
+            for (int g = 1; g < HG; g++) sum += red[g][rl][r];
+            double *o = out + rl + (int64_t)r * ldo;
             if (mode == 0) *o = prev[r] - sum;
             else if (mode == 1) *o = src[i][r] + sum;
             else *o = sum;

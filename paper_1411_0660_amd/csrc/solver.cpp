@@ -490,10 +490,10 @@ void Context::ensure_symbolic(Plan &p) {
                 int t0 = st * SSB;
                 if (d.p <= t0) continue;
                 int tend = std::min(d.p, t0 + SSB);
-                int64_t na = cdiv64(tend - t0, 64);
+                int64_t na = cdiv64(tend - t0, STEP_RW);
                 act.push_back(f);
-                fi.push_back(na + cdiv64(d.p - tend, 64));
-                bi.push_back(na + cdiv64(t0, 64));
+                fi.push_back(na + cdiv64(d.p - tend, STEP_RW));
+                bi.push_back(na + cdiv64(t0, STEP_RW));
             }
             tb.add(lv.fstep[st], act, fi);
             tb.add(lv.bstep[st], act, bi);
@@ -656,6 +656,8 @@ template <class T>
 void Context::lu_apply(Plan &p, Factor<T> &f, int nrhs, const double *b, int64_t ldb, double *x,
                        int64_t ldx) {
     const int64_t n = p.dim;
+    lu_passes++;
+    lu_pass_rhs += nrhs;
     // timing a class of the solve launches needs events between them: eager
     const bool timed = prof_on("fwd_update") || prof_on("bwd_update") || prof_on("l21") ||
                        prof_on("u12");
@@ -1252,6 +1254,7 @@ void solve_problem(Context &ctx, const mbl_problem &pr, mbl_result &res, const d
     double t_start = wall_seconds(), t0 = t_start;
     std::memset(res.t_phase, 0, sizeof(res.t_phase));
 
+    const int64_t passes0 = ctx.lu_passes, pass_rhs0 = ctx.lu_pass_rhs;
     Plan &p = ctx.plan(pr.L);
     ctx.set_realization(p, pr.J, pr.fields, pr.h, pr.seed, pr.fields == nullptr);
     res.t_phase[0] = wall_seconds() - t0;
@@ -1334,6 +1337,8 @@ void solve_problem(Context &ctx, const mbl_problem &pr, mbl_result &res, const d
     res.t_phase[7] = st.t_solve;
     res.n_restarts = ks.restarts;
     res.n_opapply = ks.napply;
+    res.n_passes = (int)(ctx.lu_passes - passes0);
+    res.n_pass_rhs = (int)(ctx.lu_pass_rhs - pass_rhs0);
     res.ir_iters_max = st.ir_iters;
     res.n_perturbed = st.n_perturbed;
     res.fallback = fell_back ? 1 : 0;

@@ -156,6 +156,9 @@ class Context {
     DevBuf d_psi, d_psi2, d_hpsi, d_e, d_cpart, d_obs, d_r_out, d_se;
     double anorm_ = 1.0;               // ||H - sigma|| estimate of the current factor
     double hnorm_ = 1.0;
+    // passes of right-hand-side blocks through the factors, and the vectors
+    // they carried (forward plus backward sweep each), since creation
+    int64_t lu_passes = 0, lu_pass_rhs = 0;
 
   private:
     std::shared_ptr<PlanCache> plans_;

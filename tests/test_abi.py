@@ -75,3 +75,29 @@ def test_disorder_average_matches_oracle():
     assert got["sigma_e"] == pytest.approx(ref["sigma_e"], rel=1e-13)
     with pytest.raises(mbl.MblError):
         mbl.mbl_disorder_average(np.zeros((0, mbl.MBL_NBIN)))
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # every ctypes structure of the binding has the size and field offsets the
+    # C compiler gives the header's struct (a drifted binding reads shifted fields)
+    structs = [mbl.mbl_problem, mbl.mbl_result, mbl.mbl_symbolic_info, mbl.mbl_kernel_profile,
+               mbl.mbl_serve_info, mbl.mbl_solve_info]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mbl.h"', 'int main(void) {']
+    for S in structs:
+        n = S.__name__
+        lines.append(f'printf("{n} size %zu\\n", sizeof({n}));')
+        for f, _ in S._fields_:
+            lines.append(f'printf("{n} {f} %zu\\n", offsetof({n}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    want = []
+    for S in structs:
+        n = S.__name__
+        want.append(f"{n} size {ctypes.sizeof(S)}")
+        want += [f"{n} {f} {getattr(S, f).offset}" for f, _ in S._fields_]
+    assert [g for g in got if g] == want
