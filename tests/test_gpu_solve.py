@@ -67,6 +67,10 @@ def test_solve_fp64_vs_oracle(ctx, L, h, seed, eps, nev):
     assert abs(g["emin"] - o["emin"]) <= 1e-12 * hn and abs(g["emax"] - o["emax"]) <= 1e-12 * hn
     assert abs(g["sigma"] - o["sigma"]) <= 1e-12 * hn
     compare(g, o, hn, nev, check_vectors=(g["evecs"], o["evecs"]))
+    # every right-hand side of the Krylov method goes through the factors at
+    # least once, in passes of at most 16 vectors (forward plus backward sweep)
+    assert g["n_pass_rhs"] >= g["n_opapply"] > 0
+    assert 16 * g["n_passes"] >= g["n_pass_rhs"] >= g["n_passes"]
 
 
 @pytest.mark.parametrize("L,h,seed,eps,nev", [(12, 3.0, 0, 0.5, 20), (12, 2.0, 7, 0.2, 40)])
