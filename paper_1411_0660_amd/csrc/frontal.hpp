@@ -35,7 +35,8 @@ struct FrontDesc {
     int32_t child0, nchild;  // children in FactorTables::child_ids[child0 .. child0 + nchild)
     int64_t poff;     // offset of the front's U12 partial products in the level scratch
     int32_t cptr_inv; // offset of the front's inverse relative map (m + 1 row pointers)
-    int32_t pad_;
+    int32_t pmoff;    // offset of the front's pull map: per child, per front row, the
+                      // child's update row landing there, or -1 (nchild blocks of m)
     int64_t yoff;     // first element of the front's forward-solution block (p x nrhs, ld p)
 };
 
@@ -59,17 +60,17 @@ struct FrontArgs {
 };
 
 // ---- factorisation ----------------------------------------------------------
+// every entry of the listed fronts from their children's update blocks (zero
+// where none contributes); one work item per front column
+constexpr int PULL_MAXCH = 8;       // children per front the pull assembly handles
 template <class T>
-void launch_front_zero(T *arena, int64_t lo, int64_t hi, hipStream_t s);
+void launch_front_pull(T *arena, const FrontDesc *fd, const int32_t *pullmap,
+                       const int32_t *child_ids, TaskList tl, hipStream_t s);
 // original entries: F[pos] += (src >= 0 ? diag[src] - sigma : offv)
 template <class T>
 void launch_front_assemble(T *arena, const FrontDesc *fd, int64_t count, const int32_t *efront,
                            const int32_t *epos, const int32_t *esrc, const double *diag,
                            double sigma, double offv, hipStream_t s);
-// parent += child contribution block, for one child per parent (list over children)
-template <class T>
-void launch_extend_add(T *arena, const FrontDesc *fd, const int32_t *relmap, TaskList tl,
-                       hipStream_t s);
 // step t of the blocked partial LU on every listed front
 template <class T>
 void launch_panel(T *arena, const FrontDesc *fd, int32_t *ipiv, int32_t *nperturbed, TaskList tl,

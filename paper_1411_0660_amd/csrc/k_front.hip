@@ -25,11 +25,64 @@
 namespace mbl {
 namespace {
 
+// Assembly of the fronts of one level from their children: every entry
+// F[i][j] = sum over children s whose update rows include both front rows i
+// and j of that child's updated entry (zero where no child contributes), so
+// each entry is written exactly once and the level needs no zero fill; the
+// original entries of H - sigma are added afterwards (k_front_assemble).  A
+// work item is one front column: the children that hold column j are found
+// once, then each lane sums its rows over them in child order.
 template <class T>
-__global__ void k_front_zero(T *a, int64_t lo, int64_t hi) {
-    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
-         i += (int64_t)gridDim.x * blockDim.x)
-        a[i] = T(0);
+__global__ __launch_bounds__(256) void k_front_pull(T *arena, const FrontDesc *__restrict__ fd,
+                                                    const int32_t *__restrict__ pullmap,
+                                                    const int32_t *__restrict__ child_ids,
+                                                    TaskList tl) {
+    __shared__ const T *colp[PULL_MAXCH];     // child column holding front column j
+    __shared__ const int32_t *rowm[PULL_MAXCH];
+    __shared__ int nsrc;
+    const int2 tk = tl.items[blockIdx.x];
+    const FrontDesc d = fd[tk.x];
+    const int j = tk.y, m = d.m;
+    if (threadIdx.x == 0) {
+        int n = 0;
+        for (int q = 0; q < d.nchild; q++) {
+            const int32_t *pm = pullmap + d.pmoff + (int64_t)q * m;
+            const int32_t cj = pm[j];
+            if (cj < 0) continue;
+            const FrontDesc c = fd[child_ids[d.child0 + q]];
+            colp[n] = arena + c.off + (int64_t)(c.p + cj) * c.m + c.p;
+            rowm[n] = pm;
+            n++;
+        }
+        nsrc = n;
+    }
+    __syncthreads();
+    const int ns = nsrc;
+    T *out = arena + d.off + (int64_t)j * m;
+    constexpr int U = 4;                      // rows per lane in flight
+    for (int i0 = threadIdx.x; i0 < m; i0 += U * blockDim.x) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) v[u] = T(0);
+        for (int q = 0; q < ns; q++) {
+            int32_t ci[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int i = i0 + u * blockDim.x;
+                ci[u] = i < m ? rowm[q][i] : -1;
+            }
+            T x[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) x[u] = ci[u] >= 0 ? colp[q][ci[u]] : T(0);
+#pragma unroll
+            for (int u = 0; u < U; u++) v[u] += x[u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int i = i0 + u * blockDim.x;
+            if (i < m) out[i] = v[u];
+        }
+    }
 }
 
 template <class T>
@@ -44,23 +97,6 @@ __global__ void k_front_assemble(T *arena, const FrontDesc *__restrict__ fd, int
     double v = (src >= 0) ? diag[src] - sigma : offv;
     T *F = arena + fd[efront[e]].off;
     F[epos[e]] += (T)v;
-}
-
-// one work item = one column of one child's contribution block
-template <class T>
-__global__ __launch_bounds__(256) void k_extend_add(T *arena, const FrontDesc *__restrict__ fd,
-                                                    const int32_t *__restrict__ relmap,
-                                                    TaskList tl) {
-    const int2 tk = tl.items[blockIdx.x];
-    int ch = tk.x;
-    int j = tk.y;
-    FrontDesc c = fd[ch];
-    FrontDesc P = fd[c.parent];
-    const int32_t *map = relmap + c.mapoff;
-    int cc = c.m - c.p;
-    const T *src = arena + c.off + (int64_t)(c.p + j) * c.m + c.p;
-    T *dst = arena + P.off + (int64_t)map[j] * P.m;
-    for (int i = threadIdx.x; i < cc; i += blockDim.x) dst[map[i]] += src[i];
 }
 
 // max of v over the 64 lanes of a wave by DPP lane moves (quad swaps, row
@@ -908,12 +944,11 @@ int64_t schur_tiles(int64_t rest) {
 }
 
 template <class T>
-void launch_front_zero(T *arena, int64_t lo, int64_t hi, hipStream_t s) {
-    if (hi <= lo) return;
-    int64_t n = hi - lo;
-    unsigned g = cdiv(n, 256 * 8);
-    if (g > 16384) g = 16384;
-    hipLaunchKernelGGL(k_front_zero<T>, dim3(g), dim3(256), 0, s, arena, lo, hi);
+void launch_front_pull(T *arena, const FrontDesc *fd, const int32_t *pullmap,
+                       const int32_t *child_ids, TaskList tl, hipStream_t s) {
+    if (tl.total == 0) return;
+    hipLaunchKernelGGL(k_front_pull<T>, dim3((unsigned)tl.total), dim3(256), 0, s, arena, fd,
+                       pullmap, child_ids, tl);
     MBL_CHECK_LAUNCH();
 }
 
@@ -924,15 +959,6 @@ void launch_front_assemble(T *arena, const FrontDesc *fd, int64_t count, const i
     if (count == 0) return;
     hipLaunchKernelGGL(k_front_assemble<T>, dim3(cdiv(count, 256)), dim3(256), 0, s, arena, fd,
                        count, efront, epos, esrc, diag, sigma, offv);
-    MBL_CHECK_LAUNCH();
-}
-
-template <class T>
-void launch_extend_add(T *arena, const FrontDesc *fd, const int32_t *relmap, TaskList tl,
-                       hipStream_t s) {
-    if (tl.total == 0) return;
-    hipLaunchKernelGGL(k_extend_add<T>, dim3((unsigned)tl.total), dim3(256), 0, s, arena, fd,
-                       relmap, tl);
     MBL_CHECK_LAUNCH();
 }
 
@@ -1009,12 +1035,11 @@ int merge_tri_items(int p) {
 
 
 #define MBL_INST_FRONT(T)                                                                       \
-    template void launch_front_zero<T>(T *, int64_t, int64_t, hipStream_t);                    \
+    template void launch_front_pull<T>(T *, const FrontDesc *, const int32_t *, const int32_t *, \
+                                       TaskList, hipStream_t);                                  \
     template void launch_front_assemble<T>(T *, const FrontDesc *, int64_t, const int32_t *,    \
                                            const int32_t *, const int32_t *, const double *,    \
                                            double, double, hipStream_t);                        \
-    template void launch_extend_add<T>(T *, const FrontDesc *, const int32_t *, TaskList,       \
-                                       hipStream_t);                                            \
     template void launch_panel<T>(T *, const FrontDesc *, int32_t *, int32_t *, TaskList, int,  \
                                   double, double *, hipStream_t);                               \
     template void launch_trsm_u<T>(T *, const FrontDesc *, const int32_t *, TaskList, int,      \

@@ -196,7 +196,6 @@ void Context::ensure_symbolic(Plan &p) {
     std::vector<int32_t> mp;
     for (int l = 0; l < t.n_levels; l++) {
         LevelTasks &lv = p.levels[l];
-        lv.zlo = off;
         lv.ebegin = (int64_t)efront.size();
         int64_t poff = 0;
         for (int f : bylev[l]) {
@@ -244,7 +243,6 @@ void Context::ensure_symbolic(Plan &p) {
                 }
             }
         }
-        lv.zhi = off;
         lv.ecount = (int64_t)efront.size() - lv.ebegin;
         lv.part_elems = poff;
         p.part_elems = std::max(p.part_elems, poff);
@@ -254,6 +252,25 @@ void Context::ensure_symbolic(Plan &p) {
         child_relative_map(t, f, mp);
         p.h_fd[f].mapoff = (int32_t)relmap.size();
         relmap.insert(relmap.end(), mp.begin(), mp.end());
+    }
+    // pull maps: for every front with children, per child and front row, the
+    // child's update row that lands on that row (or -1)
+    std::vector<int32_t> pullmap;
+    for (int f = 0; f < nf; f++) {
+        FrontDesc &d = p.h_fd[f];
+        MBL_REQUIRE(d.nchild <= PULL_MAXCH, MBL_EINVAL, "front with too many children");
+        d.pmoff = (int32_t)pullmap.size();
+        pullmap.resize(pullmap.size() + (size_t)d.nchild * d.m, -1);
+        for (int q = 0; q < d.nchild; q++) {
+            const FrontDesc &cd = p.h_fd[child_ids[d.child0 + q]];
+            int32_t *pm = pullmap.data() + d.pmoff + (int64_t)q * d.m;
+            for (int32_t k = 0; k < cd.m - cd.p; k++) {
+                const int32_t r = relmap[cd.mapoff + k];
+                MBL_REQUIRE(r >= 0 && r < d.m, MBL_EINVAL, "relative map entry outside the parent front");
+                pm[r] = k;
+            }
+        }
+        MBL_REQUIRE(pullmap.size() < (size_t)INT32_MAX, MBL_EINVAL, "pull maps too long");
     }
     p.arena_elems = off;
     p.vec_elems = voff;
@@ -359,7 +376,7 @@ void Context::ensure_symbolic(Plan &p) {
         std::vector<int64_t> one(fl.size(), 1), g, sc;
         std::vector<int32_t> ut, ur, lt, lr;
         std::vector<int64_t> uti, uri, lti, lri;
-        int maxch = 0, maxsteps = 0, maxsb = 0;
+        int maxsteps = 0, maxsb = 0;
         for (int f : fl) {
             const FrontDesc &d = p.h_fd[f];
             g.push_back(cdiv64(d.m - d.p, 256));
@@ -376,7 +393,6 @@ void Context::ensure_symbolic(Plan &p) {
                     lri.push_back(cdiv64(d.m - d.p, 256));
                 }
             }
-            maxch = std::max(maxch, d.nchild);
             maxsteps = std::max<int>(maxsteps, (int)cdiv64(d.p, FNB));
             maxsb = std::max<int>(maxsb, (int)cdiv64(d.p, SB));
         }
@@ -394,17 +410,10 @@ void Context::ensure_symbolic(Plan &p) {
             lv.l21.elems += (double)d.p * (d.m - d.p);
             lv.l21.rows += d.m;
         }
-        lv.ext.assign(maxch, TaskList{});
-        for (int s = 0; s < maxch; s++) {
-            std::vector<int32_t> ch;
+        {
             std::vector<int64_t> cols;
-            for (int f : fl)
-                if (p.h_fd[f].nchild > s) {
-                    int c = child_ids[p.h_fd[f].child0 + s];
-                    ch.push_back(c);
-                    cols.push_back(p.h_fd[c].m - p.h_fd[c].p);
-                }
-            tb.add(lv.ext[s], ch, cols);
+            for (int f : fl) cols.push_back(p.h_fd[f].m);
+            tb.add(lv.pull, fl, cols);
         }
         lv.steps.assign(maxsteps, StepTasks{});
         for (int st = 0; st < maxsteps; st++) {
@@ -515,8 +524,8 @@ void Context::ensure_symbolic(Plan &p) {
     h2d(p.d_perm.ptr<int32_t>(), t.perm.data(), p.dim, s);
     p.d_contrib.alloc(sizeof(int32_t) * std::max<size_t>(1, t.contrib.size()), &budget);
     h2d(p.d_contrib.ptr<int32_t>(), t.contrib.data(), t.contrib.size(), s);
-    p.d_relmap.alloc(sizeof(int32_t) * std::max<size_t>(1, relmap.size()), &budget);
-    h2d(p.d_relmap.ptr<int32_t>(), relmap.data(), relmap.size(), s);
+    p.d_pullmap.alloc(sizeof(int32_t) * std::max<size_t>(1, pullmap.size()), &budget);
+    h2d(p.d_pullmap.ptr<int32_t>(), pullmap.data(), pullmap.size(), s);
     p.d_child_ids.alloc(sizeof(int32_t) * std::max<size_t>(1, child_ids.size()), &budget);
     h2d(p.d_child_ids.ptr<int32_t>(), child_ids.data(), child_ids.size(), s);
     p.d_tfronts.alloc(sizeof(int32_t) * std::max<size_t>(1, tb.fr.size()), &budget);
@@ -601,12 +610,12 @@ void Context::factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel, S
     double thresh = thresh_rel * anorm_;
     for (size_t l = 0; l < p.levels.size(); l++) {
         LevelTasks &lv = p.levels[l];
-        launch_front_zero<T>(A, lv.zlo, lv.zhi, s);
+        launch_front_pull<T>(A, fd, p.d_pullmap.ptr<int32_t>(), p.d_child_ids.ptr<int32_t>(),
+                             lv.pull, s);
         launch_front_assemble<T>(A, fd, lv.ecount, p.d_efront.ptr<int32_t>() + lv.ebegin,
                                  p.d_epos.ptr<int32_t>() + lv.ebegin,
                                  p.d_esrc.ptr<int32_t>() + lv.ebegin, d_diag.ptr<double>(), sigma,
                                  offv, s);
-        for (TaskList &tl : lv.ext) launch_extend_add<T>(A, fd, p.d_relmap.ptr<int32_t>(), tl, s);
         for (size_t t = 0; t < lv.steps.size(); t++) {
             StepTasks &S = lv.steps[t];
             launch_panel<T>(A, fd, f.ipiv.template ptr<int32_t>(), f.npert.template ptr<int32_t>(),

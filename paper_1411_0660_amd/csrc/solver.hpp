@@ -31,11 +31,10 @@ struct OuterTasks {                   // one 256-wide outer block
 };
 
 struct LevelTasks {
-    int64_t zlo = 0, zhi = 0;          // arena range of the level's fronts
     int64_t ebegin = 0, ecount = 0;    // original entries of the level
     TaskList all;                      // every front, one item each
     TaskList gather, scatter;          // row chunks
-    std::vector<TaskList> ext;         // extend-add, one list per child slot
+    TaskList pull;                     // assembly from the children: one item per front column
     std::vector<StepTasks> steps;
     std::vector<OuterTasks> outer;
     // triangular solves, one list per SB-wide solve block
@@ -62,7 +61,7 @@ struct Plan {
     TaskList merge;                    // in-place triangular products of the merge
     int64_t y_elems = 0;               // forward-solution blocks (sum of p x 16)
     int64_t part_elems = 0;            // max over levels
-    DevBuf d_fd, d_perm, d_contrib, d_relmap, d_child_ids, d_tfronts, d_tprefix, d_titems;
+    DevBuf d_fd, d_perm, d_contrib, d_pullmap, d_child_ids, d_tfronts, d_tprefix, d_titems;
     DevBuf d_efront, d_epos, d_esrc, d_inv_ptr, d_inv_src;
 };
 
