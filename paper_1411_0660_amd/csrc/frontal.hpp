@@ -75,12 +75,11 @@ void launch_front_assemble(T *arena, const FrontDesc *fd, int64_t count, const i
 template <class T>
 void launch_panel(T *arena, const FrontDesc *fd, int32_t *ipiv, int32_t *nperturbed, TaskList tl,
                   int t, double thresh, double *uinv, hipStream_t s);
+// the U rows of panel t (and its row interchanges on the other columns) and
+// the L columns below it, in one launch
 template <class T>
-void launch_trsm_u(T *arena, const FrontDesc *fd, const int32_t *ipiv, TaskList tl, int t,
-                   hipStream_t s);
-template <class T>
-void launch_trsm_l(T *arena, const FrontDesc *fd, TaskList tl, int t, const double *uinv,
-                   hipStream_t s);
+void launch_trsm(T *arena, const FrontDesc *fd, const int32_t *ipiv, TaskList tu, TaskList tlo,
+                 int t, const double *uinv, hipStream_t s);
 // inner (panel t, K = 64, inside its outer block) or outer-block trailing
 // update; kind 0: inner update after panel t; 1: trailing update after outer
 // block t (even t: K = block t; odd t: K = blocks t - 1 and t); 5: after even
@@ -97,7 +96,7 @@ int merge_tri_items(int p);
 
 
 // tile sizes used by the work-item counts of the task lists
-constexpr int TRSM_U_COLS = 128;   // columns per work item of the U12 solve
+constexpr int TRSM_U_COLS = 256;   // columns per work item of the U12 solve
 constexpr int TRSM_L_ROWS = 64;    // rows per work item of the L21 solve
 constexpr int SCHUR_TILE = 128;    // square tile of the Schur update
 int64_t schur_tiles(int64_t rest);

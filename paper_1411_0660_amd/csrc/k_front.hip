@@ -229,12 +229,9 @@ __global__ __launch_bounds__(256) void k_panel(T *arena, const FrontDesc *__rest
 // panel t: the permuted block rows right of the panel solved with the unit
 // lower L_tt.  One thread per column.
 template <class T>
-__global__ __launch_bounds__(TRSM_U_COLS) void k_trsm_u(T *arena, const FrontDesc *__restrict__ fd,
-                                                        const int32_t *__restrict__ ipiv,
-                                                        TaskList tl, int t) {
-    __shared__ T Ls[FNB][FNB + 1];
-    __shared__ int src[FNB];
-    const int2 tk = tl.items[blockIdx.x];
+__device__ __forceinline__ void trsm_u_item(T *arena, const FrontDesc *__restrict__ fd,
+                                            const int32_t *__restrict__ ipiv, int2 tk, int t,
+                                            T (*Ls)[FNB + 1], int *src) {
     FrontDesc d = fd[tk.x];
     int chunk = tk.y;
     int k0 = t * FNB, kb = min(FNB, d.p - k0), k1 = k0 + kb, m = d.m;
@@ -436,13 +433,11 @@ __global__ __launch_bounds__(256) void k_invert_diag(T *arena, const FrontDesc *
 
 // L21 of panel t: every row below the panel times U_tt^-1 (computed once per
 // front by k_panel); each workgroup multiplies its 64 rows by the inverse.
+// As[k][i]: row i of the chunk, panel column k.
 template <class T>
-__global__ __launch_bounds__(256) void k_trsm_l(T *arena, const FrontDesc *__restrict__ fd,
-                                                TaskList tl, int t,
-                                                const double *__restrict__ uinv) {
-    __shared__ double Ui[FNB][FNB + 1];
-    __shared__ double As[FNB][FNB + 1];     // As[k][i]: row i of the chunk, panel column k
-    const int2 tk = tl.items[blockIdx.x];
+__device__ __forceinline__ void trsm_l_item(T *arena, const FrontDesc *__restrict__ fd, int2 tk,
+                                            int t, const double *__restrict__ uinv,
+                                            double (*Ui)[FNB + 1], double (*As)[FNB + 1]) {
     FrontDesc d = fd[tk.x];
     int chunk = tk.y;
     int k0 = t * FNB, kb = min(FNB, d.p - k0), k1 = k0 + kb, m = d.m;
@@ -468,6 +463,24 @@ __global__ __launch_bounds__(256) void k_trsm_l(T *arena, const FrontDesc *__res
 #pragma unroll
         for (int q = 0; q < 16; q++)
             if (jb + q < kb) F[(int64_t)(r0 + i) + (int64_t)(k0 + jb + q) * m] = (T)acc[q];
+}
+
+// The U-row and L-column solves of panel t in one launch (they are
+// independent once the panel is factored): the first tu.total workgroups take
+// U-row items, the rest L-column items.
+template <class T>
+__global__ __launch_bounds__(256) void k_trsm(T *arena, const FrontDesc *__restrict__ fd,
+                                              const int32_t *__restrict__ ipiv, TaskList tu,
+                                              TaskList tlo, int t,
+                                              const double *__restrict__ uinv) {
+    static_assert(TRSM_U_COLS == 256 && TRSM_L_ROWS == 64, "one thread per column / row quarter");
+    __shared__ double smem[2][FNB][FNB + 1];
+    __shared__ int src[FNB];
+    if ((int64_t)blockIdx.x < tu.total)
+        trsm_u_item<T>(arena, fd, ipiv, tu.items[blockIdx.x], t,
+                       reinterpret_cast<T (*)[FNB + 1]>(&smem[0][0][0]), src);
+    else
+        trsm_l_item<T>(arena, fd, tlo.items[blockIdx.x - tu.total], t, uinv, smem[0], smem[1]);
 }
 
 // trailing update F[k1:m, k1:m] -= F[k1:m, k0:k1] F[k0:k1, k1:m] on the matrix
@@ -971,11 +984,11 @@ void launch_panel(T *arena, const FrontDesc *fd, int32_t *ipiv, int32_t *npertur
 }
 
 template <class T>
-void launch_trsm_u(T *arena, const FrontDesc *fd, const int32_t *ipiv, TaskList tl, int t,
-                   hipStream_t s) {
-    if (tl.total == 0) return;
-    hipLaunchKernelGGL(k_trsm_u<T>, dim3((unsigned)tl.total), dim3(TRSM_U_COLS), 0, s, arena, fd,
-                       ipiv, tl, t);
+void launch_trsm(T *arena, const FrontDesc *fd, const int32_t *ipiv, TaskList tu, TaskList tlo,
+                 int t, const double *uinv, hipStream_t s) {
+    const int64_t n = tu.total + tlo.total;
+    if (n == 0) return;
+    k_trsm<T><<<dim3((unsigned)n), dim3(256), 0, s>>>(arena, fd, ipiv, tu, tlo, t, uinv);
     MBL_CHECK_LAUNCH();
 }
 
@@ -992,14 +1005,6 @@ template <class T>
 void launch_xform(T *arena, const FrontDesc *fd, TaskList tl, hipStream_t s) {
     if (tl.total == 0) return;
     hipLaunchKernelGGL(k_xform<T>, dim3((unsigned)tl.total), dim3(256), 0, s, arena, fd, tl);
-    MBL_CHECK_LAUNCH();
-}
-
-template <class T>
-void launch_trsm_l(T *arena, const FrontDesc *fd, TaskList tl, int t, const double *uinv,
-                   hipStream_t s) {
-    if (tl.total == 0) return;
-    k_trsm_l<T><<<dim3((unsigned)tl.total), dim3(256), 0, s>>>(arena, fd, tl, t, uinv);
     MBL_CHECK_LAUNCH();
 }
 
@@ -1042,10 +1047,8 @@ int merge_tri_items(int p) {
                                            double, double, hipStream_t);                        \
     template void launch_panel<T>(T *, const FrontDesc *, int32_t *, int32_t *, TaskList, int,  \
                                   double, double *, hipStream_t);                               \
-    template void launch_trsm_u<T>(T *, const FrontDesc *, const int32_t *, TaskList, int,      \
-                                   hipStream_t);                                                \
-    template void launch_trsm_l<T>(T *, const FrontDesc *, TaskList, int, const double *,       \
-                                   hipStream_t);                                                \
+    template void launch_trsm<T>(T *, const FrontDesc *, const int32_t *, TaskList, TaskList,    \
+                                 int, const double *, hipStream_t);                             \
     template void launch_xform<T>(T *, const FrontDesc *, TaskList, hipStream_t);               \
     template void launch_invert_diag<T>(T *, const FrontDesc *, const int32_t *, int32_t *,      \
                                         TaskList, int, int, hipStream_t);                        \

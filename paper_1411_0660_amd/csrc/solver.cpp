@@ -620,8 +620,8 @@ void Context::factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel, S
             StepTasks &S = lv.steps[t];
             launch_panel<T>(A, fd, f.ipiv.template ptr<int32_t>(), f.npert.template ptr<int32_t>(),
                             S.panel, (int)t, thresh, f.uinv.template ptr<double>(), s);
-            launch_trsm_u<T>(A, fd, f.ipiv.template ptr<int32_t>(), S.trsm_u, (int)t, s);
-            launch_trsm_l<T>(A, fd, S.rows_below, (int)t, f.uinv.template ptr<double>(), s);
+            launch_trsm<T>(A, fd, f.ipiv.template ptr<int32_t>(), S.trsm_u, S.rows_below, (int)t,
+                           f.uinv.template ptr<double>(), s);
             launch_schur<T>(A, fd, S.schur, (int)t, 0, s);
             // end of an outer block (for every front whose block ends here or earlier)
             int ob = (int)t / (SB / FNB);
