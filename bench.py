@@ -180,6 +180,30 @@ def run_steps(ctx, mbl, L, cases, prec, nev, tol=1e-9):
     return lat, conv, res
 
 
+def run_concurrent(mbl, L, cases, nev, slots, nwarm, ref):
+    """The steps `cases` submitted at once to `slots` serving slots of a fresh
+    context (after nwarm untimed requests); ref: the one-at-a-time results."""
+    import numpy as np
+    cs = mbl.Context(0)
+    cs.mbl_serve_start(slots)
+    for tkt in [cs.mbl_submit(L, 3.0, 1000 + i, 0.5, nev) for i in range(max(nwarm, slots))]:
+        cs.mbl_wait(tkt)
+    t0 = time.perf_counter()
+    tickets = [cs.mbl_submit(L, h, sd, eps, nev) for (sd, h, eps) in cases]
+    outs = [cs.mbl_wait(tkt) for tkt in tickets]
+    wall = time.perf_counter() - t0
+    st = cs.mbl_serve_stats()
+    cs.close()
+    conv = sum(int(sum(1 for r in o["resid"] if r <= 1e-9)) for o in outs if o["status"] == 0)
+    svc = [o["t_done"] - o["t_start"] for o in outs]
+    return {"value": conv / wall, "ms_per_step": 1e3 * wall / len(cases), "converged": conv,
+            "slots": slots, "max_running": st["max_running"],
+            "service_latency_ms": {"p50": 1e3 * percentile(svc, 0.5),
+                                   "p99": 1e3 * percentile(svc, 0.99)},
+            "bitwise_equal_to_sequential": all(
+                bool(np.array_equal(o["evals"], r["evals"])) for o, r in zip(outs, ref))}
+
+
 def cpu_baseline(L, nev, budget_s=20.0):
     """The oracle as it stands on a bounded sample: build the dense FP64
     Hamiltonian of one realization and run the first Householder steps of its
@@ -242,6 +266,7 @@ def main():
     ap.add_argument("--l19-steps", type=int, default=5)
     ap.add_argument("--slots", type=int, default=2,
                     help="timed steps run this many at a time (1: one at a time only)")
+    ap.add_argument("--l18-slots", type=int, default=4)
     a = ap.parse_args()
     if a.copy_probe > 0:
         copy_probe(a.copy_probe)
@@ -327,28 +352,11 @@ def main():
                              "latency_ms": out["latency_ms"]}
         ctx.close()
         log(f"timed FP64 steps, {a.slots} at a time")
-        cs = mbl.Context(0)
-        cs.mbl_serve_start(a.slots)
-        warm = [cs.mbl_submit(L, 3.0, 1000 + i, 0.5, nev) for i in range(max(a.warmup, a.slots))]
-        for tkt in warm:
-            cs.mbl_wait(tkt)
-        t0 = time.perf_counter()
-        tickets = [cs.mbl_submit(L, h, sd, eps, nev) for (sd, h, eps) in cases]
-        outs = [cs.mbl_wait(tkt) for tkt in tickets]
-        wall_c = time.perf_counter() - t0
-        st = cs.mbl_serve_stats()
-        cs.close()
-        conv_c = sum(int(sum(1 for r in o["resid"] if r <= 1e-9)) for o in outs if o["status"] == 0)
-        svc = [o["t_done"] - o["t_start"] for o in outs]
-        out["value"] = conv_c / wall_c
-        out["ms_per_step"] = 1e3 * wall_c / a.steps
-        out["converged"] = conv_c
-        out["concurrent"] = {
-            "slots": a.slots, "max_running": st["max_running"],
-            "service_latency_ms": {"p50": 1e3 * percentile(svc, 0.5),
-                                   "p99": 1e3 * percentile(svc, 0.99)},
-            "bitwise_equal_to_sequential": all(
-                bool(np.array_equal(o["evals"], r["evals"])) for o, r in zip(outs, res))}
+        cc = run_concurrent(mbl, L, cases, nev, a.slots, a.warmup, res)
+        out["value"] = cc.pop("value")
+        out["ms_per_step"] = cc.pop("ms_per_step")
+        out["converged"] = cc.pop("converged")
+        out["concurrent"] = cc
         out["config"]["execution"] = (f"{a.slots} independent solves at a time (serving slots, "
                                       f"one stream each)")
         log(f"FP64, {a.slots} at a time: {out['value']:.2f} eigenpairs/s")
@@ -374,13 +382,16 @@ def main():
         cases18 = workload(18, a.l18_steps)
         run_steps(ctx, mbl, 18, [(1000, 3.0, 0.5)], mbl.MBL_FP64, nev)
         t0 = time.perf_counter()
-        lat3, conv3, _ = run_steps(ctx, mbl, 18, cases18, mbl.MBL_FP64, nev)
+        lat3, conv3, res3 = run_steps(ctx, mbl, 18, cases18, mbl.MBL_FP64, nev)
         wall3 = time.perf_counter() - t0
         out["L18"] = {"value": conv3 / wall3, "unit": "eigenpairs/s",
                       "ms_per_step": 1e3 * wall3 / a.l18_steps, "dim": info18["dim"],
                       "workload": "L=18, h=3, eps=0.5, nev=50, seeds 0..%d, FP64" % (a.l18_steps - 1),
                       "latency_ms": {"p50": 1e3 * percentile(lat3, 0.5),
                                      "p99": 1e3 * percentile(lat3, 0.99)}}
+        if a.l18_slots > 1:
+            log(f"L=18 steps, {a.l18_slots} at a time")
+            out["L18"]["concurrent"] = run_concurrent(mbl, 18, cases18, nev, a.l18_slots, 1, res3)
     if a.l19_steps > 0:
         # the paper's largest odd chain, S^z = +1/2 sector
         log("L=19 steps")
