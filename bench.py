@@ -20,7 +20,8 @@ phase times.
 
 Prints one JSON line (rank 0).  Besides the contract fields it carries
 ``latency_ms`` (p50 / p99 per solve), ``mixed`` (the FP32-LU + FP64-refinement
-path on the same seeds), ``roofline`` (dominant kernel, measured with HIP
+path on the same seeds; ``L18.mixed`` on the L = 18 seeds, with the eigenvalue
+difference to the FP64 path per seed), ``roofline`` (dominant kernel, measured with HIP
 events on the library's stream during the timed FP64 steps) and
 ``cpu_baseline`` (the CPU oracle on a bounded sample of the same workload).
 """
@@ -389,6 +390,24 @@ def main():
                       "workload": "L=18, h=3, eps=0.5, nev=50, seeds 0..%d, FP64" % (a.l18_steps - 1),
                       "latency_ms": {"p50": 1e3 * percentile(lat3, 0.5),
                                      "p99": 1e3 * percentile(lat3, 0.99)}}
+        if not a.no_mixed:
+            # the FP32-LU + FP64-refinement path on the same seeds, with the
+            # largest eigenvalue difference to the FP64 path per seed
+            log("L=18 mixed-precision steps")
+            run_steps(ctx, mbl, 18, [(1000, 3.0, 0.5)], mbl.MBL_FP32_IR64, nev)
+            t0 = time.perf_counter()
+            lat6, conv6, res6 = run_steps(ctx, mbl, 18, cases18, mbl.MBL_FP32_IR64, nev)
+            wall6 = time.perf_counter() - t0
+            out["L18"]["mixed"] = {
+                "value": conv6 / wall6, "ms_per_step": 1e3 * wall6 / a.l18_steps,
+                "dtype": "fp32 LU + fp64 refinement",
+                "latency_ms": {"p50": 1e3 * percentile(lat6, 0.5),
+                               "p99": 1e3 * percentile(lat6, 0.99)},
+                "fallbacks": sum(r["fallback"] for r in res6),
+                "max_ir_sweeps": max(r["ir_iters_max"] for r in res6),
+                "max_abs_eval_diff_vs_fp64_per_seed": [
+                    float(np.abs(r2["evals"] - r1["evals"]).max()) for r1, r2 in zip(res3, res6)],
+                "hnorm_per_seed": [float(r["hnorm"]) for r in res3]}
         if a.l18_slots > 1:
             log(f"L=18 steps, {a.l18_slots} at a time")
             out["L18"]["concurrent"] = run_concurrent(mbl, 18, cases18, nev, a.l18_slots, 1, res3)
