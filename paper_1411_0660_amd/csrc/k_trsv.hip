@@ -32,6 +32,15 @@ namespace {
 constexpr int MAXRHS = 16;
 constexpr int RW = 64;          // rows per update work item (one per lane)
 
+// Workgroup b of a launch is dispatched to XCD b % 8 (round robin); each XCD
+// takes a contiguous range of the work items instead, so that neighbouring
+// row chunks of one column run, which share the cache line at their boundary,
+// are read through the same L2.  A bijection of [0, n).
+__device__ __forceinline__ unsigned xcd_item(unsigned b, unsigned n) {
+    const unsigned x = b % 8, s = b / 8, q = n / 8, r = n % 8;
+    return x * q + min(x, r) + s;
+}
+
 // column groups (waves) per 64-row work item: 16 for up to 8 right-hand sides,
 // 8 for 16 (LDS: the SSB x NR source block plus CG x 64 x NR partial sums)
 template <int NR> struct StepCfg {
@@ -101,7 +110,7 @@ __global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_solve_step(
     static_assert(CW % LS == 0, "columns per wave split over the slices");
     __shared__ double src[SSB][NR];
     __shared__ double red[HG][R][NR];
-    const int2 tk = tl.items[blockIdx.x];
+    const int2 tk = tl.items[xcd_item(blockIdx.x, gridDim.x)];
     const FrontDesc d = fd[tk.x];
     const int w = tk.y;
     const int m = d.m, p = d.p, t0 = t * SSB, st = min(SSB, p - t0), tend = t0 + st;
@@ -227,7 +236,7 @@ __global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_fwd_l21(
     constexpr int CG = StepCfg<NR>::CG, CW = StepCfg<NR>::CWU, HG = CG / 2;
     __shared__ double src[SB][NR];
     __shared__ double red[HG][RW][NR];
-    const int2 tk = tl.items[blockIdx.x];
+    const int2 tk = tl.items[xcd_item(blockIdx.x, gridDim.x)];
     const FrontDesc d = fd[tk.x];
     const int w = tk.y;
     const int m = d.m, p = d.p, c = m - p;
@@ -309,7 +318,7 @@ __global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_bwd_u12(
     constexpr int CG = StepCfg<NR>::CG, CW = StepCfg<NR>::CWU, HG = CG / 2;
     __shared__ double src[SB][NR];
     __shared__ double red[HG][RW][NR];
-    const int2 tk = tl.items[blockIdx.x];
+    const int2 tk = tl.items[xcd_item(blockIdx.x, gridDim.x)];
     const FrontDesc d = fd[tk.x];
     const int w = tk.y;
     const int m = d.m, p = d.p, c = m - p;
