@@ -4,7 +4,8 @@
 // (section "Numerical method").  Here every node of the nested-dissection tree
 // is a dense front F (m x m, column-major, pivots first).  A front is
 // assembled from the original entries of H - sigma and the contribution blocks
-// of its children (extend-add), then partially factored: a right-looking
+// of its children (extend-add, done as a gather so that each entry is written
+// once), then partially factored: a right-looking
 // blocked LU over its p pivot columns, panel width FNB.
 //
 // Pivoting: partial pivoting restricted to the FNB x FNB diagonal block of the

@@ -41,7 +41,8 @@ __device__ __forceinline__ unsigned xcd_item(unsigned b, unsigned n) {
     return x * q + min(x, r) + s;
 }
 
-// column groups (waves) per 64-row work item: 16 for up to 8 right-hand sides,
+// column groups (waves) per work item (STEP_RW rows of a solve step, 64 rows of
+// an L21 / U12 tile): 16 for up to 8 right-hand sides,
 // 8 for 16 (LDS: the SSB x NR source block plus CG x 64 x NR partial sums)
 template <int NR> struct StepCfg {
     static constexpr int CG = NR <= 8 ? 16 : 8;
