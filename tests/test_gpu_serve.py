@@ -99,3 +99,22 @@ def test_errors_and_late_arrivals():
         assert all(o["status"] == mbl.MBL_OK and o["max_resid"] <= 1e-9 for o in outs)
         with pytest.raises(mbl.MblError):
             c.mbl_poll(10 ** 9)
+
+
+def test_concurrent_large_fronts_bitwise():
+    # the benchmark's mode at a size with multi-block fronts (L = 16: outer
+    # Schur pairs, merged solve blocks, several solve steps per level): two
+    # solves in flight on two slots give bitwise the one-at-a-time results
+    cases = [(16, 3.0, 0, 0.5), (16, 2.0, 1, 0.2), (16, 4.0, 2, 0.8), (16, 1.0, 3, 0.5)]
+    with mbl.Context(0) as c:
+        alone = [c.mbl_solve(L, h, s, e, 50) for (L, h, s, e) in cases]
+    say("L=16 solves, 2 at a time")
+    with mbl.Context(0) as c:
+        c.mbl_serve_start(2)
+        outs = [c.mbl_wait(t) for t in [c.mbl_submit(L, h, s, e, 50) for (L, h, s, e) in cases]]
+        st = c.mbl_serve_stats()
+    assert st["max_running"] == 2
+    for a, o in zip(alone, outs):
+        assert o["status"] == mbl.MBL_OK and o["nconv"] == 50
+        for k in KEYS:
+            assert np.array_equal(o[k], a[k]), k
