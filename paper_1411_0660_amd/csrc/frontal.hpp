@@ -123,13 +123,13 @@ void launch_fwd_gather(const FrontDesc *fd, const int32_t *perm, const int32_t *
 template <class T>
 void launch_solve_step(const T *arena, const FrontDesc *fd, TaskList tl, int t, int nrhs, bool fwd,
                        double *vec, double *yv, hipStream_t s);
-// backward: v_f[p:m] = x(contribution rows)
-void launch_bwd_gather(const FrontDesc *fd, const int32_t *contrib, TaskList tl, int nrhs,
-                       const double *xnew, int64_t n, double *vec, hipStream_t s);
-// partial products U12 x_c over 64 x SB tiles, then their fixed-order sum into v_f[0:p]
+// backward: partial products U12 x_c over 64 x SB tiles, x_c (the contribution
+// rows, pivots of ancestors) read from xnew through the contribution-row
+// lists; then their fixed-order sum into v_f[0:p]
 template <class T>
 void launch_bwd_u12(const T *arena, const FrontDesc *fd, TaskList tl, int nrhs,
-                    const double *vec, double *part, hipStream_t s);
+                    const int32_t *contrib, const double *xnew, int64_t n, double *part,
+                    hipStream_t s);
 void launch_bwd_u12_reduce(const FrontDesc *fd, TaskList tl, int nrhs, double *yv,
                            const double *part, hipStream_t s);
 // forward contribution rows: V[p:m] -= L~21 V[0:p] (tiles into part, then the

@@ -209,21 +209,6 @@ __global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_solve_step(
     }
 }
 
-__global__ __launch_bounds__(256) void k_bwd_gather(const FrontDesc *__restrict__ fd,
-                                                    const int32_t *__restrict__ contrib,
-                                                    TaskList tl, int nrhs,
-                                                    const double *__restrict__ xnew, int64_t n,
-                                                    double *vec) {
-    const int2 tk = tl.items[blockIdx.x];
-    FrontDesc d = fd[tk.x];
-    int i = tk.y * 256 + threadIdx.x;
-    int cc = d.m - d.p;
-    if (i >= cc) return;
-    int32_t g = contrib[d.cptr + i];
-    double *v = vec + d.voff + d.p + i;
-    for (int r = 0; r < nrhs; r++) v[(int64_t)r * d.m] = xnew[g + (int64_t)r * n];
-}
-
 // Contribution rows of the forward pass: once every solve block of a front
 // is done, V[0:p] holds the source values of all blocks (a block's rows are
 // not touched after its own step), so V[p:m] -= L~21 V[0:p] in one pass with
@@ -315,7 +300,8 @@ __global__ __launch_bounds__(256) void k_fwd_l21_reduce(const FrontDesc *__restr
 template <class T, int NR>
 __global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_bwd_u12(
     const T *__restrict__ arena, const FrontDesc *__restrict__ fd, TaskList tl,
-    const double *__restrict__ vec, double *__restrict__ part) {
+    const int32_t *__restrict__ contrib, const double *__restrict__ xnew, int64_t n,
+    double *__restrict__ part) {
     constexpr int CG = StepCfg<NR>::CG, CW = StepCfg<NR>::CWU, HG = CG / 2;
     __shared__ double src[SB][NR];
     __shared__ double red[HG][RW][NR];
@@ -335,10 +321,12 @@ __global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_bwd_u12(
         for (int q = 0; q < CW; q++)
             mv[q] = (row < p && wv * CW + q < cw) ? (double)U[(int64_t)q * m] : 0.0;
     }
-    const double *v = vec + d.voff;
+    // x of the contribution rows (pivots of ancestors, already solved), read
+    // through the front's contribution-row list
+    const int32_t *cr = contrib + d.cptr + c0;
     for (int e = threadIdx.x; e < SB * NR; e += blockDim.x) {
         int j = e % SB, r = e / SB;
-        src[j][r] = j < cw ? v[p + c0 + j + (int64_t)r * m] : 0.0;
+        src[j][r] = j < cw ? xnew[cr[j] + (int64_t)r * n] : 0.0;
     }
     __syncthreads();
     double acc[NR];
@@ -456,22 +444,15 @@ void launch_solve_step(const T *arena, const FrontDesc *fd, TaskList tl, int t, 
     MBL_CHECK_LAUNCH();
 }
 
-void launch_bwd_gather(const FrontDesc *fd, const int32_t *contrib, TaskList tl, int nrhs,
-                       const double *xnew, int64_t n, double *vec, hipStream_t s) {
-    if (tl.total == 0) return;
-    hipLaunchKernelGGL(k_bwd_gather, dim3((unsigned)tl.total), dim3(256), 0, s, fd, contrib, tl,
-                       nrhs, xnew, n, vec);
-    MBL_CHECK_LAUNCH();
-}
-
 template <class T>
-void launch_bwd_u12(const T *arena, const FrontDesc *fd, TaskList tl, int nrhs, const double *vec,
-                    double *part, hipStream_t s) {
+void launch_bwd_u12(const T *arena, const FrontDesc *fd, TaskList tl, int nrhs,
+                    const int32_t *contrib, const double *xnew, int64_t n, double *part,
+                    hipStream_t s) {
     if (tl.total == 0) return;
     rhs_dispatch(nrhs, [&](auto nr) {
         constexpr int NR = decltype(nr)::value;
-        k_bwd_u12<T, NR><<<dim3((unsigned)tl.total), dim3(StepCfg<NR>::THREADS), 0, s>>>(arena, fd,
-                                                                                      tl, vec, part);
+        k_bwd_u12<T, NR><<<dim3((unsigned)tl.total), dim3(StepCfg<NR>::THREADS), 0, s>>>(
+            arena, fd, tl, contrib, xnew, n, part);
     });
     MBL_CHECK_LAUNCH();
 }
@@ -520,8 +501,8 @@ void launch_bwd_scatter(const FrontDesc *fd, const int32_t *perm, TaskList tl, i
 #define MBL_INST_TRSV(T)                                                                          \
     template void launch_solve_step<T>(const T *, const FrontDesc *, TaskList, int, int, bool,    \
                                        double *, double *, hipStream_t);                          \
-    template void launch_bwd_u12<T>(const T *, const FrontDesc *, TaskList, int, const double *,  \
-                                    double *, hipStream_t);                                        \
+    template void launch_bwd_u12<T>(const T *, const FrontDesc *, TaskList, int, const int32_t *, \
+                                    const double *, int64_t, double *, hipStream_t);               \
     template void launch_fwd_l21<T>(const T *, const FrontDesc *, TaskList, int, const double *,  \
                                     double *, hipStream_t);
 

@@ -373,13 +373,12 @@ void Context::ensure_symbolic(Plan &p) {
     for (int l = 0; l < t.n_levels; l++) {
         LevelTasks &lv = p.levels[l];
         const std::vector<int32_t> &fl = bylev[l];
-        std::vector<int64_t> one(fl.size(), 1), g, sc;
+        std::vector<int64_t> one(fl.size(), 1), sc;
         std::vector<int32_t> ut, ur, lt, lr;
         std::vector<int64_t> uti, uri, lti, lri;
         int maxsteps = 0, maxsb = 0;
         for (int f : fl) {
             const FrontDesc &d = p.h_fd[f];
-            g.push_back(cdiv64(d.m - d.p, 256));
             sc.push_back(cdiv64(d.p, 256));
             if (d.p > 0) {
                 ur.push_back(f);
@@ -397,7 +396,6 @@ void Context::ensure_symbolic(Plan &p) {
             maxsb = std::max<int>(maxsb, (int)cdiv64(d.p, SB));
         }
         tb.add(lv.all, fl, one);
-        tb.add(lv.gather, fl, g);
         tb.add(lv.scatter, fl, sc);
         tb.add(lv.u12, ut, uti);
         tb.add(lv.u12red, ur, uri);
@@ -750,10 +748,9 @@ void Context::lu_apply_seq(Plan &p, Factor<T> &f, int nrhs, const double *b, int
     }
     for (size_t l = p.levels.size(); l-- > 0;) {
         LevelTasks &lv = p.levels[l];
-        launch_bwd_gather(fd, p.d_contrib.ptr<int32_t>(), lv.gather, nrhs, xnew, p.dim, vec, s);
         bool pr = prof_on("u12") && lv.u12.total > 0;
         if (pr) prof_begin();
-        launch_bwd_u12<T>(A, fd, lv.u12, nrhs, vec, part, s);
+        launch_bwd_u12<T>(A, fd, lv.u12, nrhs, p.d_contrib.ptr<int32_t>(), xnew, p.dim, part, s);
         if (pr) prof_end(lv.u12.elems * sizeof(T) + 8.0 * nrhs * lv.u12.rows, 2.0 * nrhs * lv.u12.elems);
         launch_bwd_u12_reduce(fd, lv.u12red, nrhs, yv, part, s);
         for (size_t t = lv.bstep.size(); t-- > 0;) step(lv.bstep[t], (int)t, false);
