@@ -119,13 +119,22 @@ void launch_invert_diag(T *arena, const FrontDesc *fd, const int32_t *ipiv, int3
 void launch_fwd_gather(const FrontDesc *fd, const int32_t *perm, const int32_t *prow,
                        const int32_t *inv_ptr, const int2 *inv_src, TaskList tl, int nrhs,
                        const double *b, int64_t ldb, double *vec, hipStream_t s);
+// Where the backward steps write the solution of the pivot rows: by new index
+// (xnew, ld n) and by original index (xout through perm, ld ldx, nrhs columns).
+struct BwdIO {
+    const int32_t *perm;
+    double *xnew;
+    double *xout;
+    int64_t n, ldx;
+    int nrhs;
+};
 // solve block t of every listed front (forward or backward, see k_trsv.hip)
 template <class T>
 void launch_solve_step(const T *arena, const FrontDesc *fd, TaskList tl, int t, int nrhs, bool fwd,
-                       double *vec, double *yv, hipStream_t s);
+                       double *vec, double *yv, BwdIO bio, hipStream_t s);
 // backward: partial products U12 x_c over 64 x SB tiles, x_c (the contribution
 // rows, pivots of ancestors) read from xnew through the contribution-row
-// lists; then their fixed-order sum into v_f[0:p]
+// lists; then their fixed-order sum into the forward solution of the pivots
 template <class T>
 void launch_bwd_u12(const T *arena, const FrontDesc *fd, TaskList tl, int nrhs,
                     const int32_t *contrib, const double *xnew, int64_t n, double *part,
@@ -139,9 +148,5 @@ void launch_fwd_l21(const T *arena, const FrontDesc *fd, TaskList tl, int nrhs, 
                     double *part, hipStream_t s);
 void launch_fwd_l21_reduce(const FrontDesc *fd, TaskList tl, int nrhs, double *vec,
                            const double *part, hipStream_t s);
-// x_new[first..] = v_f[0:p] and x_out[perm[first..]] = v_f[0:p]
-void launch_bwd_scatter(const FrontDesc *fd, const int32_t *perm, TaskList tl, int nrhs,
-                        const double *vec, double *xnew, int64_t n, double *xout, int64_t ldx,
-                        hipStream_t s);
 
 }  // namespace mbl

@@ -14,9 +14,10 @@
 //     block t:  Y_t = Linv_tt V_t  and  V[rows below] -= L~[., t] V_t
 //     afterwards Y = L11^-1 P b and V[p:m] is the update the parent gathers.
 //   backward (root to leaves):
-//     V[p:m] = x(contribution rows); Y -= U12 V[p:m]   (64 x 256 tiles, fixed-order sum)
-//     block t from the last:  V_t = Uinv_tt Y_t  and  Y[rows above] -= U~[., t] Y_t
-//     afterwards V[0:p] = x of the pivots.
+//     Y -= U12 x(contribution rows)   (64 x 256 tiles reading x through the
+//                                      contribution lists, fixed-order sum)
+//     block t from the last:  x_t = Uinv_tt Y_t  and  Y[rows above] -= U~[., t] Y_t,
+//     x_t written straight to the solution vectors (by new and original index).
 // Work items of a step are STEP_RW rows x one SSB block (the off-diagonal
 // products: 64 rows x SB columns): the 8 or 16 waves of a workgroup take an
 // equal share of the columns each and are summed through LDS, which keeps the
@@ -101,10 +102,12 @@ __global__ __launch_bounds__(256) void k_fwd_gather(const FrontDesc *__restrict_
 // order through LDS.  The factor entries (and the rows updated in place) are
 // loaded before the source block is staged, so the two memory round trips
 // overlap.
+// In the backward pass the diagonal products write the solution of their rows
+// straight to xnew (by new index) and xout (by original index).
 template <class T, int NR, bool FWD>
 __global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_solve_step(
     const T *__restrict__ arena, const FrontDesc *__restrict__ fd, TaskList tl, int t,
-    double *vec, double *yv) {
+    double *vec, double *yv, BwdIO bio) {
     constexpr int CG = StepCfg<NR>::CG, CW = StepCfg<NR>::CW;
     constexpr int HG = CG / 2;                       // partial sums: two phases of CG / 2
     constexpr int R = STEP_RW, LS = 64 / R, CQ = CW / LS;
@@ -201,10 +204,17 @@ __global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_solve_step(
             double sum = red[0][rl][r];
 #pragma unroll
             for (int g = 1; g < HG; g++) sum += red[g][rl][r];
+            if (mode == 2) {               // solution of pivot row r0 + rl
+                if (r < bio.nrhs) {
+                    const int g = d.first + r0 + rl;
+                    bio.xnew[g + (int64_t)r * bio.n] = sum;
+                    bio.xout[bio.perm[g] + (int64_t)r * bio.ldx] = sum;
+                }
+                continue;
+            }
             double *o = out + rl + (int64_t)r * ldo;
             if (mode == 0) *o = prev[r] - sum;
-            else if (mode == 1) *o = src[i][r] + sum;
-            else *o = sum;
+            else *o = src[i][r] + sum;
         }
     }
 }
@@ -380,24 +390,6 @@ __global__ __launch_bounds__(256) void k_bwd_u12_reduce(const FrontDesc *__restr
     for (int r = 0; r < NR; r++) y[row + (int64_t)r * p] -= s[r];
 }
 
-__global__ __launch_bounds__(256) void k_bwd_scatter(const FrontDesc *__restrict__ fd,
-                                                     const int32_t *__restrict__ perm, TaskList tl,
-                                                     int nrhs, const double *__restrict__ vec,
-                                                     double *xnew, int64_t n, double *xout,
-                                                     int64_t ldx) {
-    const int2 tk = tl.items[blockIdx.x];
-    FrontDesc d = fd[tk.x];
-    int i = tk.y * 256 + threadIdx.x;
-    if (i >= d.p) return;
-    int g = d.first + i;
-    int32_t o = perm[g];
-    for (int r = 0; r < nrhs; r++) {
-        double x = vec[d.voff + i + (int64_t)r * d.m];
-        xnew[g + (int64_t)r * n] = x;
-        xout[o + (int64_t)r * ldx] = x;
-    }
-}
-
 inline int rhs_class(int nrhs) { return nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : nrhs <= 8 ? 8 : 16; }
 
 }  // namespace
@@ -429,17 +421,17 @@ void launch_fwd_gather(const FrontDesc *fd, const int32_t *perm, const int32_t *
 
 template <class T>
 void launch_solve_step(const T *arena, const FrontDesc *fd, TaskList tl, int t, int nrhs, bool fwd,
-                       double *vec, double *yv, hipStream_t s) {
+                       double *vec, double *yv, BwdIO bio, hipStream_t s) {
     if (tl.total == 0) return;
     rhs_dispatch(nrhs, [&](auto nr) {
         constexpr int NR = decltype(nr)::value;
         constexpr int TH = StepCfg<NR>::THREADS;
         if (fwd)
             k_solve_step<T, NR, true><<<dim3((unsigned)tl.total), dim3(TH), 0, s>>>(arena, fd, tl, t,
-                                                                                    vec, yv);
+                                                                                    vec, yv, bio);
         else
             k_solve_step<T, NR, false><<<dim3((unsigned)tl.total), dim3(TH), 0, s>>>(arena, fd, tl,
-                                                                                     t, vec, yv);
+                                                                                     t, vec, yv, bio);
     });
     MBL_CHECK_LAUNCH();
 }
@@ -489,18 +481,9 @@ void launch_bwd_u12_reduce(const FrontDesc *fd, TaskList tl, int nrhs, double *y
     MBL_CHECK_LAUNCH();
 }
 
-void launch_bwd_scatter(const FrontDesc *fd, const int32_t *perm, TaskList tl, int nrhs,
-                        const double *vec, double *xnew, int64_t n, double *xout, int64_t ldx,
-                        hipStream_t s) {
-    if (tl.total == 0) return;
-    hipLaunchKernelGGL(k_bwd_scatter, dim3((unsigned)tl.total), dim3(256), 0, s, fd, perm, tl, nrhs,
-                       vec, xnew, n, xout, ldx);
-    MBL_CHECK_LAUNCH();
-}
-
 #define MBL_INST_TRSV(T)                                                                          \
     template void launch_solve_step<T>(const T *, const FrontDesc *, TaskList, int, int, bool,    \
-                                       double *, double *, hipStream_t);                          \
+                                       double *, double *, BwdIO, hipStream_t);                   \
     template void launch_bwd_u12<T>(const T *, const FrontDesc *, TaskList, int, const int32_t *, \
                                     const double *, int64_t, double *, hipStream_t);               \
     template void launch_fwd_l21<T>(const T *, const FrontDesc *, TaskList, int, const double *,  \

@@ -373,18 +373,16 @@ void Context::ensure_symbolic(Plan &p) {
     for (int l = 0; l < t.n_levels; l++) {
         LevelTasks &lv = p.levels[l];
         const std::vector<int32_t> &fl = bylev[l];
-        std::vector<int64_t> one(fl.size(), 1), sc;
+        std::vector<int64_t> one(fl.size(), 1);
         std::vector<int32_t> ut, ur, lt, lr;
         std::vector<int64_t> uti, uri, lti, lri;
         int maxsteps = 0, maxsb = 0;
         for (int f : fl) {
             const FrontDesc &d = p.h_fd[f];
-            sc.push_back(cdiv64(d.p, 256));
             if (d.p > 0) {
                 ur.push_back(f);
-                uri.push_back(cdiv64(d.p, SB));
+                uri.push_back(cdiv64(d.p, 256));
                 if (d.m > d.p) { ut.push_back(f); uti.push_back(cdiv64(d.p, 64) * cdiv64(d.m - d.p, SB)); }
-                uri.back() = cdiv64(d.p, 256);
                 if (d.m > d.p) {
                     lt.push_back(f);
                     lti.push_back(cdiv64(d.m - d.p, 64) * cdiv64(d.p, SB));
@@ -396,7 +394,6 @@ void Context::ensure_symbolic(Plan &p) {
             maxsb = std::max<int>(maxsb, (int)cdiv64(d.p, SB));
         }
         tb.add(lv.all, fl, one);
-        tb.add(lv.scatter, fl, sc);
         tb.add(lv.u12, ut, uti);
         tb.add(lv.u12red, ur, uri);
         tb.add(lv.l21, lt, lti);
@@ -728,11 +725,12 @@ void Context::lu_apply_seq(Plan &p, Factor<T> &f, int nrhs, const double *b, int
     double *vec = d_vec.ptr<double>(), *yv = d_yv.ptr<double>();
     double *part = d_upart.ptr<double>(), *xnew = d_xnew.ptr<double>();
     const int2 *isrc = reinterpret_cast<const int2 *>(p.d_inv_src.ptr<int32_t>());
+    const BwdIO bio{p.d_perm.ptr<int32_t>(), xnew, x, p.dim, ldx, nrhs};
     auto step = [&](TaskList &tl, int t, bool fwd) {
         const char *cls = fwd ? "fwd_update" : "bwd_update";
         bool pr = prof_on(cls) && tl.total > 0;
         if (pr) prof_begin();
-        launch_solve_step<T>(A, fd, tl, t, nrhs, fwd, vec, yv, s);
+        launch_solve_step<T>(A, fd, tl, t, nrhs, fwd, vec, yv, bio, s);
         if (pr) prof_end(tl.elems * sizeof(T) + 16.0 * nrhs * tl.rows, 2.0 * nrhs * tl.elems);
     };
     for (size_t l = 0; l < p.levels.size(); l++) {
@@ -754,8 +752,6 @@ void Context::lu_apply_seq(Plan &p, Factor<T> &f, int nrhs, const double *b, int
         if (pr) prof_end(lv.u12.elems * sizeof(T) + 8.0 * nrhs * lv.u12.rows, 2.0 * nrhs * lv.u12.elems);
         launch_bwd_u12_reduce(fd, lv.u12red, nrhs, yv, part, s);
         for (size_t t = lv.bstep.size(); t-- > 0;) step(lv.bstep[t], (int)t, false);
-        launch_bwd_scatter(fd, p.d_perm.ptr<int32_t>(), lv.scatter, nrhs, vec, xnew, p.dim, x, ldx,
-                           s);
     }
 }
 

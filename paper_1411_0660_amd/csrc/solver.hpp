@@ -33,7 +33,6 @@ struct OuterTasks {                   // one 256-wide outer block
 struct LevelTasks {
     int64_t ebegin = 0, ecount = 0;    // original entries of the level
     TaskList all;                      // every front, one item each
-    TaskList scatter;                  // pivot-row chunks of the backward pass
     TaskList pull;                     // assembly from the children: one item per front column
     std::vector<StepTasks> steps;
     std::vector<OuterTasks> outer;
