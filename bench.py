@@ -44,7 +44,7 @@ HBM_PEAK_GBS = 8000.0
 # of known size); valid only for the kernel source it was measured on
 SCHUR_SRC = os.path.join(HERE, "paper_1411_0660_amd", "csrc", "k_front.hip")
 SCHUR_TRAFFIC = {"sha256": "ede0f1f2f41d2d9cad8c0ac0a8a9dea22d45e3c22d89728905e183cb227fe4f0",
-                 "bytes_per_launch": 2.506928e+10}
+                 "bytes_per_launch": 2.508910e+10}
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
