@@ -33,7 +33,7 @@ struct FrontDesc {
     int32_t mapoff;   // offset of this front's rows inside its parent (relative map), -1 at roots
     int32_t parent;
     int32_t child0, nchild;  // children in FactorTables::child_ids[child0 .. child0 + nchild)
-    int64_t poff;     // offset of the front's U12 partial products in the level scratch
+    int64_t poff;     // offset of the front's L21 / U12 partial products in the level scratch
     int32_t cptr_inv; // offset of the front's inverse relative map (m + 1 row pointers)
     int32_t pmoff;    // offset of the front's pull map: per child, per front row, the
                       // child's update row landing there, or -1 (nchild blocks of m)

@@ -27,7 +27,7 @@ size_t footprint_bytes(const Plan &p, int prec, int nev, int block) {
     bytes += 8 * (size_t)p.arena_elems + 12 * n + panel_inv;     // FP64 fronts, pivots, row maps
     if (prec == MBL_FP32_IR64) bytes += 4 * (size_t)p.arena_elems + 12 * n + panel_inv;  // FP32
     bytes += 8 * (size_t)p.vec_elems * 2 + 8 * n * 16 * 6; // solve vectors, x_new, r, d, staging
-    bytes += 8 * (size_t)p.part_elems;                      // U12 partial products
+    bytes += 8 * (size_t)p.part_elems;                      // L21 / U12 partial products
     bytes += 8 * n * cols * 2 + 8 * n * 16;                 // Krylov bases + work block
     if (prec == MBL_FP32_IR64) bytes += 8 * n * 16 * 62;    // GMRES bases (30 + 31 blocks)
     bytes += 8 * n * (size_t)(nw + 8) * 4;                  // Ritz vectors, H psi, copies

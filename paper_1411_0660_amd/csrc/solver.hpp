@@ -41,7 +41,7 @@ struct LevelTasks {
     TaskList fgather;                  // forward right-hand sides, 256-row items
     TaskList u12, u12red;              // U12 x_c tiles and their reduction
     TaskList l21, l21red;              // forward contribution rows: tiles and reduction
-    int64_t part_elems = 0;            // level scratch of the U12 partial products
+    int64_t part_elems = 0;            // level scratch of the L21 / U12 partial products
 };
 
 struct Plan {
