@@ -56,8 +56,8 @@ def lib():
         L.orc_apply_H.argtypes = [_i, _d, _pd, _pu32, _l, _pd, _pd]
         L.orc_tridiagonalize.restype = _l
         L.orc_tridiagonalize.argtypes = [_l, _pd, _pd, _pd, _pd, _l]
-        L.orc_tridiag_qr.restype = _i
-        L.orc_tridiag_qr.argtypes = [_l, _pd, _pd, _pd, _l]
+        L.orc_tridiag_ql.restype = _i
+        L.orc_tridiag_ql.argtypes = [_l, _pd, _pd, _pd, _l]
         L.orc_tridiag_invit.argtypes = [_l, _pd, _pd, _l, _pd, _pd]
         L.orc_backtransform.argtypes = [_l, _pd, _pd, _l, _pd]
         L.orc_eigvalsh.restype = _i
@@ -172,7 +172,7 @@ def eigh_full(A: np.ndarray):
 def tridiag_eigvals(d: np.ndarray, e: np.ndarray) -> np.ndarray:
     d = _f64(d).copy()
     e = np.concatenate([_f64(e), [0.0]])
-    rc = lib().orc_tridiag_qr(d.size, _p(d), _p(e), None, 0)
+    rc = lib().orc_tridiag_ql(d.size, _p(d), _p(e), None, 0)
     assert rc == 0
     return np.sort(d)
 

@@ -7,8 +7,8 @@
  * the benchmark do.  It shares no code, header, table or helper with the HIP
  * path: it enumerates its own basis (brute force), ranks by binary search,
  * builds the dense Hamiltonian and diagonalises it with a dense symmetric
- * eigensolver (Householder tridiagonalisation + implicit QR with a Wilkinson
- * shift, Golub & Van Loan, Matrix Computations, Alg. 8.3.1 / 8.3.2), with
+ * eigensolver (Householder tridiagonalisation + implicit QL with a shift from
+ * the leading 2 x 2, Golub & Van Loan, Matrix Computations, section 8.3), with
  * eigenvectors by tridiagonal inverse iteration and back-transformation.
  *
  * What it computes (paper: Luitz, Laflorencie, Alet, "Many-body localization
@@ -228,48 +228,53 @@ long orc_tridiagonalize(long n, double *A, double *d, double *e, double *tau,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Implicit symmetric tridiagonal QR with Wilkinson shift (G&VL Alg. 8.3.2)  */
-/* plus deflation.  On return d holds the eigenvalues (unsorted).  If Z is   */
-/* non-NULL (column-major ldz x n), the plane rotations are accumulated:     */
-/* Z <- Z R^T.  Returns 0 on success, -1 if an iteration cap is hit.         */
+/* Implicit symmetric tridiagonal QL with a shift from the leading 2 x 2     */
+/* (G&VL section 8.3; the QL form works from the bottom of each unreduced    */
+/* block upward, so eigenvalues deflate at its top).  d[0..n-1] diagonal,    */
+/* e[0..n-2] the coupling of i and i+1 (e must have room for n entries).     */
+/* On return d holds the eigenvalues (unsorted).  If Z is non-NULL           */
+/* (column-major ldz x n), each plane rotation G in the plane (j-1, j) is    */
+/* accumulated as Z <- Z G.  Returns 0 on success, -1 if an iteration cap is */
+/* hit.                                                                      */
 /* ------------------------------------------------------------------------ */
-int orc_tridiag_qr(long n, double *d, double *e, double *Z, long ldz)
+int orc_tridiag_ql(long n, double *d, double *e, double *Z, long ldz)
 {
-    long hi = n - 1;
-    long iters = 0, cap = 60 * (n > 1 ? n : 1);
-    while (hi > 0) {
-        for (long i = 0; i < hi; i++)
-            if (fabs(e[i]) <= DBL_EPSILON * (fabs(d[i]) + fabs(d[i + 1])))
-                e[i] = 0.0;
-        if (e[hi - 1] == 0.0) { hi--; continue; }
-        long lo = hi - 1;
-        while (lo > 0 && e[lo - 1] != 0.0) lo--;
+    long top = 0, iters = 0, cap = 60 * (n > 1 ? n : 1);
+    while (top < n) {
+        /* bottom of the unreduced block that starts at top */
+        long bot = top;
+        while (bot < n - 1 &&
+               fabs(e[bot]) > DBL_EPSILON * (fabs(d[bot]) + fabs(d[bot + 1])))
+            bot++;
+        if (bot < n - 1) e[bot] = 0.0;
+        if (bot == top) { top++; continue; }     /* d[top] has converged */
         if (++iters > cap) return -1;
-        /* Wilkinson shift from the trailing 2x2 of the unreduced block */
-        double dd = 0.5 * (d[hi - 1] - d[hi]);
-        double b2 = e[hi - 1] * e[hi - 1];
-        double den = dd + (dd >= 0.0 ? 1.0 : -1.0) * hypot(dd, e[hi - 1]);
-        double mu = d[hi] - b2 / den;
-        double x = d[lo] - mu, z = e[lo];
-        for (long k = lo; k < hi; k++) {
+        /* shift: eigenvalue of [[d_top, e_top], [e_top, d_top+1]] nearer d_top */
+        double half = 0.5 * (d[top + 1] - d[top]);
+        double den = half + (half >= 0.0 ? 1.0 : -1.0) * hypot(half, e[top]);
+        double mu = d[top] - e[top] * e[top] / den;
+        /* first rotation from the last column of T - mu I, then chase the
+         * bulge up to the top of the block */
+        double x = d[bot] - mu, z = e[bot - 1];
+        for (long j = bot; j > top; j--) {
             double r = hypot(x, z), c = 1.0, s = 0.0;
             if (r != 0.0) { c = x / r; s = z / r; }
-            if (k > lo) e[k - 1] = r;
-            double a = d[k], b = e[k], a1 = d[k + 1];
-            d[k] = c * c * a + 2.0 * c * s * b + s * s * a1;
-            d[k + 1] = s * s * a - 2.0 * c * s * b + c * c * a1;
-            e[k] = c * s * (a1 - a) + (c * c - s * s) * b;
-            if (k < hi - 1) {
-                x = e[k];
-                z = s * e[k + 1];
-                e[k + 1] = c * e[k + 1];
+            if (j < bot) e[j] = r;
+            double a = d[j], b = e[j - 1], a1 = d[j - 1];
+            d[j] = c * c * a + 2.0 * c * s * b + s * s * a1;
+            d[j - 1] = s * s * a - 2.0 * c * s * b + c * c * a1;
+            e[j - 1] = c * s * (a1 - a) + (c * c - s * s) * b;
+            if (j > top + 1) {
+                x = e[j - 1];
+                z = s * e[j - 2];
+                e[j - 2] = c * e[j - 2];
             }
             if (Z) {
-                double *zk = Z + k * ldz, *zk1 = Z + (k + 1) * ldz;
+                double *zj = Z + j * ldz, *zj1 = Z + (j - 1) * ldz;
                 for (long i = 0; i < ldz; i++) {
-                    double u = zk[i], w = zk1[i];
-                    zk[i] = c * u + s * w;
-                    zk1[i] = -s * u + c * w;
+                    double u = zj[i], w = zj1[i];
+                    zj[i] = c * u + s * w;
+                    zj1[i] = -s * u + c * w;
                 }
             }
         }
@@ -398,7 +403,7 @@ int orc_eigvalsh(long n, double *A, double *w)
     double *tau = malloc(sizeof(double) * (n > 1 ? n : 1));
     if (n >= 2) orc_tridiagonalize(n, A, w, e, tau, -1);
     else if (n == 1) w[0] = A[0];
-    int rc = (n >= 2) ? orc_tridiag_qr(n, w, e, NULL, 0) : 0;
+    int rc = (n >= 2) ? orc_tridiag_ql(n, w, e, NULL, 0) : 0;
     qsort(w, (size_t)n, sizeof(double), orc_cmp_double);
     free(e); free(tau);
     return rc;
@@ -417,7 +422,7 @@ int orc_eigh_full(long n, double *A, double *w, double *Z)
     memset(Q, 0, sizeof(double) * (size_t)n * (size_t)n);
     for (long i = 0; i < n; i++) Q[i * n + i] = 1.0;
     orc_backtransform(n, A, tau, n, Q);
-    int rc = orc_tridiag_qr(n, w, e, Q, n);
+    int rc = orc_tridiag_ql(n, w, e, Q, n);
     /* selection sort of eigenpairs, ascending */
     for (long i = 0; i < n; i++) {
         long m = i;
@@ -465,7 +470,7 @@ int orc_nearest_eigenpairs_multi(long dim, double *H, long nt, const double *eps
     else orc_tridiagonalize(dim, H, d, e, tau, -1);
     memcpy(w, d, sizeof(double) * dim);
     memcpy(ew, e, sizeof(double) * dim);
-    if (dim > 1) rc = orc_tridiag_qr(dim, w, ew, NULL, 0);
+    if (dim > 1) rc = orc_tridiag_ql(dim, w, ew, NULL, 0);
     qsort(w, (size_t)dim, sizeof(double), orc_cmp_double);
     double emin = w[0], emax = w[dim - 1];
     if (all_evals) memcpy(all_evals, w, sizeof(double) * dim);

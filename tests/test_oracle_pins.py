@@ -150,7 +150,7 @@ def test_J0_diagonal_limit():
 
 # -------------------------------------------------------- eigensolver pins
 
-def test_tridiagonal_qr_laplacian_closed_form():
+def test_tridiagonal_ql_laplacian_closed_form():
     n = 200
     w = oracle.tridiag_eigvals(np.full(n, 2.0), np.full(n - 1, -1.0))
     k = np.arange(1, n + 1)
@@ -333,6 +333,21 @@ def test_kl_two_state_closed_form():
     assert abs(oracle.kl_divergence(psi, phi) - exp) < 1e-15
     phi2 = np.zeros(6); phi2[0] = 1.0
     assert oracle.kl_divergence(psi, phi2) == math.inf
+
+
+def test_dynamical_fraction_pins_the_wave_vector():
+    # Supplementary "Dynamical spin fraction": M = sum_j S^z_j exp(2 pi i j / L),
+    # site j = bit j-1.  L = 4, psi = 1/2 |word 3> + sqrt(3)/2 |word 5>:
+    # word 3 (sites 1, 2 up) has m = (i - 1 - (-i) - 1) / 2 = i - 1, word 5
+    # (sites 1, 3 up) has m = (i + 1 - i - 1) / 2 = 0, so <M> = (i - 1) / 4,
+    # |<M>|^2 = 1/8, <|M|^2> = |i - 1|^2 / 4 = 1/2 and f = 1 - 1/4 = 3/4.
+    # Another wave-vector changes it (pi / L gives 0.17, 4 pi / L gives 1/4).
+    L = 4
+    b = oracle.basis(L)
+    psi = np.zeros(b.size)
+    psi[oracle.rank(b, 3)] = 0.5
+    psi[oracle.rank(b, 5)] = math.sqrt(3.0) / 2.0
+    assert abs(oracle.dynamical_fraction(L, psi, b) - 0.75) < 1e-14
 
 
 def test_dynamical_fraction_two_configurations():
