@@ -68,6 +68,17 @@ typedef enum {
 #define MBL_WANT_VECTORS  1u  /* copy eigenvectors to result.evecs */
 #define MBL_WANT_OBS      2u  /* compute r, S_1, S_E into result (default on in mbl_problem_init) */
 #define MBL_WANT_OBS_EXTRA 4u /* also S_2, F, f and KL (result.s2, .fluct, .dynfrac, .kl) */
+/* Test hooks: each forces one failure path of the request so that its
+ * documented outcome can be checked; the context stays usable afterwards. */
+#define MBL_HOOK_IR_STALL32 0x100u /* refinement with FP32 factors reports stagnation at its
+                                      first sweep: the request refactors in FP64 and goes on
+                                      (result.fallback = 1, MBL_OK) */
+#define MBL_HOOK_IR_STALL64 0x200u /* refinement with FP64 factors reports stagnation at its
+                                      first sweep: MBL_ENUMERIC (no wider precision to fall
+                                      back to) */
+#define MBL_HOOK_NO_CONV    0x400u /* the Krylov convergence test never passes: the iteration
+                                      stops after max_restarts restarts and the request ends
+                                      with MBL_ENOTCONV and its partial results */
 
 /* One shift-invert eigenproblem (section "Numerical method"). */
 typedef struct {
@@ -85,6 +96,9 @@ typedef struct {
     int block;             /* Krylov block size b (right-hand sides per LU pass); 0 -> default */
     int ncv;               /* Krylov basis size; 0 -> default from nev and block */
     int max_restarts;      /* 0 -> default */
+    size_t fail_alloc_bytes; /* test hook: 0 = off; otherwise every device allocation of this
+                              request fails (MBL_ENOMEM) once the request has allocated this many
+                              bytes in total; the context stays usable */
 } mbl_problem;
 
 /* Results; every pointer is a caller-owned host buffer or NULL (not wanted). */
@@ -172,6 +186,18 @@ int mbl_extremal(mbl_ctx *ctx, int L, double J, const double *fields_host,
 int mbl_symbolic(mbl_ctx *ctx, int L, mbl_symbolic_info *info);
 /* Fill-reducing permutation: perm_host[k] = basis index eliminated k-th. */
 int mbl_ordering(mbl_ctx *ctx, int L, int32_t *perm_host);
+/* The assembly tree of dense fronts behind mbl_symbolic (test and inspection
+ * hook).  Front f (post-order: children before parents) eliminates the
+ * permuted indices first[f] .. first[f] + npiv[f] - 1 and passes an update to
+ * the ncontrib[f] contribution rows contrib[cptr[f] .. cptr[f] + ncontrib[f] - 1]
+ * (permuted indices, ascending) on to front parent[f] (-1 for a root).  Call
+ * with NULL arrays to get *n_fronts and *n_contrib, then again with host arrays
+ * of those lengths (first, npiv, ncontrib, parent: n_fronts int32; cptr:
+ * n_fronts int64; contrib: n_contrib int32).  Either size pointer may be NULL
+ * on the second call. */
+int mbl_front_tree(mbl_ctx *ctx, int L, int32_t *first, int32_t *npiv, int32_t *ncontrib,
+                   int32_t *parent, int64_t *cptr, int32_t *contrib, int64_t *n_fronts,
+                   int64_t *n_contrib);
 /* x = (H - sigma)^-1 b for nrhs right-hand sides (column-major dim x nrhs):
  * multifrontal LU of H - sigma in precision prec, then forward/back solves
  * with FP64 iterative refinement. */

@@ -22,6 +22,7 @@ MBL_OK, MBL_EINVAL, MBL_ENOMEM, MBL_ENOTCONV = 0, -1, -2, -3
 MBL_ENUMERIC, MBL_EDEVICE, MBL_EBUSY, MBL_ENOTFOUND = -4, -5, -6, -7
 MBL_FP64, MBL_FP32_IR64 = 0, 1
 MBL_WANT_VECTORS, MBL_WANT_OBS, MBL_WANT_OBS_EXTRA = 1, 2, 4
+MBL_HOOK_IR_STALL32, MBL_HOOK_IR_STALL64, MBL_HOOK_NO_CONV = 0x100, 0x200, 0x400
 MBL_NBIN = 10
 BIN_NAMES = ("r", "s1", "s2", "se", "se2", "fluct", "dynfrac", "kl", "edens", "nconv")
 MBL_L_MAX = 22
@@ -29,7 +30,8 @@ MBL_L_MAX = 22
 # every symbol include/mbl.h declares
 EXPORTS = ("mbl_create", "mbl_destroy", "mbl_strerror", "mbl_last_error", "mbl_problem_init",
            "mbl_sector_dim", "mbl_fields", "mbl_basis", "mbl_rank", "mbl_hamiltonian",
-           "mbl_spmv", "mbl_extremal", "mbl_symbolic", "mbl_ordering", "mbl_shift_solve",
+           "mbl_spmv", "mbl_extremal", "mbl_symbolic", "mbl_ordering", "mbl_front_tree",
+           "mbl_shift_solve",
            "mbl_observables", "mbl_observables_extra", "mbl_solve", "mbl_footprint",
            "mbl_serve_start", "mbl_submit", "mbl_poll", "mbl_wait", "mbl_serve_stats",
            "mbl_profile_enable", "mbl_profile_read", "mbl_sweep", "mbl_disorder_average")
@@ -43,7 +45,8 @@ class mbl_problem(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int), ("J", _d), ("h", _d), ("seed", ctypes.c_uint64),
                 ("fields", _pd), ("eps", _d), ("sigma", _d), ("nev", ctypes.c_int),
                 ("prec", ctypes.c_int), ("tol", _d), ("flags", ctypes.c_uint32),
-                ("block", ctypes.c_int), ("ncv", ctypes.c_int), ("max_restarts", ctypes.c_int)]
+                ("block", ctypes.c_int), ("ncv", ctypes.c_int), ("max_restarts", ctypes.c_int),
+                ("fail_alloc_bytes", ctypes.c_size_t)]
 
 
 class mbl_result(ctypes.Structure):
@@ -112,6 +115,10 @@ def lib() -> ctypes.CDLL:
     L.mbl_extremal.argtypes = [vp, ctypes.c_int, _d, _pd, _pd, _pd]
     L.mbl_symbolic.argtypes = [vp, ctypes.c_int, ctypes.POINTER(mbl_symbolic_info)]
     L.mbl_ordering.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]
+    _pi32 = ctypes.POINTER(ctypes.c_int32)
+    L.mbl_front_tree.argtypes = [vp, ctypes.c_int, _pi32, _pi32, _pi32, _pi32,
+                                 ctypes.POINTER(_i64), _pi32, ctypes.POINTER(_i64),
+                                 ctypes.POINTER(_i64)]
     L.mbl_shift_solve.argtypes = [vp, ctypes.c_int, _d, _pd, _d, ctypes.c_int, ctypes.c_int, _pd,
                                   _pd, ctypes.POINTER(mbl_solve_info)]
     L.mbl_observables.argtypes = [vp, ctypes.c_int, ctypes.c_int, _pd, _pd, _pd, _pd, _pd]
@@ -257,6 +264,23 @@ class Context:
                "mbl_ordering")
         return out
 
+    def mbl_front_tree(self, L: int) -> dict:
+        """Fronts of the symbolic analysis: first, npiv, ncontrib, parent, cptr
+        (per front, post-order) and the concatenated contribution rows."""
+        nf, nc = _i64(), _i64()
+        _check(lib().mbl_front_tree(self._h, L, None, None, None, None, None, None,
+                                    ctypes.byref(nf), ctypes.byref(nc)), "mbl_front_tree")
+        out = {k: np.zeros(nf.value, dtype=np.int32) for k in ("first", "npiv", "ncontrib", "parent")}
+        out["cptr"] = np.zeros(nf.value, dtype=np.int64)
+        out["contrib"] = np.zeros(max(nc.value, 1), dtype=np.int32)
+        p32 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        _check(lib().mbl_front_tree(self._h, L, p32(out["first"]), p32(out["npiv"]),
+                                    p32(out["ncontrib"]), p32(out["parent"]),
+                                    out["cptr"].ctypes.data_as(ctypes.POINTER(_i64)),
+                                    p32(out["contrib"]), None, None), "mbl_front_tree")
+        out["contrib"] = out["contrib"][:nc.value]
+        return out
+
     def mbl_shift_solve(self, L: int, J: float, fields, sigma: float, b, prec: int = MBL_FP64):
         f = np.ascontiguousarray(fields, dtype=np.float64)
         b = np.asfortranarray(b, dtype=np.float64)
@@ -288,17 +312,18 @@ class Context:
 
     # -- whole path
     def _prepare(self, L, h, seed, eps, nev, J, prec, fields, sigma, tol, vectors, extra, block,
-                 ncv, entanglement):
+                 ncv, entanglement, hooks=0, max_restarts=0, fail_alloc=0):
         pr = mbl_problem()
         lib().mbl_problem_init(ctypes.byref(pr))
         pr.L, pr.J, pr.h, pr.seed, pr.eps, pr.sigma, pr.nev = L, J, h, seed, eps, sigma, nev
         pr.prec, pr.tol, pr.block, pr.ncv = prec, tol, block, ncv
+        pr.max_restarts, pr.fail_alloc_bytes = max_restarts, fail_alloc
         f = None
         if fields is not None:
             f = np.ascontiguousarray(fields, dtype=np.float64)
             pr.fields = _pd_of(f)
         pr.flags = MBL_WANT_OBS | (MBL_WANT_VECTORS if vectors else 0) | \
-            (MBL_WANT_OBS_EXTRA if extra else 0)
+            (MBL_WANT_OBS_EXTRA if extra else 0) | hooks
         n = mbl_sector_dim(L) if 2 <= L <= MBL_L_MAX else 1
         nb = max(nev, 1)
         bufs = dict(evals=np.zeros(nb), resid=np.zeros(nb), r=np.zeros(max(nev - 2, 1)),
@@ -333,9 +358,11 @@ class Context:
     def mbl_solve(self, L: int, h: float, seed: int, eps: float, nev: int, *, J: float = 1.0,
                   prec: int = MBL_FP64, fields=None, sigma: float = math.nan, tol: float = 0.0,
                   vectors: bool = False, extra: bool = False, block: int = 0, ncv: int = 0,
-                  entanglement: bool = True, allow_notconv: bool = False) -> dict:
+                  entanglement: bool = True, allow_notconv: bool = False, hooks: int = 0,
+                  max_restarts: int = 0, fail_alloc: int = 0) -> dict:
         pr, res, bufs, _f = self._prepare(L, h, seed, eps, nev, J, prec, fields, sigma, tol,
-                                          vectors, extra, block, ncv, entanglement)
+                                          vectors, extra, block, ncv, entanglement, hooks,
+                                          max_restarts, fail_alloc)
         code = lib().mbl_solve(self._h, ctypes.byref(pr), ctypes.byref(res))
         _check(code, "mbl_solve", allow=(MBL_ENOTCONV,) if allow_notconv else ())
         out = self._collect(res, bufs, nev, vectors)

@@ -249,6 +249,32 @@ int mbl_ordering(mbl_ctx *ctx, int L, int32_t *perm_host) {
     });
 }
 
+int mbl_front_tree(mbl_ctx *ctx, int L, int32_t *first, int32_t *npiv, int32_t *ncontrib,
+                   int32_t *parent, int64_t *cptr, int32_t *contrib, int64_t *n_fronts,
+                   int64_t *n_contrib) {
+    if (!ctx) return MBL_EINVAL;
+    return guarded([&] {
+        std::lock_guard<std::recursive_mutex> lk(ctx->c->mu);
+        check_L(L);
+        Context &c = *ctx->c;
+        MBL_HIP(hipSetDevice(c.device));
+        Plan &p = c.plan(L);
+        c.ensure_symbolic(p);
+        const FrontTree &t = p.tree;
+        if (n_fronts) *n_fronts = (int64_t)t.fronts.size();
+        if (n_contrib) *n_contrib = (int64_t)t.contrib.size();
+        for (size_t f = 0; f < t.fronts.size(); f++) {
+            const Front &F = t.fronts[f];
+            if (first) first[f] = F.first;
+            if (npiv) npiv[f] = F.p;
+            if (ncontrib) ncontrib[f] = F.c;
+            if (parent) parent[f] = F.parent;
+            if (cptr) cptr[f] = F.cptr;
+        }
+        if (contrib) std::memcpy(contrib, t.contrib.data(), sizeof(int32_t) * t.contrib.size());
+    });
+}
+
 int mbl_shift_solve(mbl_ctx *ctx, int L, double J, const double *fields_host, double sigma,
                     int prec, int nrhs, const double *b_host, double *x_host,
                     mbl_solve_info *info) {
@@ -326,6 +352,10 @@ static int observables_impl(mbl_ctx *ctx, int L, int nev, const double *evals_ho
         }
         d2h(qh.data(), q.ptr<double>(), qh.size(), c.stream);
         MBL_HIP(hipStreamSynchronize(c.stream));
+        if (se_host)
+            for (int j = 0; j < nev; j++)
+                if (!std::isfinite(se_host[j]))
+                    throw Error(MBL_ENUMERIC, "entanglement: non-finite result");
         for (int j = 0; j < nev; j++) {
             const double *v = &qh[(size_t)j * OBS_NQ];
             if (s1_host) s1_host[j] = v[1];

@@ -44,6 +44,9 @@ void set_last_error(const std::string &msg);
 // Device allocation accounting against the context budget.
 struct Budget {
     size_t limit = 0, used = 0, peak = 0;
+    // test hook: allocations fail once `armed` bytes have been allocated since
+    // the hook was armed (0 = off)
+    size_t armed = 0, since_armed = 0;
 };
 
 // Owning device buffer of bytes (typed views through ptr<T>()).
@@ -63,6 +66,12 @@ class DevBuf {
             throw Error(MBL_ENOMEM, "device budget exceeded: need " + std::to_string(bytes) +
                                         " B with " + std::to_string(b->used) + " of " +
                                         std::to_string(b->limit) + " B in use");
+        if (b && b->armed) {
+            if (b->since_armed + bytes > b->armed)
+                throw Error(MBL_ENOMEM, "device allocation of " + std::to_string(bytes) +
+                                            " B refused by the fail_alloc_bytes test hook");
+            b->since_armed += bytes;
+        }
         void *p = nullptr;
         hipError_t e = hipMalloc(&p, bytes);
         if (e != hipSuccess)

@@ -7,11 +7,13 @@
 //
 // S_E: with A = sites 1..L/2 (low bits b) and B the rest (high bits a), the
 // amplitude matrix M[a][b] = psi(a b) vanishes unless popcount(a) + popcount(b)
-// = L/2, so it is block diagonal over k = popcount(b): block k is
-// C(L/2, k) x C(L/2, k) and the blocks tile the sector exactly (Vandermonde).
-// rho_A is the direct sum of G_k = M_k^T M_k.  Each (vector, block) is one
-// workgroup: Gram matrix, Householder tridiagonalisation, then all eigenvalues
-// by Sturm-sequence bisection in parallel, and -sum lambda ln lambda.
+// is the sector's up-spin count, so it is block diagonal over k = popcount(b):
+// block k is C(L - L/2, nup - k) x C(L/2, k) and the blocks tile the sector
+// exactly (Vandermonde).  The Schmidt values of psi are the singular values of
+// these blocks.  Each (vector, block) is one workgroup: Golub-Kahan-Lanczos
+// bidiagonalisation of the block with full reorthogonalisation, then the
+// singular values of the bidiagonal by Sturm bisection on its Golub-Kahan
+// tridiagonal, and -sum lambda ln lambda over lambda = sigma^2 / |psi|^2.
 #include <cmath>
 
 #include "common.hpp"
@@ -44,19 +46,23 @@ __device__ __forceinline__ int sub_rank(uint32_t w) {
     return r;
 }
 
-// destination of each sector state in the concatenated blocks (row a, col b,
-// row-major): block k holds the states with k up spins in A (the low la =
-// L / 2 bits b), C(L - la, nup - k) rows a by C(la, k) columns b
+// destination of each sector state in the concatenated blocks: block k holds
+// the states with k up spins in A (the low la = L / 2 bits b), nr = C(L - la,
+// nup - k) rows a by d = C(la, k) columns b, stored as the fewer of the two
+// kinds of lines, each contiguous (row-major if nr <= d, else column-major)
 __global__ void k_block_index(int L, int64_t dim, const uint32_t *basis, const int64_t *blockoff,
                               int32_t *dst) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= dim) return;
-    int la = L / 2;
+    int la = L / 2, lb = L - la, nup = (L + 1) / 2;
     uint32_t s = basis[i];
     uint32_t b = s & ((1u << la) - 1u), a = s >> la;
     int k = __popc(b);
     int d = (int)o_binom[la][k];
-    dst[i] = (int32_t)(blockoff[k] + (int64_t)sub_rank(a) * d + sub_rank(b));
+    int nr = (int)o_binom[lb][nup - k];
+    int ra = sub_rank(a), rb = sub_rank(b);
+    int64_t o = (nr <= d) ? (int64_t)ra * d + rb : (int64_t)rb * nr + ra;
+    dst[i] = (int32_t)(blockoff[k] + o);
 }
 
 __global__ void k_scatter_blocks(int64_t dim, int nvec, const int32_t *dst, const double *psi,
@@ -81,121 +87,204 @@ __device__ double block_reduce_sum(double v, double *sh) {
     return r;
 }
 
-// Sturm count: number of eigenvalues of the tridiagonal (d, e) below x
-__device__ int sturm_count(int n, const double *d, const double *e2, double x, double pivmin) {
-    int cnt = 0;
-    double q = d[0] - x;
-    if (fabs(q) < pivmin) q = -pivmin;
-    if (q < 0) cnt++;
-    for (int i = 1; i < n; i++) {
-        q = d[i] - x - e2[i - 1] / q;
-        if (fabs(q) < pivmin) q = -pivmin;
-        if (q < 0) cnt++;
-    }
-    return cnt;
+constexpr int SGT = 256;                  // threads of an S_E workgroup
+constexpr int SGW = SGT / 64;             // its wavefronts
+constexpr int SG_MAXN = 512;              // longest line (C(11, 5) = 462 at L = 22)
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
 }
 
-// one workgroup per (vector, block): entropy contribution of block k of vector v
-// (rows a: the nup - k up spins of B among L - la sites; columns b: the k up
-// spins of A; square for even L, one site more on the B side for odd L)
-__global__ __launch_bounds__(SEB) void k_se_block(int L, int nup, int nvec, int64_t dim,
-                                                  const int64_t *blockoff, const double *norms2,
-                                                  const double *M,
-                                                  double *scratch, int64_t scratch_stride,
-                                                  double *part) {
-    __shared__ double sh[SEB];
-    __shared__ double dd[512], ee[512], e2[512], vv[512], pp[512];
+// sum over the workgroup, same value in every thread
+__device__ __forceinline__ double group_sum(double v, double *red) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int q = 0; q < SGW; q++) t += red[q];
+    __syncthreads();
+    return t;
+}
+
+// Components in [-1/2, 1/2) of the start / restart vectors: SplitMix64
+// (Steele, Lea, Flood 2014) of a key per (block, draw) and the index.
+__device__ __forceinline__ double gkl_rand(uint64_t key, int i) {
+    uint64_t z = key + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
+// x (length n, LDS) <- x - Q Q^T x twice (classical Gram-Schmidt, two
+// passes) against the k orthonormal vectors Q[q * n ...], q < k (global)
+__device__ void gkl_orth(double *x, int n, const double *Q, int k, double *coef) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int pass = 0; pass < 2 && k > 0; pass++) {
+        for (int q = wv; q < k; q += SGW) {
+            const double *qv = Q + (int64_t)q * n;
+            double a = 0.0;
+            for (int e = lane; e < n; e += 64) a += qv[e] * x[e];
+            a = wave_sum(a);
+            if (lane == 0) coef[q] = a;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < n; e += SGT) {
+            double a = x[e];
+            for (int q = 0; q < k; q++) a -= coef[q] * Q[(int64_t)q * n + e];
+            x[e] = a;
+        }
+        __syncthreads();
+    }
+}
+
+// x <- x / |x| if |x| > tiny; otherwise x <- a fresh direction orthogonal to
+// the k vectors of Q (random, key).  Returns |x| or 0 for a fresh direction.
+__device__ double gkl_normalize(double *x, int n, const double *Q, int k, double tiny,
+                                uint64_t key, double *coef, double *red) {
+    double nr = sqrt(group_sum([&] {
+        double a = 0.0;
+        for (int e = threadIdx.x; e < n; e += SGT) a += x[e] * x[e];
+        return a;
+    }(), red));
+    double keep = nr;
+    for (int draw = 0; nr <= tiny && draw < 4; draw++) {
+        keep = 0.0;
+        for (int e = threadIdx.x; e < n; e += SGT) x[e] = gkl_rand(key + 7919ULL * draw, e);
+        __syncthreads();
+        gkl_orth(x, n, Q, k, coef);
+        nr = sqrt(group_sum([&] {
+            double a = 0.0;
+            for (int e = threadIdx.x; e < n; e += SGT) a += x[e] * x[e];
+            return a;
+        }(), red));
+    }
+    const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
+    for (int e = threadIdx.x; e < n; e += SGT) x[e] *= inv;
+    __syncthreads();
+    return keep;
+}
+
+// number of eigenvalues below x of the symmetric tridiagonal with zero
+// diagonal and squared off-diagonals e2[0 .. m-2] (Sturm sequence)
+__device__ int gk_count(int m, const double *e2, double x, double pivmin) {
+    int c = 0;
+    double q = -x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) c++;
+    for (int i = 1; i < m; i++) {
+        q = -x - e2[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        if (q < 0.0) c++;
+    }
+    return c;
+}
+
+// One workgroup per (vector, block): entropy contribution of block k of vector
+// v.  The block is cnt lines of length len (cnt <= len).  Its singular values
+// come from the Golub-Kahan-Lanczos bidiagonalisation with full
+// reorthogonalisation (Golub & Kahan 1965): U^T M V = B, lower bidiagonal with
+// diagonal alpha and subdiagonal beta, after cnt steps (a step whose new
+// vector vanishes continues from a fresh orthogonal direction with a zero
+// coupling, so U is a basis of the whole line space and sigma(B) = sigma(M)).
+// The singular values of B are the positive eigenvalues of the 2 cnt x 2 cnt
+// tridiagonal with zero diagonal and off-diagonals alpha_0, beta_1, alpha_1,
+// ..., alpha_cnt-1, found by Sturm bisection, one thread per value.
+// scratch: per (vector, block) cnt x cnt for U and cnt x len for V.
+__global__ __launch_bounds__(SGT) void k_se_gkl(int L, int nup, int64_t dim,
+                                                const int64_t *blockoff, const int64_t *gkloff,
+                                                int64_t gkl_stride, const double *norms2,
+                                                const double *M, double *scratch, double *part) {
+    __shared__ double xr[SG_MAXN], xp[SG_MAXN], uj[SG_MAXN], coef[SG_MAXN];
+    __shared__ double al[SG_MAXN], be[SG_MAXN], e2[2 * SG_MAXN];
+    __shared__ double red[SGW];
     const int la = L / 2, lb = L - la;
-    int v = blockIdx.x / (la + 1), k = blockIdx.x % (la + 1);
-    int d = (int)o_binom[la][k];
-    int nr = (nup - k >= 0 && nup - k <= lb) ? (int)o_binom[lb][nup - k] : 0;
-    if (nr == 0 || d == 0) {                      // no state of the sector in this block
+    const int v = blockIdx.x / (la + 1), k = blockIdx.x % (la + 1);
+    const int d = (int)o_binom[la][k];
+    const int nr = (nup - k >= 0 && nup - k <= lb) ? (int)o_binom[lb][nup - k] : 0;
+    const int cnt = min(nr, d), len = max(nr, d);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (cnt == 0) {                               // no state of the sector in this block
         if (threadIdx.x == 0) part[blockIdx.x] = 0.0;
         return;
     }
-    const double *Mk = M + (int64_t)v * dim + blockoff[k];   // nr x d, row a, col b
-    double *G = scratch + (int64_t)blockIdx.x * scratch_stride;  // d x d column-major
-    // Gram G = Mk^T Mk (the reduced density matrix of A on this block)
-    for (int e = threadIdx.x; e < d * d; e += SEB) {
-        int i = e % d, j = e / d;
-        double s = 0.0;
-        for (int a = 0; a < nr; a++) s += Mk[(int64_t)a * d + i] * Mk[(int64_t)a * d + j];
-        G[e] = s;
+    const double *X = M + (int64_t)v * dim + blockoff[k];
+    double *U = scratch + (int64_t)v * gkl_stride + gkloff[k];
+    double *V = U + (int64_t)cnt * cnt;
+    const double fro2 = group_sum([&] {
+        double a = 0.0;
+        for (int64_t e = threadIdx.x; e < (int64_t)cnt * len; e += SGT) a += X[e] * X[e];
+        return a;
+    }(), red);
+    // a new vector below tiny counts as vanished: its share of sigma is
+    // below the rounding of the bidiagonalisation
+    const double tiny = 1e-14 * sqrt(fro2);
+    const uint64_t key = 0x5E5EC0DEULL + 0x100000001B3ULL * (uint64_t)blockIdx.x;
+    for (int i = threadIdx.x; i < cnt; i += SGT) uj[i] = gkl_rand(key, i);
+    __syncthreads();
+    gkl_normalize(uj, cnt, U, 0, -1.0, key + 1, coef, red);
+    for (int i = threadIdx.x; i < cnt; i += SGT) U[i] = uj[i];
+    double bprev = 0.0;                           // beta_j, coupling of u_j to v_j-1
+    for (int j = 0; j < cnt; j++) {
+        // xr = M^T u_j - beta_j v_j-1
+        for (int e = threadIdx.x; e < len; e += SGT) {
+            double a = 0.0;
+            for (int i = 0; i < cnt; i++) a += X[(int64_t)i * len + e] * uj[i];
+            if (j > 0) a -= bprev * V[(int64_t)(j - 1) * len + e];
+            xr[e] = a;
+        }
+        __syncthreads();
+        gkl_orth(xr, len, V, j, coef);
+        double a = gkl_normalize(xr, len, V, j, tiny, key + 2 * (uint64_t)j + 2, coef, red);
+        if (threadIdx.x == 0) al[j] = a;
+        for (int e = threadIdx.x; e < len; e += SGT) V[(int64_t)j * len + e] = xr[e];
+        __syncthreads();
+        if (j + 1 == cnt) break;
+        // xp = M v_j - alpha_j u_j
+        for (int i = wv; i < cnt; i += SGW) {
+            const double *xi = X + (int64_t)i * len;
+            double t = 0.0;
+            for (int e = lane; e < len; e += 64) t += xi[e] * xr[e];
+            t = wave_sum(t);
+            if (lane == 0) xp[i] = t - a * uj[i];
+        }
+        __syncthreads();
+        gkl_orth(xp, cnt, U, j + 1, coef);
+        double b = gkl_normalize(xp, cnt, U, j + 1, tiny, key + 2 * (uint64_t)j + 3, coef, red);
+        if (threadIdx.x == 0) be[j + 1] = b;
+        for (int i = threadIdx.x; i < cnt; i += SGT) {
+            U[(int64_t)(j + 1) * cnt + i] = xp[i];
+            uj[i] = xp[i];
+        }
+        bprev = b;
+        __syncthreads();
+    }
+    // squared off-diagonals of the Golub-Kahan tridiagonal: alpha_0, beta_1, alpha_1, ...
+    const int m = 2 * cnt;
+    for (int i = threadIdx.x; i < m - 1; i += SGT) {
+        double x = (i & 1) ? be[(i + 1) / 2] : al[i / 2];
+        e2[i] = x * x;
     }
     __syncthreads();
-    // Householder tridiagonalisation of G (full symmetric storage)
-    for (int c = 0; c + 2 < d; c++) {
-        int mm = d - c - 1;
-        double sig = 0.0;
-        for (int i = 1 + threadIdx.x; i < mm; i += SEB) {
-            double x = G[(c + 1 + i) + (int64_t)c * d];
-            sig += x * x;
-        }
-        sig = block_reduce_sum(sig, sh);
-        double alpha = G[(c + 1) + (int64_t)c * d];
-        if (threadIdx.x == 0) dd[c] = G[c + (int64_t)c * d];
-        if (sig == 0.0) {
-            if (threadIdx.x == 0) ee[c] = alpha;
-            __syncthreads();
-            continue;
-        }
-        double nrm = sqrt(alpha * alpha + sig);
-        double beta = (alpha <= 0.0) ? nrm : -nrm;
-        double tau = (beta - alpha) / beta;
-        double scal = 1.0 / (alpha - beta);
-        for (int i = threadIdx.x; i < mm; i += SEB)
-            vv[i] = (i == 0) ? 1.0 : G[(c + 1 + i) + (int64_t)c * d] * scal;
-        if (threadIdx.x == 0) ee[c] = beta;
-        __syncthreads();
-        // p = tau * B v with B = G[c+1.., c+1..]
-        for (int i = threadIdx.x; i < mm; i += SEB) {
-            double s = 0.0;
-            for (int j = 0; j < mm; j++) s += G[(c + 1 + i) + (int64_t)(c + 1 + j) * d] * vv[j];
-            pp[i] = tau * s;
-        }
-        __syncthreads();
-        double pv = 0.0;
-        for (int i = threadIdx.x; i < mm; i += SEB) pv += pp[i] * vv[i];
-        pv = block_reduce_sum(pv, sh);
-        double K = 0.5 * tau * pv;
-        for (int i = threadIdx.x; i < mm; i += SEB) pp[i] -= K * vv[i];
-        __syncthreads();
-        for (int e = threadIdx.x; e < mm * mm; e += SEB) {
-            int i = e % mm, j = e / mm;
-            G[(c + 1 + i) + (int64_t)(c + 1 + j) * d] -= vv[i] * pp[j] + pp[i] * vv[j];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        if (d >= 2) {
-            dd[d - 2] = G[(d - 2) + (int64_t)(d - 2) * d];
-            ee[d - 2] = G[(d - 1) + (int64_t)(d - 2) * d];
-        }
-        dd[d - 1] = G[(d - 1) + (int64_t)(d - 1) * d];
-    }
-    __syncthreads();
-    // bisection for every eigenvalue, in parallel
-    double lo = 1e300, hi = -1e300, tmax = 0.0;
-    for (int i = 0; i < d; i++) {
-        double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < d ? fabs(ee[i]) : 0.0);
-        lo = fmin(lo, dd[i] - r);
-        hi = fmax(hi, dd[i] + r);
-        tmax = fmax(tmax, fabs(dd[i]) + r);
-    }
-    for (int i = threadIdx.x; i + 1 < d; i += SEB) e2[i] = ee[i] * ee[i];
-    __syncthreads();
-    double pivmin = 1e-300 + 1e-30 * tmax * tmax;
+    double bound = 0.0;
+    for (int i = 0; i < m - 1; i++) bound = fmax(bound, sqrt(e2[i]));
+    bound = 2.0 * bound + 1e-300;
+    const double pivmin = 1e-300 + 1e-30 * bound * bound;
+    const double inv = 1.0 / norms2[v];
     double ent = 0.0;
-    for (int idx = threadIdx.x; idx < d; idx += SEB) {
-        double a = lo, b = hi;
-        for (int it = 0; it < 100 && b - a > 4e-17 * fmax(tmax, 1e-300); it++) {
-            double mid = 0.5 * (a + b);
-            if (sturm_count(d, dd, e2, mid, pivmin) > idx) b = mid; else a = mid;
+    for (int i = threadIdx.x; i < cnt; i += SGT) {
+        // sigma_i, the i-th smallest singular value: count(x) >= cnt + i + 1 iff sigma_i < x
+        double lo = 0.0, hi = bound;
+        for (int it = 0; it < 200 && hi - lo > 2.3e-16 * bound; it++) {
+            const double mid = 0.5 * (lo + hi);
+            if (gk_count(m, e2, mid, pivmin) >= cnt + i + 1) hi = mid; else lo = mid;
         }
-        double lam = 0.5 * (a + b) / norms2[v];
+        const double sg = 0.5 * (lo + hi);
+        const double lam = sg * sg * inv;
         if (lam > 0.0) ent -= lam * log(lam);
     }
-    ent = block_reduce_sum(ent, sh);
+    ent = group_sum(ent, red);
     if (threadIdx.x == 0) part[blockIdx.x] = ent;
 }
 
@@ -296,14 +385,17 @@ void ObsWork::prepare(int L_, const uint32_t *basis, int64_t dim_, int nvec_max,
     nvmax = nvec_max;
     const int la = L / 2, lb = L - la, nup = sector_nup(L);
     std::vector<int64_t> off(la + 2, 0);
-    int64_t maxd = 0;
+    std::vector<int64_t> goff(la + 1, 0);
+    gkl_stride_ = 0;
     for (int k = 0; k <= la; k++) {
         int64_t d = binom(la, k), nr = (nup - k >= 0 && nup - k <= lb) ? binom(lb, nup - k) : 0;
         off[k + 1] = off[k] + nr * d;
-        maxd = std::max(maxd, d);
+        const int64_t cnt = std::min(nr, d), len = std::max(nr, d);
+        MBL_REQUIRE(len <= SG_MAXN, MBL_EINVAL, "entanglement: subsystem block above 512");
+        goff[k] = gkl_stride_;
+        gkl_stride_ += cnt * (cnt + len);           // U (cnt x cnt) and V (cnt x len)
     }
     MBL_REQUIRE(off[la + 1] == dim_, MBL_EINVAL, "entanglement blocks do not cover the sector");
-    maxd_ = maxd;
     d_blockoff.alloc(sizeof(int64_t) * (la + 2), bud);
     h2d(d_blockoff.ptr<int64_t>(), off.data(), off.size(), s);
     d_dst.alloc(sizeof(int32_t) * dim, bud);
@@ -311,7 +403,9 @@ void ObsWork::prepare(int L_, const uint32_t *basis, int64_t dim_, int nvec_max,
                        d_blockoff.ptr<int64_t>(), d_dst.ptr<int32_t>());
     MBL_CHECK_LAUNCH();
     d_M.alloc(sizeof(double) * dim * nvmax, bud);
-    d_scratch.alloc(sizeof(double) * maxd * maxd * (la + 1) * nvmax, bud);
+    d_gkloff.alloc(sizeof(int64_t) * (la + 1), bud);
+    h2d(d_gkloff.ptr<int64_t>(), goff.data(), goff.size(), s);
+    d_gkl.alloc(sizeof(double) * gkl_stride_ * nvmax, bud);
     d_part.alloc(sizeof(double) * (size_t)std::max<int64_t>((int64_t)(la + 1) * nvmax,
                                                             (int64_t)OBS_PARTS * NQ * nvmax), bud);
     d_out.alloc(sizeof(double) * NQ * nvmax + sizeof(double) * 4 * nvmax, bud);
@@ -323,10 +417,9 @@ void ObsWork::entanglement(const double *psi, int64_t ldpsi, int nvec, const dou
     hipLaunchKernelGGL(k_scatter_blocks, dim3(cdiv(dim, 256)), dim3(256), 0, s, dim, nvec,
                        d_dst.ptr<int32_t>(), psi, ldpsi, d_M.ptr<double>());
     MBL_CHECK_LAUNCH();
-    MBL_REQUIRE(maxd_ <= 512, MBL_EINVAL, "entanglement: subsystem block above 512");
-    hipLaunchKernelGGL(k_se_block, dim3(nvec * (la + 1)), dim3(SEB), 0, s, L, sector_nup(L), nvec, dim,
-                       d_blockoff.ptr<int64_t>(), norms2, d_M.ptr<double>(), d_scratch.ptr<double>(),
-                       (int64_t)(maxd_ * maxd_), d_part.ptr<double>());
+    hipLaunchKernelGGL(k_se_gkl, dim3(nvec * (la + 1)), dim3(SGT), 0, s, L, sector_nup(L), dim,
+                       d_blockoff.ptr<int64_t>(), d_gkloff.ptr<int64_t>(), gkl_stride_, norms2,
+                       d_M.ptr<double>(), d_gkl.ptr<double>(), d_part.ptr<double>());
     MBL_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_se_sum, dim3(cdiv(nvec, 64)), dim3(64), 0, s, la + 1, nvec,
                        d_part.ptr<double>(), se_dev);

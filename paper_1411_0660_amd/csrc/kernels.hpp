@@ -57,4 +57,12 @@ void launch_bcomb(int64_t n, int nb, int nrhs, const double *V, int64_t bs, cons
 void launch_sub_scaled_cols(int64_t n, int ncol, const double *e, const double *X, int64_t ldx,
                             double *Y, int64_t ldy, hipStream_t s);
 
+
+// ---- small dense symmetric eigenproblems (k_jacobi.hip) ---------------------
+// A (m x m symmetric, column-major, overwritten) -> eigenvalues w[m] (unsorted)
+// and eigenvectors V (m x m, column j for w[j]); *info = sweeps used or -1.
+// One workgroup; m <= 1024.
+void launch_jacobi_eig(int m, double *A, double *V, double *w, int *info, double tol_abs,
+                       hipStream_t s);
+
 }  // namespace mbl

@@ -22,7 +22,7 @@ class ObsWork {
                  hipStream_t s);
     void vector_sums(const uint32_t *basis, const double *psi, int64_t ld, int nvec,
                      double *out_dev, hipStream_t s);
-    // norms2: |psi_v|^2 on the device (column 0 of vector_sums output, stride OBS_NQ)
+    // norms2: |psi_v|^2 on the device (column 0 of vector_sums output, stride OBS_NQ);
     void entanglement(const double *psi, int64_t ldpsi, int nvec, const double *norms2,
                       double *se_dev, hipStream_t s);
     void gap_ratios(int nev, const double *E_dev, double *r_dev, hipStream_t s);
@@ -30,8 +30,8 @@ class ObsWork {
 
   private:
     int L = -1, nvmax = 0;
-    int64_t dim = 0, maxd_ = 0;
-    DevBuf d_blockoff, d_dst, d_M, d_scratch, d_part, d_out;
+    int64_t dim = 0, gkl_stride_ = 0;     // bidiagonalisation scratch per vector (doubles)
+    DevBuf d_blockoff, d_dst, d_M, d_gkloff, d_gkl, d_part, d_out;
 };
 
 }  // namespace mbl

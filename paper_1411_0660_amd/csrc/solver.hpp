@@ -132,6 +132,9 @@ class Context {
         double tmin = 0.0, tmax = 0.0;   // extreme Ritz values of the last Rayleigh-Ritz
         int restarts = 0, napply = 0, nconv = 0;
     };
+    // all eigenpairs of a small symmetric matrix (host in, host out; device Jacobi)
+    void small_eig(int m, const std::vector<double> &A, std::vector<double> &w,
+                   std::vector<double> &Z);
     KSOut krylov_schur(int64_t n, int b, int ncv, int nkeep, int nwant, Want want,
                        const std::function<void(const double *, double *, int)> &op,
                        const std::function<bool(double, double)> &conv, int max_restarts,
@@ -152,6 +155,7 @@ class Context {
 
     ObsWork obs;
     DevBuf d_psi, d_psi2, d_hpsi, d_e, d_cpart, d_obs, d_r_out, d_se;
+    uint32_t hooks = 0;                // MBL_HOOK_* of the request being solved
     double anorm_ = 1.0;               // ||H - sigma|| estimate of the current factor
     double hnorm_ = 1.0;
     // passes of right-hand-side blocks through the factors, and the vectors
@@ -163,7 +167,7 @@ class Context {
     bool owns_plans_ = true;
     Factor<float> f32_;
     Factor<double> f64_;
-    DevBuf d_vec, d_yv, d_upart, d_xnew, d_r, d_d, d_part, d_V, d_V2, d_W, d_small, d_tnpart;
+    DevBuf d_vec, d_yv, d_upart, d_xnew, d_r, d_d, d_part, d_V, d_V2, d_W, d_small, d_ritz, d_tnpart;
     DevBuf d_gV, d_gZ, d_gpart, d_gcoef;   // GMRES refinement: bases, partials, coefficients
     PinnedBuf h_stage;                     // Krylov coefficients copied back asynchronously
     template <class T> void factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel,

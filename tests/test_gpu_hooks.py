@@ -1,0 +1,125 @@
+"""Failure paths of mbl_solve forced by the test hooks of include/mbl.h, each
+checked for its documented status code and for a context that stays usable
+(a later plain request gives the same results as a fresh context)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1411_0660_amd as mbl
+
+pytestmark = pytest.mark.gpu
+
+EIG_TOL = 1e-10
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ref():
+    """One plain FP64 request per case, from its own context."""
+    out = {}
+    with mbl.Context(0) as c:
+        for key, (L, h, seed, eps, nev) in CASES.items():
+            out[key] = c.mbl_solve(L, h, seed, eps, nev)
+    return out
+
+
+CASES = {"L12": (12, 3.0, 0, 0.5, 20), "L10": (10, 2.0, 1, 0.3, 12)}
+
+
+def same(a, b):
+    for k in ("evals", "resid", "s1", "se", "r"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_fp32_stall_falls_back_to_fp64(ref):
+    L, h, seed, eps, nev = CASES["L12"]
+    say("hook ir-stall32")
+    with mbl.Context(0) as c:
+        g = c.mbl_solve(L, h, seed, eps, nev, prec=mbl.MBL_FP32_IR64,
+                        hooks=mbl.MBL_HOOK_IR_STALL32)
+        assert g["status"] == mbl.MBL_OK and g["fallback"] == 1
+        hn = g["hnorm"]
+        assert np.abs(g["evals"] - ref["L12"]["evals"]).max() <= EIG_TOL * hn
+        assert g["max_resid"] <= 1e-9
+        # the hook ends with the request: the next FP32 request does not fall back
+        g2 = c.mbl_solve(L, h, seed, eps, nev, prec=mbl.MBL_FP32_IR64)
+        assert g2["fallback"] == 0 and g2["max_resid"] <= 1e-9
+        same(c.mbl_solve(L, h, seed, eps, nev), ref["L12"])
+
+
+def test_fp64_stall_is_enumeric(ref):
+    L, h, seed, eps, nev = CASES["L12"]
+    say("hook ir-stall64")
+    with mbl.Context(0) as c:
+        with pytest.raises(mbl.MblError) as ei:
+            c.mbl_solve(L, h, seed, eps, nev, hooks=mbl.MBL_HOOK_IR_STALL64)
+        assert ei.value.code == mbl.MBL_ENUMERIC
+        same(c.mbl_solve(L, h, seed, eps, nev), ref["L12"])
+
+
+@pytest.mark.parametrize("restarts", [1, 3])
+def test_forced_nonconvergence_is_enotconv(ref, restarts):
+    L, h, seed, eps, nev = CASES["L12"]
+    say("hook no-conv", restarts)
+    with mbl.Context(0) as c:
+        g = c.mbl_solve(L, h, seed, eps, nev, hooks=mbl.MBL_HOOK_NO_CONV, max_restarts=restarts,
+                        allow_notconv=True)
+        assert g["status"] == mbl.MBL_ENOTCONV
+        assert g["n_restarts"] == restarts and g["nconv"] < nev
+        # partial results are written: energies of the returned Ritz pairs
+        assert np.all(np.isfinite(g["evals"])) and np.all(np.diff(g["evals"]) >= 0)
+        same(c.mbl_solve(L, h, seed, eps, nev), ref["L12"])
+
+
+def test_restart_limit_without_hook_is_enotconv_or_complete(ref):
+    """A restart limit too small for the Krylov method to converge ends in
+    MBL_ENOTCONV; a request may only return MBL_OK when its window is
+    certified (every returned pair converged and no unconverged pair nearer
+    sigma)."""
+    L, h, seed, eps, nev = 14, 3.0, 2, 0.5, 50
+    say("restart limit", L)
+    with mbl.Context(0) as c:
+        full = c.mbl_solve(L, h, seed, eps, nev)
+        g = c.mbl_solve(L, h, seed, eps, nev, max_restarts=1, allow_notconv=True)
+        if g["status"] == mbl.MBL_OK:
+            assert np.abs(g["evals"] - full["evals"]).max() <= EIG_TOL * full["hnorm"]
+        else:
+            assert g["status"] == mbl.MBL_ENOTCONV and g["nconv"] < nev
+        assert full["n_restarts"] > 1
+
+
+@pytest.mark.parametrize("limit", [1 << 10, 1 << 16, 1 << 20, 1 << 22, 1 << 24])
+def test_allocation_failure_leaves_context_usable(ref, limit):
+    """Every device allocation of the request fails once it has taken `limit`
+    bytes (a fresh context, so the per-L plans are allocated by the request
+    too): the request ends with MBL_ENOMEM, and the next request on the same
+    context gives bitwise the results of an undisturbed context."""
+    L, h, seed, eps, nev = CASES["L10"]
+    say("hook fail-alloc", limit)
+    with mbl.Context(0) as c:
+        try:
+            g = c.mbl_solve(L, h, seed, eps, nev, fail_alloc=limit)
+            same(g, ref["L10"])            # the whole request fitted below the limit
+        except mbl.MblError as e:
+            assert e.code == mbl.MBL_ENOMEM
+        same(c.mbl_solve(L, h, seed, eps, nev), ref["L10"])
+        # and a second size on the same context
+        L2, h2, s2, e2, n2 = CASES["L12"]
+        same(c.mbl_solve(L2, h2, s2, e2, n2), ref["L12"])
+
+
+def test_allocation_failure_in_fp32_path(ref):
+    L, h, seed, eps, nev = CASES["L12"]
+    o = oracle.solve(L, h, seed, eps, nev, vectors=False, observables=False)
+    with mbl.Context(0) as c:
+        c.mbl_solve(8, 1.0, 0, 0.5, 5)                 # plans of another size in place
+        with pytest.raises(mbl.MblError) as ei:
+            c.mbl_solve(L, h, seed, eps, nev, prec=mbl.MBL_FP32_IR64, fail_alloc=1 << 18)
+        assert ei.value.code == mbl.MBL_ENOMEM
+        g = c.mbl_solve(L, h, seed, eps, nev, prec=mbl.MBL_FP32_IR64)
+        assert np.abs(g["evals"] - o["evals"]).max() <= EIG_TOL * o["hnorm"]

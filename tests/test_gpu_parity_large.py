@@ -6,10 +6,12 @@ make_oracle_golden.py from the dense oracle).
 
 L = 18 and 20, where the dense oracle does not fit: certificates the oracle
 computes one eigenpair at a time, in the launch configuration the benchmark
-times (mbl_solve, FP64, nev = 50): residuals ||H psi - E psi|| with H applied
-by the oracle's own CPU code, Rayleigh quotients, S_1 and S_E of sampled
-eigenvectors, orthonormality, and window completeness from a second solve
-at a shifted target whose window overlaps the first.
+times (mbl_solve, FP64, nev = 50): residuals ||H psi - E psi|| and Rayleigh
+quotients of every pair with H applied by the oracle's own CPU code, S_1 of
+every vector and S_E of all (L = 18) or eight (L = 20) vectors recomputed by
+the oracle, orthonormality, and window completeness from a second solve at a
+shifted target whose window overlaps the first; the FP32 LU + FP64 refinement
+path at L = 20 under the same certificates and against the FP64 path.
 """
 import glob
 import json
@@ -22,6 +24,7 @@ import pytest
 
 import oracle
 import paper_1411_0660_amd as mbl
+from parity import assert_subspaces, kl_tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -77,42 +80,38 @@ def test_golden_parity(ctx, path):
         rmask = np.minimum(gaps[:-1], gaps[1:]) >= GAP_MIN * hn
         d = np.abs(g["r"] - np.array(t["r"]))[rmask]
         assert d.max(initial=0.0) <= OBS_TOL, (t["eps"], "r", d.max())
-        # KL(p_n | p_n+1) = sum p ln(p/q) is ill-conditioned where components of
-        # the neighbour are tiny (strongly localized states).  Its first-order
-        # error for a componentwise vector error delta (Davis-Kahan: residual /
-        # gap to the other levels) is est = sum_i p_i min(1, 2 delta / |phi_i|)
-        # + sum_i |ln(p_i / q_i)| min(p_i, 2 delta |psi_i|); the gate is
-        # 1e-7 + 10 est, on pairs separated from their neighbours
+        # residuals of the GPU vectors with H applied by the oracle's own code
         Z = g["evecs"]
         Eg = g["evals"]
+        b = oracle.basis(L)
+        ores = np.array([oracle.residual(L, 1.0, f, Z[:, k], Eg[k], b) for k in range(nev)])
+        assert ores.max() <= RES_TOL * hn, ores.max() / hn
+        # levels closer than GAP_MIN ||H||: eigenvectors compared as subspaces
+        # against the oracle's vectors of the whole cluster (stored at L = 14)
+        if "clusters" in t:
+            for cl in t["clusters"]:
+                Ec = np.array(cl["evals"])
+                Zo = np.array(cl["vecs"]).T
+                inside = np.flatnonzero((Eg >= Ec[0] - EIG_TOL * hn) & (Eg <= Ec[-1] + EIG_TOL * hn))
+                assert inside.size >= 1
+                assert_subspaces(Eg[inside], Z[:, inside], Ec, Zo, hn)
+        # KL(p_n | p_n+1), gated on separated pairs with a tolerance from the
+        # oracle's residuals of the GPU vectors (tests/parity.py: kl_tolerance)
         kmask = sep[:-1] & sep[1:]
-        ktol = np.full(nev - 1, 1e-7)
-        for k in range(nev - 1):
-            gaps_k = [abs(Eg[k + 1] - Eg[k])]
-            if k > 0:
-                gaps_k.append(abs(Eg[k] - Eg[k - 1]))
-            if k + 2 < nev:
-                gaps_k.append(abs(Eg[k + 2] - Eg[k + 1]))
-            delta = max(g["resid"][k], g["resid"][k + 1]) * hn / min(gaps_k) + 1e-14
-            psi, phi = np.abs(Z[:, k]), np.abs(Z[:, k + 1])
-            p_, q_ = psi ** 2, phi ** 2
-            nz = (phi > 0) & (psi > 0)
-            est = np.sum(p_[phi > 0] * np.minimum(1.0, 2 * delta / phi[phi > 0]))
-            est += np.sum(np.abs(np.log(p_[nz] / q_[nz])) * np.minimum(p_[nz], 2 * delta * psi[nz]))
-            ktol[k] += 10.0 * est
+        ktol = kl_tolerance(Z, Eg, ores, hn)
         d = np.abs(g["kl"] - np.array(t["kl"]))
         assert np.all(d[kmask] <= ktol[kmask]), (t["eps"], "kl", (d - ktol)[kmask].max())
 
 
-# (L, h, seed, eps, vectors whose S_E the oracle recomputes)
-LARGE = [(18, 3.0, 0, 0.5, (0, 17, 49)), (20, 2.0, 0, 0.2, (0, 49)), (20, 3.0, 1, 0.8, (25,))]
+# (L, h, seed, eps, vectors whose S_E the oracle recomputes: all at L = 18,
+# eight spread over the window at L = 20, where each takes the oracle seconds)
+SPREAD = (0, 7, 14, 21, 28, 35, 42, 49)
+LARGE = [(18, 3.0, 0, 0.5, tuple(range(50))), (20, 2.0, 0, 0.2, SPREAD), (20, 3.0, 1, 0.8, SPREAD)]
 
 
-@pytest.mark.parametrize("L,h,seed,eps,se_idx", LARGE, ids=[f"L{c[0]}-h{c[1]}-s{c[2]}-e{c[3]}" for c in LARGE])
-def test_large_certificates(ctx, L, h, seed, eps, se_idx):
-    nev = 50
-    say("certificates", L, h, seed, eps)
-    g = ctx.mbl_solve(L, h, seed, eps, nev, vectors=True)
+def certify(ctx, g, L, h, seed, eps, nev, se_idx):
+    """Certificates of one L >= 18 window, every one computed by the oracle's
+    own code from the GPU's eigenvectors."""
     Z, E = g["evecs"], g["evals"]
     n = math.comb(L, L // 2)
     assert Z.shape == (n, nev)
@@ -123,14 +122,12 @@ def test_large_certificates(ctx, L, h, seed, eps, se_idx):
     # orthonormality of the returned basis
     G = Z.T @ Z
     assert np.abs(G - np.eye(nev)).max() <= 1e-12
-    # ascending, and the nev nearest sigma: every returned |E - sigma| is at most
-    # the window radius (checked for completeness below)
     assert np.all(np.diff(E) >= 0)
-    # residuals and Rayleigh quotients with H applied by the oracle, sampled
-    for k in (0, 1, nev // 2, nev - 2, nev - 1):
+    # residuals and Rayleigh quotients of every pair with H applied by the oracle
+    for k in range(nev):
         res = oracle.residual(L, 1.0, f, Z[:, k], E[k], b)
         assert res <= RES_TOL * hn, (k, res / hn)
-        assert abs(oracle.rayleigh(L, 1.0, f, Z[:, k], b) - E[k]) <= EIG_TOL * hn
+        assert abs(oracle.rayleigh(L, 1.0, f, Z[:, k], b) - E[k]) <= EIG_TOL * hn, k
     # observables of the returned vectors recomputed by the oracle
     sep, gaps = _separated(E, hn)
     for k in range(nev):
@@ -140,6 +137,16 @@ def test_large_certificates(ctx, L, h, seed, eps, se_idx):
     ro, _ = oracle.gap_ratios(E)
     rmask = np.minimum(gaps[:-1], gaps[1:]) >= GAP_MIN * hn
     assert np.abs(ro - g["r"])[rmask].max(initial=0.0) <= 1e-12
+    return sep
+
+
+@pytest.mark.parametrize("L,h,seed,eps,se_idx", LARGE, ids=[f"L{c[0]}-h{c[1]}-s{c[2]}-e{c[3]}" for c in LARGE])
+def test_large_certificates(ctx, L, h, seed, eps, se_idx):
+    nev = 50
+    say("certificates", L, h, seed, eps)
+    g = ctx.mbl_solve(L, h, seed, eps, nev, vectors=True)
+    certify(ctx, g, L, h, seed, eps, nev, se_idx)
+    E, hn = g["evals"], g["hnorm"]
     # window completeness: a second, independent solve centred half a window
     # above; inside the overlap of the two windows both must list the same levels
     half = 0.5 * (E[-1] - g["sigma"])
@@ -162,5 +169,24 @@ def test_fp32_refined_matches_fp64_L18(ctx):
     assert g32["max_resid"] <= RES_TOL
     assert np.abs(g32["evals"] - g64["evals"]).max() <= EIG_TOL * hn
     sep, _ = _separated(g64["evals"], hn)
+    for key in ("s1", "se"):
+        assert np.abs(g32[key] - g64[key])[sep].max() <= OBS_TOL, key
+
+
+def test_fp32_refined_certificates_L20(ctx):
+    """The L = 20 benchmark configuration at its own precision (FP32 LU on the
+    matrix cores, every shifted solve refined in FP64): the FP64 certificates
+    computed by the oracle, and per-eigenpair agreement with the FP64 path."""
+    L, h, seed, eps, nev = 20, 3.0, 0, 0.5, 50
+    say("fp32+ir certificates L20")
+    g32 = ctx.mbl_solve(L, h, seed, eps, nev, prec=mbl.MBL_FP32_IR64, vectors=True)
+    assert g32["max_resid"] <= RES_TOL
+    sep = certify(ctx, g32, L, h, seed, eps, nev, (0, 25, 49))
+    g64 = ctx.mbl_solve(L, h, seed, eps, nev, vectors=True)
+    hn = g64["hnorm"]
+    dE = np.abs(g32["evals"] - g64["evals"])
+    say(f"  fp32+ir vs fp64: max |dE| / ||H|| = {dE.max() / hn:.2e}, fallback={g32['fallback']}")
+    assert dE.max() <= EIG_TOL * hn
+    assert_subspaces(g32["evals"], g32["evecs"], g64["evals"], g64["evecs"], hn)
     for key in ("s1", "se"):
         assert np.abs(g32[key] - g64[key])[sep].max() <= OBS_TOL, key
