@@ -213,6 +213,35 @@ int mbl_observables_extra(mbl_ctx *ctx, int L, int nev, const double *evecs_host
                           double *s2_host, double *fluct_host, double *dynfrac_host,
                           double *kl_host);
 
+/* ---- allocation-free observables -------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  It computes
+ * what mbl_observables computes (gap ratios, S_1, S_E of nev given unit
+ * vectors), with the same kernels, but the inputs and outputs are device
+ * buffers the caller owns on the calling thread's current HIP device, and the
+ * work buffers are one fixed array of MBL_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each device it runs on until the process ends.  No call
+ * allocates or frees device memory.
+ *   evals_dev  [nev] ascending energies (read only when r_dev is not NULL)
+ *   evecs_dev  column-major dim x nev, leading dimension ld >= dim (basis order)
+ *   r_dev [nev - 2], s1_dev [nev], se_dev [nev]; a NULL output is skipped
+ *   hip_stream a hipStream_t of the current device (NULL = the null stream);
+ *              the call only enqueues work on it and returns, so results are
+ *              ready once the stream is synchronised.
+ * Limits: nev <= MBL_NOALLOC_MAX_NEV; S_E is computed in chunks of as many
+ * vectors as the array holds (one at L = 22); a size beyond the array returns
+ * MBL_EINVAL with a message.  The first call on a device looks up the array's
+ * device address and loads small constant tables, so it should not be the
+ * call that is captured.  Every call on one device shares that device's
+ * array and leaves its contents behind: calls that overlap in time on one
+ * device (several streams or threads) race and must be serialised by the
+ * caller. */
+#define MBL_NOALLOC_SCRATCH_BYTES (32u << 20)
+#define MBL_NOALLOC_MAX_NEV 256
+int mbl_observables_noalloc(int L, int nev, const double *evals_dev, const double *evecs_dev,
+                            int64_t ld, double *r_dev, double *s1_dev, double *se_dev,
+                            void *hip_stream);
+
 /* ---- the whole path ------------------------------------------------------ */
 /* Fields -> assembly -> E_min/E_max -> sigma -> LU of H - sigma -> block
  * Krylov-Schur on (H - sigma)^-1 -> nev pairs nearest sigma -> observables. */

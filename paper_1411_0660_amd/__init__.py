@@ -32,7 +32,8 @@ EXPORTS = ("mbl_create", "mbl_destroy", "mbl_strerror", "mbl_last_error", "mbl_p
            "mbl_sector_dim", "mbl_fields", "mbl_basis", "mbl_rank", "mbl_hamiltonian",
            "mbl_spmv", "mbl_extremal", "mbl_symbolic", "mbl_ordering", "mbl_front_tree",
            "mbl_shift_solve",
-           "mbl_observables", "mbl_observables_extra", "mbl_solve", "mbl_footprint",
+           "mbl_observables", "mbl_observables_extra", "mbl_observables_noalloc", "mbl_solve",
+           "mbl_footprint",
            "mbl_serve_start", "mbl_submit", "mbl_poll", "mbl_wait", "mbl_serve_stats",
            "mbl_profile_enable", "mbl_profile_read", "mbl_sweep", "mbl_disorder_average")
 
@@ -123,6 +124,7 @@ def lib() -> ctypes.CDLL:
                                   _pd, ctypes.POINTER(mbl_solve_info)]
     L.mbl_observables.argtypes = [vp, ctypes.c_int, ctypes.c_int, _pd, _pd, _pd, _pd, _pd]
     L.mbl_observables_extra.argtypes = [vp, ctypes.c_int, ctypes.c_int, _pd, _pd, _pd, _pd, _pd]
+    L.mbl_observables_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, _i64, vp, vp, vp, vp]
     L.mbl_solve.argtypes = [vp, ctypes.POINTER(mbl_problem), ctypes.POINTER(mbl_result)]
     L.mbl_footprint.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                 ctypes.POINTER(ctypes.c_size_t)]
@@ -171,6 +173,15 @@ def mbl_disorder_average(bins) -> dict:
     _check(lib().mbl_disorder_average(_pd_of(b), b.shape[0], _pd_of(mean), _pd_of(sem),
                                       ctypes.byref(sig)), "mbl_disorder_average")
     return {"mean": mean, "sem": sem, "sigma_e": sig.value}
+
+
+def mbl_observables_noalloc(L: int, nev: int, evals_dev: int, evecs_dev: int, ld: int,
+                            r_dev: int, s1_dev: int, se_dev: int, stream: int = 0) -> int:
+    """Allocation-free observables on device buffers (addresses as ints, 0 for
+    NULL) of the current device; enqueues on `stream` and returns its status."""
+    return lib().mbl_observables_noalloc(L, nev, evals_dev or None, evecs_dev or None, ld,
+                                         r_dev or None, s1_dev or None, se_dev or None,
+                                         stream or None)
 
 
 def mbl_fields(L: int, h: float, seed: int) -> np.ndarray:

@@ -367,6 +367,15 @@ static int observables_impl(mbl_ctx *ctx, int L, int nev, const double *evals_ho
     });
 }
 
+int mbl_observables_noalloc(int L, int nev, const double *evals_dev, const double *evecs_dev,
+                            int64_t ld, double *r_dev, double *s1_dev, double *se_dev,
+                            void *hip_stream) {
+    return guarded([&] {
+        observables_noalloc(L, nev, evals_dev, evecs_dev, ld, r_dev, s1_dev, se_dev,
+                            static_cast<hipStream_t>(hip_stream));
+    });
+}
+
 int mbl_observables(mbl_ctx *ctx, int L, int nev, const double *evals_host,
                     const double *evecs_host, double *r_host, double *s1_host, double *se_host) {
     if (!ctx || !evecs_host) return MBL_EINVAL;

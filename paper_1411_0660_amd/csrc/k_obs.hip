@@ -15,8 +15,10 @@
 // singular values of the bidiagonal by Sturm bisection on its Golub-Kahan
 // tridiagonal, and -sum lambda ln lambda over lambda = sigma^2 / |psi|^2.
 #include <cmath>
+#include <mutex>
 
 #include "common.hpp"
+#include "kernels.hpp"
 #include "obs.hpp"
 
 namespace mbl {
@@ -34,6 +36,16 @@ void ensure_obinom() {
     g_obinom_ready = true;
 }
 
+// Where each magnetization block of the reshaped vector lives: block k starts
+// at off[k] of a vector's concatenated blocks (cnt_k lines of len_k values),
+// and its bidiagonalisation scratch (U: cnt_k^2, V: cnt_k len_k doubles) at
+// goff[k] of a per-vector stride gstride.  Passed to the kernels by value.
+struct SeLayout {
+    int L = 0, nup = 0, la = 0;
+    int64_t dim = 0, gstride = 0;
+    int64_t off[MBL_L_MAX / 2 + 2] = {}, goff[MBL_L_MAX / 2 + 1] = {};
+};
+
 // index of word w among the words of its popcount (colex = ascending order)
 __device__ __forceinline__ int sub_rank(uint32_t w) {
     int r = 0, j = 1;
@@ -50,11 +62,10 @@ __device__ __forceinline__ int sub_rank(uint32_t w) {
 // the states with k up spins in A (the low la = L / 2 bits b), nr = C(L - la,
 // nup - k) rows a by d = C(la, k) columns b, stored as the fewer of the two
 // kinds of lines, each contiguous (row-major if nr <= d, else column-major)
-__global__ void k_block_index(int L, int64_t dim, const uint32_t *basis, const int64_t *blockoff,
-                              int32_t *dst) {
+__global__ void k_block_index(SeLayout lay, const uint32_t *basis, int32_t *dst) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= dim) return;
-    int la = L / 2, lb = L - la, nup = (L + 1) / 2;
+    if (i >= lay.dim) return;
+    const int la = lay.la, lb = lay.L - la, nup = lay.nup;
     uint32_t s = basis[i];
     uint32_t b = s & ((1u << la) - 1u), a = s >> la;
     int k = __popc(b);
@@ -62,7 +73,7 @@ __global__ void k_block_index(int L, int64_t dim, const uint32_t *basis, const i
     int nr = (int)o_binom[lb][nup - k];
     int ra = sub_rank(a), rb = sub_rank(b);
     int64_t o = (nr <= d) ? (int64_t)ra * d + rb : (int64_t)rb * nr + ra;
-    dst[i] = (int32_t)(blockoff[k] + o);
+    dst[i] = (int32_t)(lay.off[k] + o);
 }
 
 __global__ void k_scatter_blocks(int64_t dim, int nvec, const int32_t *dst, const double *psi,
@@ -191,15 +202,13 @@ __device__ int gk_count(int m, const double *e2, double x, double pivmin) {
 // The singular values of B are the positive eigenvalues of the 2 cnt x 2 cnt
 // tridiagonal with zero diagonal and off-diagonals alpha_0, beta_1, alpha_1,
 // ..., alpha_cnt-1, found by Sturm bisection, one thread per value.
-// scratch: per (vector, block) cnt x cnt for U and cnt x len for V.
-__global__ __launch_bounds__(SGT) void k_se_gkl(int L, int nup, int64_t dim,
-                                                const int64_t *blockoff, const int64_t *gkloff,
-                                                int64_t gkl_stride, const double *norms2,
-                                                const double *M, double *scratch, double *part) {
+// work: per (vector, block) cnt x cnt for U and cnt x len for V.
+__global__ __launch_bounds__(SGT) void k_se_gkl(SeLayout lay, const double *norms2,
+                                                const double *M, double *work, double *part) {
     __shared__ double xr[SG_MAXN], xp[SG_MAXN], uj[SG_MAXN], coef[SG_MAXN];
     __shared__ double al[SG_MAXN], be[SG_MAXN], e2[2 * SG_MAXN];
     __shared__ double red[SGW];
-    const int la = L / 2, lb = L - la;
+    const int la = lay.la, lb = lay.L - la, nup = lay.nup;
     const int v = blockIdx.x / (la + 1), k = blockIdx.x % (la + 1);
     const int d = (int)o_binom[la][k];
     const int nr = (nup - k >= 0 && nup - k <= lb) ? (int)o_binom[lb][nup - k] : 0;
@@ -209,8 +218,8 @@ __global__ __launch_bounds__(SGT) void k_se_gkl(int L, int nup, int64_t dim,
         if (threadIdx.x == 0) part[blockIdx.x] = 0.0;
         return;
     }
-    const double *X = M + (int64_t)v * dim + blockoff[k];
-    double *U = scratch + (int64_t)v * gkl_stride + gkloff[k];
+    const double *X = M + (int64_t)v * lay.dim + lay.off[k];
+    double *U = work + (int64_t)v * lay.gstride + lay.goff[k];
     double *V = U + (int64_t)cnt * cnt;
     const double fro2 = group_sum([&] {
         double a = 0.0;
@@ -220,7 +229,9 @@ __global__ __launch_bounds__(SGT) void k_se_gkl(int L, int nup, int64_t dim,
     // a new vector below tiny counts as vanished: its share of sigma is
     // below the rounding of the bidiagonalisation
     const double tiny = 1e-14 * sqrt(fro2);
-    const uint64_t key = 0x5E5EC0DEULL + 0x100000001B3ULL * (uint64_t)blockIdx.x;
+    // start vectors depend on the block only, so a vector's result does not
+    // depend on which other vectors share the launch
+    const uint64_t key = 0x5E5EC0DEULL + 0x100000001B3ULL * (uint64_t)k;
     for (int i = threadIdx.x; i < cnt; i += SGT) uj[i] = gkl_rand(key, i);
     __syncthreads();
     gkl_normalize(uj, cnt, U, 0, -1.0, key + 1, coef, red);
@@ -376,81 +387,181 @@ inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b);
 
 }  // namespace
 
+namespace {
+
+SeLayout se_layout(int L) {
+    SeLayout lay;
+    lay.L = L;
+    lay.la = L / 2;
+    lay.nup = sector_nup(L);
+    lay.dim = binom(L, lay.nup);
+    const int la = lay.la, lb = L - la;
+    for (int k = 0; k <= la; k++) {
+        int64_t d = binom(la, k), nr = (lay.nup - k >= 0 && lay.nup - k <= lb) ? binom(lb, lay.nup - k) : 0;
+        lay.off[k + 1] = lay.off[k] + nr * d;
+        const int64_t cnt = std::min(nr, d), len = std::max(nr, d);
+        MBL_REQUIRE(len <= SG_MAXN, MBL_EINVAL, "entanglement: subsystem block above 512");
+        lay.goff[k] = lay.gstride;
+        lay.gstride += cnt * (cnt + len);           // U (cnt x cnt) and V (cnt x len)
+    }
+    MBL_REQUIRE(lay.off[la + 1] == lay.dim, MBL_EINVAL, "entanglement blocks do not cover the sector");
+    return lay;
+}
+
+// S_E of nvec vectors psi (ld) into se_dev: scatter into blocks, bidiagonalise,
+// sum the block entropies.  M: dim x nvec, gkl: gstride x nvec, part: (la + 1) nvec.
+void se_launch(const SeLayout &lay, const int32_t *dst, const double *psi, int64_t ldpsi, int nvec,
+               const double *norms2, double *M, double *gkl, double *part, double *se_dev,
+               hipStream_t s) {
+    const int la = lay.la;
+    hipLaunchKernelGGL(k_scatter_blocks, dim3(cdiv(lay.dim, 256)), dim3(256), 0, s, lay.dim, nvec,
+                       dst, psi, ldpsi, M);
+    MBL_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_se_gkl, dim3(nvec * (la + 1)), dim3(SGT), 0, s, lay, norms2, M, gkl, part);
+    MBL_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_se_sum, dim3(cdiv(nvec, 64)), dim3(64), 0, s, la + 1, nvec, part, se_dev);
+    MBL_CHECK_LAUNCH();
+}
+
+// Norms (pass 0), then S_1, S_2, F, f moments and KL (pass 1) of nvec vectors;
+// out: NQ doubles per vector; nrm: nvec norms; part: OBS_PARTS NQ nvec.
+void sums_launch(int L, int64_t dim, const uint32_t *basis, const double *psi, int64_t ld, int nvec,
+                 double *part, double *nrm, double *out_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_vec_sums, dim3(OBS_PARTS, nvec), dim3(SEB), 0, s, L, dim, nvec, basis, psi,
+                       ld, nrm, 0, part);
+    MBL_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_vec_final, dim3(cdiv(nvec, 64)), dim3(64), 0, s, nvec, OBS_PARTS, part,
+                       out_dev, 0);
+    MBL_CHECK_LAUNCH();
+    // gather the norms (column 0 of out) into nrm
+    hipLaunchKernelGGL(k_stride_copy, dim3(cdiv(nvec, 64)), dim3(64), 0, s, nvec, out_dev, NQ, nrm);
+    MBL_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_vec_sums, dim3(OBS_PARTS, nvec), dim3(SEB), 0, s, L, dim, nvec, basis, psi,
+                       ld, nrm, 1, part);
+    MBL_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_vec_final, dim3(cdiv(nvec, 64)), dim3(64), 0, s, nvec, OBS_PARTS, part,
+                       out_dev, 1);
+    MBL_CHECK_LAUNCH();
+}
+
+}  // namespace
+
 void ObsWork::prepare(int L_, const uint32_t *basis, int64_t dim_, int nvec_max, Budget *bud,
                       hipStream_t s) {
     ensure_obinom();
     if (L == L_ && dim == dim_ && nvec_max <= nvmax) return;
+    const SeLayout lay = se_layout(L_);
+    MBL_REQUIRE(lay.dim == dim_, MBL_EINVAL, "observables: sector dimension mismatch");
     L = L_;
     dim = dim_;
     nvmax = nvec_max;
-    const int la = L / 2, lb = L - la, nup = sector_nup(L);
-    std::vector<int64_t> off(la + 2, 0);
-    std::vector<int64_t> goff(la + 1, 0);
-    gkl_stride_ = 0;
-    for (int k = 0; k <= la; k++) {
-        int64_t d = binom(la, k), nr = (nup - k >= 0 && nup - k <= lb) ? binom(lb, nup - k) : 0;
-        off[k + 1] = off[k] + nr * d;
-        const int64_t cnt = std::min(nr, d), len = std::max(nr, d);
-        MBL_REQUIRE(len <= SG_MAXN, MBL_EINVAL, "entanglement: subsystem block above 512");
-        goff[k] = gkl_stride_;
-        gkl_stride_ += cnt * (cnt + len);           // U (cnt x cnt) and V (cnt x len)
-    }
-    MBL_REQUIRE(off[la + 1] == dim_, MBL_EINVAL, "entanglement blocks do not cover the sector");
-    d_blockoff.alloc(sizeof(int64_t) * (la + 2), bud);
-    h2d(d_blockoff.ptr<int64_t>(), off.data(), off.size(), s);
+    gkl_stride_ = lay.gstride;
     d_dst.alloc(sizeof(int32_t) * dim, bud);
-    hipLaunchKernelGGL(k_block_index, dim3(cdiv(dim, 256)), dim3(256), 0, s, L, dim, basis,
-                       d_blockoff.ptr<int64_t>(), d_dst.ptr<int32_t>());
+    hipLaunchKernelGGL(k_block_index, dim3(cdiv(dim, 256)), dim3(256), 0, s, lay, basis,
+                       d_dst.ptr<int32_t>());
     MBL_CHECK_LAUNCH();
     d_M.alloc(sizeof(double) * dim * nvmax, bud);
-    d_gkloff.alloc(sizeof(int64_t) * (la + 1), bud);
-    h2d(d_gkloff.ptr<int64_t>(), goff.data(), goff.size(), s);
     d_gkl.alloc(sizeof(double) * gkl_stride_ * nvmax, bud);
-    d_part.alloc(sizeof(double) * (size_t)std::max<int64_t>((int64_t)(la + 1) * nvmax,
+    d_part.alloc(sizeof(double) * (size_t)std::max<int64_t>((int64_t)(lay.la + 1) * nvmax,
                                                             (int64_t)OBS_PARTS * NQ * nvmax), bud);
     d_out.alloc(sizeof(double) * NQ * nvmax + sizeof(double) * 4 * nvmax, bud);
 }
 
 void ObsWork::entanglement(const double *psi, int64_t ldpsi, int nvec, const double *norms2,
                            double *se_dev, hipStream_t s) {
-    int la = L / 2;
-    hipLaunchKernelGGL(k_scatter_blocks, dim3(cdiv(dim, 256)), dim3(256), 0, s, dim, nvec,
-                       d_dst.ptr<int32_t>(), psi, ldpsi, d_M.ptr<double>());
-    MBL_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_se_gkl, dim3(nvec * (la + 1)), dim3(SGT), 0, s, L, sector_nup(L), dim,
-                       d_blockoff.ptr<int64_t>(), d_gkloff.ptr<int64_t>(), gkl_stride_, norms2,
-                       d_M.ptr<double>(), d_gkl.ptr<double>(), d_part.ptr<double>());
-    MBL_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_se_sum, dim3(cdiv(nvec, 64)), dim3(64), 0, s, la + 1, nvec,
-                       d_part.ptr<double>(), se_dev);
-    MBL_CHECK_LAUNCH();
+    se_launch(se_layout(L), d_dst.ptr<int32_t>(), psi, ldpsi, nvec, norms2, d_M.ptr<double>(),
+              d_gkl.ptr<double>(), d_part.ptr<double>(), se_dev, s);
 }
 
 void ObsWork::vector_sums(const uint32_t *basis, const double *psi, int64_t ld, int nvec,
                           double *out_dev, hipStream_t s) {
     // pass 0: norms; pass 1: everything else with the normalised weights
-    double *nrm = d_out.ptr<double>() + NQ * nvmax;
-    hipLaunchKernelGGL(k_vec_sums, dim3(OBS_PARTS, nvec), dim3(SEB), 0, s, L, dim, nvec, basis, psi,
-                       ld, nrm, 0, d_part.ptr<double>());
-    MBL_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_vec_final, dim3(cdiv(nvec, 64)), dim3(64), 0, s, nvec, OBS_PARTS,
-                       d_part.ptr<double>(), out_dev, 0);
-    MBL_CHECK_LAUNCH();
-    // gather the norms (column 0 of out) into nrm
-    hipLaunchKernelGGL(k_stride_copy, dim3(cdiv(nvec, 64)), dim3(64), 0, s, nvec, out_dev, NQ, nrm);
-    MBL_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_vec_sums, dim3(OBS_PARTS, nvec), dim3(SEB), 0, s, L, dim, nvec, basis, psi,
-                       ld, nrm, 1, d_part.ptr<double>());
-    MBL_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_vec_final, dim3(cdiv(nvec, 64)), dim3(64), 0, s, nvec, OBS_PARTS,
-                       d_part.ptr<double>(), out_dev, 1);
-    MBL_CHECK_LAUNCH();
+    sums_launch(L, dim, basis, psi, ld, nvec, d_part.ptr<double>(), d_out.ptr<double>() + NQ * nvmax,
+                out_dev, s);
 }
 
 void ObsWork::gap_ratios(int nev, const double *E_dev, double *r_dev, hipStream_t s) {
     if (nev < 3) return;
     hipLaunchKernelGGL(k_gap_ratio, dim3(cdiv(nev, 64)), dim3(64), 0, s, nev, E_dev, r_dev);
     MBL_CHECK_LAUNCH();
+}
+
+// ---- allocation-free observables --------------------------------------------
+// One fixed work array per device, for callers that cannot allocate device
+// memory.  In host code the array's name stands for a host-side placeholder;
+// its device address on each device comes from hipGetSymbolAddress, taken once
+// per device with that device current, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[MBL_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[64] = {};
+
+unsigned char *noalloc_scratch(int dev) {
+    MBL_REQUIRE(dev >= 0 && dev < 64, MBL_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        MBL_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_noalloc_ptr[dev] = p;
+    }
+    return static_cast<unsigned char *>(g_noalloc_ptr[dev]);
+}
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+}  // namespace
+
+void observables_noalloc(int L, int nev, const double *evals_dev, const double *psi_dev,
+                         int64_t ld, double *r_dev, double *s1_dev, double *se_dev,
+                         hipStream_t s) {
+    MBL_REQUIRE(L >= 2 && L <= MBL_L_MAX, MBL_EINVAL, "L must satisfy 2 <= L <= 22");
+    MBL_REQUIRE(nev >= 1 && nev <= MBL_NOALLOC_MAX_NEV, MBL_EINVAL,
+                "mbl_observables_noalloc: nev must satisfy 1 <= nev <= 256");
+    MBL_REQUIRE(psi_dev != nullptr, MBL_EINVAL, "mbl_observables_noalloc: evecs_dev is NULL");
+    MBL_REQUIRE(!r_dev || evals_dev, MBL_EINVAL, "mbl_observables_noalloc: r needs evals_dev");
+    const SeLayout lay = se_layout(L);
+    const int64_t dim = lay.dim;
+    MBL_REQUIRE(ld >= dim, MBL_EINVAL, "mbl_observables_noalloc: ld below the sector dimension");
+    int dev = 0;
+    MBL_HIP(hipGetDevice(&dev));
+    unsigned char *base = noalloc_scratch(dev);
+    ensure_obinom();
+    // layout of the work array
+    const int nmax = MBL_NOALLOC_MAX_NEV;
+    size_t o = 0;
+    uint32_t *basis = reinterpret_cast<uint32_t *>(base + o);  o += align256(sizeof(uint32_t) * dim);
+    int32_t *dst = reinterpret_cast<int32_t *>(base + o);      o += align256(sizeof(int32_t) * dim);
+    double *part = reinterpret_cast<double *>(base + o);       o += align256(sizeof(double) * OBS_PARTS * NQ * nmax);
+    double *out = reinterpret_cast<double *>(base + o);        o += align256(sizeof(double) * NQ * nmax);
+    double *nrm = reinterpret_cast<double *>(base + o);        o += align256(sizeof(double) * nmax);
+    double *separt = reinterpret_cast<double *>(base + o);     o += align256(sizeof(double) * (MBL_L_MAX / 2 + 1) * nmax);
+    MBL_REQUIRE(o < MBL_NOALLOC_SCRATCH_BYTES, MBL_EINVAL,
+                "mbl_observables_noalloc: sector too large for the fixed work array");
+    // vectors whose entanglement blocks and bidiagonalisation fit at once
+    const size_t per_vec = sizeof(double) * (size_t)(dim + lay.gstride);
+    const int64_t chunk = std::min<int64_t>(nev, (int64_t)((MBL_NOALLOC_SCRATCH_BYTES - o) / per_vec));
+    MBL_REQUIRE(!se_dev || chunk >= 1, MBL_EINVAL,
+                "mbl_observables_noalloc: one vector's entanglement work exceeds the fixed work array");
+    double *M = reinterpret_cast<double *>(base + o);
+    double *gkl = M + (chunk > 0 ? chunk : 0) * dim;
+
+    launch_basis(L, dim, basis, s);
+    hipLaunchKernelGGL(k_block_index, dim3(cdiv(dim, 256)), dim3(256), 0, s, lay, basis, dst);
+    MBL_CHECK_LAUNCH();
+    sums_launch(L, dim, basis, psi_dev, ld, nev, part, nrm, out, s);
+    if (s1_dev) {
+        hipLaunchKernelGGL(k_stride_copy, dim3(cdiv(nev, 64)), dim3(64), 0, s, nev, out + 1, NQ, s1_dev);
+        MBL_CHECK_LAUNCH();
+    }
+    if (r_dev && nev >= 3) {
+        hipLaunchKernelGGL(k_gap_ratio, dim3(cdiv(nev, 64)), dim3(64), 0, s, nev, evals_dev, r_dev);
+        MBL_CHECK_LAUNCH();
+    }
+    if (se_dev)
+        for (int64_t v0 = 0; v0 < nev; v0 += chunk) {
+            const int cv = (int)std::min<int64_t>(chunk, nev - v0);
+            se_launch(lay, dst, psi_dev + v0 * ld, ld, cv, nrm + v0, M, gkl, separt, se_dev + v0, s);
+        }
 }
 
 }  // namespace mbl

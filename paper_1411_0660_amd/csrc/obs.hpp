@@ -31,7 +31,14 @@ class ObsWork {
   private:
     int L = -1, nvmax = 0;
     int64_t dim = 0, gkl_stride_ = 0;     // bidiagonalisation scratch per vector (doubles)
-    DevBuf d_blockoff, d_dst, d_M, d_gkloff, d_gkl, d_part, d_out;
+    DevBuf d_dst, d_M, d_gkl, d_part, d_out;
 };
+
+// r, S_1 and S_E of nev vectors (device in, device out) with no device
+// allocation: work in the library's fixed per-device array (mbl.h,
+// mbl_observables_noalloc).
+void observables_noalloc(int L, int nev, const double *evals_dev, const double *psi_dev,
+                         int64_t ld, double *r_dev, double *s1_dev, double *se_dev,
+                         hipStream_t s);
 
 }  // namespace mbl
