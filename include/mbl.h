@@ -320,7 +320,8 @@ int mbl_disorder_average(const double *bins, int n_real, double *mean, double *s
  * own HIP stream and host thread, so their work overlaps on the device) when a
  * slot is idle and the device bytes all slots hold, plus the request's
  * predicted footprint (mbl_footprint; an FP32 request also counts the FP64
- * factor of its fallback), fit `budget_bytes`.  A request that does not fit
+ * factor of its fallback), fit `budget_bytes`; while it runs, a slot's
+ * allocations are capped at the footprint it was admitted with.  A request that does not fit
  * lets later ones pass, at most 2 x slots times.  The per-L plans are built
  * once by the context and shared.  A request's arithmetic does not depend on
  * its slot or on the other requests: its result is the same alone and in the
@@ -335,6 +336,10 @@ typedef struct {
     int64_t max_running;        /* largest number of requests on the device at once */
     int64_t bypasses;           /* admissions ahead of an earlier request */
     int64_t trims;              /* idle slots that gave their buffers back */
+    int64_t retries;            /* requests run again after their slot gave back buffers
+                                   kept from earlier requests to stay within its admission */
+    size_t max_slot_peak;       /* largest device bytes one slot has held; a slot may hold
+                                   no more than the footprint it was admitted with */
 } mbl_serve_info;
 
 /* Start the server with `slots` (1..16; 0 = 4) slots and a budget (0 = the

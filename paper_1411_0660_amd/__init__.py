@@ -76,7 +76,8 @@ class mbl_serve_info(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int), ("budget_bytes", ctypes.c_size_t),
                 ("held_bytes", ctypes.c_size_t), ("submitted", _i64), ("admitted", _i64),
                 ("completed", _i64), ("running", _i64), ("queued", _i64), ("max_running", _i64),
-                ("bypasses", _i64), ("trims", _i64)]
+                ("bypasses", _i64), ("trims", _i64), ("retries", _i64),
+                ("max_slot_peak", ctypes.c_size_t)]
 
 
 class mbl_solve_info(ctypes.Structure):

@@ -31,6 +31,15 @@ size_t footprint_bytes(const Plan &p, int prec, int nev, int block) {
     bytes += 8 * n * cols * 2 + 8 * n * 16;                 // Krylov bases + work block
     if (prec == MBL_FP32_IR64) bytes += 8 * n * 16 * 62;    // GMRES bases (30 + 31 blocks)
     bytes += 8 * n * (size_t)(nw + 8) * 4;                  // Ritz vectors, H psi, copies
+    // observables: the scattered magnetization blocks and the Golub-Kahan
+    // bases of every returned vector (at most 2 dim per vector), block map,
+    // per-vector reduction partials
+    bytes += 8 * n * (size_t)nev * 3 + 4 * n + 8 * (size_t)nev * (64 * 9 + 64);
+    // projected-matrix buffers: staging, Jacobi matrix and vectors, and the
+    // partial sums of the tall-skinny products (at most 512 row ranges)
+    const size_t c = cols + 16;
+    bytes += 8 * (2 * c * c) + 8 * (2 * c * c + c + 1) + 8 * 512 * c * 16;
+    bytes += (size_t)1 << 20;                               // small per-request buffers
     return bytes;
 }
 
@@ -235,19 +244,35 @@ void Server::worker(int s) {
         uint64_t t = sl.ticket;
         mbl_problem prob = reqs_[t].prob;
         mbl_result *res = reqs_[t].res;
+        const size_t admitted = sl.held;
         lk.unlock();
         int st = MBL_OK;
-        try {
+        bool retried = false;
+        for (int attempt = 0; attempt < 2; attempt++) {
+            st = MBL_OK;
+            try {
+                std::lock_guard<std::recursive_mutex> g(sl.ctx->mu);
+                // the slot may hold no more device memory than it was admitted with
+                sl.ctx->budget.limit = admitted;
+                solve_problem(*sl.ctx, prob, *res);
+            } catch (const Error &e) {
+                st = e.code;
+            } catch (const std::bad_alloc &) {
+                st = MBL_ENOMEM;
+            } catch (const std::exception &) {
+                st = MBL_EDEVICE;
+            }
+            // buffers kept from earlier, differently sized requests can push a
+            // slot past its admission: it gives them back and runs once more
+            if (st != MBL_ENOMEM || attempt > 0) break;
             std::lock_guard<std::recursive_mutex> g(sl.ctx->mu);
-            solve_problem(*sl.ctx, prob, *res);
-        } catch (const Error &e) {
-            st = e.code;
-        } catch (const std::bad_alloc &) {
-            st = MBL_ENOMEM;
-        } catch (const std::exception &) {
-            st = MBL_EDEVICE;
+            if (sl.ctx->budget.used == 0) break;
+            sl.ctx->trim();
+            retried = true;
         }
         lk.lock();
+        if (retried) stats_.retries++;
+        stats_.max_slot_peak = std::max<size_t>(stats_.max_slot_peak, sl.ctx->budget.peak);
         sl.busy = false;
         running_--;
         finish_locked(t, st);

@@ -78,6 +78,9 @@ def test_admission_by_footprint():
         st = c.mbl_serve_stats()
     assert all(o["status"] == mbl.MBL_OK for o in outs)
     assert st["max_running"] <= 3
+    # a slot never held more device memory than the footprint it was admitted
+    # with (the largest admitted footprint here is the L = 14 one)
+    assert 0 < st["max_slot_peak"] <= fp14
     # no two L = 14 requests were ever on the device together
     spans = sorted((o["t_start"], o["t_done"]) for (L, *_), o in zip(reqs, outs) if L == 14)
     for (a0, a1), (b0, b1) in zip(spans, spans[1:]):
