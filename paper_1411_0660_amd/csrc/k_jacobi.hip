@@ -29,6 +29,7 @@ constexpr int JT = 1024;                // threads of the workgroup
 constexpr int JLDS_MAX = 128;           // largest order kept in LDS
 constexpr int JMAX = 1024;              // largest order supported
 constexpr int JMAX_SWEEPS = 40;
+constexpr int VB = 8;                   // V items per thread with loads in flight together
 
 // index pair k of round r of the circle schedule over mp (even) indices
 __device__ __forceinline__ void round_pair(int mp, int r, int k, int &p, int &q) {
@@ -67,17 +68,22 @@ __device__ __forceinline__ void jacobi_rounds(int m, double *T, double *V, doubl
                                          : copysign(1.0, theta) / (at + sqrt(theta * theta + 1.0));
                         c = 1.0 / sqrt(t * t + 1.0);
                         s = t * c;
-                        if (s != 0.0) atomicAdd(nrot, 1);   // else the identity: nothing moves
                     }
                 }
                 cs_c[k] = c; cs_s[k] = s; cs_t[k] = t; cs_a[k] = apq;
                 pp[k] = p; pq[k] = q;
+                // rotations of this wave (s == 0 is the identity: nothing moves)
+                const unsigned long long rot = __ballot(s != 0.0);
+                if ((tid & 63) == 0 && rot) atomicAdd(nrot, __popcll(rot));
             }
             __syncthreads();
-            // T <- J^T T J, one 2 x 2 block (and its transpose) per item
-            for (int it = tid; it < nh * nh; it += JT) {
-                const int k1 = it % nh, k2 = it / nh;
-                if (k1 > k2) continue;
+            // T <- J^T T J, one 2 x 2 block (and its transpose) per item; the
+            // items are the pairs k1 <= k2, numbered column by column
+            for (int it = tid; it < nh * (nh + 1) / 2; it += JT) {
+                int k2 = (int)((sqrtf(8.0f * (float)it + 1.0f) - 1.0f) * 0.5f);
+                while (k2 * (k2 + 1) / 2 > it) k2--;
+                while ((k2 + 1) * (k2 + 2) / 2 <= it) k2++;
+                const int k1 = it - k2 * (k2 + 1) / 2;
                 const double s1 = cs_s[k1], s2 = cs_s[k2];
                 if (s1 == 0.0 && s2 == 0.0) continue;
                 const int p1 = pp[k1], q1 = pq[k1], p2 = pp[k2], q2 = pq[k2];
@@ -107,16 +113,34 @@ __device__ __forceinline__ void jacobi_rounds(int m, double *T, double *V, doubl
                 if (vq1) { T[q1 + (int64_t)p2 * m] = z2; T[p2 + (int64_t)q1 * m] = z2; }
                 if (vq1 && vq2) { T[q1 + (int64_t)q2 * m] = u2; T[q2 + (int64_t)q1 * m] = u2; }
             }
-            // V <- V J, one row of one column pair per item
-            for (int it = tid; it < m * nh; it += JT) {
-                const int i = it % m, k = it / m;
-                const double s = cs_s[k];
-                if (s == 0.0) continue;
-                const double c = cs_c[k];
-                double *vp = V + (int64_t)pp[k] * m, *vq = V + (int64_t)pq[k] * m;
-                double a = vp[i], b = vq[i];
-                vp[i] = c * a - s * b;
-                vq[i] = s * a + c * b;
+            // V <- V J, one row of one column pair per item; items are taken
+            // VB at a time with all their loads issued before any store, since
+            // V lives in global memory (L2) and each load is a round trip
+            for (int base = 0; base < m * nh; base += VB * JT) {
+                double va[VB], vb[VB];
+#pragma unroll
+                for (int u = 0; u < VB; u++) {
+                    const int it = base + u * JT + tid;
+                    va[u] = vb[u] = 0.0;
+                    if (it < m * nh) {
+                        const int i = it % m, k = it / m;
+                        if (cs_s[k] != 0.0) {
+                            va[u] = V[(int64_t)pp[k] * m + i];
+                            vb[u] = V[(int64_t)pq[k] * m + i];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < VB; u++) {
+                    const int it = base + u * JT + tid;
+                    if (it >= m * nh) continue;
+                    const int i = it % m, k = it / m;
+                    const double s = cs_s[k];
+                    if (s == 0.0) continue;
+                    const double c = cs_c[k];
+                    V[(int64_t)pp[k] * m + i] = c * va[u] - s * vb[u];
+                    V[(int64_t)pq[k] * m + i] = s * va[u] + c * vb[u];
+                }
             }
             __syncthreads();
         }

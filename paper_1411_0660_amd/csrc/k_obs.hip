@@ -9,11 +9,11 @@
 // amplitude matrix M[a][b] = psi(a b) vanishes unless popcount(a) + popcount(b)
 // is the sector's up-spin count, so it is block diagonal over k = popcount(b):
 // block k is C(L - L/2, nup - k) x C(L/2, k) and the blocks tile the sector
-// exactly (Vandermonde).  The Schmidt values of psi are the singular values of
-// these blocks.  Each (vector, block) is one workgroup: Golub-Kahan-Lanczos
-// bidiagonalisation of the block with full reorthogonalisation, then the
-// singular values of the bidiagonal by Sturm bisection on its Golub-Kahan
-// tridiagonal, and -sum lambda ln lambda over lambda = sigma^2 / |psi|^2.
+// exactly (Vandermonde).  The squared Schmidt values of psi are the squared
+// singular values of these blocks, i.e. the eigenvalues of their Gram
+// matrices.  Each (vector, block) is one workgroup: the Gram matrix, its
+// Lanczos tridiagonalisation with full reorthogonalisation, Sturm bisection on
+// the tridiagonal, and -sum lambda ln lambda over lambda = sigma^2 / |psi|^2.
 #include <cmath>
 #include <mutex>
 
@@ -38,8 +38,8 @@ void ensure_obinom() {
 
 // Where each magnetization block of the reshaped vector lives: block k starts
 // at off[k] of a vector's concatenated blocks (cnt_k lines of len_k values),
-// and its bidiagonalisation scratch (U: cnt_k^2, V: cnt_k len_k doubles) at
-// goff[k] of a per-vector stride gstride.  Passed to the kernels by value.
+// and its Lanczos scratch (3 cnt_k^2 doubles) at goff[k] of a per-vector
+// stride gstride.  Passed to the kernels by value.
 struct SeLayout {
     int L = 0, nup = 0, la = 0;
     int64_t dim = 0, gstride = 0;
@@ -98,9 +98,11 @@ __device__ double block_reduce_sum(double v, double *sh) {
     return r;
 }
 
-constexpr int SGT = 256;                  // threads of an S_E workgroup
+constexpr int SGT = 1024;                 // threads of an S_E workgroup
 constexpr int SGW = SGT / 64;             // its wavefronts
 constexpr int SG_MAXN = 512;              // longest line (C(11, 5) = 462 at L = 22)
+constexpr int SG_LDSG = 96;               // Gram matrices up to this order live in LDS
+constexpr int SG_PARTS = 4;               // partial sums per output in the Lanczos passes
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -128,48 +130,75 @@ __device__ __forceinline__ double gkl_rand(uint64_t key, int i) {
     return (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
 }
 
-// x (length n, LDS) <- x - Q Q^T x twice (classical Gram-Schmidt, two
-// passes) against the k orthonormal vectors Q[q * n ...], q < k (global)
-__device__ void gkl_orth(double *x, int n, const double *Q, int k, double *coef) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+// sum_{t < n} A[t sa] B[t sb] with four partial sums, unrolled so that the
+// loads of several terms are in flight at once (the operands sit in L2 / LDS
+// and the loop would otherwise wait one round trip per term)
+__device__ __forceinline__ double dot_s(const double *A, int64_t sa, const double *B, int64_t sb,
+                                        int n) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int t = 0;
+#pragma unroll 2
+    for (; t + 4 <= n; t += 4) {
+        a0 += A[(int64_t)t * sa] * B[(int64_t)t * sb];
+        a1 += A[(int64_t)(t + 1) * sa] * B[(int64_t)(t + 1) * sb];
+        a2 += A[(int64_t)(t + 2) * sa] * B[(int64_t)(t + 2) * sb];
+        a3 += A[(int64_t)(t + 3) * sa] * B[(int64_t)(t + 3) * sb];
+    }
+    for (; t < n; t++) a0 += A[(int64_t)t * sa] * B[(int64_t)t * sb];
+    return (a0 + a1) + (a2 + a3);
+}
+
+// y[r] = sum_{c < nc} A[c lda + r] x[c] for r < nr (A in global or LDS, x and
+// y in LDS): each output is split over SG_PARTS threads, each summing a
+// contiguous quarter of c (so a pass is a few batches of loads per thread),
+// and the quarters are added in a fixed order.  sign = -1 subtracts from y.
+__device__ void pass_sum(const double *A, int64_t lda, const double *x, int nr, int nc,
+                         double *y, double sign, double *pbuf) {
+    const int chunk = (nc + SG_PARTS - 1) / SG_PARTS;
+    for (int t = threadIdx.x; t < nr * SG_PARTS; t += SGT) {
+        const int r = t % nr, part = t / nr;
+        const int c0 = part * chunk, c1 = min(nc, c0 + chunk);
+        pbuf[part * SG_MAXN + r] = c1 > c0 ? dot_s(A + (int64_t)c0 * lda + r, lda, x + c0, 1, c1 - c0) : 0.0;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < nr; r += SGT) {
+        double a = 0.0;
+        for (int part = 0; part < SG_PARTS; part++) a += pbuf[part * SG_MAXN + r];
+        y[r] = (sign > 0.0) ? a : y[r] - a;
+    }
+    __syncthreads();
+}
+
+// Orthogonalise x (length n, LDS) against the k orthonormal vectors of Q,
+// classical Gram-Schmidt applied twice.  Q is kept in two layouts so that both
+// halves of a pass read coalesced: Qt (component e of every vector at Qt + e
+// ld) for the coefficients, Qv (vector q at Qv + q ld) for the update.
+__device__ void lz_orth(double *x, int n, const double *Qv, const double *Qt, int ld, int k,
+                        double *coef, double *pbuf) {
     for (int pass = 0; pass < 2 && k > 0; pass++) {
-        for (int q = wv; q < k; q += SGW) {
-            const double *qv = Q + (int64_t)q * n;
-            double a = 0.0;
-            for (int e = lane; e < n; e += 64) a += qv[e] * x[e];
-            a = wave_sum(a);
-            if (lane == 0) coef[q] = a;
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < n; e += SGT) {
-            double a = x[e];
-            for (int q = 0; q < k; q++) a -= coef[q] * Q[(int64_t)q * n + e];
-            x[e] = a;
-        }
-        __syncthreads();
+        pass_sum(Qt, ld, x, k, n, coef, 1.0, pbuf);      // coef = Q^T x
+        pass_sum(Qv, ld, coef, n, k, x, -1.0, pbuf);     // x -= Q coef
     }
 }
 
 // x <- x / |x| if |x| > tiny; otherwise x <- a fresh direction orthogonal to
-// the k vectors of Q (random, key).  Returns |x| or 0 for a fresh direction.
-__device__ double gkl_normalize(double *x, int n, const double *Q, int k, double tiny,
-                                uint64_t key, double *coef, double *red) {
-    double nr = sqrt(group_sum([&] {
+// the k vectors of Q (random, key).  Returns |x|, or 0 for a fresh direction.
+__device__ double lz_normalize(double *x, int n, const double *Qv, const double *Qt, int ld,
+                               int k, double tiny, uint64_t key, double *coef, double *red,
+                               double *pbuf) {
+    auto norm2 = [&] {
         double a = 0.0;
         for (int e = threadIdx.x; e < n; e += SGT) a += x[e] * x[e];
-        return a;
-    }(), red));
+        return group_sum(a, red);
+    };
+    double nr = sqrt(norm2());
     double keep = nr;
     for (int draw = 0; nr <= tiny && draw < 4; draw++) {
         keep = 0.0;
         for (int e = threadIdx.x; e < n; e += SGT) x[e] = gkl_rand(key + 7919ULL * draw, e);
         __syncthreads();
-        gkl_orth(x, n, Q, k, coef);
-        nr = sqrt(group_sum([&] {
-            double a = 0.0;
-            for (int e = threadIdx.x; e < n; e += SGT) a += x[e] * x[e];
-            return a;
-        }(), red));
+        lz_orth(x, n, Qv, Qt, ld, k, coef, pbuf);
+        nr = sqrt(norm2());
     }
     const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
     for (int e = threadIdx.x; e < n; e += SGT) x[e] *= inv;
@@ -177,15 +206,15 @@ __device__ double gkl_normalize(double *x, int n, const double *Q, int k, double
     return keep;
 }
 
-// number of eigenvalues below x of the symmetric tridiagonal with zero
-// diagonal and squared off-diagonals e2[0 .. m-2] (Sturm sequence)
-__device__ int gk_count(int m, const double *e2, double x, double pivmin) {
+// number of eigenvalues below x of the symmetric tridiagonal (a, b2 = squared
+// off-diagonals), by the Sturm sequence of its LDL^T pivots
+__device__ int tri_count(int m, const double *a, const double *b2, double x, double pivmin) {
     int c = 0;
-    double q = -x;
+    double q = a[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0.0) c++;
     for (int i = 1; i < m; i++) {
-        q = -x - e2[i - 1] / q;
+        q = a[i] - x - b2[i - 1] / q;
         if (fabs(q) < pivmin) q = -pivmin;
         if (q < 0.0) c++;
     }
@@ -193,106 +222,110 @@ __device__ int gk_count(int m, const double *e2, double x, double pivmin) {
 }
 
 // One workgroup per (vector, block): entropy contribution of block k of vector
-// v.  The block is cnt lines of length len (cnt <= len).  Its singular values
-// come from the Golub-Kahan-Lanczos bidiagonalisation with full
-// reorthogonalisation (Golub & Kahan 1965): U^T M V = B, lower bidiagonal with
-// diagonal alpha and subdiagonal beta, after cnt steps (a step whose new
-// vector vanishes continues from a fresh orthogonal direction with a zero
-// coupling, so U is a basis of the whole line space and sigma(B) = sigma(M)).
-// The singular values of B are the positive eigenvalues of the 2 cnt x 2 cnt
-// tridiagonal with zero diagonal and off-diagonals alpha_0, beta_1, alpha_1,
-// ..., alpha_cnt-1, found by Sturm bisection, one thread per value.
-// work: per (vector, block) cnt x cnt for U and cnt x len for V.
-__global__ __launch_bounds__(SGT) void k_se_gkl(SeLayout lay, const double *norms2,
-                                                const double *M, double *work, double *part) {
-    __shared__ double xr[SG_MAXN], xp[SG_MAXN], uj[SG_MAXN], coef[SG_MAXN];
-    __shared__ double al[SG_MAXN], be[SG_MAXN], e2[2 * SG_MAXN];
+// v.  The block M is cnt lines of length len (cnt <= len); the squared Schmidt
+// values are the eigenvalues of its Gram matrix G = M M^T (cnt x cnt).  G is
+// formed once, then reduced to a tridiagonal T = Q^T G Q by the Lanczos
+// recurrence with full reorthogonalisation (a step whose new vector vanishes
+// continues from a fresh orthogonal direction with a zero coupling, so after
+// cnt steps Q is square and T has the eigenvalues of G), and the eigenvalues
+// of T are found by Sturm bisection, one thread each.
+// work: per (vector, block) 3 cnt^2 doubles (G, Q by vector, Q by component).
+__global__ __launch_bounds__(SGT) void k_se_lanczos(SeLayout lay, const double *norms2,
+                                                    const double *M, double *work, double *part) {
+    __shared__ double xw[SG_MAXN], qj[SG_MAXN], qp[SG_MAXN], coef[SG_MAXN];
+    __shared__ double al[SG_MAXN], b2[SG_MAXN];
     __shared__ double red[SGW];
+    __shared__ double Gl[SG_LDSG * SG_LDSG];      // G itself when cnt <= SG_LDSG
+    __shared__ double pbuf[SG_PARTS * SG_MAXN];   // partial sums of the passes
     const int la = lay.la, lb = lay.L - la, nup = lay.nup;
     const int v = blockIdx.x / (la + 1), k = blockIdx.x % (la + 1);
     const int d = (int)o_binom[la][k];
     const int nr = (nup - k >= 0 && nup - k <= lb) ? (int)o_binom[lb][nup - k] : 0;
     const int cnt = min(nr, d), len = max(nr, d);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (cnt == 0) {                               // no state of the sector in this block
         if (threadIdx.x == 0) part[blockIdx.x] = 0.0;
         return;
     }
     const double *X = M + (int64_t)v * lay.dim + lay.off[k];
-    double *U = work + (int64_t)v * lay.gstride + lay.goff[k];
-    double *V = U + (int64_t)cnt * cnt;
-    const double fro2 = group_sum([&] {
-        double a = 0.0;
-        for (int64_t e = threadIdx.x; e < (int64_t)cnt * len; e += SGT) a += X[e] * X[e];
-        return a;
-    }(), red);
-    // a new vector below tiny counts as vanished: its share of sigma is
-    // below the rounding of the bidiagonalisation
-    const double tiny = 1e-14 * sqrt(fro2);
+    double *Gw = work + (int64_t)v * lay.gstride + lay.goff[k];
+    double *Qv = Gw + (int64_t)cnt * cnt, *Qt = Qv + (int64_t)cnt * cnt;
+    double *G = (cnt <= SG_LDSG) ? Gl : Gw;
+    // G = X X^T, register tiles of 2 x 2 entries (upper triangle, mirrored)
+    const int nt = (cnt + 1) / 2;
+    for (int t = threadIdx.x; t < nt * nt; t += SGT) {
+        const int ti = t % nt, tj = t / nt;
+        if (ti > tj) continue;
+        const int i0 = 2 * ti, j0 = 2 * tj;
+        const bool i1 = i0 + 1 < cnt, j1 = j0 + 1 < cnt;
+        const double *xa = X + (int64_t)i0 * len, *xb = X + (int64_t)(i1 ? i0 + 1 : i0) * len;
+        const double *ya = X + (int64_t)j0 * len, *yb = X + (int64_t)(j1 ? j0 + 1 : j0) * len;
+        double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+#pragma unroll 4
+        for (int e = 0; e < len; e++) {
+            const double a0 = xa[e], a1 = xb[e], c0 = ya[e], c1 = yb[e];
+            s00 += a0 * c0; s01 += a0 * c1; s10 += a1 * c0; s11 += a1 * c1;
+        }
+        G[(int64_t)j0 * cnt + i0] = s00; G[(int64_t)i0 * cnt + j0] = s00;
+        if (j1) { G[(int64_t)(j0 + 1) * cnt + i0] = s01; G[(int64_t)i0 * cnt + j0 + 1] = s01; }
+        if (i1) { G[(int64_t)j0 * cnt + i0 + 1] = s10; G[(int64_t)(i0 + 1) * cnt + j0] = s10; }
+        if (i1 && j1) { G[(int64_t)(j0 + 1) * cnt + i0 + 1] = s11; G[(int64_t)(i0 + 1) * cnt + j0 + 1] = s11; }
+    }
+    double tr = 0.0;                               // trace of G = |M|^2
+    for (int64_t e = threadIdx.x; e < (int64_t)cnt * len; e += SGT) tr += X[e] * X[e];
+    tr = group_sum(tr, red);                       // (its barriers also publish G)
+    // a new Lanczos vector below tiny counts as vanished
+    const double tiny = 1e-13 * tr;
     // start vectors depend on the block only, so a vector's result does not
     // depend on which other vectors share the launch
     const uint64_t key = 0x5E5EC0DEULL + 0x100000001B3ULL * (uint64_t)k;
-    for (int i = threadIdx.x; i < cnt; i += SGT) uj[i] = gkl_rand(key, i);
+    for (int i = threadIdx.x; i < cnt; i += SGT) { qj[i] = gkl_rand(key, i); qp[i] = 0.0; }
     __syncthreads();
-    gkl_normalize(uj, cnt, U, 0, -1.0, key + 1, coef, red);
-    for (int i = threadIdx.x; i < cnt; i += SGT) U[i] = uj[i];
-    double bprev = 0.0;                           // beta_j, coupling of u_j to v_j-1
+    lz_normalize(qj, cnt, Qv, Qt, cnt, 0, -1.0, key + 1, coef, red, pbuf);
+    double bprev = 0.0;
     for (int j = 0; j < cnt; j++) {
-        // xr = M^T u_j - beta_j v_j-1
-        for (int e = threadIdx.x; e < len; e += SGT) {
-            double a = 0.0;
-            for (int i = 0; i < cnt; i++) a += X[(int64_t)i * len + e] * uj[i];
-            if (j > 0) a -= bprev * V[(int64_t)(j - 1) * len + e];
-            xr[e] = a;
-        }
-        __syncthreads();
-        gkl_orth(xr, len, V, j, coef);
-        double a = gkl_normalize(xr, len, V, j, tiny, key + 2 * (uint64_t)j + 2, coef, red);
-        if (threadIdx.x == 0) al[j] = a;
-        for (int e = threadIdx.x; e < len; e += SGT) V[(int64_t)j * len + e] = xr[e];
-        __syncthreads();
-        if (j + 1 == cnt) break;
-        // xp = M v_j - alpha_j u_j
-        for (int i = wv; i < cnt; i += SGW) {
-            const double *xi = X + (int64_t)i * len;
-            double t = 0.0;
-            for (int e = lane; e < len; e += 64) t += xi[e] * xr[e];
-            t = wave_sum(t);
-            if (lane == 0) xp[i] = t - a * uj[i];
-        }
-        __syncthreads();
-        gkl_orth(xp, cnt, U, j + 1, coef);
-        double b = gkl_normalize(xp, cnt, U, j + 1, tiny, key + 2 * (uint64_t)j + 3, coef, red);
-        if (threadIdx.x == 0) be[j + 1] = b;
         for (int i = threadIdx.x; i < cnt; i += SGT) {
-            U[(int64_t)(j + 1) * cnt + i] = xp[i];
-            uj[i] = xp[i];
+            Qv[(int64_t)j * cnt + i] = qj[i];
+            Qt[(int64_t)i * cnt + j] = qj[i];
         }
+        __syncthreads();
+        // w = G q_j (G symmetric: read by columns, coalesced)
+        pass_sum(G, cnt, qj, cnt, cnt, xw, 1.0, pbuf);
+        const double a = group_sum([&] {
+            double t = 0.0;
+            for (int i = threadIdx.x; i < cnt; i += SGT) t += qj[i] * xw[i];
+            return t;
+        }(), red);
+        if (threadIdx.x == 0) al[j] = a;
+        if (j + 1 == cnt) break;
+        for (int i = threadIdx.x; i < cnt; i += SGT) xw[i] -= a * qj[i] + bprev * qp[i];
+        __syncthreads();
+        lz_orth(xw, cnt, Qv, Qt, cnt, j + 1, coef, pbuf);
+        const double b = lz_normalize(xw, cnt, Qv, Qt, cnt, j + 1, tiny,
+                                      key + 2 * (uint64_t)j + 3, coef, red, pbuf);
+        if (threadIdx.x == 0) b2[j] = b * b;
+        for (int i = threadIdx.x; i < cnt; i += SGT) { qp[i] = qj[i]; qj[i] = xw[i]; }
         bprev = b;
         __syncthreads();
     }
-    // squared off-diagonals of the Golub-Kahan tridiagonal: alpha_0, beta_1, alpha_1, ...
-    const int m = 2 * cnt;
-    for (int i = threadIdx.x; i < m - 1; i += SGT) {
-        double x = (i & 1) ? be[(i + 1) / 2] : al[i / 2];
-        e2[i] = x * x;
-    }
     __syncthreads();
-    double bound = 0.0;
-    for (int i = 0; i < m - 1; i++) bound = fmax(bound, sqrt(e2[i]));
-    bound = 2.0 * bound + 1e-300;
-    const double pivmin = 1e-300 + 1e-30 * bound * bound;
+    // Gershgorin interval of T, then bisection for every eigenvalue
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < cnt; i++) {
+        const double r = (i > 0 ? sqrt(b2[i - 1]) : 0.0) + (i + 1 < cnt ? sqrt(b2[i]) : 0.0);
+        lo = fmin(lo, al[i] - r);
+        hi = fmax(hi, al[i] + r);
+    }
+    const double span = fmax(hi - lo, 1e-300);
+    const double pivmin = 1e-300 + 1e-30 * span * span;
     const double inv = 1.0 / norms2[v];
     double ent = 0.0;
     for (int i = threadIdx.x; i < cnt; i += SGT) {
-        // sigma_i, the i-th smallest singular value: count(x) >= cnt + i + 1 iff sigma_i < x
-        double lo = 0.0, hi = bound;
-        for (int it = 0; it < 200 && hi - lo > 2.3e-16 * bound; it++) {
-            const double mid = 0.5 * (lo + hi);
-            if (gk_count(m, e2, mid, pivmin) >= cnt + i + 1) hi = mid; else lo = mid;
+        double a = lo, c = hi;                      // count(a) <= i < count(c)
+        for (int it = 0; it < 200 && c - a > 2.3e-16 * span; it++) {
+            const double mid = 0.5 * (a + c);
+            if (tri_count(cnt, al, b2, mid, pivmin) > i) c = mid; else a = mid;
         }
-        const double sg = 0.5 * (lo + hi);
-        const double lam = sg * sg * inv;
+        const double lam = 0.5 * (a + c) * inv;
         if (lam > 0.0) ent -= lam * log(lam);
     }
     ent = group_sum(ent, red);
@@ -402,7 +435,7 @@ SeLayout se_layout(int L) {
         const int64_t cnt = std::min(nr, d), len = std::max(nr, d);
         MBL_REQUIRE(len <= SG_MAXN, MBL_EINVAL, "entanglement: subsystem block above 512");
         lay.goff[k] = lay.gstride;
-        lay.gstride += cnt * (cnt + len);           // U (cnt x cnt) and V (cnt x len)
+        lay.gstride += 3 * cnt * cnt;               // G and the Lanczos basis in two layouts
     }
     MBL_REQUIRE(lay.off[la + 1] == lay.dim, MBL_EINVAL, "entanglement blocks do not cover the sector");
     return lay;
@@ -417,7 +450,7 @@ void se_launch(const SeLayout &lay, const int32_t *dst, const double *psi, int64
     hipLaunchKernelGGL(k_scatter_blocks, dim3(cdiv(lay.dim, 256)), dim3(256), 0, s, lay.dim, nvec,
                        dst, psi, ldpsi, M);
     MBL_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_se_gkl, dim3(nvec * (la + 1)), dim3(SGT), 0, s, lay, norms2, M, gkl, part);
+    hipLaunchKernelGGL(k_se_lanczos, dim3(nvec * (la + 1)), dim3(SGT), 0, s, lay, norms2, M, gkl, part);
     MBL_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_se_sum, dim3(cdiv(nvec, 64)), dim3(64), 0, s, la + 1, nvec, part, se_dev);
     MBL_CHECK_LAUNCH();

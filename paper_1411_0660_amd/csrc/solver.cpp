@@ -987,6 +987,7 @@ void Context::small_eig(int m, const std::vector<double> &A, std::vector<double>
     d2h(&info, dinfo, 1, s);
     MBL_HIP(hipStreamSynchronize(s));
     if (info < 0) throw Error(MBL_ENUMERIC, "Jacobi eigensolver: sweep limit reached");
+    if (debug_level() > 1) std::fprintf(stderr, "[mbl] jacobi m=%d sweeps=%d\n", m, info);
     std::vector<int> perm(m);
     std::iota(perm.begin(), perm.end(), 0);
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int c) { return wu[a] < wu[c]; });
