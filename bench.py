@@ -274,6 +274,62 @@ def cpu_baseline(nev, L_gpu):
                          f"needs {8.0 * nG * nG / 1e9:.0f} GB, so it is not run")}}
 
 
+def refine_diagnostics(cases):
+    """Per solve (each in a child process with MBL_DEBUG=1, whose refinement
+    lines give the backward error after every sweep of every application):
+    kappa(H - sigma_f) = ||H - sigma_f|| / min |E - sigma_f| from the solve's
+    own window, the median first-solve backward error, and the median
+    contraction be(sweep 1) / be(sweep 0), for FP64 and FP32 factors."""
+    import re
+    import subprocess
+    rows = []
+    for L, seed in cases:
+        for prec in (0, 1):
+            env = dict(os.environ, MBL_DEBUG="1")
+            p = subprocess.run([sys.executable, os.path.abspath(__file__), "--refine-child",
+                                f"{L},{seed},{prec}"], capture_output=True, text=True, env=env,
+                               timeout=900)
+            res = json.loads([ln for ln in p.stdout.splitlines() if ln.startswith("{")][-1])
+            apps, cur = [], []
+            for line in p.stderr.splitlines():
+                m = re.search(r"refine L=\d+ prec=\w+ it=(\d+) be=([0-9.e+-]+)", line)
+                if m:
+                    it, be = int(m.group(1)), float(m.group(2))
+                    if it == 0 and cur:
+                        apps.append(cur)
+                        cur = []
+                    cur.append(be)
+            if cur:
+                apps.append(cur)
+            first = sorted(a[0] for a in apps)
+            ratios = sorted(a[1] / a[0] for a in apps if len(a) > 1 and a[0] > 0)
+            u = 1.11e-16 if prec == 0 else 5.96e-8
+            res.update({"applications": len(apps),
+                        "be_first_median": first[len(first) // 2] if first else None,
+                        "contraction_median": ratios[len(ratios) // 2] if ratios else None})
+            if res["be_first_median"]:
+                res["be_first_over_kappa_u"] = res["be_first_median"] / (res["kappa"] * u)
+            if res["contraction_median"]:
+                res["contraction_over_kappa_u"] = res["contraction_median"] / (res["kappa"] * u)
+            rows.append(res)
+            print(json.dumps(res), flush=True)
+    return rows
+
+
+def refine_child(spec):
+    import paper_1411_0660_amd as mbl
+    L, seed, prec = (int(x) for x in spec.split(","))
+    with mbl.Context(0) as c:
+        g = c.mbl_solve(L, 3.0, seed, 0.5, 50, prec=prec, allow_notconv=True)
+    hn, sf = g["hnorm"], g["sigma"] + 1e-6 * g["hnorm"]
+    dmin = min(abs(e - sf) for e in g["evals"])
+    anorm = max(abs(g["emin"] - sf), abs(g["emax"] - sf))
+    print(json.dumps({"L": L, "seed": seed, "prec": "fp32" if prec else "fp64",
+                      "kappa": anorm / dmin, "fallback": g["fallback"],
+                      "ir_iters_max": g["ir_iters_max"], "passes": g["n_passes"],
+                      "status": g["status"]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,7 +349,17 @@ def main():
     ap.add_argument("--slots", type=int, default=2,
                     help="timed steps run this many at a time (1: one at a time only)")
     ap.add_argument("--l18-slots", type=int, default=4)
+    ap.add_argument("--refine-diagnostics", action="store_true",
+                    help="only measure kappa and the refinement of FP64 / FP32 factors "
+                         "(L = 16, 18, 20, h = 3, eps = 0.5)")
+    ap.add_argument("--refine-child", default="", help=argparse.SUPPRESS)
     a = ap.parse_args()
+    if a.refine_child:
+        refine_child(a.refine_child)
+        return
+    if a.refine_diagnostics:
+        refine_diagnostics([(16, 0), (16, 1), (16, 2), (18, 0), (18, 1), (18, 2), (20, 0), (20, 1)])
+        return
     if a.copy_probe > 0:
         copy_probe(a.copy_probe)
         return
