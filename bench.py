@@ -115,11 +115,13 @@ def serve_stream(n, seed=0):
              i, 0.05 + 0.9 * u[3 * i + 2]) for i in range(n)]
 
 
-def run_served(mbl, reqs, prec, rate, slots, nev=20):
+def run_served(mbl, reqs, prec, rate, slots, nev=20, max_batch=16):
     """Submit reqs at Poisson arrival times (rate per second; 0 = all at once)
-    to a fresh serving context; returns throughput and latency figures."""
+    to a fresh serving context (at most max_batch requests solved as one
+    batch); returns throughput and latency figures."""
     import threading
     ctx = mbl.Context(0)
+    ctx.mbl_serve_batch_limit(max_batch)
     ctx.mbl_serve_start(slots)
     for L in sorted({r[0] for r in reqs}):          # plans built before the clock starts
         ctx.mbl_footprint(L, prec, nev)
@@ -158,7 +160,9 @@ def run_served(mbl, reqs, prec, rate, slots, nev=20):
             "requests_per_s": len(reqs) / wall, "eigenpairs_per_s": conv / wall,
             "latency_ms": {"p50": 1e3 * percentile(lat, 0.5), "p99": 1e3 * percentile(lat, 0.99)},
             "fallbacks": sum(o["fallback"] for o in ok), "max_running": st["max_running"],
-            "bypasses": st["bypasses"]}, outs
+            "bypasses": st["bypasses"], "batches": st["batches"], "batched": st["batched"],
+            "solved_in_batches": sum(1 for o in ok if o["batch"] > 1),
+            "max_batch": max_batch}, outs
 
 
 def workload(L, steps):

@@ -131,6 +131,7 @@ typedef struct {
                               6 total, 7 of which shifted solves */
     double t_submit, t_start, t_done; /* requests (mbl_submit): seconds since the server
                               started at submission, admission and completion */
+    int batch;             /* problems solved in one batch with this one (1: alone) */
 } mbl_result;
 
 /* Statistics of the per-L symbolic analysis (fill-reducing nested dissection,
@@ -246,6 +247,21 @@ int mbl_observables_noalloc(int L, int nev, const double *evals_dev, const doubl
 /* Fields -> assembly -> E_min/E_max -> sigma -> LU of H - sigma -> block
  * Krylov-Schur on (H - sigma)^-1 -> nev pairs nearest sigma -> observables. */
 int mbl_solve(mbl_ctx *ctx, const mbl_problem *prob, mbl_result *res);
+/* Several disorder realizations or targets solved together (batching): the
+ * `count` problems (1..16) are factored, solved and iterated in shared launches
+ * on a block-diagonal plan whose front tree is `count` copies of the lone one,
+ * and each problem's arithmetic is exactly that of mbl_solve (its results are
+ * bitwise the same as a separate call).  Problems batch when they share L
+ * (sector dimension >= 128), J, nev, prec, tol, block, ncv and max_restarts
+ * and set no test hook other than MBL_HOOK_IR_STALL32/64; otherwise, or when
+ * the batch does not fit in memory, they are solved one after another.  A
+ * problem whose lone solve takes a path the batch cannot follow (GMRES
+ * refinement or an FP64 fallback of an FP32 factor, a refinement failure)
+ * leaves the batch and is solved alone after it.  probs[k] -> results[k] (the mbl_result buffers as for
+ * mbl_solve); status[k] = that problem's mbl status.  t_phase of batched
+ * problems are the batch's.  Returns MBL_OK, or the first nonzero status. */
+int mbl_solve_batch(mbl_ctx *ctx, int count, const mbl_problem *probs, mbl_result *results,
+                    int *status);
 /* Predicted device bytes of one request (factor fronts + Krylov basis + work). */
 int mbl_footprint(mbl_ctx *ctx, int L, int prec, int nev, int block, size_t *bytes);
 
@@ -323,8 +339,10 @@ int mbl_disorder_average(const double *bins, int n_real, double *mean, double *s
  * factor of its fallback), fit `budget_bytes`; while it runs, a slot's
  * allocations are capped at the footprint it was admitted with.  A request that does not fit
  * lets later ones pass, at most 2 x slots times.  The per-L plans are built
- * once by the context and shared.  A request's arithmetic does not depend on
- * its slot or on the other requests: its result is the same alone and in the
+ * once by the context and shared.  Queued requests that can share launches
+ * are admitted to one slot together and solved as a batch (mbl_solve_batch,
+ * mbl_serve_batch_limit).  A request's arithmetic does not depend on its slot,
+ * its batch or the other requests: its result is the same alone and in the
  * mix (bitwise, given the same device).  Requests whose footprint exceeds the
  * budget complete with MBL_ENOMEM. */
 typedef struct {
@@ -340,12 +358,20 @@ typedef struct {
                                    kept from earlier requests to stay within its admission */
     size_t max_slot_peak;       /* largest device bytes one slot has held; a slot may hold
                                    no more than the footprint it was admitted with */
+    int64_t batches;            /* admissions of two or more requests solved together */
+    int64_t batched;            /* requests admitted in those */
 } mbl_serve_info;
 
 /* Start the server with `slots` (1..16; 0 = 4) slots and a budget (0 = the
  * context's budget).  Optional: mbl_submit starts it with the defaults.
  * MBL_EBUSY if it is already running. */
 int mbl_serve_start(mbl_ctx *ctx, int slots, size_t budget_bytes);
+/* Queued requests that mbl_solve_batch would batch (one L, the same J, nev,
+ * precision, tolerance and Krylov settings) are admitted together, up to
+ * max_batch (1..16; default 16; 1 = every request alone) per slot; a batch is
+ * admitted with the footprints of all its requests.  Applies to the running
+ * server, or to the next one started. */
+int mbl_serve_batch_limit(mbl_ctx *ctx, int max_batch);
 /* Queue one request; `prob` is copied, but prob->fields (if set), `res` and the
  * buffers it points to must stay valid until mbl_wait returns for the ticket.
  * Errors of the solve itself are reported by mbl_wait's status. */

@@ -33,8 +33,8 @@ EXPORTS = ("mbl_create", "mbl_destroy", "mbl_strerror", "mbl_last_error", "mbl_p
            "mbl_spmv", "mbl_extremal", "mbl_symbolic", "mbl_ordering", "mbl_front_tree",
            "mbl_shift_solve",
            "mbl_observables", "mbl_observables_extra", "mbl_observables_noalloc", "mbl_solve",
-           "mbl_footprint",
-           "mbl_serve_start", "mbl_submit", "mbl_poll", "mbl_wait", "mbl_serve_stats",
+           "mbl_solve_batch", "mbl_footprint",
+           "mbl_serve_start", "mbl_serve_batch_limit", "mbl_submit", "mbl_poll", "mbl_wait", "mbl_serve_stats",
            "mbl_profile_enable", "mbl_profile_read", "mbl_sweep", "mbl_disorder_average")
 
 _d = ctypes.c_double
@@ -59,7 +59,7 @@ class mbl_result(ctypes.Structure):
                 ("n_pass_rhs", ctypes.c_int), ("ir_iters_max", ctypes.c_int),
                 ("n_perturbed", ctypes.c_int), ("fallback", ctypes.c_int),
                 ("t_phase", _d * 8),
-                ("t_submit", _d), ("t_start", _d), ("t_done", _d)]
+                ("t_submit", _d), ("t_start", _d), ("t_done", _d), ("batch", ctypes.c_int)]
 
 
 class mbl_symbolic_info(ctypes.Structure):
@@ -77,7 +77,7 @@ class mbl_serve_info(ctypes.Structure):
                 ("held_bytes", ctypes.c_size_t), ("submitted", _i64), ("admitted", _i64),
                 ("completed", _i64), ("running", _i64), ("queued", _i64), ("max_running", _i64),
                 ("bypasses", _i64), ("trims", _i64), ("retries", _i64),
-                ("max_slot_peak", ctypes.c_size_t)]
+                ("max_slot_peak", ctypes.c_size_t), ("batches", _i64), ("batched", _i64)]
 
 
 class mbl_solve_info(ctypes.Structure):
@@ -127,9 +127,12 @@ def lib() -> ctypes.CDLL:
     L.mbl_observables_extra.argtypes = [vp, ctypes.c_int, ctypes.c_int, _pd, _pd, _pd, _pd, _pd]
     L.mbl_observables_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, _i64, vp, vp, vp, vp]
     L.mbl_solve.argtypes = [vp, ctypes.POINTER(mbl_problem), ctypes.POINTER(mbl_result)]
+    L.mbl_solve_batch.argtypes = [vp, ctypes.c_int, ctypes.POINTER(mbl_problem),
+                                  ctypes.POINTER(mbl_result), ctypes.POINTER(ctypes.c_int)]
     L.mbl_footprint.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                 ctypes.POINTER(ctypes.c_size_t)]
     L.mbl_serve_start.argtypes = [vp, ctypes.c_int, ctypes.c_size_t]
+    L.mbl_serve_batch_limit.argtypes = [vp, ctypes.c_int]
     L.mbl_serve_stats.argtypes = [vp, ctypes.POINTER(mbl_serve_info)]
     L.mbl_submit.argtypes = [vp, ctypes.POINTER(mbl_problem), ctypes.POINTER(mbl_result),
                              ctypes.POINTER(ctypes.c_uint64)]
@@ -361,8 +364,8 @@ class Context:
         if vectors:
             out["evecs"] = out["evecs"].T.copy()      # dim x nev
         for k in ("emin", "emax", "sigma", "hnorm", "r_mean", "max_resid", "nconv", "n_restarts",
-                  "n_opapply", "n_passes", "n_pass_rhs", "ir_iters_max", "n_perturbed", "fallback", "t_submit", "t_start",
-                  "t_done"):
+                  "n_opapply", "n_passes", "n_pass_rhs", "ir_iters_max", "n_perturbed", "fallback",
+                  "t_submit", "t_start", "t_done", "batch"):
             out[k] = getattr(res, k)
         out["t_phase"] = list(res.t_phase)
         return out
@@ -379,6 +382,37 @@ class Context:
         _check(code, "mbl_solve", allow=(MBL_ENOTCONV,) if allow_notconv else ())
         out = self._collect(res, bufs, nev, vectors)
         out["status"] = code
+        return out
+
+    def mbl_solve_batch(self, L: int, nev: int, items, *, J: float = 1.0, prec: int = MBL_FP64,
+                        tol: float = 0.0, vectors: bool = False, extra: bool = False,
+                        block: int = 0, ncv: int = 0, entanglement: bool = True,
+                        max_restarts: int = 0) -> list:
+        """Solve the problems ``items`` (dicts with h, seed, eps and optionally
+        sigma, fields or hooks) together; one result dict (as mbl_solve, plus
+        ``status``) per item."""
+        items = list(items)
+        k = len(items)
+        prs = (mbl_problem * k)()
+        ress = (mbl_result * k)()
+        keep = []
+        for q, it in enumerate(items):
+            pr, res, bufs, f = self._prepare(L, it["h"], it["seed"], it.get("eps", 0.5), nev, J,
+                                             prec, it.get("fields"), it.get("sigma", math.nan),
+                                             tol, vectors, extra, block, ncv, entanglement,
+                                             it.get("hooks", 0), max_restarts, 0)
+            prs[q] = pr
+            ress[q] = res
+            keep.append((bufs, f))
+        status = (ctypes.c_int * max(k, 1))(*([MBL_EBUSY] * max(k, 1)))
+        code = lib().mbl_solve_batch(self._h, k, prs, ress, status)
+        if code == MBL_EDEVICE or all(status[q] == MBL_EBUSY for q in range(k)):
+            _check(code, "mbl_solve_batch")     # a device error, or nothing attempted
+        out = []
+        for q in range(k):
+            d = self._collect(ress[q], keep[q][0], nev, vectors)
+            d["status"] = status[q]
+            out.append(d)
         return out
 
     def mbl_sweep(self, L: int, h: float, seed: int, eps, nev: int, *, J: float = 1.0,
@@ -400,6 +434,9 @@ class Context:
     # -- serving (continuous batching)
     def mbl_serve_start(self, slots: int = 0, budget_bytes: int = 0):
         _check(lib().mbl_serve_start(self._h, slots, budget_bytes), "mbl_serve_start")
+
+    def mbl_serve_batch_limit(self, max_batch: int):
+        _check(lib().mbl_serve_batch_limit(self._h, max_batch), "mbl_serve_batch_limit")
 
     def mbl_submit(self, L: int, h: float, seed: int, eps: float, nev: int, *, J: float = 1.0,
                    prec: int = MBL_FP64, fields=None, sigma: float = math.nan, tol: float = 0.0,

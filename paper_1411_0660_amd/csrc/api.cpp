@@ -20,6 +20,7 @@ struct mbl_ctx {
     mbl::Context *c;
     mbl::Server *srv;
     std::mutex srv_mu;
+    int max_batch = mbl::MBL_SEG_MAX;   // of the server (mbl_serve_batch_limit)
 };
 
 using namespace mbl;
@@ -399,6 +400,35 @@ int mbl_solve(mbl_ctx *ctx, const mbl_problem *prob, mbl_result *res) {
     });
 }
 
+int mbl_solve_batch(mbl_ctx *ctx, int count, const mbl_problem *probs, mbl_result *results,
+                    int *status) {
+    if (!ctx || !probs || !results || !status || count < 1 || count > MBL_SEG_MAX)
+        return MBL_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(ctx->c->mu);
+    for (int k = 0; k < count; k++) status[k] = MBL_EBUSY;
+    bool done = false;
+    int rc = guarded([&] {
+        MBL_HIP(hipSetDevice(ctx->c->device));
+        done = solve_batch(*ctx->c, count, probs, results, status);
+    });
+    if (rc == MBL_EINVAL) {
+        // an invalid problem: each gets its own status from its lone solve
+        done = false;
+    } else if (rc != MBL_OK) {
+        for (int k = 0; k < count; k++) status[k] = rc;
+        return rc;
+    }
+    if (!done)
+        for (int k = 0; k < count; k++)
+            status[k] = guarded([&] {
+                MBL_HIP(hipSetDevice(ctx->c->device));
+                solve_problem(*ctx->c, probs[k], results[k]);
+            });
+    for (int k = 0; k < count; k++)
+        if (status[k] != MBL_OK) return status[k];
+    return MBL_OK;
+}
+
 namespace {
 // One realization's bin for one target: averages over its nev eigenstates
 // (the per-sample binning of the "Numerical method" section).
@@ -542,8 +572,16 @@ int mbl_serve_start(mbl_ctx *ctx, int slots, size_t budget_bytes) {
         MBL_REQUIRE(!ctx->srv, MBL_EBUSY, "server already running");
         MBL_HIP(hipSetDevice(ctx->c->device));
         ctx->srv = new Server(ctx->c, slots ? slots : 4,
-                              budget_bytes ? budget_bytes : ctx->c->budget.limit);
+                              budget_bytes ? budget_bytes : ctx->c->budget.limit, ctx->max_batch);
     });
+}
+
+int mbl_serve_batch_limit(mbl_ctx *ctx, int max_batch) {
+    if (!ctx || max_batch < 1 || max_batch > MBL_SEG_MAX) return MBL_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->srv_mu);
+    ctx->max_batch = max_batch;
+    if (ctx->srv) ctx->srv->set_max_batch(max_batch);
+    return MBL_OK;
 }
 
 int mbl_submit(mbl_ctx *ctx, const mbl_problem *prob, mbl_result *res, uint64_t *ticket) {
@@ -553,7 +591,7 @@ int mbl_submit(mbl_ctx *ctx, const mbl_problem *prob, mbl_result *res, uint64_t 
             std::lock_guard<std::mutex> lk(ctx->srv_mu);
             if (!ctx->srv) {
                 MBL_HIP(hipSetDevice(ctx->c->device));
-                ctx->srv = new Server(ctx->c, 4, ctx->c->budget.limit);
+                ctx->srv = new Server(ctx->c, 4, ctx->c->budget.limit, ctx->max_batch);
             }
         }
         *ticket = ctx->srv->submit(*prob, res);

@@ -38,6 +38,7 @@ struct FrontDesc {
     int32_t pmoff;    // offset of the front's pull map: per child, per front row, the
                       // child's update row landing there, or -1 (nchild blocks of m)
     int64_t yoff;     // first element of the front's forward-solution block (p x nrhs, ld p)
+    int32_t seg;      // problem of a batch the front belongs to (0 for a lone problem)
 };
 
 // A set of fronts processed by one launch and the prefix sums of the work
@@ -71,10 +72,11 @@ template <class T>
 void launch_front_assemble(T *arena, const FrontDesc *fd, int64_t count, const int32_t *efront,
                            const int32_t *epos, const int32_t *esrc, const double *diag,
                            double sigma, double offv, hipStream_t s);
-// step t of the blocked partial LU on every listed front
+// step t of the blocked partial LU on every listed front; pivots below
+// thresh[front's problem] are perturbed to it
 template <class T>
 void launch_panel(T *arena, const FrontDesc *fd, int32_t *ipiv, int32_t *nperturbed, TaskList tl,
-                  int t, double thresh, double *uinv, hipStream_t s);
+                  int t, const double *thresh, double *uinv, hipStream_t s);
 // the U rows of panel t (and its row interchanges on the other columns) and
 // the L columns below it, in one launch
 template <class T>

@@ -38,7 +38,10 @@ __global__ __launch_bounds__(BS) void k_spmv(int64_t n, const int32_t *__restric
     }
 }
 
-// r = b - (H - shift) x; per-block partial sums of r^2, x^2, b^2 per vector
+// r = b - (H - shift) x; per-block partial sums of r^2, x^2, b^2 per vector.
+// Segment blockIdx.y is rows [seg n, (seg + 1) n) of a block-diagonal H (the
+// CSR columns are global), vectors packed with ld = nseg n; its partials
+// follow those of the segments before it.
 __global__ __launch_bounds__(BS) void k_residual(int64_t n, const int32_t *__restrict__ rowptr,
                                                  const int32_t *__restrict__ col,
                                                  const double *__restrict__ diag, double offv,
@@ -46,23 +49,26 @@ __global__ __launch_bounds__(BS) void k_residual(int64_t n, const int32_t *__res
                                                  const double *__restrict__ b,
                                                  const double *__restrict__ x,
                                                  double *__restrict__ r,
-                                                 double *__restrict__ partials) {
+                                                 double *__restrict__ partials, int64_t ld) {
     __shared__ double red[3][BS];
+    const int64_t g0 = (int64_t)blockIdx.y * n;
+    partials += (int64_t)blockIdx.y * gridDim.x * nvec * 3;
     for (int v = 0; v < nvec; v++) {
-        const double *xv = x + (int64_t)v * n;
-        const double *bv = b + (int64_t)v * n;
+        const double *xv = x + (int64_t)v * ld;
+        const double *bv = b + (int64_t)v * ld;
         double sr = 0.0, sx = 0.0, sb = 0.0;
         for (int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x; k < n;
              k += (int64_t)gridDim.x * BS) {
-            int32_t a = rowptr[k], e = rowptr[k + 1];
+            const int64_t gk = g0 + k;
+            int32_t a = rowptr[gk], e = rowptr[gk + 1];
             double acc = 0.0;
             for (int32_t p = a; p < e; p++) {
                 int32_t c = col[p];
-                if (c != k) acc += xv[c];
+                if (c != gk) acc += xv[c];
             }
-            double xk = xv[k], bk = bv[k];
-            double rk = bk - ((diag[k] - shift) * xk + offv * acc);
-            r[(int64_t)v * n + k] = rk;
+            double xk = xv[gk], bk = bv[gk];
+            double rk = bk - ((diag[gk] - shift) * xk + offv * acc);
+            r[(int64_t)v * ld + gk] = rk;
             sr += rk * rk; sx += xk * xk; sb += bk * bk;
         }
         red[0][threadIdx.x] = sr; red[1][threadIdx.x] = sx; red[2][threadIdx.x] = sb;
@@ -92,8 +98,13 @@ __global__ __launch_bounds__(BS) void k_gemm_tn_part(int64_t n, int k, int b,
                                                      const double *__restrict__ A, int64_t lda,
                                                      const double *__restrict__ B, int64_t ldb,
                                                      double *__restrict__ partials,
-                                                     int64_t rows_per_part) {
+                                                     int64_t rows_per_part, int64_t segA,
+                                                     int64_t segB) {
     extern __shared__ double sm[];
+    // segment blockIdx.z: its own rows of A and B, its own partials
+    A += (int64_t)blockIdx.z * segA;
+    B += (int64_t)blockIdx.z * segB;
+    partials += (int64_t)blockIdx.z * gridDim.x * (int64_t)k * b;
     const int c0 = blockIdx.y * TN_KC;
     const int kc = min(TN_KC, k - c0);
     const int lda_s = kc + 1;                 // odd stride: rows of a tile fall in different banks
@@ -147,8 +158,10 @@ constexpr int SP_G = 8;
 
 __global__ __launch_bounds__(64 * SP_G) void k_sum_parts(int kb, int nparts,
                                                         const double *__restrict__ partials,
-                                                        double *__restrict__ C) {
+                                                        double *__restrict__ C, int64_t segC) {
     __shared__ double red[SP_G][64];
+    partials += (int64_t)blockIdx.y * nparts * (int64_t)kb;   // segment blockIdx.y
+    C += (int64_t)blockIdx.y * segC;
     int l = threadIdx.x % 64, g = threadIdx.x / 64;
     int o = blockIdx.x * 64 + l;
     int p0 = (int)((int64_t)nparts * g / SP_G), p1 = (int)((int64_t)nparts * (g + 1) / SP_G);
@@ -178,8 +191,12 @@ template <int NB>
 __global__ __launch_bounds__(BS) void k_gemm_nn(int64_t n, int k, int b, double alpha,
                                                 const double *__restrict__ A, int64_t lda,
                                                 const double *__restrict__ Y, int ldy, double beta,
-                                                double *__restrict__ C, int64_t ldc) {
+                                                double *__restrict__ C, int64_t ldc, int64_t segA,
+                                                int64_t segY, int64_t segC) {
     extern __shared__ double sm[];
+    A += (int64_t)blockIdx.y * segA;                 // segment blockIdx.y
+    Y += (int64_t)blockIdx.y * segY;
+    C += (int64_t)blockIdx.y * segC;
     double *sY = sm;                                  // [k][NB]
     double *red = sm + (int64_t)k * NB;               // [NN_KG][NN_ROWS][NB]
     for (int t = threadIdx.x; t < k * NB; t += BS) {
@@ -224,15 +241,19 @@ __global__ void k_gather(int64_t n, int nvec, const int32_t *__restrict__ idx,
     for (int v = 0; v < nvec; v++) y[(int64_t)v * n + i] = x[(int64_t)v * n + s];
 }
 
-// start block: components u - 1/2 with u from SplitMix64 (counter based)
-__global__ void k_fill_start(int64_t n, int nvec, uint64_t seed, double *v) {
+// start block: components u - 1/2 with u from SplitMix64 (counter based);
+// segment blockIdx.y draws from its own seed, element (i, j) with counter
+// i + j n, stored at v[i + segment n + j ld]
+__global__ void k_fill_start(int64_t n, int nvec, SegSeeds seeds, double *v, int64_t ld) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * nvec) return;
-    uint64_t z = seed + (uint64_t)(e + 1) * 0x9E3779B97F4A7C15ULL;
+    const int sg = blockIdx.y;
+    uint64_t z = seeds.seed[sg] + (uint64_t)(e + 1) * 0x9E3779B97F4A7C15ULL;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
     z ^= z >> 31;
-    v[e] = (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    const int64_t i = e % n, j = e / n;
+    v[i + sg * n + j * ld] = (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
 }
 
 __global__ void k_copy(int64_t count, const double *__restrict__ x, double *__restrict__ y) {
@@ -246,12 +267,34 @@ __global__ void k_axpy(int64_t count, double a, const double *__restrict__ x,
     if (i < count) y[i] += a * x[i];
 }
 
+__global__ void k_shift_seg(int64_t n, const double *__restrict__ x, SegVals shift,
+                            double *__restrict__ y) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int sg = blockIdx.y;
+    if (i < n) y[i + sg * n] = x[i + sg * n] - shift.v[sg];
+}
+
+// y += x on the segments whose flag is set (packed vectors: nseg segments of n
+// rows per column, nvec columns of ld = nseg n)
+__global__ void k_axpy_masked(int64_t n, int nseg, int nvec, const int *__restrict__ on,
+                              const double *__restrict__ x, double *__restrict__ y) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int sg = blockIdx.y;
+    if (i >= n * nvec || !on[sg]) return;
+    const int64_t r = i % n, j = i / n, o = r + sg * n + j * n * nseg;
+    y[o] += x[o];
+}
+
 // out[j] = sum_i A[i, j] B[i, j] for j < ncol (partials per block, fixed order)
 __global__ __launch_bounds__(BS) void k_coldot_part(int64_t n, int ncol, const double *__restrict__ A,
                                                     int64_t lda, const double *__restrict__ B,
-                                                    int64_t ldb, double *__restrict__ part) {
+                                                    int64_t ldb, double *__restrict__ part,
+                                                    int64_t seg) {
     __shared__ double red[BS];
     int j = blockIdx.y;
+    A += (int64_t)blockIdx.z * seg;                  // segment blockIdx.z: rows, partials
+    B += (int64_t)blockIdx.z * seg;
+    part += (int64_t)blockIdx.z * ncol * gridDim.x;
     double s = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS)
         s += A[i + (int64_t)j * lda] * B[i + (int64_t)j * ldb];
@@ -267,6 +310,8 @@ __global__ __launch_bounds__(BS) void k_coldot_part(int64_t n, int ncol, const d
 __global__ void k_coldot_sum(int ncol, int nparts, const double *__restrict__ part,
                              double *__restrict__ out) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
+    part += (int64_t)blockIdx.y * ncol * nparts;     // segment blockIdx.y
+    out += (int64_t)blockIdx.y * ncol;
     if (j >= ncol) return;
     double s = 0.0;
     for (int p = 0; p < nparts; p++) s += part[(int64_t)j * nparts + p];
@@ -279,6 +324,9 @@ __global__ void k_sub_scaled_cols(int64_t n, int ncol, const double *__restrict_
                                   int64_t ldy) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int j = blockIdx.y;
+    e += (int64_t)blockIdx.z * ncol;                 // segment blockIdx.z
+    X += (int64_t)blockIdx.z * n;
+    Y += (int64_t)blockIdx.z * n;
     if (i < n) Y[i + (int64_t)j * ldy] -= e[j] * X[i + (int64_t)j * ldx];
 }
 
@@ -341,9 +389,14 @@ __global__ __launch_bounds__(BS) void k_bcomb(int64_t n, int nb, int nrhs,
 // Rinv; *flag = 1 if a pivot fell below rel_tiny * max diag (it is then
 // floored there, so the factor stays finite).
 __global__ void k_small_chol(int b, const double *__restrict__ G, double *__restrict__ Rout,
-                             double *__restrict__ Rinv, int *__restrict__ flag, double rel_tiny) {
+                             double *__restrict__ Rinv, int *__restrict__ flag, double rel_tiny,
+                             int64_t segG, int64_t segR, int64_t segF) {
     __shared__ double R[16 * 16], Ri[16 * 16];
     if (threadIdx.x != 0) return;
+    G += blockIdx.x * segG;                          // matrix blockIdx.x
+    Rout += blockIdx.x * segR;
+    Rinv += blockIdx.x * segR;
+    flag += blockIdx.x * segF;
     double dmax = 0.0;
     for (int i = 0; i < b; i++) dmax = fmax(dmax, G[i * b + i]);
     int fl = 0;
@@ -373,30 +426,48 @@ __global__ void k_small_chol(int b, const double *__restrict__ G, double *__rest
 
 }  // namespace
 
+void launch_coldot_seg(int nseg, int64_t n, int ncol, const double *A, int64_t lda,
+                       const double *B, int64_t ldb, int64_t seg, double *out, double *partials,
+                       int nparts, hipStream_t s) {
+    if (ncol == 0 || nseg == 0) return;
+    hipLaunchKernelGGL(k_coldot_part, dim3(nparts, ncol, nseg), dim3(BS), 0, s, n, ncol, A, lda, B,
+                       ldb, partials, seg);
+    MBL_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_coldot_sum, dim3(grid_for(ncol, 64), nseg), dim3(64), 0, s, ncol, nparts,
+                       partials, out);
+    MBL_CHECK_LAUNCH();
+}
+
 void launch_coldot(int64_t n, int ncol, const double *A, int64_t lda, const double *B, int64_t ldb,
                    double *out, double *partials, int nparts, hipStream_t s) {
-    if (ncol == 0) return;
-    hipLaunchKernelGGL(k_coldot_part, dim3(nparts, ncol), dim3(BS), 0, s, n, ncol, A, lda, B, ldb,
-                       partials);
-    MBL_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_coldot_sum, dim3(grid_for(ncol, 64)), dim3(64), 0, s, ncol, nparts,
-                       partials, out);
+    launch_coldot_seg(1, n, ncol, A, lda, B, ldb, 0, out, partials, nparts, s);
+}
+
+void launch_sub_scaled_cols_seg(int nseg, int64_t n, int ncol, const double *e, const double *X,
+                                int64_t ldx, double *Y, int64_t ldy, hipStream_t s) {
+    if (ncol == 0 || n == 0 || nseg == 0) return;
+    hipLaunchKernelGGL(k_sub_scaled_cols, dim3(grid_for(n, 256), ncol, nseg), dim3(256), 0, s, n,
+                       ncol, e, X, ldx, Y, ldy);
     MBL_CHECK_LAUNCH();
 }
 
 void launch_sub_scaled_cols(int64_t n, int ncol, const double *e, const double *X, int64_t ldx,
                             double *Y, int64_t ldy, hipStream_t s) {
-    if (ncol == 0 || n == 0) return;
-    hipLaunchKernelGGL(k_sub_scaled_cols, dim3(grid_for(n, 256), ncol), dim3(256), 0, s, n, ncol, e,
-                       X, ldx, Y, ldy);
+    launch_sub_scaled_cols_seg(1, n, ncol, e, X, ldx, Y, ldy, s);
+}
+
+void launch_small_chol_batch(int count, int b, const double *G, int64_t segG, double *R,
+                             double *Rinv, int64_t segR, int *flag, int64_t segF, double rel_tiny,
+                             hipStream_t s) {
+    MBL_REQUIRE(b >= 1 && b <= 16, MBL_EINVAL, "small_chol: b must be 1..16");
+    if (count == 0) return;
+    k_small_chol<<<dim3(count), dim3(64), 0, s>>>(b, G, R, Rinv, flag, rel_tiny, segG, segR, segF);
     MBL_CHECK_LAUNCH();
 }
 
 void launch_small_chol(int b, const double *G, double *R, double *Rinv, int *flag,
                        double rel_tiny, hipStream_t s) {
-    MBL_REQUIRE(b >= 1 && b <= 16, MBL_EINVAL, "small_chol: b must be 1..16");
-    k_small_chol<<<dim3(1), dim3(64), 0, s>>>(b, G, R, Rinv, flag, rel_tiny);
-    MBL_CHECK_LAUNCH();
+    launch_small_chol_batch(1, b, G, 0, R, Rinv, 0, flag, 0, rel_tiny, s);
 }
 
 void launch_bdot(int64_t n, int nb, int nrhs, const double *V, int64_t bs, const double *W,
@@ -407,7 +478,7 @@ void launch_bdot(int64_t n, int nb, int nrhs, const double *V, int64_t bs, const
                                                                             partials);
     MBL_CHECK_LAUNCH();
     int kb = nb * nrhs;
-    k_sum_parts<<<dim3(grid_for(kb, 64)), dim3(64 * SP_G), 0, s>>>(kb, nparts, partials, out);
+    k_sum_parts<<<dim3(grid_for(kb, 64)), dim3(64 * SP_G), 0, s>>>(kb, nparts, partials, out, 0);
     MBL_CHECK_LAUNCH();
 }
 
@@ -427,12 +498,19 @@ void launch_spmv(int64_t n, const int32_t *rowptr, const int32_t *col, const dou
     MBL_CHECK_LAUNCH();
 }
 
+void launch_residual_seg(int nseg, int64_t n, const int32_t *rowptr, const int32_t *col,
+                         const double *diag, double offv, double shift, int nvec, const double *b,
+                         const double *x, double *r, double *partials, int nparts, hipStream_t s) {
+    if (nseg == 0) return;
+    hipLaunchKernelGGL(k_residual, dim3(nparts, nseg), dim3(BS), 0, s, n, rowptr, col, diag, offv,
+                       shift, nvec, b, x, r, partials, n * nseg);
+    MBL_CHECK_LAUNCH();
+}
+
 void launch_residual(int64_t n, const int32_t *rowptr, const int32_t *col, const double *diag,
                      double offv, double shift, int nvec, const double *b, const double *x,
                      double *r, double *partials, int nparts, hipStream_t s) {
-    hipLaunchKernelGGL(k_residual, dim3(nparts), dim3(BS), 0, s, n, rowptr, col, diag, offv, shift,
-                       nvec, b, x, r, partials);
-    MBL_CHECK_LAUNCH();
+    launch_residual_seg(1, n, rowptr, col, diag, offv, shift, nvec, b, x, r, partials, nparts, s);
 }
 
 int gemm_tn_parts(int64_t n) {
@@ -445,8 +523,14 @@ int gemm_tn_parts(int64_t n) {
 
 void launch_gemm_tn(int64_t n, int k, int b, const double *A, int64_t lda, const double *B,
                     int64_t ldb, double *C, double *partials, int nparts, hipStream_t s) {
+    launch_gemm_tn_seg(1, n, k, b, A, lda, 0, B, ldb, 0, C, 0, partials, nparts, s);
+}
+
+void launch_gemm_tn_seg(int nseg, int64_t n, int k, int b, const double *A, int64_t lda,
+                        int64_t segA, const double *B, int64_t ldb, int64_t segB, double *C,
+                        int64_t segC, double *partials, int nparts, hipStream_t s) {
     MBL_REQUIRE(b >= 0 && b <= NN_MAXB && k >= 0, MBL_EINVAL, "gemm_tn: b must be at most 16");
-    if (k == 0 || b == 0) return;
+    if (k == 0 || b == 0 || nseg == 0) return;
     int64_t rpp = (n + nparts - 1) / nparts;
     rpp = (rpp + TN_ROWS - 1) / TN_ROWS * TN_ROWS;
     int kc = std::min(k, TN_KC);
@@ -456,21 +540,29 @@ void launch_gemm_tn(int64_t n, int k, int b, const double *A, int64_t lda, const
         size_t tile = sizeof(double) * TN_ROWS * ((size_t)kc + 1 + NB);
         size_t red = sizeof(double) * (size_t)G * NB * kc;
         size_t sh = std::max(tile, red);
-        k_gemm_tn_part<NB><<<dim3((unsigned)nparts, (unsigned)((k + TN_KC - 1) / TN_KC)), dim3(BS),
-                             sh, s>>>(n, k, b, A, lda, B, ldb, partials, rpp);
+        k_gemm_tn_part<NB><<<dim3((unsigned)nparts, (unsigned)((k + TN_KC - 1) / TN_KC),
+                                  (unsigned)nseg), dim3(BS), sh, s>>>(n, k, b, A, lda, B, ldb,
+                                                                      partials, rpp, segA, segB);
     };
     if (b <= 4) go(std::integral_constant<int, 4>{});
     else if (b <= 8) go(std::integral_constant<int, 8>{});
     else go(std::integral_constant<int, 16>{});
     MBL_CHECK_LAUNCH();
     int kb = k * b;
-    k_sum_parts<<<dim3(grid_for(kb, 64)), dim3(64 * SP_G), 0, s>>>(kb, nparts, partials, C);
+    k_sum_parts<<<dim3(grid_for(kb, 64), (unsigned)nseg), dim3(64 * SP_G), 0, s>>>(kb, nparts,
+                                                                                 partials, C, segC);
     MBL_CHECK_LAUNCH();
 }
 
 void launch_gemm_nn(int64_t n, int k, int b, double alpha, const double *A, int64_t lda,
                     const double *Y, int ldy, double beta, double *C, int64_t ldc, hipStream_t s) {
-    if (n == 0 || b == 0) return;
+    launch_gemm_nn_seg(1, n, k, b, alpha, A, lda, 0, Y, ldy, 0, beta, C, ldc, 0, s);
+}
+
+void launch_gemm_nn_seg(int nseg, int64_t n, int k, int b, double alpha, const double *A,
+                        int64_t lda, int64_t segA, const double *Y, int ldy, int64_t segY,
+                        double beta, double *C, int64_t ldc, int64_t segC, hipStream_t s) {
+    if (n == 0 || b == 0 || nseg == 0) return;
     constexpr int KN = 256;    // columns of A per launch (LDS for Y stays under 64 KB)
     for (int j0 = 0; j0 < b; j0 += NN_MAXB) {
         int bb = (b - j0) < NN_MAXB ? (b - j0) : NN_MAXB;
@@ -479,9 +571,9 @@ void launch_gemm_nn(int64_t n, int k, int b, double alpha, const double *A, int6
             for (int k0 = 0; k0 < std::max(k, 1); k0 += KN) {
                 int kk = std::min(KN, k - k0);
                 size_t sh = sizeof(double) * ((size_t)kk * NB + (size_t)NN_KG * NN_ROWS * NB);
-                k_gemm_nn<NB><<<dim3(grid_for(n, NN_ROWS)), dim3(BS), sh, s>>>(
+                k_gemm_nn<NB><<<dim3(grid_for(n, NN_ROWS), (unsigned)nseg), dim3(BS), sh, s>>>(
                     n, kk, bb, alpha, A + (int64_t)k0 * lda, lda, Y + k0 + (int64_t)j0 * ldy, ldy,
-                    k0 == 0 ? beta : 1.0, C + (int64_t)j0 * ldc, ldc);
+                    k0 == 0 ? beta : 1.0, C + (int64_t)j0 * ldc, ldc, segA, segY, segC);
             }
         };
         if (bb <= 4) go(std::integral_constant<int, 4>{});
@@ -498,10 +590,34 @@ void launch_gather(int64_t n, int nvec, const int32_t *idx, const double *x, dou
     MBL_CHECK_LAUNCH();
 }
 
+void launch_fill_start_seg(int nseg, int64_t n, int nvec, const uint64_t *seeds, double *v,
+                           int64_t ld, hipStream_t s) {
+    MBL_REQUIRE(nseg >= 0 && nseg <= MBL_SEG_MAX, MBL_EINVAL, "fill_start: too many segments");
+    if (n * nvec == 0 || nseg == 0) return;
+    SegSeeds sd;
+    for (int q = 0; q < nseg; q++) sd.seed[q] = seeds[q];
+    hipLaunchKernelGGL(k_fill_start, dim3(grid_for(n * nvec, 256), nseg), dim3(256), 0, s, n, nvec,
+                       sd, v, ld);
+    MBL_CHECK_LAUNCH();
+}
+
 void launch_fill_start(int64_t n, int nvec, uint64_t seed, double *v, hipStream_t s) {
-    if (n * nvec == 0) return;
-    hipLaunchKernelGGL(k_fill_start, dim3(grid_for(n * nvec, 256)), dim3(256), 0, s, n, nvec, seed,
-                       v);
+    launch_fill_start_seg(1, n, nvec, &seed, v, n, s);
+}
+
+void launch_axpy_masked(int64_t n, int nseg, int nvec, const int *on, const double *x, double *y,
+                        hipStream_t s) {
+    if (n * nvec == 0 || nseg == 0) return;
+    hipLaunchKernelGGL(k_axpy_masked, dim3(grid_for(n * nvec, 256), nseg), dim3(256), 0, s, n, nseg,
+                       nvec, on, x, y);
+    MBL_CHECK_LAUNCH();
+}
+
+void launch_shift_seg(int nseg, int64_t n, const double *x, SegVals shift, double *y,
+                      hipStream_t s) {
+    MBL_REQUIRE(nseg >= 0 && nseg <= MBL_SEG_MAX, MBL_EINVAL, "shift_seg: at most 16 segments");
+    if (n == 0 || nseg == 0) return;
+    hipLaunchKernelGGL(k_shift_seg, dim3(grid_for(n, 256), nseg), dim3(256), 0, s, n, x, shift, y);
     MBL_CHECK_LAUNCH();
 }
 

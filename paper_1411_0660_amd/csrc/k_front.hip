@@ -132,7 +132,8 @@ template <class T>
 __global__ __launch_bounds__(256) void k_panel(T *arena, const FrontDesc *__restrict__ fd,
                                                int32_t *__restrict__ ipiv,
                                                int32_t *__restrict__ nperturbed, TaskList tl,
-                                               int t, double thresh, double *__restrict__ uinv) {
+                                               int t, const double *__restrict__ thresh,
+                                               double *__restrict__ uinv) {
     constexpr int H = FNB / 2;
     __shared__ T D[FNB][FNB + 1];
     __shared__ double Ui[FNB][FNB + 1];
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(256) void k_panel(T *arena, const FrontDesc *__rest
     for (int i = g; i < FNB; i += 4)
         D[i][c] = (i < kb && c < kb) ? F[(int64_t)(k0 + i) + (int64_t)(k0 + c) * m] : T(0);
     __syncthreads();
-    const T th = (T)thresh;
+    const T th = (T)thresh[d.seg];                   // the static-pivot threshold of its problem
     for (int j = 0; j < kb; j++) {
         if (g == 0) {
             // pivot: argmax over rows i >= j of |D[i][j]| (lane = row), first on
@@ -176,7 +177,7 @@ __global__ __launch_bounds__(256) void k_panel(T *arena, const FrontDesc *__rest
         if (threadIdx.x == 0) {
             D[j][j] = pv;
             rpv[j] = rp;
-            if (pert) atomicAdd(nperturbed, 1);
+            if (pert) atomicAdd(nperturbed + d.seg, 1);   // per problem of a batch
         }
     }
     __syncthreads();
@@ -978,7 +979,7 @@ void launch_front_assemble(T *arena, const FrontDesc *fd, int64_t count, const i
 
 template <class T>
 void launch_panel(T *arena, const FrontDesc *fd, int32_t *ipiv, int32_t *nperturbed, TaskList tl,
-                  int t, double thresh, double *uinv, hipStream_t s) {
+                  int t, const double *thresh, double *uinv, hipStream_t s) {
     if (tl.n == 0) return;
     k_panel<T><<<dim3(tl.n), dim3(256), 0, s>>>(arena, fd, ipiv, nperturbed, tl, t, thresh, uinv);
     MBL_CHECK_LAUNCH();
@@ -1047,7 +1048,7 @@ int merge_tri_items(int p) {
                                            const int32_t *, const int32_t *, const double *,    \
                                            double, double, hipStream_t);                        \
     template void launch_panel<T>(T *, const FrontDesc *, int32_t *, int32_t *, TaskList, int,  \
-                                  double, double *, hipStream_t);                               \
+                                  const double *, double *, hipStream_t);                       \
     template void launch_trsm<T>(T *, const FrontDesc *, const int32_t *, TaskList, TaskList,    \
                                  int, const double *, hipStream_t);                             \
     template void launch_xform<T>(T *, const FrontDesc *, TaskList, hipStream_t);               \

@@ -154,11 +154,19 @@ __device__ __forceinline__ void jacobi_rounds(int m, double *T, double *V, doubl
 // A (m x m, column-major, symmetric; overwritten), V (m x m) <- eigenvectors,
 // w[m] <- eigenvalues (unsorted, w[j] belongs to column j of V),
 // info <- sweeps used, or -1 if the sweep limit was reached.
+// Matrix blockIdx.x of a batch: operands at strides m^2 (A, V), m (w), 1
+// (info); its threshold tol_abs[blockIdx.x].
 __global__ __launch_bounds__(JT) void k_jacobi_eig(int m, double *A, double *V, double *w,
-                                                   int *info, double tol_abs) {
+                                                   int *info, const double *tol) {
     __shared__ double Tl[JLDS_MAX * JLDS_MAX];
     __shared__ double cs_c[JMAX / 2], cs_s[JMAX / 2], cs_t[JMAX / 2], cs_a[JMAX / 2];
     __shared__ int pp[JMAX / 2], pq[JMAX / 2], nrot;
+    const int64_t mm = (int64_t)m * m;
+    A += blockIdx.x * mm;
+    V += blockIdx.x * mm;
+    w += (int64_t)blockIdx.x * m;
+    info += blockIdx.x;
+    const double tol_abs = tol[blockIdx.x];
     for (int it = threadIdx.x; it < m * m; it += JT)
         V[it] = ((it % m) == (it / m)) ? 1.0 : 0.0;
     if (m <= JLDS_MAX) {
@@ -173,10 +181,11 @@ __global__ __launch_bounds__(JT) void k_jacobi_eig(int m, double *A, double *V, 
 
 }  // namespace
 
-void launch_jacobi_eig(int m, double *A, double *V, double *w, int *info, double tol_abs,
-                       hipStream_t s) {
+void launch_jacobi_eig_batch(int count, int m, double *A, double *V, double *w, int *info,
+                             const double *tol_abs, hipStream_t s) {
     MBL_REQUIRE(m >= 1 && m <= JMAX, MBL_EINVAL, "Jacobi eigensolver: order out of range");
-    hipLaunchKernelGGL(k_jacobi_eig, dim3(1), dim3(JT), 0, s, m, A, V, w, info, tol_abs);
+    if (count == 0) return;
+    hipLaunchKernelGGL(k_jacobi_eig, dim3(count), dim3(JT), 0, s, m, A, V, w, info, tol_abs);
     MBL_CHECK_LAUNCH();
 }
 

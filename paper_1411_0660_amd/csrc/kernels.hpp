@@ -7,6 +7,17 @@
 
 namespace mbl {
 
+// Segmented launches: nseg independent problems of the same size n whose
+// vectors are stacked (segment s is rows [s n, (s + 1) n) of a packed column,
+// ld = nseg n), each processed with exactly the arithmetic of a lone launch.
+constexpr int MBL_SEG_MAX = 16;
+struct SegSeeds {
+    uint64_t seed[MBL_SEG_MAX];
+};
+struct SegVals {
+    double v[MBL_SEG_MAX];
+};
+
 // ---- basis, ranking, assembly (k_basis.hip) ---------------------------------
 void launch_fields(int L, double h, uint64_t seed, double *out, hipStream_t s);
 void launch_basis(int L, int64_t dim, uint32_t *basis, hipStream_t s);
@@ -21,6 +32,35 @@ void launch_diag(int L, double J, const double *fields, int64_t dim, const uint3
                  double *diag, hipStream_t s);
 
 // ---- sparse and dense FP64 level-1/2/3 helpers (k_blas.hip) -----------------
+// segmented variants (see MBL_SEG_MAX): segment s offsets its operands by
+// s * seg* elements; partial-sum scratch grows nseg times
+void launch_gemm_tn_seg(int nseg, int64_t n, int k, int b, const double *A, int64_t lda,
+                        int64_t segA, const double *B, int64_t ldb, int64_t segB, double *C,
+                        int64_t segC, double *partials, int nparts, hipStream_t s);
+void launch_gemm_nn_seg(int nseg, int64_t n, int k, int b, double alpha, const double *A,
+                        int64_t lda, int64_t segA, const double *Y, int ldy, int64_t segY,
+                        double beta, double *C, int64_t ldc, int64_t segC, hipStream_t s);
+void launch_small_chol_batch(int count, int b, const double *G, int64_t segG, double *R,
+                             double *Rinv, int64_t segR, int *flag, int64_t segF, double rel_tiny,
+                             hipStream_t s);
+void launch_fill_start_seg(int nseg, int64_t n, int nvec, const uint64_t *seeds, double *v,
+                           int64_t ld, hipStream_t s);
+void launch_coldot_seg(int nseg, int64_t n, int ncol, const double *A, int64_t lda,
+                       const double *B, int64_t ldb, int64_t seg, double *out, double *partials,
+                       int nparts, hipStream_t s);
+void launch_sub_scaled_cols_seg(int nseg, int64_t n, int ncol, const double *e, const double *X,
+                                int64_t ldx, double *Y, int64_t ldy, hipStream_t s);
+// rows of segment s of a block-diagonal H: [s n, (s + 1) n), CSR columns global
+void launch_residual_seg(int nseg, int64_t n, const int32_t *rowptr, const int32_t *col,
+                         const double *diag, double offv, double shift, int nvec, const double *b,
+                         const double *x, double *r, double *partials, int nparts, hipStream_t s);
+// y[s n + i] = x[s n + i] - shift.v[s] (one shift per segment)
+void launch_shift_seg(int nseg, int64_t n, const double *x, SegVals shift, double *y,
+                      hipStream_t s);
+// y += x on the segments s with on[s] != 0 (device flags)
+void launch_axpy_masked(int64_t n, int nseg, int nvec, const int *on, const double *x, double *y,
+                        hipStream_t s);
+
 // y = (H - shift) x for nvec column-major vectors; off-diagonal value offv.
 void launch_spmv(int64_t n, const int32_t *rowptr, const int32_t *col, const double *diag,
                  double offv, double shift, int nvec, const double *x, double *y, hipStream_t s);
@@ -60,9 +100,11 @@ void launch_sub_scaled_cols(int64_t n, int ncol, const double *e, const double *
 
 // ---- small dense symmetric eigenproblems (k_jacobi.hip) ---------------------
 // A (m x m symmetric, column-major, overwritten) -> eigenvalues w[m] (unsorted)
-// and eigenvectors V (m x m, column j for w[j]); *info = sweeps used or -1.
-// One workgroup; m <= 1024.
-void launch_jacobi_eig(int m, double *A, double *V, double *w, int *info, double tol_abs,
-                       hipStream_t s);
+// and eigenvectors V (m x m, column j for w[j]); *info = sweeps used or -1;
+// m <= 1024.
+// count independent matrices at strides m^2 (A, V), m (w), 1 (info), each
+// with its own threshold tol_abs[k] (device), one workgroup each
+void launch_jacobi_eig_batch(int count, int m, double *A, double *V, double *w, int *info,
+                             const double *tol_abs, hipStream_t s);
 
 }  // namespace mbl

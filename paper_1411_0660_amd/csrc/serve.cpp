@@ -9,7 +9,10 @@
 // idle slots give back their buffers when that makes it fit.  Each slot solves
 // on its own stream in its own thread, so requests overlap on the device; the
 // arithmetic of a request does not depend on the slot or on what else runs, so
-// its result is the same alone and in the mix.
+// its result is the same alone and in the mix.  Queued requests that can share
+// launches (one chain length and the same solver settings) are admitted
+// together, up to the batch limit, and solved as one batch (solve_batch), each
+// with its lone arithmetic.
 #include "serve.hpp"
 
 #include <algorithm>
@@ -43,7 +46,9 @@ size_t footprint_bytes(const Plan &p, int prec, int nev, int block) {
     return bytes;
 }
 
-Server::Server(Context *owner, int slots, size_t budget) : owner_(owner), budget_(budget) {
+Server::Server(Context *owner, int slots, size_t budget, int max_batch)
+    : owner_(owner), budget_(budget) {
+    set_max_batch(max_batch);
     t0_ = wall_seconds();
     stats_.slots = slots;
     stats_.budget_bytes = budget;
@@ -69,6 +74,11 @@ Server::~Server() {
     std::lock_guard<std::mutex> lk(mu_);
     for (uint64_t t : queue_) finish_locked(t, MBL_EBUSY);   // never started
     queue_.clear();
+}
+
+void Server::set_max_batch(int m) {
+    std::lock_guard<std::mutex> lk(mu_);
+    max_batch_ = std::max(1, std::min(m, MBL_SEG_MAX));
 }
 
 uint64_t Server::submit(const mbl_problem &prob, mbl_result *res) {
@@ -129,6 +139,22 @@ bool Server::admit_locked() {
     bool any = false;
     const int nslots = (int)slots_.size();
     std::vector<uint64_t> skipped;
+    // the idle slot a request of `need` bytes fits in with the least growth
+    auto find_slot = [&](size_t need) {
+        size_t total = 0;
+        for (auto &sl : slots_) total += sl->held;
+        int best = -1;
+        size_t best_growth = 0;
+        for (int s = 0; s < nslots; s++) {
+            Slot &sl = *slots_[s];
+            if (sl.busy) continue;
+            size_t grown = std::max(sl.held, need);
+            if (total - sl.held + grown > budget_) continue;
+            size_t growth = grown - sl.held;
+            if (best < 0 || growth < best_growth) { best = s; best_growth = growth; }
+        }
+        return best;
+    };
     for (auto it = queue_.begin(); it != queue_.end();) {
         uint64_t t = *it;
         Req &r = reqs_[t];
@@ -138,34 +164,45 @@ bool Server::admit_locked() {
             finish_locked(t, MBL_ENOMEM);
             continue;
         }
-        size_t total = 0, busy_held = 0;
-        for (auto &sl : slots_) {
-            total += sl->held;
-            if (sl->busy) busy_held += sl->held;
+        // queued requests that can share this one's launches, in arrival order
+        std::vector<uint64_t> batch{t};
+        if (max_batch_ > 1) {
+            for (auto jt = std::next(it); jt != queue_.end() && (int)batch.size() < max_batch_; ++jt) {
+                Req &u = reqs_[*jt];
+                if (!u.sized) break;
+                mbl_problem pair[2] = {r.prob, u.prob};
+                if (batchable(pair, 2)) batch.push_back(*jt);
+            }
         }
-        int best = -1;
-        size_t best_growth = 0;
-        for (int s = 0; s < nslots; s++) {
-            Slot &sl = *slots_[s];
-            if (sl.busy) continue;
-            size_t grown = std::max(sl.held, r.fp);
-            if (total - sl.held + grown > budget_) continue;
-            size_t growth = grown - sl.held;
-            if (best < 0 || growth < best_growth) { best = s; best_growth = growth; }
+        // the largest part of the batch that fits an idle slot (each problem
+        // of a batch holds what it would alone)
+        size_t count = batch.size();
+        int best = find_slot(count * r.fp);
+        while (best < 0 && count > 1) {
+            count /= 2;
+            best = find_slot(count * r.fp);
         }
-        if (best < 0 && busy_held + r.fp <= budget_) {
-            // idle slots give their buffers back until the request fits
-            for (int s = 0; s < nslots && best < 0; s++) {
-                Slot &sl = *slots_[s];
-                if (sl.busy || sl.held == 0) continue;
-                {
-                    std::lock_guard<std::recursive_mutex> g(sl.ctx->mu);
-                    sl.ctx->trim();
+        if (best < 0) {
+            count = 1;
+            size_t busy_held = 0, total = 0;
+            for (auto &sl : slots_) {
+                total += sl->held;
+                if (sl->busy) busy_held += sl->held;
+            }
+            if (busy_held + r.fp <= budget_) {
+                // idle slots give their buffers back until the request fits
+                for (int s = 0; s < nslots && best < 0; s++) {
+                    Slot &sl = *slots_[s];
+                    if (sl.busy || sl.held == 0) continue;
+                    {
+                        std::lock_guard<std::recursive_mutex> g(sl.ctx->mu);
+                        sl.ctx->trim();
+                    }
+                    total -= sl.held;
+                    sl.held = 0;
+                    stats_.trims++;
+                    if (total + r.fp <= budget_) best = s;
                 }
-                total -= sl.held;
-                sl.held = 0;
-                stats_.trims++;
-                if (total + r.fp <= budget_) best = s;
             }
         }
         if (best < 0) {
@@ -174,19 +211,34 @@ bool Server::admit_locked() {
             ++it;
             continue;
         }
+        batch.resize(count);
         Slot &sl = *slots_[best];
-        sl.held = std::max(sl.held, r.fp);
+        sl.held = std::max(sl.held, count * r.fp);
         sl.busy = true;
-        sl.ticket = t;
-        r.t_start = wall_seconds() - t0_;
-        running_++;
-        stats_.admitted++;
+        sl.tickets = batch;
+        const double now = wall_seconds() - t0_;
+        for (uint64_t u : batch) reqs_[u].t_start = now;
+        running_ += (int)count;
+        stats_.admitted += (int64_t)count;
+        if (count > 1) {
+            stats_.batches++;
+            stats_.batched += (int64_t)count;
+        }
         stats_.max_running = std::max<int64_t>(stats_.max_running, running_);
         for (uint64_t u : skipped) {
             reqs_[u].bypassed++;
             stats_.bypasses++;
         }
-        it = queue_.erase(it);
+        // the batch leaves the queue (its companions all queued after the head);
+        // the scan goes on from the head's place
+        const auto pos = it - queue_.begin();
+        queue_.erase(std::remove_if(queue_.begin() + pos, queue_.end(),
+                                    [&](uint64_t u) {
+                                        return std::find(batch.begin(), batch.end(), u) !=
+                                               batch.end();
+                                    }),
+                     queue_.end());
+        it = queue_.begin() + pos;
         sl.cv.notify_one();
         any = true;
     }
@@ -234,6 +286,35 @@ void Server::dispatcher() {
     }
 }
 
+// One request on a slot, capped at the bytes the slot was admitted with.
+int Server::solve_alone(Slot &sl, size_t admitted, const mbl_problem &prob, mbl_result *res,
+                        bool &retried) {
+    int st = MBL_OK;
+    for (int attempt = 0; attempt < 2; attempt++) {
+        st = MBL_OK;
+        try {
+            std::lock_guard<std::recursive_mutex> g(sl.ctx->mu);
+            // the slot may hold no more device memory than it was admitted with
+            sl.ctx->budget.limit = admitted;
+            solve_problem(*sl.ctx, prob, *res);
+        } catch (const Error &e) {
+            st = e.code;
+        } catch (const std::bad_alloc &) {
+            st = MBL_ENOMEM;
+        } catch (const std::exception &) {
+            st = MBL_EDEVICE;
+        }
+        // buffers kept from earlier, differently sized requests can push a
+        // slot past its admission: it gives them back and runs once more
+        if (st != MBL_ENOMEM || attempt > 0) break;
+        std::lock_guard<std::recursive_mutex> g(sl.ctx->mu);
+        if (sl.ctx->budget.used == 0) break;
+        sl.ctx->trim();
+        retried = true;
+    }
+    return st;
+}
+
 void Server::worker(int s) {
     (void)hipSetDevice(owner_->device);
     Slot &sl = *slots_[s];
@@ -241,41 +322,45 @@ void Server::worker(int s) {
     for (;;) {
         sl.cv.wait(lk, [&] { return stop_ || sl.busy; });
         if (!sl.busy) return;                     // stopping, nothing assigned
-        uint64_t t = sl.ticket;
-        mbl_problem prob = reqs_[t].prob;
-        mbl_result *res = reqs_[t].res;
+        const std::vector<uint64_t> tickets = sl.tickets;
+        const int count = (int)tickets.size();
+        std::vector<mbl_problem> probs(count);
+        std::vector<mbl_result *> outs(count);
+        for (int q = 0; q < count; q++) {
+            probs[q] = reqs_[tickets[q]].prob;
+            outs[q] = reqs_[tickets[q]].res;
+        }
         const size_t admitted = sl.held;
         lk.unlock();
-        int st = MBL_OK;
-        bool retried = false;
-        for (int attempt = 0; attempt < 2; attempt++) {
-            st = MBL_OK;
+        std::vector<int> st(count, MBL_OK);
+        bool retried = false, done = false;
+        if (count > 1) {
+            // one batch: its plan is built by the owning context, then every
+            // problem is solved with its lone arithmetic in shared launches
+            std::vector<mbl_result> res(count);
+            for (int q = 0; q < count; q++) res[q] = *outs[q];
             try {
+                {
+                    std::lock_guard<std::recursive_mutex> g(owner_->mu);
+                    owner_->batch_plan(probs[0].L, count);
+                }
                 std::lock_guard<std::recursive_mutex> g(sl.ctx->mu);
-                // the slot may hold no more device memory than it was admitted with
                 sl.ctx->budget.limit = admitted;
-                solve_problem(*sl.ctx, prob, *res);
-            } catch (const Error &e) {
-                st = e.code;
-            } catch (const std::bad_alloc &) {
-                st = MBL_ENOMEM;
+                done = solve_batch(*sl.ctx, count, probs.data(), res.data(), st.data());
             } catch (const std::exception &) {
-                st = MBL_EDEVICE;
+                done = false;
             }
-            // buffers kept from earlier, differently sized requests can push a
-            // slot past its admission: it gives them back and runs once more
-            if (st != MBL_ENOMEM || attempt > 0) break;
-            std::lock_guard<std::recursive_mutex> g(sl.ctx->mu);
-            if (sl.ctx->budget.used == 0) break;
-            sl.ctx->trim();
-            retried = true;
+            if (done)
+                for (int q = 0; q < count; q++) *outs[q] = res[q];
         }
+        if (!done)
+            for (int q = 0; q < count; q++) st[q] = solve_alone(sl, admitted, probs[q], outs[q], retried);
         lk.lock();
         if (retried) stats_.retries++;
         stats_.max_slot_peak = std::max<size_t>(stats_.max_slot_peak, sl.ctx->budget.peak);
         sl.busy = false;
-        running_--;
-        finish_locked(t, st);
+        running_ -= count;
+        for (int q = 0; q < count; q++) finish_locked(tickets[q], st[q]);
         cv_.notify_all();
     }
 }

@@ -2,7 +2,8 @@
 // mbl_wait): a fixed set of slots, each a solver context with its own HIP
 // stream and host thread, so the work of several requests overlaps on the
 // device; requests are admitted in arrival order as slots and device memory
-// free up, by the predicted footprint of their factor and Krylov storage.
+// free up, by the predicted footprint of their factor and Krylov storage, and
+// queued requests that can share launches are solved as one batch.
 #pragma once
 
 #include <condition_variable>
@@ -15,6 +16,7 @@
 #include <vector>
 
 #include "../../include/mbl.h"
+#include "kernels.hpp"
 #include "solver.hpp"
 
 namespace mbl {
@@ -27,8 +29,10 @@ size_t footprint_bytes(const Plan &p, int prec, int nev, int block);
 class Server {
   public:
     // `owner` builds the per-L plans that the slots share; `budget` bounds the
-    // device bytes the slots hold together (grow-only work buffers included).
-    Server(Context *owner, int slots, size_t budget);
+    // device bytes the slots hold together (grow-only work buffers included);
+    // at most max_batch queued requests that can be batched are solved together.
+    Server(Context *owner, int slots, size_t budget, int max_batch);
+    void set_max_batch(int m);
     ~Server();
     uint64_t submit(const mbl_problem &prob, mbl_result *res);
     int poll(uint64_t ticket, int *done);
@@ -51,11 +55,13 @@ class Server {
         std::thread th;
         std::condition_variable cv;
         bool busy = false;
-        uint64_t ticket = 0;
+        std::vector<uint64_t> tickets;   // the request, or the batch, it solves
         size_t held = 0;           // bytes its work buffers may hold (largest admitted)
     };
     void dispatcher();
     void worker(int s);
+    int solve_alone(Slot &sl, size_t admitted, const mbl_problem &prob, mbl_result *res,
+                    bool &retried);
     bool admit_locked();
     void finish_locked(uint64_t t, int status);
 
@@ -70,6 +76,7 @@ class Server {
     uint64_t next_ = 1;
     bool stop_ = false;
     int running_ = 0;
+    int max_batch_ = MBL_SEG_MAX;
     mbl_serve_info stats_{};
     double t0_ = 0.0;
 };

@@ -91,7 +91,15 @@ void Context::trim() {
                       &d_gcoef, &d_psi, &d_psi2, &d_hpsi, &d_e, &d_cpart, &d_obs, &d_r_out,
                       &d_se})
         b->reset();
-    for (DevBuf *b : {&f32_.uinv, &f64_.uinv}) b->reset();
+    for (DevBuf *b : {&f32_.uinv, &f64_.uinv, &f32_.thr, &f64_.thr, &fb64_.arena, &fb64_.ipiv,
+                      &fb64_.prow, &fb64_.npert, &fb64_.uinv, &fb64_.thr, &fb32_.arena,
+                      &fb32_.ipiv, &fb32_.prow, &fb32_.npert, &fb32_.uinv, &fb32_.thr, &d_on,
+                      &d_bdiag, &d_bshift})
+        b->reset();
+    fb64_.valid = false;
+    fb64_.L = -1;
+    fb32_.valid = false;
+    fb32_.L = -1;
     f32_.valid = false;
     f64_.valid = false;
     f32_.L = -1;                       // buffers freed: the next factorization reallocates
@@ -104,6 +112,7 @@ Context::~Context() {
     for (auto &e : prof.pool) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     if (owns_plans_) {
         std::lock_guard<std::recursive_mutex> lk(plans_->mu);
+        plans_->batched.clear();
         plans_->plans.clear();
     }
     if (own_stream) (void)hipStreamDestroy(stream);
@@ -180,8 +189,17 @@ void Context::ensure_symbolic(Plan &p) {
     A.col = p.h_col;
     NdOptions opt;
     p.tree = build_front_tree(A, opt);
+    build_tables(p);
+}
+
+// Device tables of a plan from its front tree and CSR pattern: front
+// descriptors, the maps of the extend-add and of the solves, the original
+// entries of every front, and the per-level task lists.  A batch plan's tree
+// is nseg copies of one tree, so every launch covers all its problems.
+void Context::build_tables(Plan &p) {
     FrontTree &t = p.tree;
     int nf = (int)t.fronts.size();
+    const int nf1 = nf / std::max(1, p.nseg);         // fronts per problem
     MBL_REQUIRE(t.max_m < 46340, MBL_EINVAL, "front too large for 32-bit local positions");
     MBL_REQUIRE((int64_t)t.contrib.size() < INT32_MAX, MBL_EINVAL, "contribution lists too long");
 
@@ -210,6 +228,7 @@ void Context::ensure_symbolic(Plan &p) {
             d.parent = F.parent;
             d.child0 = (int32_t)child_ids.size();
             d.nchild = (int32_t)F.children.size();
+            d.seg = nf1 > 0 ? f / nf1 : 0;
             for (int c : F.children) child_ids.push_back(c);
             off += (int64_t)d.m * d.m;
             voff += (int64_t)d.m * MAXRHS;
@@ -551,6 +570,75 @@ void Context::ensure_symbolic(Plan &p) {
     p.have_symbolic = true;
 }
 
+// The plan of nseg problems of one chain length solved together: the
+// block-diagonal matrix of nseg copies of the sector Hamiltonian, its front
+// tree nseg copies of the lone problem's (so each problem is factored and
+// solved with exactly its lone arithmetic), built once per (L, nseg).
+Plan &Context::batch_plan(int L, int nseg) {
+    MBL_REQUIRE(nseg >= 1 && nseg <= MBL_SEG_MAX, MBL_EINVAL, "batch of 1..16 problems");
+    std::lock_guard<std::recursive_mutex> lk(plans_->mu);
+    Plan &base = plan(L);
+    if (nseg == 1) return base;
+    ensure_symbolic(base);
+    const int key = L * 100 + nseg;
+    auto it = plans_->batched.find(key);
+    if (it != plans_->batched.end()) return *it->second;
+    MBL_REQUIRE(owns_plans_, MBL_EINVAL, "batch plan not prepared by the owning context");
+    std::unique_ptr<Plan> bp(new Plan);
+    const int64_t n = base.dim, nz = base.nnz;
+    bp->L = L;
+    bp->nseg = nseg;
+    bp->dim = n * nseg;
+    bp->nnz = nz * nseg;
+    MBL_REQUIRE(bp->nnz < INT32_MAX, MBL_EINVAL, "batch too large for 32-bit indices");
+    bp->h_rowptr.resize(bp->dim + 1);
+    bp->h_col.resize(bp->nnz);
+    for (int sg = 0; sg < nseg; sg++) {
+        for (int64_t i = 0; i < n; i++) bp->h_rowptr[sg * n + i] = base.h_rowptr[i] + (int32_t)(sg * nz);
+        for (int64_t e = 0; e < nz; e++) bp->h_col[sg * nz + e] = base.h_col[e] + (int32_t)(sg * n);
+    }
+    bp->h_rowptr[bp->dim] = (int32_t)bp->nnz;
+    bp->rowptr.alloc(sizeof(int32_t) * (bp->dim + 1), &budget);
+    bp->col.alloc(sizeof(int32_t) * bp->nnz, &budget);
+    h2d(bp->rowptr.ptr<int32_t>(), bp->h_rowptr.data(), bp->h_rowptr.size(), stream);
+    h2d(bp->col.ptr<int32_t>(), bp->h_col.data(), bp->h_col.size(), stream);
+    // the front tree, nseg times
+    const FrontTree &t = base.tree;
+    FrontTree &T = bp->tree;
+    const int nf = (int)t.fronts.size();
+    const int64_t nc = (int64_t)t.contrib.size();
+    T.n = bp->dim;
+    T.perm.resize(bp->dim);
+    T.iperm.resize(bp->dim);
+    T.fronts.resize((size_t)nf * nseg);
+    T.contrib.resize((size_t)nc * nseg);
+    for (int sg = 0; sg < nseg; sg++) {
+        for (int64_t i = 0; i < n; i++) {
+            T.perm[sg * n + i] = t.perm[i] + (int32_t)(sg * n);
+            T.iperm[sg * n + i] = t.iperm[i] + (int32_t)(sg * n);
+        }
+        for (int64_t e = 0; e < nc; e++) T.contrib[sg * nc + e] = t.contrib[e] + (int32_t)(sg * n);
+        for (int f = 0; f < nf; f++) {
+            Front F = t.fronts[f];
+            F.first += (int32_t)(sg * n);
+            F.cptr += sg * nc;
+            if (F.parent >= 0) F.parent += sg * nf;
+            for (auto &c : F.children) c += sg * nf;
+            T.fronts[(size_t)sg * nf + f] = F;
+        }
+    }
+    T.n_levels = t.n_levels;
+    T.nnz_factor = t.nnz_factor * nseg;
+    T.front_entries = t.front_entries * nseg;
+    T.max_m = t.max_m;
+    T.max_p = t.max_p;
+    T.flops = t.flops * nseg;
+    build_tables(*bp);
+    Plan &ref = *bp;
+    plans_->batched[key] = std::move(bp);
+    return ref;
+}
+
 void Context::set_realization(Plan &p, double J_, const double *fields_host, double h,
                               uint64_t seed, bool use_seed) {
     J = J_;
@@ -570,11 +658,12 @@ void Context::set_realization(Plan &p, double J_, const double *fields_host, dou
     MBL_HIP(hipStreamSynchronize(stream));
 }
 
-void Context::spmv(Plan &p, double shift, int nvec, const double *x, double *y) {
+void Context::spmv(Plan &p, double shift, int nvec, const double *x, double *y,
+                   const double *diag) {
     bool pr = prof_on("spmv");
     if (pr) prof_begin();
-    launch_spmv(p.dim, p.rowptr.ptr<int32_t>(), p.col.ptr<int32_t>(), d_diag.ptr<double>(), offv,
-                shift, nvec, x, y, stream);
+    launch_spmv(p.dim, p.rowptr.ptr<int32_t>(), p.col.ptr<int32_t>(),
+                diag ? diag : d_diag.ptr<double>(), offv, shift, nvec, x, y, stream);
     // per vector: columns (4 B/nnz), rowptr, diagonal, x gathered, y written
     if (pr) prof_end(4.0 * p.nnz + 4.0 * p.dim + 8.0 * p.dim + nvec * 16.0 * p.dim,
                      2.0 * nvec * (double)p.nnz);
@@ -583,9 +672,11 @@ void Context::spmv(Plan &p, double shift, int nvec, const double *x, double *y) 
 // ---------------------------------------------------------------- factor
 
 template <class T>
-void Context::factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel, SolveStats &st) {
+void Context::factor_t(Plan &p, Factor<T> &f, const double *diag, double sigma,
+                       const std::vector<double> &thresh, SolveStats &st) {
     hipStream_t s = stream;
-    if (f.L != p.L) {
+    MBL_REQUIRE((int)thresh.size() == p.nseg, MBL_EINVAL, "factor: one threshold per problem");
+    if (f.L != p.L || f.dim != p.dim) {
         // invalid until every buffer is in place: an allocation that throws
         // part way must not leave buffers of another size behind a valid L
         f.L = -1;
@@ -594,27 +685,29 @@ void Context::factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel, S
         f.arena.alloc(sizeof(T) * p.arena_elems, &budget);
         f.ipiv.alloc(sizeof(int32_t) * std::max<int64_t>(1, p.dim), &budget);
         f.prow.alloc(sizeof(int32_t) * std::max<int64_t>(1, p.dim), &budget);
-        f.npert.alloc(sizeof(int32_t), &budget);
+        f.npert.alloc(sizeof(int32_t) * MBL_SEG_MAX, &budget);
         f.uinv.alloc(sizeof(double) * FNB * FNB * std::max<size_t>(1, p.h_fd.size()), &budget);
+        f.thr.alloc(sizeof(double) * MBL_SEG_MAX, &budget);
         f.L = p.L;
+        f.dim = p.dim;
     }
     f.valid = false;
-    MBL_HIP(hipMemsetAsync(f.npert.template ptr<int32_t>(), 0, sizeof(int32_t), s));
+    MBL_HIP(hipMemsetAsync(f.npert.template ptr<int32_t>(), 0, sizeof(int32_t) * p.nseg, s));
     T *A = f.arena.template ptr<T>();
     const FrontDesc *fd = p.d_fd.ptr<FrontDesc>();
-    double thresh = thresh_rel * anorm_;
+    h2d(f.thr.template ptr<double>(), thresh.data(), thresh.size(), s);
     for (size_t l = 0; l < p.levels.size(); l++) {
         LevelTasks &lv = p.levels[l];
         launch_front_pull<T>(A, fd, p.d_pullmap.ptr<int32_t>(), p.d_child_ids.ptr<int32_t>(),
                              lv.pull, s);
         launch_front_assemble<T>(A, fd, lv.ecount, p.d_efront.ptr<int32_t>() + lv.ebegin,
                                  p.d_epos.ptr<int32_t>() + lv.ebegin,
-                                 p.d_esrc.ptr<int32_t>() + lv.ebegin, d_diag.ptr<double>(), sigma,
-                                 offv, s);
+                                 p.d_esrc.ptr<int32_t>() + lv.ebegin, diag, sigma, offv, s);
         for (size_t t = 0; t < lv.steps.size(); t++) {
             StepTasks &S = lv.steps[t];
             launch_panel<T>(A, fd, f.ipiv.template ptr<int32_t>(), f.npert.template ptr<int32_t>(),
-                            S.panel, (int)t, thresh, f.uinv.template ptr<double>(), s);
+                            S.panel, (int)t, f.thr.template ptr<double>(),
+                            f.uinv.template ptr<double>(), s);
             launch_trsm<T>(A, fd, f.ipiv.template ptr<int32_t>(), S.trsm_u, S.rows_below, (int)t,
                            f.uinv.template ptr<double>(), s);
             launch_schur<T>(A, fd, S.schur, (int)t, 0, s);
@@ -639,10 +732,11 @@ void Context::factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel, S
         launch_schur<T>(A, fd, p.fold_up[tp], (int)tp, 3, s);
     }
     launch_merge_tri<T>(A, fd, p.merge, s);
-    int32_t np = 0;
-    d2h(&np, f.npert.template ptr<int32_t>(), 1, s);
+    st.perturbed.assign(p.nseg, 0);
+    d2h(st.perturbed.data(), f.npert.template ptr<int32_t>(), p.nseg, s);
     MBL_HIP(hipStreamSynchronize(s));
-    st.n_perturbed = np;
+    st.n_perturbed = 0;
+    for (int v : st.perturbed) st.n_perturbed += v;
     f.valid = true;
     f.sigma = sigma;
 }
@@ -651,8 +745,9 @@ void Context::factor(Plan &p, int prec, double sigma, double anorm, SolveStats &
     ensure_symbolic(p);
     anorm_ = anorm;
     double t0 = wall_seconds();
-    if (prec == MBL_FP32_IR64) factor_t<float>(p, f32_, sigma, 1e-7, st);
-    else factor_t<double>(p, f64_, sigma, 1e-14, st);
+    // static pivots: below 1e-7 ||A|| (FP32 factors) or 1e-14 ||A|| (FP64)
+    if (prec == MBL_FP32_IR64) factor_t<float>(p, f32_, d_diag.ptr<double>(), sigma, {1e-7 * anorm}, st);
+    else factor_t<double>(p, f64_, d_diag.ptr<double>(), sigma, {1e-14 * anorm}, st);
     st.t_factor = wall_seconds() - t0;
 }
 
@@ -678,7 +773,7 @@ void Context::lu_apply(Plan &p, Factor<T> &f, int nrhs, const double *b, int64_t
     d_xnew.ensure(sizeof(double) * n * MAXRHS, &budget);
     d_gin.ensure(sizeof(double) * n * MAXRHS, &budget);
     d_gout.ensure(sizeof(double) * n * MAXRHS, &budget);
-    GraphKey key{p.L, (int)sizeof(T), nrhs,
+    GraphKey key{&p, p.L, (int)sizeof(T), nrhs,
                  {f.arena.template ptr<void>(), f.prow.template ptr<void>(), d_vec.ptr<void>(),
                   d_yv.ptr<void>(),
                   d_upart.ptr<void>(), d_xnew.ptr<void>(), d_gin.ptr<void>(), d_gout.ptr<void>()}};
@@ -961,68 +1056,207 @@ void Context::shift_solve(Plan &p, int prec, int nrhs, const double *B, double *
     st.t_solve += wall_seconds() - t0;
 }
 
-// ---------------------------------------------------------------- Krylov-Schur
+// ---------------------------------------------------------------- batches
 
-// All eigenpairs of the symmetric m x m matrix A (host, column-major) by the
-// device Jacobi kernel: w ascending, Z (m x m) the unit eigenvectors in the
-// same order.
-void Context::small_eig(int m, const std::vector<double> &A, std::vector<double> &w,
-                        std::vector<double> &Z) {
+void Context::factor_batch(Plan &bp, int prec, const double *shifted,
+                           const std::vector<double> &anorm, SolveStats &st) {
+    MBL_REQUIRE((int)anorm.size() == bp.nseg, MBL_EINVAL, "factor_batch: one norm per problem");
+    double t0 = wall_seconds();
+    // the static-pivot thresholds of lone factors, per problem; the diagonals
+    // arrive shifted, so the assembly subtracts zero
+    std::vector<double> th(bp.nseg);
+    for (int sg = 0; sg < bp.nseg; sg++) th[sg] = (prec == MBL_FP32_IR64 ? 1e-7 : 1e-14) * anorm[sg];
+    if (prec == MBL_FP32_IR64) factor_t<float>(bp, fb32_, shifted, 0.0, th, st);
+    else factor_t<double>(bp, fb64_, shifted, 0.0, th, st);
+    st.t_factor = wall_seconds() - t0;
+}
+
+// Refinement of the problems of a batch, each deciding when to stop exactly as
+// refine() does for a lone problem (same residuals, same tests, in the same
+// order); a problem that has stopped keeps its X while the others go on.  Where
+// a lone solve would leave the plain refinement (FP32 contracting slowly, or
+// no convergence), the batch cannot follow it: the problem is dropped from the
+// batch (bs.dropped) and solved alone afterwards.
+template <class T>
+void Context::refine_batch(Plan &p, Factor<T> &f, int nrhs, const double *B, double *X,
+                           const double *shifted, const std::vector<double> &anorm,
+                           const std::vector<char> &skip, BatchSolveStats &bs) {
     hipStream_t s = stream;
-    const size_t mm = (size_t)m * m;
-    d_ritz.ensure(sizeof(double) * (2 * mm + m + 1), &budget);
-    double *dA = d_ritz.ptr<double>(), *dV = dA + mm, *dw = dV + mm;
-    int *dinfo = reinterpret_cast<int *>(dw + m);
-    double fro = 0.0;
-    for (double x : A) fro += x * x;
-    fro = std::sqrt(fro);
-    h2d(dA, A.data(), mm, s);
-    // off-diagonal entries at or below 1e-17 ||A||_F are left in place: their
-    // effect on the eigenvalues is below the rounding of ||A||
-    launch_jacobi_eig(m, dA, dV, dw, dinfo, 1e-17 * fro, s);
-    std::vector<double> wu(m), Vu(mm);
-    int info = 0;
-    d2h(wu.data(), dw, m, s);
-    d2h(Vu.data(), dV, mm, s);
-    d2h(&info, dinfo, 1, s);
-    MBL_HIP(hipStreamSynchronize(s));
-    if (info < 0) throw Error(MBL_ENUMERIC, "Jacobi eigensolver: sweep limit reached");
-    if (debug_level() > 1) std::fprintf(stderr, "[mbl] jacobi m=%d sweeps=%d\n", m, info);
-    std::vector<int> perm(m);
-    std::iota(perm.begin(), perm.end(), 0);
-    std::stable_sort(perm.begin(), perm.end(), [&](int a, int c) { return wu[a] < wu[c]; });
-    w.resize(m);
-    Z.resize(mm);
-    for (int j = 0; j < m; j++) {
-        w[j] = wu[perm[j]];
-        std::copy(Vu.begin() + (size_t)perm[j] * m, Vu.begin() + (size_t)(perm[j] + 1) * m,
-                  Z.begin() + (size_t)j * m);
+    const int nseg = p.nseg;
+    const int64_t N = p.dim, n = N / nseg;
+    d_r.ensure(sizeof(double) * N * MAXRHS, &budget);
+    d_d.ensure(sizeof(double) * N * MAXRHS, &budget);
+    d_part.ensure(sizeof(double) * RES_PARTS * MAXRHS * 3 * nseg, &budget);
+    d_on.ensure(sizeof(int) * MBL_SEG_MAX, &budget);
+    double *r = d_r.ptr<double>(), *dd = d_d.ptr<double>();
+    std::vector<int> on(nseg);
+    for (int sg = 0; sg < nseg; sg++) on[sg] = (skip[sg] || bs.dropped[sg]) ? 0 : 1;
+    auto count_pass = [&]() {
+        for (int sg = 0; sg < nseg; sg++)
+            if (on[sg]) { bs.passes[sg]++; bs.pass_rhs[sg] += nrhs; }
+    };
+    lu_apply<T>(p, f, nrhs, B, N, X, N);
+    count_pass();
+    std::vector<double> part((size_t)RES_PARTS * nrhs * 3 * nseg), prev(nseg, 1e300), be(nseg, 0.0);
+    const double target = 1e-13;
+    for (int it = 0;; it++) {
+        launch_residual_seg(nseg, n, p.rowptr.ptr<int32_t>(), p.col.ptr<int32_t>(), shifted, offv,
+                            0.0, nrhs, B, X, r, d_part.ptr<double>(), RES_PARTS, s);
+        d2h(part.data(), d_part.ptr<double>(), part.size(), s);
+        MBL_HIP(hipStreamSynchronize(s));
+        int active = 0;
+        for (int sg = 0; sg < nseg; sg++) {
+            if (!on[sg]) continue;
+            const double *ps = &part[(size_t)sg * RES_PARTS * nrhs * 3];
+            double e_max = 0.0;
+            for (int v = 0; v < nrhs; v++) {
+                double sr = 0, sx = 0, sb = 0;
+                for (int q = 0; q < RES_PARTS; q++) {
+                    const double *pp = &ps[((size_t)q * nrhs + v) * 3];
+                    sr += pp[0]; sx += pp[1]; sb += pp[2];
+                }
+                double den = anorm[sg] * std::sqrt(sx) + std::sqrt(sb);
+                double e = den > 0 ? std::sqrt(sr) / den : 0.0;
+                e_max = std::max(e_max, e);
+            }
+            be[sg] = e_max;
+            if (bs.hooks[sg] & (sizeof(T) == 4 ? MBL_HOOK_IR_STALL32 : MBL_HOOK_IR_STALL64)) {
+                on[sg] = 0;                        // the lone solve fails here (test hook)
+                bs.dropped[sg] = 1;
+                continue;
+            }
+            bool stop = (e_max <= target || it >= 12);
+            if (!stop && sizeof(T) == 4 && it >= 1 && e_max > 0.25 * prev[sg]) {
+                on[sg] = 0;                        // a lone solve goes on with GMRES
+                bs.dropped[sg] = 1;
+                continue;
+            }
+            if (!stop && e_max > 0.5 * prev[sg] && it >= 3) stop = true;    // stagnation
+            if (stop) {
+                on[sg] = 0;
+                bs.ir_iters[sg] = std::max(bs.ir_iters[sg], it);
+                if (e_max > 1e-10) bs.dropped[sg] = 1;    // a lone solve reports the failure
+                continue;
+            }
+            prev[sg] = e_max;
+            active++;
+        }
+        if (debug_level() > 0)
+            std::fprintf(stderr, "[mbl] refine batch L=%d x%d prec=%s it=%d active=%d\n", p.L, nseg,
+                         sizeof(T) == 4 ? "fp32" : "fp64", it, active);
+        if (!active) break;
+        h2d(d_on.ptr<int>(), on.data(), nseg, s);
+        lu_apply<T>(p, f, nrhs, r, N, dd, N);
+        count_pass();
+        launch_axpy_masked(n, nseg, nrhs, d_on.ptr<int>(), dd, X, s);
     }
 }
 
-Context::KSOut Context::krylov_schur(int64_t n, int b, int ncv, int nkeep, int nwant, Want want,
-                                     const std::function<void(const double *, double *, int)> &op,
-                                     const std::function<bool(double, double)> &conv,
-                                     int max_restarts, uint64_t seed, double *out) {
+void Context::shift_solve_batch(Plan &bp, int prec, int nrhs, const double *B, double *X,
+                                const double *shifted, const std::vector<double> &anorm,
+                                const std::vector<char> &skip, BatchSolveStats &bs) {
+    double t0 = wall_seconds();
+    for (int c = 0; c < nrhs; c += MAXRHS) {
+        int nb = std::min(MAXRHS, nrhs - c);
+        const int64_t o = (int64_t)c * bp.dim;
+        if (prec == MBL_FP32_IR64) refine_batch<float>(bp, fb32_, nb, B + o, X + o, shifted, anorm, skip, bs);
+        else refine_batch<double>(bp, fb64_, nb, B + o, X + o, shifted, anorm, skip, bs);
+    }
+    bs.t_solve += wall_seconds() - t0;
+}
+
+// ---------------------------------------------------------------- Krylov-Schur
+
+// All eigenpairs of count symmetric m x m matrices A[k] (host, column-major)
+// by the device Jacobi kernel, one workgroup each: w[k] ascending, Z[k]
+// (m x m) the unit eigenvectors in the same order.
+void Context::small_eig_batch(int count, int m, const std::vector<std::vector<double>> &A,
+                              std::vector<std::vector<double>> &w,
+                              std::vector<std::vector<double>> &Z) {
+    hipStream_t s = stream;
+    const size_t mm = (size_t)m * m;
+    d_ritz.ensure(sizeof(double) * ((2 * mm + m + 2) * (size_t)count + 8), &budget);
+    double *dA = d_ritz.ptr<double>(), *dV = dA + mm * count, *dw = dV + mm * count;
+    double *dtol = dw + (size_t)m * count;
+    int *dinfo = reinterpret_cast<int *>(dtol + count);
+    std::vector<double> tol(count);
+    for (int k = 0; k < count; k++) {
+        double fro = 0.0;
+        for (double x : A[k]) fro += x * x;
+        // off-diagonal entries at or below 1e-17 ||A||_F are left in place:
+        // their effect on the eigenvalues is below the rounding of ||A||
+        tol[k] = 1e-17 * std::sqrt(fro);
+        h2d(dA + mm * k, A[k].data(), mm, s);
+    }
+    h2d(dtol, tol.data(), (size_t)count, s);
+    launch_jacobi_eig_batch(count, m, dA, dV, dw, dinfo, dtol, s);
+    std::vector<double> wu((size_t)m * count), Vu(mm * count);
+    std::vector<int> info(count);
+    d2h(wu.data(), dw, wu.size(), s);
+    d2h(Vu.data(), dV, Vu.size(), s);
+    d2h(info.data(), dinfo, (size_t)count, s);
+    MBL_HIP(hipStreamSynchronize(s));
+    w.assign(count, {});
+    Z.assign(count, {});
+    for (int k = 0; k < count; k++) {
+        if (info[k] < 0) throw Error(MBL_ENUMERIC, "Jacobi eigensolver: sweep limit reached");
+        if (debug_level() > 1) std::fprintf(stderr, "[mbl] jacobi m=%d sweeps=%d\n", m, info[k]);
+        const double *wk = wu.data() + (size_t)m * k, *vk = Vu.data() + mm * k;
+        std::vector<int> perm(m);
+        std::iota(perm.begin(), perm.end(), 0);
+        std::stable_sort(perm.begin(), perm.end(), [&](int a, int c) { return wk[a] < wk[c]; });
+        w[k].resize(m);
+        Z[k].resize(mm);
+        for (int j = 0; j < m; j++) {
+            w[k][j] = wk[perm[j]];
+            std::copy(vk + (size_t)perm[j] * m, vk + (size_t)(perm[j] + 1) * m,
+                      Z[k].begin() + (size_t)j * m);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- Krylov-Schur
+
+// Thick-restart block Krylov-Schur on nseg independent problems of order n at
+// once (dropped, if given: problems the operator gave up, which stop at the
+// next Rayleigh-Ritz step without a result).  Their vectors are packed (problem s is rows [s n, (s + 1) n) of every
+// column, ld = nseg n), the operator acts on packed blocks, and every
+// reduction, small factorisation and Rayleigh-Ritz step is done per problem
+// with exactly the arithmetic of a lone problem, so each problem's results do
+// not depend on the others.  A problem whose wanted pairs have converged (or
+// that reached max_restarts) writes its Ritz vectors to its rows of out and
+// stops changing; the iteration ends when every problem has.
+void Context::krylov_schur(int64_t n, int nseg, int b, int ncv, int nkeep, int nwant, Want want,
+                           const KSOp &op, const std::function<bool(int, double, double)> &conv,
+                           int max_restarts, const uint64_t *seeds, double *out,
+                           std::vector<KSOut> &result, const std::vector<char> *dropped) {
     hipStream_t s = stream;
     const int cols = ncv + b;
     const bool full = (ncv >= n);   // the basis can span the whole space
+    const int64_t ldv = n * nseg;
     MBL_REQUIRE(nwant <= nkeep && nkeep <= ncv && ncv % b == 0 && (full || nkeep + b <= ncv) &&
                     (full || nkeep % b == 0) && (!full || b == 1),
                 MBL_EINVAL, "krylov_schur: inconsistent basis sizes");
-    d_V.ensure(sizeof(double) * n * cols, &budget);
-    d_V2.ensure(sizeof(double) * n * cols, &budget);
-    d_W.ensure(sizeof(double) * n * b, &budget);
-    d_small.ensure(sizeof(double) * (size_t)cols * std::max(cols, b) * 2, &budget);
+    MBL_REQUIRE(nseg >= 1 && nseg <= MBL_SEG_MAX && (nseg == 1 || b > 1), MBL_EINVAL,
+                "krylov_schur: batched problems need a block size above one");
+    d_V.ensure(sizeof(double) * ldv * cols, &budget);
+    d_V2.ensure(sizeof(double) * ldv * cols, &budget);
+    d_W.ensure(sizeof(double) * ldv * b, &budget);
+    // per problem: coefficient / projection block, Gram matrix, R, R^-1
+    const int64_t SMS = (int64_t)cols * std::max(cols, b) + 3 * (int64_t)b * b;
+    d_small.ensure(sizeof(double) * SMS * nseg + sizeof(int) * 2 * nseg + 64, &budget);
     int nparts = gemm_tn_parts(n);
-    d_tnpart.ensure(sizeof(double) * (size_t)nparts * cols * b, &budget);
+    d_tnpart.ensure(sizeof(double) * (size_t)nparts * cols * b * nseg, &budget);
     double *V = d_V.ptr<double>(), *V2 = d_V2.ptr<double>(), *W = d_W.ptr<double>();
     double *sm = d_small.ptr<double>();
     double *tnp = d_tnpart.ptr<double>();
-    std::vector<double> T((size_t)cols * cols, 0.0);
-    auto Tat = [&](int i, int j) -> double & { return T[(size_t)j * cols + i]; };
+    double *smG = sm + (int64_t)cols * std::max(cols, b), *smR = smG + b * b, *smRi = smR + b * b;
+    int *dflag = reinterpret_cast<int *>(sm + SMS * nseg);
+    std::vector<std::vector<double>> T(nseg, std::vector<double>((size_t)cols * cols, 0.0));
+    auto Tat = [&](int sg, int i, int j) -> double & { return T[sg][(size_t)j * cols + i]; };
 
-    // classical Gram-Schmidt, twice, of blk against V[:, 0:c0]; coefficients summed
+    // classical Gram-Schmidt, twice, of blk against V[:, 0:c0]; coefficients
+    // summed (single problem, vector at a time)
     std::vector<double> hh;
     auto project = [&](int c0, double *blk, std::vector<double> &hsum) {
         hsum.assign((size_t)c0 * b, 0.0);
@@ -1036,7 +1270,8 @@ Context::KSOut Context::krylov_schur(int64_t n, int b, int ncv, int nkeep, int n
             for (size_t q = 0; q < hh.size(); q++) hsum[q] += hh[q];
         }
     };
-    // dst = src R^-1 (Cholesky QR, two passes); src is used as scratch
+    // dst = src R^-1 (Cholesky QR, two passes, host factors; single problem);
+    // src is used as scratch
     std::vector<double> G, Ri;
     auto cholqr = [&](double *src, double *dst, std::vector<double> &R) -> bool {
         G.resize((size_t)b * b);
@@ -1067,91 +1302,117 @@ Context::KSOut Context::krylov_schur(int64_t n, int b, int ncv, int nkeep, int n
     // Blocks of more than one vector expand without host round trips: the
     // Cholesky factors are computed on the device, the projection coefficients
     // and R factors are copied to page-locked memory asynchronously, and the
-    // projected matrix is assembled once per restart cycle.
+    // projected matrices are assembled once per restart cycle.
     const bool async = (b > 1);
-    struct Stage { int cur; size_t h1, h2, r1, r2; };
+    std::vector<char> finished(nseg, 0);
+    struct Stage { int cur; size_t h1, h2, r1, r2, fl; };
     std::vector<Stage> stages;
-    const size_t stage_max = (size_t)(cols / b + 1) * (2 * (size_t)cols * b + 2 * (size_t)b * b);
-    double *smG = sm + (size_t)cols * std::max(cols, b), *smR = smG + b * b, *smRi = smR + b * b;
-    int *dflag = reinterpret_cast<int *>(smRi + b * b);
-    if (async) h_stage.ensure(sizeof(double) * stage_max + sizeof(int) * 2 * (cols / b + 1));
+    const size_t stage_max =
+        (size_t)(cols / b + 1) * (2 * (size_t)cols * b + 2 * (size_t)b * b) * nseg;
+    const size_t flag_max = (size_t)2 * (cols / b + 1) * nseg;
+    if (async) h_stage.ensure(sizeof(double) * stage_max + sizeof(int) * flag_max);
     double *hp = h_stage.ptr<double>();
     int *hflag = async ? reinterpret_cast<int *>(hp + stage_max) : nullptr;
-    size_t hoff = 0;
+    size_t hoff = 0, foff = 0;
+    // copy one block of `count` doubles per problem from the device (stride SMS)
+    // to consecutive host blocks at hp + hoff
+    auto stage_copy = [&](const double *src, size_t count) {
+        if (count == 0) return hoff;
+        MBL_HIP(hipMemcpy2DAsync(hp + hoff, sizeof(double) * count, src, sizeof(double) * SMS,
+                                 sizeof(double) * count, nseg, hipMemcpyDeviceToHost, s));
+        size_t at = hoff;
+        hoff += count * nseg;
+        return at;
+    };
     auto stage_block = [&](int c0, double *blk, double *dst) {
-        Stage stg{c0, 0, 0, 0, 0};
-        const int k = (int)stages.size();
+        Stage stg{c0, 0, 0, 0, 0, 0};
         for (int pass = 0; pass < 2; pass++) {             // CGS2 against V[:, 0:c0]
-            launch_gemm_tn(n, c0, b, V, n, blk, n, sm, tnp, nparts, s);
-            launch_gemm_nn(n, c0, b, -1.0, V, n, sm, c0, 1.0, blk, n, s);
-            (pass ? stg.h2 : stg.h1) = hoff;
-            MBL_HIP(hipMemcpyAsync(hp + hoff, sm, sizeof(double) * c0 * b,
-                                   hipMemcpyDeviceToHost, s));
-            hoff += (size_t)c0 * b;
+            launch_gemm_tn_seg(nseg, n, c0, b, V, ldv, n, blk, ldv, n, sm, SMS, tnp, nparts, s);
+            launch_gemm_nn_seg(nseg, n, c0, b, -1.0, V, ldv, n, sm, c0, SMS, 1.0, blk, ldv, n, s);
+            (pass ? stg.h2 : stg.h1) = stage_copy(sm, (size_t)c0 * b);
         }
         double *from = blk, *to = dst;                      // Cholesky QR, twice
         for (int pass = 0; pass < 2; pass++) {
-            launch_gemm_tn(n, b, b, from, n, from, n, smG, tnp, nparts, s);
-            launch_small_chol(b, smG, smR, smRi, dflag + pass, 1e-24, s);
-            (pass ? stg.r2 : stg.r1) = hoff;
-            MBL_HIP(hipMemcpyAsync(hp + hoff, smR, sizeof(double) * b * b, hipMemcpyDeviceToHost,
-                                   s));
-            hoff += (size_t)b * b;
-            launch_gemm_nn(n, b, b, 1.0, from, n, smRi, b, 0.0, to, n, s);
+            launch_gemm_tn_seg(nseg, n, b, b, from, ldv, n, from, ldv, n, smG, SMS, tnp, nparts, s);
+            launch_small_chol_batch(nseg, b, smG, SMS, smR, smRi, SMS, dflag + pass, 2, 1e-24, s);
+            (pass ? stg.r2 : stg.r1) = stage_copy(smR, (size_t)b * b);
+            launch_gemm_nn_seg(nseg, n, b, b, 1.0, from, ldv, n, smRi, b, SMS, 0.0, to, ldv, n, s);
             std::swap(from, to);
         }
-        launch_copy(n * b, from, dst, s);                   // from == blk after two passes
-        MBL_HIP(hipMemcpyAsync(hflag + 2 * k, dflag, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+        launch_copy(ldv * b, from, dst, s);                 // from == blk after two passes
+        MBL_HIP(hipMemcpyAsync(hflag + foff, dflag, sizeof(int) * 2 * nseg, hipMemcpyDeviceToHost,
+                               s));
+        stg.fl = foff;
+        foff += 2 * nseg;
         stages.push_back(stg);
     };
     auto assemble_stages = [&]() {
         MBL_HIP(hipStreamSynchronize(s));
         for (size_t k = 0; k < stages.size(); k++) {
             const Stage &stg = stages[k];
-            if (hflag[2 * k] || hflag[2 * k + 1]) throw Error(MBL_ENUMERIC, "block Krylov breakdown");
             const int c0 = stg.cur;
-            for (int j = 0; j < b; j++)
-                for (int i = 0; i < c0; i++) {
-                    double v = hp[stg.h1 + (size_t)j * c0 + i] + hp[stg.h2 + (size_t)j * c0 + i];
-                    Tat(i, c0 - b + j) = v;
-                    Tat(c0 - b + j, i) = v;
-                }
-            const double *R1 = hp + stg.r1, *R2 = hp + stg.r2;   // R = R2 R1
-            for (int j = 0; j < b; j++)
-                for (int i = 0; i < b; i++) {
-                    double acc = 0.0;
-                    for (int q = 0; q < b; q++) acc += R2[(size_t)q * b + i] * R1[(size_t)j * b + q];
-                    Tat(c0 + i, c0 - b + j) = acc;
-                    Tat(c0 - b + j, c0 + i) = acc;
-                }
+            for (int sg = 0; sg < nseg; sg++) {
+                if (finished[sg] || (dropped && (*dropped)[sg])) continue;   // basis unused
+                if (hflag[stg.fl + 2 * sg] || hflag[stg.fl + 2 * sg + 1])
+                    throw Error(MBL_ENUMERIC, "block Krylov breakdown");
+                if (c0 == 0) continue;            // the start block: no coupling to keep
+                const double *h1 = hp + stg.h1 + (size_t)sg * c0 * b;
+                const double *h2 = hp + stg.h2 + (size_t)sg * c0 * b;
+                for (int j = 0; j < b; j++)
+                    for (int i = 0; i < c0; i++) {
+                        double v = h1[(size_t)j * c0 + i] + h2[(size_t)j * c0 + i];
+                        Tat(sg, i, c0 - b + j) = v;
+                        Tat(sg, c0 - b + j, i) = v;
+                    }
+                const double *R1 = hp + stg.r1 + (size_t)sg * b * b;   // R = R2 R1
+                const double *R2 = hp + stg.r2 + (size_t)sg * b * b;
+                for (int j = 0; j < b; j++)
+                    for (int i = 0; i < b; i++) {
+                        double acc = 0.0;
+                        for (int q = 0; q < b; q++) acc += R2[(size_t)q * b + i] * R1[(size_t)j * b + q];
+                        Tat(sg, c0 + i, c0 - b + j) = acc;
+                        Tat(sg, c0 - b + j, c0 + i) = acc;
+                    }
+            }
         }
         stages.clear();
         hoff = 0;
+        foff = 0;
     };
 
-    KSOut res;
+    result.assign(nseg, KSOut{});
+    int nfinished = 0;
     std::vector<double> R, hsum;
-    launch_fill_start(n, b, seed, W, s);
-    if (!cholqr(W, V, R)) throw Error(MBL_ENUMERIC, "start block is rank deficient");
+    launch_fill_start_seg(nseg, n, b, seeds, W, ldv, s);
+    if (async) {
+        // the start block through the same device Cholesky QR as the expansion
+        // (its coupling to an empty basis is not used)
+        stage_block(0, W, V);
+        assemble_stages();
+    } else if (!cholqr(W, V, R)) {
+        throw Error(MBL_ENUMERIC, "start block is rank deficient");
+    }
+    for (auto &t : T) std::fill(t.begin(), t.end(), 0.0);
     int cur = b;
     for (int restart = 0;; restart++) {
         while (async && cur < cols) {
-            op(V + (int64_t)(cur - b) * n, W, b);
-            res.napply += b;
-            stage_block(cur, W, V + (int64_t)cur * n);
+            op(V + (int64_t)(cur - b) * ldv, W, b, finished);
+            for (int sg = 0; sg < nseg; sg++)
+                if (!finished[sg]) result[sg].napply += b;
+            stage_block(cur, W, V + (int64_t)cur * ldv);
             cur += b;
         }
         if (async) assemble_stages();
         while (cur < cols) {
-            // expand the block [cur - b, cur) into [cur, cur + b)
-            op(V + (int64_t)(cur - b) * n, W, b);
-            res.napply += b;
+            // expand the block [cur - b, cur) into [cur, cur + b) (single problem)
+            op(V + (int64_t)(cur - b) * n, W, b, finished);
+            result[0].napply += b;
             project(cur, W, hsum);
             for (int j = 0; j < b; j++)
                 for (int i = 0; i < cur; i++) {
                     double v = hsum[(size_t)j * cur + i];
-                    Tat(i, cur - b + j) = v;
-                    Tat(cur - b + j, i) = v;
+                    Tat(0, i, cur - b + j) = v;
+                    Tat(0, cur - b + j, i) = v;
                 }
             bool ok = cholqr(W, V + (int64_t)cur * n, R);
             if (!ok) {
@@ -1162,7 +1423,7 @@ Context::KSOut Context::krylov_schur(int64_t n, int b, int ncv, int nkeep, int n
                 std::vector<double> R0;
                 bool ok2 = false;
                 if (cur < n) {
-                    launch_fill_start(n, 1, seed + 977ULL * (uint64_t)(cur + 1), W, s);
+                    launch_fill_start(n, 1, seeds[0] + 977ULL * (uint64_t)(cur + 1), W, s);
                     project(cur, W, hh);
                     ok2 = cholqr(W, V + (int64_t)cur * n, R0);
                 }
@@ -1170,78 +1431,117 @@ Context::KSOut Context::krylov_schur(int64_t n, int b, int ncv, int nkeep, int n
             }
             for (int j = 0; j < b; j++)
                 for (int i = 0; i < b; i++) {
-                    Tat(cur + i, cur - b + j) = R[(size_t)j * b + i];
-                    Tat(cur - b + j, cur + i) = R[(size_t)j * b + i];
+                    Tat(0, cur + i, cur - b + j) = R[(size_t)j * b + i];
+                    Tat(0, cur - b + j, cur + i) = R[(size_t)j * b + i];
                 }
             cur += b;
         }
-        // Rayleigh-Ritz on the first m columns; the last block is the residual
-        int m = cur - b;
-        std::vector<double> Tm((size_t)m * m), C((size_t)b * m);
-        for (int j = 0; j < m; j++) {
-            for (int i = 0; i < m; i++) Tm[(size_t)j * m + i] = Tat(i, j);
-            for (int i = 0; i < b; i++) C[(size_t)j * b + i] = Tat(m + i, j);
-        }
-        std::vector<double> wall, Z, Y;
-        small_eig(m, Tm, wall, Z);
-        res.tmin = wall.front();
-        res.tmax = wall.back();
-        std::vector<int> order(m);
-        std::iota(order.begin(), order.end(), 0);
-        if (want == Want::LargestAbs) {
-            std::stable_sort(order.begin(), order.end(),
-                             [&](int a, int c) { return std::fabs(wall[a]) > std::fabs(wall[c]); });
-        } else {
-            order.clear();
-            for (int lo = 0, hi = m - 1; lo <= hi; lo++, hi--) {
-                order.push_back(lo);
-                if (hi != lo) order.push_back(hi);
+        // Rayleigh-Ritz on the first m columns of every running problem; the
+        // last block is the residual
+        const int m = cur - b;
+        // problems dropped by the operator stop here, with no result
+        for (int sg = 0; sg < nseg; sg++)
+            if (!finished[sg] && dropped && (*dropped)[sg]) {
+                finished[sg] = 1;
+                nfinished++;
             }
-        }
-        std::vector<int> sel(order.begin(), order.begin() + nkeep);
-        Y.resize((size_t)m * nkeep);
-        for (int q = 0; q < nkeep; q++)
-            std::copy(Z.begin() + (size_t)sel[q] * m, Z.begin() + (size_t)(sel[q] + 1) * m,
-                      Y.begin() + (size_t)q * m);
-        const std::vector<double> &w = wall;
-        res.theta.assign(nkeep, 0.0);
-        res.rho.assign(nkeep, 0.0);
-        std::vector<double> CY((size_t)b * nkeep, 0.0);
-        for (int q = 0; q < nkeep; q++) {
-            res.theta[q] = w[sel[q]];
-            double acc = 0.0;
-            for (int i = 0; i < b; i++) {
-                double v = 0.0;
-                for (int j = 0; j < m; j++) v += C[(size_t)j * b + i] * Y[(size_t)q * m + j];
-                CY[(size_t)q * b + i] = v;
-                acc += v * v;
-            }
-            res.rho[q] = std::sqrt(acc);
-        }
-        int nconv = 0;
-        for (int q = 0; q < nwant; q++) nconv += conv(res.theta[q], res.rho[q]) ? 1 : 0;
-        res.nconv = nconv;
-        res.restarts = restart;
-        bool done = (nconv == nwant) || restart >= max_restarts;
-        h2d(sm, Y.data(), Y.size(), s);
-        if (done) {
-            launch_gemm_nn(n, m, nwant, 1.0, V, n, sm, m, 0.0, out, n, s);
+        if (nfinished == nseg) {
             MBL_HIP(hipStreamSynchronize(s));
-            res.theta.resize(nwant);
-            res.rho.resize(nwant);
-            return res;
+            return;
         }
-        // thick restart: kept Ritz vectors, then the residual block
-        launch_gemm_nn(n, m, nkeep, 1.0, V, n, sm, m, 0.0, V2, n, s);
-        launch_copy(n * b, V + (int64_t)m * n, V2 + (int64_t)nkeep * n, s);
-        std::swap(V, V2);
-        std::fill(T.begin(), T.end(), 0.0);
-        for (int q = 0; q < nkeep; q++) Tat(q, q) = res.theta[q];
-        for (int q = 0; q < nkeep; q++)
-            for (int i = 0; i < b; i++) {
-                Tat(nkeep + i, q) = CY[(size_t)q * b + i];
-                Tat(q, nkeep + i) = CY[(size_t)q * b + i];
+        std::vector<int> live;
+        for (int sg = 0; sg < nseg; sg++)
+            if (!finished[sg]) live.push_back(sg);
+        std::vector<std::vector<double>> Tm(live.size()), wall, Z;
+        for (size_t q = 0; q < live.size(); q++) {
+            Tm[q].resize((size_t)m * m);
+            for (int j = 0; j < m; j++)
+                for (int i = 0; i < m; i++) Tm[q][(size_t)j * m + i] = Tat(live[q], i, j);
+        }
+        small_eig_batch((int)live.size(), m, Tm, wall, Z);
+        std::vector<std::vector<double>> CYs(nseg);
+        std::vector<int> to_finish;
+        for (size_t q = 0; q < live.size(); q++) {
+            const int sg = live[q];
+            KSOut &res = result[sg];
+            const std::vector<double> &w = wall[q];
+            res.tmin = w.front();
+            res.tmax = w.back();
+            std::vector<int> order(m);
+            std::iota(order.begin(), order.end(), 0);
+            if (want == Want::LargestAbs) {
+                std::stable_sort(order.begin(), order.end(),
+                                 [&](int a, int c) { return std::fabs(w[a]) > std::fabs(w[c]); });
+            } else {
+                order.clear();
+                for (int lo = 0, hi = m - 1; lo <= hi; lo++, hi--) {
+                    order.push_back(lo);
+                    if (hi != lo) order.push_back(hi);
+                }
             }
+            std::vector<int> sel(order.begin(), order.begin() + nkeep);
+            std::vector<double> Y((size_t)m * nkeep);
+            for (int k = 0; k < nkeep; k++)
+                std::copy(Z[q].begin() + (size_t)sel[k] * m, Z[q].begin() + (size_t)(sel[k] + 1) * m,
+                          Y.begin() + (size_t)k * m);
+            res.theta.assign(nkeep, 0.0);
+            res.rho.assign(nkeep, 0.0);
+            std::vector<double> &CY = CYs[sg];
+            CY.assign((size_t)b * nkeep, 0.0);
+            for (int k = 0; k < nkeep; k++) {
+                res.theta[k] = w[sel[k]];
+                double acc = 0.0;
+                for (int i = 0; i < b; i++) {
+                    double v = 0.0;
+                    for (int j = 0; j < m; j++) v += Tat(sg, m + i, j) * Y[(size_t)k * m + j];
+                    CY[(size_t)k * b + i] = v;
+                    acc += v * v;
+                }
+                res.rho[k] = std::sqrt(acc);
+            }
+            int nconv = 0;
+            for (int k = 0; k < nwant; k++) nconv += conv(sg, res.theta[k], res.rho[k]) ? 1 : 0;
+            res.nconv = nconv;
+            res.restarts = restart;
+            h2d(sm + SMS * sg, Y.data(), Y.size(), s);
+            if (nconv == nwant || restart >= max_restarts) to_finish.push_back(sg);
+        }
+        for (int sg : to_finish) {
+            launch_gemm_nn_seg(1, n, m, nwant, 1.0, V + (int64_t)sg * n, ldv, 0, sm + SMS * sg, m, 0,
+                               0.0, out + (int64_t)sg * n, ldv, 0, s);
+            result[sg].theta.resize(nwant);
+            result[sg].rho.resize(nwant);
+            finished[sg] = 1;
+            nfinished++;
+        }
+        if (nfinished == nseg) {
+            MBL_HIP(hipStreamSynchronize(s));
+            return;
+        }
+        // thick restart: kept Ritz vectors, then the residual block.  Every
+        // problem moves; one that finished earlier keeps the first nkeep
+        // columns of its basis (identity coefficients), so its unused columns
+        // stay orthonormal and bounded.
+        if ((int)live.size() < nseg) {
+            std::vector<double> I((size_t)m * nkeep, 0.0);
+            for (int k = 0; k < nkeep; k++) I[(size_t)k * m + k] = 1.0;
+            for (int sg = 0; sg < nseg; sg++)
+                if (std::find(live.begin(), live.end(), sg) == live.end())
+                    h2d(sm + SMS * sg, I.data(), I.size(), s);
+        }
+        launch_gemm_nn_seg(nseg, n, m, nkeep, 1.0, V, ldv, n, sm, m, SMS, 0.0, V2, ldv, n, s);
+        launch_copy(ldv * b, V + (int64_t)m * ldv, V2 + (int64_t)nkeep * ldv, s);
+        std::swap(V, V2);
+        for (int sg : live) {
+            if (finished[sg]) continue;
+            std::fill(T[sg].begin(), T[sg].end(), 0.0);
+            for (int k = 0; k < nkeep; k++) Tat(sg, k, k) = result[sg].theta[k];
+            for (int k = 0; k < nkeep; k++)
+                for (int i = 0; i < b; i++) {
+                    Tat(sg, nkeep + i, k) = CYs[sg][(size_t)k * b + i];
+                    Tat(sg, k, nkeep + i) = CYs[sg][(size_t)k * b + i];
+                }
+        }
         cur = nkeep + b;
         MBL_HIP(hipStreamSynchronize(s));
     }
@@ -1252,39 +1552,50 @@ Context::KSOut Context::krylov_schur(int64_t n, int b, int ncv, int nkeep, int n
 namespace mbl {
 
 void Context::extremal(Plan &p, double &emin, double &emax, int &napply) {
-    int64_t n = p.dim;
+    extremal_seg(p, d_diag.ptr<double>(), &emin, &emax, &napply);
+}
+
+void Context::extremal_seg(Plan &p, const double *diag, double *emin, double *emax,
+                           int *napply) {
+    const int nseg = p.nseg;
+    const int64_t n = p.dim / nseg;
     int b = n >= 128 ? 4 : 1;
     int ncv = 64, nkeep = 16, nwant = 2;
     if (ncv >= n) { b = 1; ncv = (int)n; nkeep = std::max(1, (int)n - 1); nwant = std::min(2, nkeep); }
-    d_psi.ensure(sizeof(double) * n * nwant, &budget);
-    double scale = 1.0;
-    auto op = [&](const double *X, double *Y, int nb) { spmv(p, 0.0, nb, X, Y); };
-    auto conv = [&](double th, double rho) { return rho <= 1e-12 * scale; };
-    // scale from a first pass: |theta| extremes
-    scale = 1.0;
-    KSOut r = krylov_schur(n, b, ncv, nkeep, nwant, Want::BothEnds, op,
-                           [&](double th, double rho) {
-                               scale = std::max(scale, std::fabs(th));
-                               return conv(th, rho);
-                           },
-                           300, 0x6A09E667F3BCC909ULL, d_psi.ptr<double>());
-    emin = std::min(r.tmin, r.theta.empty() ? r.tmin : r.theta[0]);
-    emax = std::max(r.tmax, r.theta.empty() ? r.tmax : r.theta.back());
-    if (!r.theta.empty()) {
-        emin = r.theta[0];
-        emax = (nwant > 1) ? r.theta[1] : r.tmax;
-        if (emin > emax) std::swap(emin, emax);
+    d_psi.ensure(sizeof(double) * p.dim * nwant, &budget);
+    std::vector<double> scale(nseg, 1.0);
+    auto op = [&](const double *X, double *Y, int nb, const std::vector<char> &) {
+        spmv(p, 0.0, nb, X, Y, diag);
+    };
+    std::vector<uint64_t> seeds(nseg, 0x6A09E667F3BCC909ULL);
+    std::vector<KSOut> rs;
+    // scale: the largest |theta| seen so far
+    krylov_schur(n, nseg, b, ncv, nkeep, nwant, Want::BothEnds, op,
+                 [&](int sg, double th, double rho) {
+                     scale[sg] = std::max(scale[sg], std::fabs(th));
+                     return rho <= 1e-12 * scale[sg];
+                 },
+                 300, seeds.data(), d_psi.ptr<double>(), rs);
+    for (int sg = 0; sg < nseg; sg++) {
+        const KSOut &r = rs[sg];
+        double lo = r.tmin, hi = r.tmax;
+        if (!r.theta.empty()) {
+            lo = r.theta[0];
+            hi = (nwant > 1) ? r.theta[1] : r.tmax;
+            if (lo > hi) std::swap(lo, hi);
+        }
+        emin[sg] = lo;
+        emax[sg] = hi;
+        napply[sg] = r.napply;
+        if (r.nconv < nwant && ncv < n)
+            throw Error(MBL_ENOTCONV, "extremal eigenvalues did not converge");
     }
-    napply = r.napply;
-    if (r.nconv < nwant && ncv < n)
-        throw Error(MBL_ENOTCONV, "extremal eigenvalues did not converge");
 }
 
 namespace {
 int round_up(int a, int b) { return (a + b - 1) / b * b; }
-}
 
-void solve_problem(Context &ctx, const mbl_problem &pr, mbl_result &res, const double *extremal) {
+void check_problem(const mbl_problem &pr) {
     MBL_REQUIRE(pr.L >= 2 && pr.L <= MBL_L_MAX, MBL_EINVAL, "L must satisfy 2 <= L <= 22");
     int64_t n = binom(pr.L, sector_nup(pr.L));
     MBL_REQUIRE(pr.nev >= 1 && pr.nev <= n, MBL_EINVAL, "nev must satisfy 1 <= nev <= dim");
@@ -1292,133 +1603,101 @@ void solve_problem(Context &ctx, const mbl_problem &pr, mbl_result &res, const d
                 "eps must lie in [0, 1]");
     MBL_REQUIRE(pr.prec == MBL_FP64 || pr.prec == MBL_FP32_IR64, MBL_EINVAL, "unknown precision");
     MBL_REQUIRE(pr.nev <= 256, MBL_EINVAL, "nev above 256 is not supported");
-    hipStream_t s = ctx.stream;
-    // test hooks of this request, cleared however the request ends
-    struct HookScope {
-        Context &c;
-        HookScope(Context &cx, const mbl_problem &q) : c(cx) {
-            c.hooks = q.flags & (MBL_HOOK_IR_STALL32 | MBL_HOOK_IR_STALL64 | MBL_HOOK_NO_CONV);
-            c.budget.armed = q.fail_alloc_bytes;
-            c.budget.since_armed = 0;
-        }
-        ~HookScope() { c.hooks = 0; c.budget.armed = 0; c.budget.since_armed = 0; }
-    } hook_scope(ctx, pr);
-    double tol = pr.tol > 0 ? pr.tol : 1e-10;
-    double t_start = wall_seconds(), t0 = t_start;
-    std::memset(res.t_phase, 0, sizeof(res.t_phase));
+}
 
-    const int64_t passes0 = ctx.lu_passes, pass_rhs0 = ctx.lu_pass_rhs;
-    Plan &p = ctx.plan(pr.L);
-    ctx.set_realization(p, pr.J, pr.fields, pr.h, pr.seed, pr.fields == nullptr);
-    res.t_phase[0] = wall_seconds() - t0;
-
-    t0 = wall_seconds();
-    double emin = 0, emax = 0;
-    int nap = 0;
-    if (extremal) { emin = extremal[0]; emax = extremal[1]; }
-    else ctx.extremal(p, emin, emax, nap);
-    double hnorm = std::max(std::fabs(emin), std::fabs(emax));
-    if (hnorm == 0.0) hnorm = 1.0;
-    ctx.hnorm_ = hnorm;
-    double sigma = std::isfinite(pr.sigma) ? pr.sigma : emin + pr.eps * (emax - emin);
-    res.emin = emin; res.emax = emax; res.sigma = sigma; res.hnorm = hnorm;
-    res.t_phase[1] = wall_seconds() - t0;
-
-    t0 = wall_seconds();
-    ctx.ensure_symbolic(p);
-    res.t_phase[2] = wall_seconds() - t0;
-
-    // The LU is taken at sigma_f = sigma -+ delta: a shift that coincides with an
-    // eigenvalue (eps = 0 or 1 puts sigma on E_min / E_max) would make H - sigma
-    // singular.  delta is far below the level spacing; a few extra pairs are
-    // converged around sigma_f and the nev nearest sigma are selected, with a
-    // check that the window provably contains them.
-    t0 = wall_seconds();
-    const double delta = 1e-6 * hnorm;
-    const bool upper = std::isfinite(pr.sigma) ? true : (pr.eps >= 0.5);
-    const double sigma_f = sigma + (upper ? delta : -delta);
-    double anorm = hnorm + std::fabs(sigma_f);
-    SolveStats st;
-    int prec = pr.prec;
-    ctx.factor(p, prec, sigma_f, anorm, st);
-    res.t_phase[3] = wall_seconds() - t0;
-
-    // block Krylov-Schur on (H - sigma_f)^-1
-    t0 = wall_seconds();
-    int nev = pr.nev;
-    int nw = (int)std::min<int64_t>(n, nev + 2 + nev / 16);
-    int b = pr.block > 0 ? std::min(pr.block, 16) : default_block((int64_t)n);
-    int nkeep = round_up(nw + std::max(8, nw / 2), b);
-    int ncv = pr.ncv > 0 ? round_up(pr.ncv, b) : round_up(std::max(2 * nw + 2 * b, nkeep + 3 * b), b);
-    if (ncv + b > n) {               // small sector: a full-space basis, vector at a time
-        b = 1;
-        ncv = (int)n;
-        nkeep = std::min<int>(nkeep, (int)n);
+// Basis sizes of the shift-invert iteration: nw pairs converged (a few more
+// than nev, so that the selection can be certified), block b, nkeep kept at a
+// restart, ncv basis columns.
+struct KShape {
+    int nw, b, nkeep, ncv;
+};
+KShape krylov_shape(int64_t n, const mbl_problem &pr) {
+    KShape k;
+    const int nev = pr.nev;
+    k.nw = (int)std::min<int64_t>(n, nev + 2 + nev / 16);
+    k.b = pr.block > 0 ? std::min(pr.block, 16) : default_block(n);
+    k.nkeep = round_up(k.nw + std::max(8, k.nw / 2), k.b);
+    k.ncv = pr.ncv > 0 ? round_up(pr.ncv, k.b)
+                       : round_up(std::max(2 * k.nw + 2 * k.b, k.nkeep + 3 * k.b), k.b);
+    if (k.ncv + k.b > n) {              // small sector: a full-space basis, vector at a time
+        k.b = 1;
+        k.ncv = (int)n;
+        k.nkeep = std::min<int>(k.nkeep, (int)n);
     }
-    nkeep = std::max(nkeep, nw);
-    int max_restarts = pr.max_restarts > 0 ? pr.max_restarts : 300;
-    ctx.d_psi.ensure(sizeof(double) * n * nw, &ctx.budget);
-    bool fell_back = false;
-    auto op = [&](const double *X, double *Y, int nb) {
-        try {
-            ctx.shift_solve(p, prec, nb, X, Y, st);
-            if (prec == MBL_FP32_IR64 && st.gmres_inner > 8) {
-                // the FP32 factor needs many GMRES steps per solve here (kappa u_32
-                // near one): this result stands, later solves use an FP64 factor
-                prec = MBL_FP64;
-                fell_back = true;
-                SolveStats s2;
-                ctx.factor(p, prec, sigma_f, anorm, s2);
-            }
-        } catch (const Error &e) {
-            if (e.code != MBL_ENUMERIC || prec != MBL_FP32_IR64) throw;
-            // FP32 refinement did not reach the target: refactor in FP64
-            prec = MBL_FP64;
-            fell_back = true;
-            SolveStats s2;
-            ctx.factor(p, prec, sigma_f, anorm, s2);
-            ctx.shift_solve(p, prec, nb, X, Y, st);
-        }
-    };
-    const bool never_conv = (ctx.hooks & MBL_HOOK_NO_CONV) != 0;
-    auto conv = [&](double th, double rho) {
-        return !never_conv && th != 0.0 && rho * anorm <= 0.1 * tol * hnorm * std::fabs(th);
-    };
-    uint64_t kseed = pr.seed ^ 0xA5A5A5A5A5A5A5A5ULL;
-    Context::KSOut ks = ctx.krylov_schur(n, b, ncv, nkeep, nw, Context::Want::LargestAbs, op, conv,
-                                         max_restarts, kseed, ctx.d_psi.ptr<double>());
-    res.t_phase[4] = wall_seconds() - t0;
-    res.t_phase[7] = st.t_solve;
-    res.n_restarts = ks.restarts;
-    res.n_opapply = ks.napply;
-    res.n_passes = (int)(ctx.lu_passes - passes0);
-    res.n_pass_rhs = (int)(ctx.lu_pass_rhs - pass_rhs0);
-    res.ir_iters_max = st.ir_iters;
-    res.n_perturbed = st.n_perturbed;
-    res.fallback = fell_back ? 1 : 0;
+    k.nkeep = std::max(k.nkeep, k.nw);
+    return k;
+}
 
-    // energies (Rayleigh quotients) and FP64 residuals ||H psi - E psi||
-    t0 = wall_seconds();
-    ctx.d_hpsi.ensure(sizeof(double) * n * nw, &ctx.budget);
+// The shift of the LU and the norm its refinement is measured against.  The LU
+// is taken at sigma_f = sigma -+ delta: a shift that coincides with an
+// eigenvalue (eps = 0 or 1 puts sigma on E_min / E_max) would make H - sigma
+// singular.  delta is far below the level spacing; a few extra pairs are
+// converged around sigma_f and the nev nearest sigma are selected, with a
+// check that the window provably contains them.
+struct Shift {
+    double emin, emax, hnorm, sigma, delta, sigma_f, anorm;
+};
+Shift make_shift(const mbl_problem &pr, double emin, double emax) {
+    Shift z;
+    z.emin = emin;
+    z.emax = emax;
+    z.hnorm = std::max(std::fabs(emin), std::fabs(emax));
+    if (z.hnorm == 0.0) z.hnorm = 1.0;
+    z.sigma = std::isfinite(pr.sigma) ? pr.sigma : emin + pr.eps * (emax - emin);
+    z.delta = 1e-6 * z.hnorm;
+    const bool upper = std::isfinite(pr.sigma) ? true : (pr.eps >= 0.5);
+    z.sigma_f = z.sigma + (upper ? z.delta : -z.delta);
+    z.anorm = z.hnorm + std::fabs(z.sigma_f);
+    return z;
+}
+
+// Rayleigh quotients E, squared norms nrm and squared FP64 residuals
+// rr = ||H psi - E psi||^2 of the nw packed Ritz vectors of every problem of p
+// (psi: p.dim x nw; diag: the diagonals of H, packed); E[s * nw + j].
+void rayleigh_residuals(Context &ctx, Plan &p, const double *diag, int nw, double *psi,
+                        std::vector<double> &E, std::vector<double> &nrm,
+                        std::vector<double> &rr) {
+    hipStream_t s = ctx.stream;
+    const int nseg = p.nseg;
+    const int64_t N = p.dim, n = N / nseg;
+    const size_t cnt = (size_t)nseg * nw;
+    ctx.d_hpsi.ensure(sizeof(double) * N * nw, &ctx.budget);
+    ctx.d_e.ensure(sizeof(double) * 4 * std::max<size_t>(cnt, 256), &ctx.budget);
+    const int nparts = 64;
+    ctx.d_cpart.ensure(sizeof(double) * nparts * cnt, &ctx.budget);
+    double *hpsi = ctx.d_hpsi.ptr<double>(), *de = ctx.d_e.ptr<double>();
+    double *cp = ctx.d_cpart.ptr<double>();
+    ctx.spmv(p, 0.0, nw, psi, hpsi, diag);
+    launch_coldot_seg(nseg, n, nw, psi, N, psi, N, n, de + cnt, cp, nparts, s);
+    launch_coldot_seg(nseg, n, nw, psi, N, hpsi, N, n, de, cp, nparts, s);
+    E.resize(cnt);
+    nrm.resize(cnt);
+    rr.resize(cnt);
+    d2h(E.data(), de, cnt, s);
+    d2h(nrm.data(), de + cnt, cnt, s);
+    MBL_HIP(hipStreamSynchronize(s));
+    for (size_t j = 0; j < cnt; j++) E[j] /= nrm[j];
+    h2d(de, E.data(), cnt, s);
+    launch_sub_scaled_cols_seg(nseg, n, nw, de, psi, N, hpsi, N, s);
+    launch_coldot_seg(nseg, n, nw, hpsi, N, hpsi, N, n, de + 2 * cnt, cp, nparts, s);
+    d2h(rr.data(), de + 2 * cnt, cnt, s);
+    MBL_HIP(hipStreamSynchronize(s));
+}
+
+// Selection of the nev pairs nearest sigma among the nw Ritz pairs of one
+// problem (vectors psi, column stride ld; E, nrm, rr as above), the check that
+// the window holds them, and the observables of the selected vectors into res.
+// Returns the number of certified pairs.
+int select_and_observe(Context &ctx, Plan &p, const mbl_problem &pr, mbl_result &res,
+                       const double *psi, int64_t ld, const double *E, const double *nrm,
+                       const double *rr, int nw, const Shift &z, double tol, int ks_nconv) {
+    hipStream_t s = ctx.stream;
+    const int64_t n = p.dim;
+    const int nev = pr.nev;
+    const double sigma = z.sigma, sigma_f = z.sigma_f, hnorm = z.hnorm;
     ctx.d_psi2.ensure(sizeof(double) * n * nev, &ctx.budget);
-    ctx.d_e.ensure(sizeof(double) * 4 * nw, &ctx.budget);
-    int nparts = 64;
-    ctx.d_cpart.ensure(sizeof(double) * nparts * nw, &ctx.budget);
-    double *psi = ctx.d_psi.ptr<double>(), *hpsi = ctx.d_hpsi.ptr<double>();
+    ctx.d_e.ensure(sizeof(double) * 4 * std::max(nw, 256), &ctx.budget);
     double *de = ctx.d_e.ptr<double>();
-    ctx.spmv(p, 0.0, nw, psi, hpsi);
-    launch_coldot(n, nw, psi, n, psi, n, de + nw, ctx.d_cpart.ptr<double>(), nparts, s);
-    launch_coldot(n, nw, psi, n, hpsi, n, de, ctx.d_cpart.ptr<double>(), nparts, s);
-    std::vector<double> E(nw), nrm(nw), rr(nw);
-    d2h(E.data(), de, nw, s);
-    d2h(nrm.data(), de + nw, nw, s);
-    MBL_HIP(hipStreamSynchronize(s));
-    for (int j = 0; j < nw; j++) E[j] /= nrm[j];
-    h2d(de, E.data(), nw, s);
-    launch_sub_scaled_cols(n, nw, de, psi, n, hpsi, n, s);
-    launch_coldot(n, nw, hpsi, n, hpsi, n, de + 2 * nw, ctx.d_cpart.ptr<double>(), nparts, s);
-    d2h(rr.data(), de + 2 * nw, nw, s);
-    MBL_HIP(hipStreamSynchronize(s));
     // the nev nearest sigma (ties: lower energy first), then ascending energy
     std::vector<int> ord(nw);
     std::iota(ord.begin(), ord.end(), 0);
@@ -1440,8 +1719,8 @@ void solve_problem(Context &ctx, const mbl_problem &pr, mbl_result &res, const d
         if (dj < unconv) Rwin = std::max(Rwin, dj);
     }
     for (int j : ord) rsel = std::max(rsel, std::fabs(E[j] - sigma));
-    bool window_ok = (nw == n && ks.nconv == nw) ||
-                     (rsel + delta <= Rwin * (1.0 + 1e-12) && rsel + delta < unconv);
+    bool window_ok = (nw == n && ks_nconv == nw) ||
+                     (rsel + z.delta <= Rwin * (1.0 + 1e-12) && rsel + z.delta < unconv);
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) { return E[a] < E[c]; });
     std::vector<double> Es(nev), rs(nev);
     int nconv = 0;
@@ -1449,14 +1728,14 @@ void solve_problem(Context &ctx, const mbl_problem &pr, mbl_result &res, const d
     for (int j = 0; j < nev; j++) {
         Es[j] = E[ord[j]];
         rs[j] = std::sqrt(rr[ord[j]] / nrm[ord[j]]) / hnorm;
-        launch_copy(n, psi + (int64_t)ord[j] * n, ctx.d_psi2.ptr<double>() + (int64_t)j * n, s);
+        launch_copy(n, psi + (int64_t)ord[j] * ld, ctx.d_psi2.ptr<double>() + (int64_t)j * n, s);
         if (rs[j] <= tol) nconv++;
         maxr = std::max(maxr, rs[j]);
     }
     if (!window_ok) nconv = std::min(nconv, nev - 1);
     // the Krylov method stopped at its restart limit: nothing is certified
     // beyond the pairs its own test accepted
-    if (ks.nconv < nw) nconv = std::min(nconv, ks.nconv);
+    if (ks_nconv < nw) nconv = std::min(nconv, ks_nconv);
     h2d(de, Es.data(), nev, s);
     double *psis = ctx.d_psi2.ptr<double>();
     res.nconv = nconv;
@@ -1506,10 +1785,264 @@ void solve_problem(Context &ctx, const mbl_problem &pr, mbl_result &res, const d
         d2h(res.evecs, psis, (size_t)n * nev, s);
         MBL_HIP(hipStreamSynchronize(s));
     }
+    return nconv;
+}
+
+void set_shift(mbl_result &res, const Shift &z) {
+    res.emin = z.emin;
+    res.emax = z.emax;
+    res.sigma = z.sigma;
+    res.hnorm = z.hnorm;
+}
+
+const uint32_t HOOKS = MBL_HOOK_IR_STALL32 | MBL_HOOK_IR_STALL64 | MBL_HOOK_NO_CONV;
+const uint64_t KRYLOV_SEED = 0xA5A5A5A5A5A5A5A5ULL;   // xor-ed with the disorder seed
+}  // namespace
+
+void solve_problem(Context &ctx, const mbl_problem &pr, mbl_result &res, const double *extremal) {
+    check_problem(pr);
+    const int64_t n = binom(pr.L, sector_nup(pr.L));
+    // test hooks of this request, cleared however the request ends
+    struct HookScope {
+        Context &c;
+        HookScope(Context &cx, const mbl_problem &q) : c(cx) {
+            c.hooks = q.flags & HOOKS;
+            c.budget.armed = q.fail_alloc_bytes;
+            c.budget.since_armed = 0;
+        }
+        ~HookScope() { c.hooks = 0; c.budget.armed = 0; c.budget.since_armed = 0; }
+    } hook_scope(ctx, pr);
+    double tol = pr.tol > 0 ? pr.tol : 1e-10;
+    double t_start = wall_seconds(), t0 = t_start;
+    std::memset(res.t_phase, 0, sizeof(res.t_phase));
+
+    const int64_t passes0 = ctx.lu_passes, pass_rhs0 = ctx.lu_pass_rhs;
+    Plan &p = ctx.plan(pr.L);
+    ctx.set_realization(p, pr.J, pr.fields, pr.h, pr.seed, pr.fields == nullptr);
+    res.t_phase[0] = wall_seconds() - t0;
+
+    t0 = wall_seconds();
+    double emin = 0, emax = 0;
+    int nap = 0;
+    if (extremal) { emin = extremal[0]; emax = extremal[1]; }
+    else ctx.extremal(p, emin, emax, nap);
+    const Shift z = make_shift(pr, emin, emax);
+    ctx.hnorm_ = z.hnorm;
+    set_shift(res, z);
+    res.t_phase[1] = wall_seconds() - t0;
+
+    t0 = wall_seconds();
+    ctx.ensure_symbolic(p);
+    res.t_phase[2] = wall_seconds() - t0;
+
+    t0 = wall_seconds();
+    SolveStats st;
+    int prec = pr.prec;
+    ctx.factor(p, prec, z.sigma_f, z.anorm, st);
+    res.t_phase[3] = wall_seconds() - t0;
+
+    // block Krylov-Schur on (H - sigma_f)^-1
+    t0 = wall_seconds();
+    const KShape k = krylov_shape(n, pr);
+    int max_restarts = pr.max_restarts > 0 ? pr.max_restarts : 300;
+    ctx.d_psi.ensure(sizeof(double) * n * k.nw, &ctx.budget);
+    bool fell_back = false;
+    auto op = [&](const double *X, double *Y, int nb, const std::vector<char> &) {
+        try {
+            ctx.shift_solve(p, prec, nb, X, Y, st);
+            if (prec == MBL_FP32_IR64 && st.gmres_inner > 8) {
+                // the FP32 factor needs many GMRES steps per solve here (kappa u_32
+                // near one): this result stands, later solves use an FP64 factor
+                prec = MBL_FP64;
+                fell_back = true;
+                SolveStats s2;
+                ctx.factor(p, prec, z.sigma_f, z.anorm, s2);
+            }
+        } catch (const Error &e) {
+            if (e.code != MBL_ENUMERIC || prec != MBL_FP32_IR64) throw;
+            // FP32 refinement did not reach the target: refactor in FP64
+            prec = MBL_FP64;
+            fell_back = true;
+            SolveStats s2;
+            ctx.factor(p, prec, z.sigma_f, z.anorm, s2);
+            ctx.shift_solve(p, prec, nb, X, Y, st);
+        }
+    };
+    const bool never_conv = (ctx.hooks & MBL_HOOK_NO_CONV) != 0;
+    auto conv = [&](int, double th, double rho) {
+        return !never_conv && th != 0.0 && rho * z.anorm <= 0.1 * tol * z.hnorm * std::fabs(th);
+    };
+    uint64_t kseed = pr.seed ^ KRYLOV_SEED;
+    std::vector<Context::KSOut> kss;
+    ctx.krylov_schur(n, 1, k.b, k.ncv, k.nkeep, k.nw, Context::Want::LargestAbs, op, conv,
+                     max_restarts, &kseed, ctx.d_psi.ptr<double>(), kss);
+    const Context::KSOut &ks = kss[0];
+    res.t_phase[4] = wall_seconds() - t0;
+    res.t_phase[7] = st.t_solve;
+    res.n_restarts = ks.restarts;
+    res.n_opapply = ks.napply;
+    res.n_passes = (int)(ctx.lu_passes - passes0);
+    res.n_pass_rhs = (int)(ctx.lu_pass_rhs - pass_rhs0);
+    res.ir_iters_max = st.ir_iters;
+    res.n_perturbed = st.n_perturbed;
+    res.fallback = fell_back ? 1 : 0;
+    res.batch = 1;
+
+    // energies (Rayleigh quotients) and FP64 residuals ||H psi - E psi||, the
+    // selection and the observables
+    t0 = wall_seconds();
+    std::vector<double> E, nrm, rr;
+    rayleigh_residuals(ctx, p, ctx.d_diag.ptr<double>(), k.nw, ctx.d_psi.ptr<double>(), E, nrm, rr);
+    int nconv = select_and_observe(ctx, p, pr, res, ctx.d_psi.ptr<double>(), n, E.data(),
+                                   nrm.data(), rr.data(), k.nw, z, tol, ks.nconv);
     res.t_phase[5] = wall_seconds() - t0;
     res.t_phase[6] = wall_seconds() - t_start;
-    if (nconv < nev) throw Error(MBL_ENOTCONV, "only " + std::to_string(nconv) + " of " +
-                                                   std::to_string(nev) + " pairs reached tol");
+    if (nconv < pr.nev)
+        throw Error(MBL_ENOTCONV, "only " + std::to_string(nconv) + " of " +
+                                      std::to_string(pr.nev) + " pairs reached tol");
+}
+
+bool batchable(const mbl_problem *prs, int count) {
+    if (count < 2 || count > MBL_SEG_MAX) return false;
+    const mbl_problem &a = prs[0];
+    if (a.L < 2 || a.L > MBL_L_MAX) return false;
+    const int64_t n = binom(a.L, sector_nup(a.L));
+    // block iterations throughout (extremal energies and shift-invert)
+    if (n < 128) return false;
+    for (int q = 0; q < count; q++) {
+        const mbl_problem &c = prs[q];
+        if (c.L != a.L || c.J != a.J || c.nev != a.nev || c.prec != a.prec || c.tol != a.tol ||
+            c.block != a.block || c.ncv != a.ncv || c.max_restarts != a.max_restarts)
+            return false;
+        // the refinement-stall hooks are followed inside a batch (the problem
+        // leaves it); the others are not
+        if ((c.flags & MBL_HOOK_NO_CONV) || c.fail_alloc_bytes) return false;
+        if (c.nev < 1 || c.nev > std::min<int64_t>(n, 256)) return false;
+    }
+    return krylov_shape(n, a).b > 1;
+}
+
+bool solve_batch(Context &ctx, int count, const mbl_problem *prs, mbl_result *res, int *status) {
+    if (!batchable(prs, count)) return false;
+    for (int q = 0; q < count; q++) check_problem(prs[q]);
+    const mbl_problem &a = prs[0];
+    const int L = a.L, nseg = count;
+    const int64_t n = binom(L, sector_nup(L)), N = n * nseg;
+    const double tol = a.tol > 0 ? a.tol : 1e-10;
+    const int prec = a.prec;
+    hipStream_t s = ctx.stream;
+    try {
+        double t_start = wall_seconds(), t0 = t_start;
+        double tph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        Plan &p = ctx.plan(L);
+        ctx.ensure_symbolic(p);
+        Plan &bp = ctx.batch_plan(L, nseg);
+        // diagonals of every problem, packed
+        ctx.d_bdiag.ensure(sizeof(double) * N, &ctx.budget);
+        ctx.d_bshift.ensure(sizeof(double) * N, &ctx.budget);
+        for (int q = 0; q < nseg; q++) {
+            const mbl_problem &c = prs[q];
+            ctx.set_realization(p, c.J, c.fields, c.h, c.seed, c.fields == nullptr);
+            launch_copy(n, ctx.d_diag.ptr<double>(), ctx.d_bdiag.ptr<double>() + q * n, s);
+        }
+        tph[0] = wall_seconds() - t0;
+
+        t0 = wall_seconds();
+        std::vector<double> emin(nseg), emax(nseg);
+        std::vector<int> nap(nseg);
+        ctx.extremal_seg(bp, ctx.d_bdiag.ptr<double>(), emin.data(), emax.data(), nap.data());
+        std::vector<Shift> z(nseg);
+        std::vector<double> anorm(nseg);
+        SegVals sf{};
+        for (int q = 0; q < nseg; q++) {
+            z[q] = make_shift(prs[q], emin[q], emax[q]);
+            anorm[q] = z[q].anorm;
+            sf.v[q] = z[q].sigma_f;
+        }
+        tph[1] = wall_seconds() - t0;
+
+        t0 = wall_seconds();
+        launch_shift_seg(nseg, n, ctx.d_bdiag.ptr<double>(), sf, ctx.d_bshift.ptr<double>(), s);
+        SolveStats st;
+        ctx.factor_batch(bp, prec, ctx.d_bshift.ptr<double>(), anorm, st);
+        tph[3] = wall_seconds() - t0;
+
+        // block Krylov-Schur on every (H_s - sigma_f,s)^-1
+        t0 = wall_seconds();
+        const KShape k = krylov_shape(n, a);
+        const int max_restarts = a.max_restarts > 0 ? a.max_restarts : 300;
+        ctx.d_psi.ensure(sizeof(double) * N * k.nw, &ctx.budget);
+        Context::BatchSolveStats bs(nseg);
+        for (int q = 0; q < nseg; q++)
+            bs.hooks[q] = prs[q].flags & (MBL_HOOK_IR_STALL32 | MBL_HOOK_IR_STALL64);
+        auto op = [&](const double *X, double *Y, int nb, const std::vector<char> &finished) {
+            ctx.shift_solve_batch(bp, prec, nb, X, Y, ctx.d_bshift.ptr<double>(), anorm, finished, bs);
+        };
+        // dropped problems whose extremal energies are known need not wait for
+        // the Krylov run: they are solved alone at the end
+        auto conv = [&](int sg, double th, double rho) {
+            return th != 0.0 && rho * z[sg].anorm <= 0.1 * tol * z[sg].hnorm * std::fabs(th);
+        };
+        std::vector<uint64_t> seeds(nseg);
+        for (int q = 0; q < nseg; q++) seeds[q] = prs[q].seed ^ KRYLOV_SEED;
+        std::vector<Context::KSOut> kss;
+        ctx.krylov_schur(n, nseg, k.b, k.ncv, k.nkeep, k.nw, Context::Want::LargestAbs, op, conv,
+                         max_restarts, seeds.data(), ctx.d_psi.ptr<double>(), kss, &bs.dropped);
+        tph[4] = wall_seconds() - t0;
+        tph[7] = bs.t_solve;
+
+        t0 = wall_seconds();
+        std::vector<double> E, nrm, rr;
+        rayleigh_residuals(ctx, bp, ctx.d_bdiag.ptr<double>(), k.nw, ctx.d_psi.ptr<double>(), E, nrm,
+                           rr);
+        std::vector<int> nconv(nseg);
+        for (int q = 0; q < nseg; q++) {
+            if (bs.dropped[q]) continue;
+            mbl_result &r = res[q];
+            set_shift(r, z[q]);
+            r.n_restarts = kss[q].restarts;
+            r.n_opapply = kss[q].napply;
+            r.n_passes = bs.passes[q];
+            r.n_pass_rhs = bs.pass_rhs[q];
+            r.ir_iters_max = bs.ir_iters[q];
+            r.n_perturbed = st.perturbed[q];
+            r.fallback = 0;
+            r.batch = nseg;
+            const size_t o = (size_t)q * k.nw;
+            nconv[q] = select_and_observe(ctx, p, prs[q], r, ctx.d_psi.ptr<double>() + q * n, N,
+                                          E.data() + o, nrm.data() + o, rr.data() + o, k.nw, z[q],
+                                          tol, kss[q].nconv);
+        }
+        tph[5] = wall_seconds() - t0;
+        tph[6] = wall_seconds() - t_start;
+        int ndropped = 0;
+        for (int q = 0; q < nseg; q++) {
+            if (bs.dropped[q]) { ndropped++; continue; }
+            std::copy(tph, tph + 8, res[q].t_phase);
+            status[q] = nconv[q] < prs[q].nev ? MBL_ENOTCONV : MBL_OK;
+        }
+        if (ndropped) {
+            // the dropped problems alone, on fresh buffers (those of the batch
+            // are given back first)
+            ctx.trim();
+            for (int q = 0; q < nseg; q++) {
+                if (!bs.dropped[q]) continue;
+                try {
+                    solve_problem(ctx, prs[q], res[q]);
+                    status[q] = MBL_OK;
+                } catch (const Error &e) {
+                    set_last_error(e.what());
+                    status[q] = e.code;
+                }
+            }
+        }
+    } catch (const Error &e) {
+        if (e.code != MBL_ENOMEM) throw;
+        // the batch's buffers do not fit: the problems go alone, on fresh buffers
+        ctx.trim();
+        return false;
+    }
+    return true;
 }
 
 }  // namespace mbl

@@ -46,7 +46,8 @@ struct LevelTasks {
 
 struct Plan {
     int L = 0;
-    int64_t dim = 0, nnz = 0;
+    int nseg = 1;                      // problems of a batch plan (copies of one front tree)
+    int64_t dim = 0, nnz = 0;          // of the whole (block-diagonal) matrix
     DevBuf basis, rowptr, col;
     std::vector<int32_t> h_rowptr, h_col;
     bool have_symbolic = false;
@@ -67,7 +68,8 @@ struct Plan {
 template <class T>
 struct Factor {
     int L = -1;
-    DevBuf arena, ipiv, prow, npert;
+    int64_t dim = 0;                   // order of the factored (possibly batched) matrix
+    DevBuf arena, ipiv, prow, npert, thr;
     DevBuf uinv;                       // per front: U_tt^-1 of the current panel (FNB x FNB)
     bool valid = false;
     double sigma = 0.0;
@@ -76,6 +78,7 @@ struct Factor {
 struct SolveStats {
     int ir_iters = 0;
     int n_perturbed = 0;
+    std::vector<int> perturbed;        // per problem of a batch plan
     double backward_error = 0.0;
     double t_factor = 0.0, t_solve = 0.0;
     int n_rhs = 0;
@@ -88,6 +91,7 @@ struct SolveStats {
 struct PlanCache {
     std::recursive_mutex mu;
     std::map<int, std::unique_ptr<Plan>> plans;
+    std::map<int, std::unique_ptr<Plan>> batched;     // key L * 100 + problems
 };
 
 class Context {
@@ -105,6 +109,8 @@ class Context {
 
     Plan &plan(int L);                 // basis + CSR on the device (cached)
     void ensure_symbolic(Plan &p);     // ordering + front tables (cached)
+    void build_tables(Plan &p);        // front tables of a plan whose tree is set
+    Plan &batch_plan(int L, int nseg); // nseg copies of plan(L), solved together (cached)
     // free the per-request work buffers (factors, solve vectors, Krylov bases)
     void trim();
 
@@ -115,14 +121,42 @@ class Context {
     DevBuf d_fields, d_diag;
     std::vector<double> h_fields;
 
-    void spmv(Plan &p, double shift, int nvec, const double *x, double *y);
+    // y = (H - shift) x; diag: the diagonal of H (nullptr: d_diag)
+    void spmv(Plan &p, double shift, int nvec, const double *x, double *y,
+              const double *diag = nullptr);
     // extremal eigenvalues by Krylov-Schur on H
     void extremal(Plan &p, double &emin, double &emax, int &napply);
+    // the same for the p.nseg problems of a batch plan (diag: their diagonals,
+    // packed); emin, emax, napply: one per problem
+    void extremal_seg(Plan &p, const double *diag, double *emin, double *emax, int *napply);
 
     // shifted LU + refined solves
     void factor(Plan &p, int prec, double sigma, double anorm, SolveStats &st);
     // X = (H - sigma)^-1 B (device, original basis order, ld = dim), refined in FP64
     void shift_solve(Plan &p, int prec, int nrhs, const double *B, double *X, SolveStats &st);
+
+    // Batches: the p.nseg problems of a batch plan, each at its own shift.
+    // LU of every problem; shifted: their diagonals of H - sigma_s, packed
+    void factor_batch(Plan &bp, int prec, const double *shifted, const std::vector<double> &anorm,
+                      SolveStats &st);
+    struct BatchSolveStats {
+        std::vector<int> ir_iters, passes, pass_rhs;   // per problem
+        // problems whose lone solve would leave the plain refinement (GMRES,
+        // a refinement failure): no longer refined, solved alone afterwards
+        std::vector<char> dropped;
+        std::vector<uint32_t> hooks;                  // refinement-stall test hooks
+        double t_solve = 0.0;
+        explicit BatchSolveStats(int nseg)
+            : ir_iters(nseg, 0), passes(nseg, 0), pass_rhs(nseg, 0), dropped(nseg, 0),
+              hooks(nseg, 0) {}
+    };
+    // X = (H_s - sigma_s)^-1 B per problem (packed columns, ld = bp.dim), each
+    // refined as a lone solve is; problems with skip[s] or bs.dropped[s] get
+    // one unrefined pass
+    void shift_solve_batch(Plan &bp, int prec, int nrhs, const double *B, double *X,
+                           const double *shifted, const std::vector<double> &anorm,
+                           const std::vector<char> &skip, BatchSolveStats &bs);
+    DevBuf d_bdiag, d_bshift;          // diagonals of a batch's H and H - sigma, packed
 
     // block Krylov-Schur on an operator; Ritz vectors of the nwant selected
     // values (priority order) land in out (dim x nwant)
@@ -132,13 +166,20 @@ class Context {
         double tmin = 0.0, tmax = 0.0;   // extreme Ritz values of the last Rayleigh-Ritz
         int restarts = 0, napply = 0, nconv = 0;
     };
-    // all eigenpairs of a small symmetric matrix (host in, host out; device Jacobi)
-    void small_eig(int m, const std::vector<double> &A, std::vector<double> &w,
-                   std::vector<double> &Z);
-    KSOut krylov_schur(int64_t n, int b, int ncv, int nkeep, int nwant, Want want,
-                       const std::function<void(const double *, double *, int)> &op,
-                       const std::function<bool(double, double)> &conv, int max_restarts,
-                       uint64_t seed, double *out);
+    // all eigenpairs of count small symmetric matrices (host in, host out;
+    // device Jacobi, one workgroup each)
+    void small_eig_batch(int count, int m, const std::vector<std::vector<double>> &A,
+                         std::vector<std::vector<double>> &w,
+                         std::vector<std::vector<double>> &Z);
+    // block Krylov-Schur on nseg problems of order n with packed vectors (ld
+    // nseg n); conv(problem, theta, rho); seeds[nseg]; out: nseg n x nwant
+    // op(X, Y, nb, finished): Y = Op X for nb packed columns; finished[s] != 0
+    // marks problems whose result is final (their columns are not used)
+    using KSOp = std::function<void(const double *, double *, int, const std::vector<char> &)>;
+    void krylov_schur(int64_t n, int nseg, int b, int ncv, int nkeep, int nwant, Want want,
+                      const KSOp &op, const std::function<bool(int, double, double)> &conv,
+                      int max_restarts, const uint64_t *seeds, double *out,
+                      std::vector<KSOut> &result, const std::vector<char> *dropped = nullptr);
 
     // per-launch timing of one kernel class (mbl_profile_enable)
     struct Prof {
@@ -167,18 +208,25 @@ class Context {
     bool owns_plans_ = true;
     Factor<float> f32_;
     Factor<double> f64_;
+    Factor<double> fb64_;              // factors of a batch of problems (one replicated plan)
+    Factor<float> fb32_;
+    DevBuf d_on;                       // per problem of a batch: still refining
     DevBuf d_vec, d_yv, d_upart, d_xnew, d_r, d_d, d_part, d_V, d_V2, d_W, d_small, d_ritz, d_tnpart;
     DevBuf d_gV, d_gZ, d_gpart, d_gcoef;   // GMRES refinement: bases, partials, coefficients
     PinnedBuf h_stage;                     // Krylov coefficients copied back asynchronously
-    template <class T> void factor_t(Plan &p, Factor<T> &f, double sigma, double thresh_rel,
-                                     SolveStats &st);
+    // LU of the plan's matrix with diagonal diag - sigma; thresh: static-pivot
+    // threshold of each problem of the plan
+    template <class T> void factor_t(Plan &p, Factor<T> &f, const double *diag, double sigma,
+                                     const std::vector<double> &thresh, SolveStats &st);
     template <class T> void lu_apply_seq(Plan &p, Factor<T> &f, int nrhs, const double *b,
                                          int64_t ldb, double *x, int64_t ldx);
     // captured launch sequences of lu_apply (see lu_apply)
     struct GraphKey {
+        const Plan *plan;              // lone and batch plans of one L differ
         int L, tsize, nrhs;
         const void *bufs[8];
         bool operator<(const GraphKey &o) const {
+            if (plan != o.plan) return std::less<const Plan *>()(plan, o.plan);
             if (L != o.L) return L < o.L;
             if (tsize != o.tsize) return tsize < o.tsize;
             if (nrhs != o.nrhs) return nrhs < o.nrhs;
@@ -197,6 +245,10 @@ class Context {
                                          double *X, double target, SolveStats &st);
     template <class T> void refine(Plan &p, Factor<T> &f, int nrhs, const double *B, double *X,
                                    SolveStats &st);
+    template <class T> void refine_batch(Plan &p, Factor<T> &f, int nrhs, const double *B,
+                                         double *X, const double *shifted,
+                                         const std::vector<double> &anorm,
+                                         const std::vector<char> &skip, BatchSolveStats &bs);
 };
 
 // Block size of the shift-invert Krylov iteration (right-hand sides per pass
@@ -208,5 +260,19 @@ inline int default_block(int64_t n) { return n >= 100000 ? 8 : (n >= 128 ? 4 : 1
 // (energy sweeps reuse them); nullptr computes them.
 void solve_problem(Context &ctx, const mbl_problem &prob, mbl_result &res,
                    const double *extremal = nullptr);
+
+// Whether count problems can be solved as one batch: one chain length (sector
+// of dimension >= 128), J, nev, precision, tolerance and Krylov settings, no
+// test hooks but the refinement-stall ones, 2 <= count <= 16.
+bool batchable(const mbl_problem *probs, int count);
+// Solves a batchable set on the batch plan of nseg = count copies: every
+// problem's arithmetic is that of solve_problem (results bitwise the same),
+// the launches are shared.  A problem whose lone solve takes a path the batch
+// cannot follow (GMRES refinement of an FP32 factor, a refinement failure)
+// leaves the batch and is solved alone after it.  status[k]: that problem's
+// status (MBL_ENOTCONV results are still written).  Returns false, with
+// nothing valid written, when the set is not batchable or the batch does not
+// fit in memory: then the caller solves the problems one at a time.
+bool solve_batch(Context &ctx, int count, const mbl_problem *probs, mbl_result *res, int *status);
 
 }  // namespace mbl

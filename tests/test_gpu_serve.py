@@ -113,6 +113,7 @@ def test_concurrent_large_fronts_bitwise():
         alone = [c.mbl_solve(L, h, s, e, 50) for (L, h, s, e) in cases]
     say("L=16 solves, 2 at a time")
     with mbl.Context(0) as c:
+        c.mbl_serve_batch_limit(1)                # every request alone on its slot
         c.mbl_serve_start(2)
         outs = [c.mbl_wait(t) for t in [c.mbl_submit(L, h, s, e, 50) for (L, h, s, e) in cases]]
         st = c.mbl_serve_stats()
@@ -121,3 +122,31 @@ def test_concurrent_large_fronts_bitwise():
         assert o["status"] == mbl.MBL_OK and o["nconv"] == 50
         for k in KEYS:
             assert np.array_equal(o[k], a[k]), k
+
+
+def test_batched_serving_bitwise():
+    """Requests queued together are admitted as batches (one L, one precision);
+    every result equals its lone solve bitwise, batches of FP32 requests too."""
+    rng = np.random.default_rng(4)
+    reqs = []
+    for i in range(40):
+        L = int(rng.choice([10, 12, 14]))
+        prec = mbl.MBL_FP32_IR64 if i % 2 else mbl.MBL_FP64
+        reqs.append((L, float(rng.uniform(0.5, 5.0)), 300 + i, float(rng.uniform(0.05, 0.95)), prec))
+    say("batched serving", len(reqs), "requests on 2 slots")
+    with mbl.Context(0) as c:
+        c.mbl_serve_start(2)
+        tickets = [c.mbl_submit(L, h, s, e, 20, prec=p) for (L, h, s, e, p) in reqs]
+        outs = [c.mbl_wait(t) for t in tickets]
+        st = c.mbl_serve_stats()
+    say("stats", st)
+    assert st["completed"] == len(reqs) and st["batches"] >= 2
+    assert 4 <= sum(o["batch"] > 1 for o in outs) <= st["batched"]
+    with mbl.Context(0) as c2:
+        for (L, h, s, e, p), o in zip(reqs, outs):
+            assert o["status"] == mbl.MBL_OK
+            a = c2.mbl_solve(L, h, s, e, 20, prec=p)
+            for k in KEYS:
+                assert np.array_equal(o[k], a[k]), (L, h, s, e, p, k, o["batch"])
+            for k in ("n_restarts", "n_opapply", "n_passes", "ir_iters_max", "fallback"):
+                assert o[k] == a[k], (k, o["batch"])
