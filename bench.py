@@ -115,10 +115,11 @@ def serve_stream(n, seed=0):
              i, 0.05 + 0.9 * u[3 * i + 2]) for i in range(n)]
 
 
-def run_served(mbl, reqs, prec, rate, slots, nev=20, max_batch=16):
+def run_served(mbl, reqs, prec, rate, slots, nev=20, max_batch=16, vectors_for=()):
     """Submit reqs at Poisson arrival times (rate per second; 0 = all at once)
     to a fresh serving context (at most max_batch requests solved as one
-    batch); returns throughput and latency figures."""
+    batch; eigenvectors returned for the request indices in vectors_for);
+    returns throughput and latency figures."""
     import threading
     ctx = mbl.Context(0)
     ctx.mbl_serve_batch_limit(max_batch)
@@ -142,12 +143,13 @@ def run_served(mbl, reqs, prec, rate, slots, nev=20, max_batch=16):
     t0 = time.perf_counter()
     th.start()
     t_next = t0
-    for (L, h, s, e), g in zip(reqs, gaps):
+    want = set(vectors_for)
+    for i, ((L, h, s, e), g) in enumerate(zip(reqs, gaps)):
         t_next += g
         dt = t_next - time.perf_counter()
         if dt > 0:
             time.sleep(dt)
-        tickets.append(ctx.mbl_submit(L, h, s, e, nev, prec=prec))
+        tickets.append(ctx.mbl_submit(L, h, s, e, nev, prec=prec, vectors=i in want))
     done_evt.wait()
     wall = time.perf_counter() - t0
     th.join()
@@ -163,6 +165,89 @@ def run_served(mbl, reqs, prec, rate, slots, nev=20, max_batch=16):
             "bypasses": st["bypasses"], "batches": st["batches"], "batched": st["batched"],
             "solved_in_batches": sum(1 for o in ok if o["batch"] > 1),
             "max_batch": max_batch}, outs
+
+
+def _spot_check(args):
+    """Oracle check of one served result (host only).  L <= 12: the dense
+    oracle's window (energies, gap ratios, S_1 of separated levels); larger L:
+    certificates by the oracle's own code (residual and Rayleigh quotient of
+    every returned pair with H applied by the oracle, S_1 recomputed)."""
+    import numpy as np
+
+    import oracle
+    (L, h, seed, eps), nev, E, Z, r, s1, hn = args
+    out = {"L": L, "seed": seed}
+    if L <= 12:
+        ref = oracle.solve(L, h, seed, eps, nev)
+        gaps = np.diff(ref["evals"])
+        sep = np.ones(nev, dtype=bool)
+        sep[:-1] &= gaps >= 1e-6 * hn
+        sep[1:] &= gaps >= 1e-6 * hn
+        rm = np.minimum(gaps[:-1], gaps[1:]) >= 1e-6 * hn
+        out.update(kind="dense", eval_err=float(np.abs(E - ref["evals"]).max() / hn),
+                   s1_err=float(np.abs(s1 - ref["s1"])[sep].max(initial=0.0)),
+                   r_err=float(np.abs(r - ref["r"])[rm].max(initial=0.0)))
+        out["ok"] = out["eval_err"] <= 1e-10 and out["s1_err"] <= 1e-8 and out["r_err"] <= 1e-8
+    else:
+        f = oracle.fields(L, h, seed)
+        b = oracle.basis(L)
+        res = max(oracle.residual(L, 1.0, f, Z[:, k], E[k], b) for k in range(nev)) / hn
+        ray = max(abs(oracle.rayleigh(L, 1.0, f, Z[:, k], b) - E[k]) for k in range(nev)) / hn
+        s1e = max(abs(oracle.participation_entropy(Z[:, k]) - s1[k]) for k in range(nev))
+        out.update(kind="certificate", resid=float(res), rayleigh_err=float(ray),
+                   s1_err=float(s1e))
+        out["ok"] = res <= 1e-9 and ray <= 1e-10 and s1e <= 1e-8
+    return out
+
+
+def serve_config4(mbl, n=4096, slots=4, nev=20):
+    """The served workload at full size: closed-loop capacity of the FP32 +
+    refinement and the FP64 paths, then Poisson arrivals at 0.5, 0.8 and 0.95
+    of the FP32 + refinement capacity, the FP64 path at 0.8 of it for
+    comparison, and a 1% oracle spot check of the 0.8 run."""
+    import multiprocessing as mp
+
+    import numpy as np
+    reqs = serve_stream(n)
+    log(f"config 4: {n} requests, closed loop, FP32 + refinement")
+    cap32, _ = run_served(mbl, reqs, mbl.MBL_FP32_IR64, 0.0, slots, nev)
+    log("config 4: closed loop, FP64")
+    cap64, _ = run_served(mbl, reqs, mbl.MBL_FP64, 0.0, slots, nev)
+    c = cap32["requests_per_s"]
+    sample = list(range(0, n, 100))
+    runs = {}
+    outs80 = None
+    for frac in (0.5, 0.8, 0.95):
+        log(f"config 4: Poisson at {frac} x {c:.1f}/s, FP32 + refinement")
+        r, outs = run_served(mbl, reqs, mbl.MBL_FP32_IR64, frac * c, slots, nev,
+                             vectors_for=sample if frac == 0.8 else ())
+        runs[str(frac)] = r
+        if frac == 0.8:
+            outs80 = outs
+    log(f"config 4: Poisson at 0.8 x {c:.1f}/s, FP64")
+    r64, outs64 = run_served(mbl, reqs, mbl.MBL_FP64, 0.8 * c, slots, nev)
+    err = [float(np.abs(a["evals"] - b["evals"]).max() / b["hnorm"])
+           for a, b in zip(outs80, outs64) if a["status"] == 0 and b["status"] == 0]
+    log(f"config 4: oracle spot check of {len(sample)} requests")
+    jobs = [(reqs[i], nev, outs80[i]["evals"], outs80[i]["evecs"], outs80[i]["r"],
+             outs80[i]["s1"], outs80[i]["hnorm"]) for i in sample]
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+        checks = pool.map(_spot_check, jobs)
+    return {
+        "workload": (f"{n} requests, L uniform in {{10,12,14,16}}, h ~ U[0.5,5], "
+                     f"eps ~ U[0.05,0.95], nev={nev}, seed = request index, {slots} slots, "
+                     f"footprint admission, batches of up to 16 requests of one L"),
+        "capacity_per_s": {"fp32_refined": c, "fp64": cap64["requests_per_s"]},
+        "closed_loop": {"fp32_refined": cap32, "fp64": cap64},
+        "poisson_fp32_refined": runs, "poisson_fp64_at_0.8": r64,
+        "max_eval_err_fp32_vs_fp64_over_hnorm": max(err) if err else None,
+        "spot_check": {"requests": len(checks), "passed": sum(1 for x in checks if x["ok"]),
+                       "max_eval_err": max((x["eval_err"] for x in checks if "eval_err" in x),
+                                           default=None),
+                       "max_resid": max((x["resid"] for x in checks if "resid" in x),
+                                        default=None),
+                       "max_s1_err": max(x["s1_err"] for x in checks), "cases": checks},
+    }
 
 
 def workload(L, steps):
@@ -357,6 +442,9 @@ def main():
                     help="only measure kappa and the refinement of FP64 / FP32 factors "
                          "(L = 16, 18, 20, h = 3, eps = 0.5)")
     ap.add_argument("--refine-child", default="", help=argparse.SUPPRESS)
+    ap.add_argument("--serve-config4", action="store_true",
+                    help="only run the served workload at full size (4096 requests, "
+                         "capacity, 0.5 / 0.8 / 0.95 x capacity, FP64, oracle spot check)")
     a = ap.parse_args()
     if a.refine_child:
         refine_child(a.refine_child)
@@ -366,6 +454,10 @@ def main():
         return
     if a.copy_probe > 0:
         copy_probe(a.copy_probe)
+        return
+    if a.serve_config4:
+        import paper_1411_0660_amd as mbl
+        print(json.dumps({"served_config4": serve_config4(mbl, slots=a.serve_slots)}), flush=True)
         return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no collectives); use --gpus 1",
@@ -546,21 +638,34 @@ def main():
                                     "se_over_L": mid["mean"][3] / 18, "sigma_e": mid["sigma_e"]}}
     ctx.close()
     if a.serve_requests > 0:
-        log("served stream: closed-loop capacity")
+        log("served stream: closed-loop capacity, requests alone")
         reqs = serve_stream(a.serve_requests)
-        cap, _ = run_served(mbl, reqs[:min(256, len(reqs))], mbl.MBL_FP32_IR64, 0.0, a.serve_slots)
+        head = reqs[:min(256, len(reqs))]
+        cap, _ = run_served(mbl, head, mbl.MBL_FP32_IR64, 0.0, a.serve_slots, max_batch=1)
+        cap64, _ = run_served(mbl, head, mbl.MBL_FP64, 0.0, a.serve_slots, max_batch=1)
+        log("served stream: closed-loop capacity, batches of up to 16")
+        head = reqs[:min(512, len(reqs))]
+        capb, _ = run_served(mbl, head, mbl.MBL_FP32_IR64, 0.0, a.serve_slots)
+        capb64, _ = run_served(mbl, head, mbl.MBL_FP64, 0.0, a.serve_slots)
         rate = 0.8 * cap["requests_per_s"]
         log(f"served stream: {len(reqs)} requests at {rate:.1f}/s, FP32+refinement")
-        mixed, outs32 = run_served(mbl, reqs, mbl.MBL_FP32_IR64, rate, a.serve_slots)
+        mixed, outs32 = run_served(mbl, reqs, mbl.MBL_FP32_IR64, rate, a.serve_slots, max_batch=1)
         log("served stream: FP64")
-        plain, outs64 = run_served(mbl, reqs, mbl.MBL_FP64, rate, a.serve_slots)
+        plain, outs64 = run_served(mbl, reqs, mbl.MBL_FP64, rate, a.serve_slots, max_batch=1)
         err = [float(np.abs(o32["evals"] - o64["evals"]).max() / o64["hnorm"])
                for o32, o64 in zip(outs32, outs64) if o32["status"] == 0 and o64["status"] == 0]
         out["served"] = {
             "workload": (f"{len(reqs)} requests, L uniform in {{10,12,14,16}}, h ~ U[0.5,5], "
                          f"eps ~ U[0.05,0.95], nev=20, Poisson arrivals at 0.8 x the closed-loop "
-                         f"capacity of the mixed path, {a.serve_slots} slots, footprint admission"),
-            "arrival_rate_per_s": rate, "closed_loop_capacity_per_s": cap["requests_per_s"],
+                         f"capacity of the mixed path with every request alone, {a.serve_slots} "
+                         f"slots, footprint admission"),
+            "arrival_rate_per_s": rate,
+            "closed_loop_capacity_per_s": {
+                "fp32_refined_alone": cap["requests_per_s"], "fp64_alone": cap64["requests_per_s"],
+                "fp32_refined_batched": capb["requests_per_s"],
+                "fp64_batched": capb64["requests_per_s"],
+                "requests": {"alone": min(256, len(reqs)), "batched": min(512, len(reqs))}},
+            "closed_loop_batched": {"fp32_refined": capb, "fp64": capb64},
             "fp32_refined": mixed, "fp64": plain,
             "max_eval_err_fp32_vs_fp64_over_hnorm": max(err) if err else None}
     if not a.no_cpu:

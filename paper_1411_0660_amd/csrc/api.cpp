@@ -411,13 +411,14 @@ int mbl_solve_batch(mbl_ctx *ctx, int count, const mbl_problem *probs, mbl_resul
         MBL_HIP(hipSetDevice(ctx->c->device));
         done = solve_batch(*ctx->c, count, probs, results, status);
     });
-    if (rc == MBL_EINVAL) {
-        // an invalid problem: each gets its own status from its lone solve
-        done = false;
-    } else if (rc != MBL_OK) {
+    if (rc == MBL_EDEVICE) {
         for (int k = 0; k < count; k++) status[k] = rc;
         return rc;
     }
+    // any other failure of the batch as a whole (an invalid problem, extremal
+    // energies of one problem not converging): each problem gets the status
+    // of its lone solve
+    if (rc != MBL_OK) done = false;
     if (!done)
         for (int k = 0; k < count; k++)
             status[k] = guarded([&] {

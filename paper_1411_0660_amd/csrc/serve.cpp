@@ -155,7 +155,15 @@ bool Server::admit_locked() {
         }
         return best;
     };
+    auto idle = [&] {
+        for (auto &sl : slots_)
+            if (!sl->busy) return true;
+        return false;
+    };
     for (auto it = queue_.begin(); it != queue_.end();) {
+        // nothing can be admitted while every slot is busy (the queue may be
+        // long: do not walk it then)
+        if (!idle()) break;
         uint64_t t = *it;
         Req &r = reqs_[t];
         if (!r.sized) break;                      // arrival order: size first
@@ -167,7 +175,9 @@ bool Server::admit_locked() {
         // queued requests that can share this one's launches, in arrival order
         std::vector<uint64_t> batch{t};
         if (max_batch_ > 1) {
-            for (auto jt = std::next(it); jt != queue_.end() && (int)batch.size() < max_batch_; ++jt) {
+            int looked = 0;                       // companions come from the next 256 requests
+            for (auto jt = std::next(it);
+                 jt != queue_.end() && (int)batch.size() < max_batch_ && looked < 256; ++jt, ++looked) {
                 Req &u = reqs_[*jt];
                 if (!u.sized) break;
                 mbl_problem pair[2] = {r.prob, u.prob};
