@@ -121,13 +121,20 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// LU with partial pivoting of the kb x kb diagonal block of panel t (one
-// workgroup per front, block in LDS), plus U_tt^-1 for the L-column solves of
-// the rows below (stored once per front in uinv, FNB x FNB column major,
-// identity beyond kb).  The multipliers of column j are used as D[i][j] /
-// pivot_j in the updates and the column is scaled at the end (the scaling of
-// a row commutes with the later interchanges).  Thread (column c = tid % 64,
-// row group g = tid / 64) updates rows i = g (mod 4) of its column.
+// LU with partial pivoting of panel t (one workgroup per front): the pivot
+// of column j is the largest |entry| among all rows of the 256-row outer block
+// at or below row j (rows [k0 + j, K1), K1 = the end of the outer block or of
+// the pivot rows), not only the rows of the 64 x 64 diagonal block, which
+// keeps the element growth of the restricted pivoting small.  The candidate
+// rows (at most SB x FNB) are factored in LDS: the U rows of the panel, and the
+// multipliers of every other candidate row, which are final L entries.  Plus
+// U_tt^-1 for the L-column solves of the rows below K1 (stored once per front
+// in uinv, FNB x FNB column major, identity beyond kb).  The multipliers of
+// column j are used as D[i][j] / pivot_j in the updates and the column is
+// scaled at the end (the scaling of a row commutes with the later
+// interchanges).  Thread (column c = tid % 64, row group g = tid / 64) updates
+// rows i = g (mod 4) of its column.  ipiv[first + k0 + j] = the candidate row
+// (relative to k0, in [j, K1 - k0)) swapped with row j.
 template <class T>
 __global__ __launch_bounds__(256) void k_panel(T *arena, const FrontDesc *__restrict__ fd,
                                                int32_t *__restrict__ ipiv,
@@ -135,35 +142,59 @@ __global__ __launch_bounds__(256) void k_panel(T *arena, const FrontDesc *__rest
                                                int t, const double *__restrict__ thresh,
                                                double *__restrict__ uinv) {
     constexpr int H = FNB / 2;
-    __shared__ T D[FNB][FNB + 1];
-    __shared__ double Ui[FNB][FNB + 1];
-    __shared__ double Tm[H][H + 1];
+    constexpr int LD = FNB + 1;
+    // the candidate rows; after they are written back, the same space holds
+    // U_tt^-1 (FNB x LD doubles) and a scratch block (H x (H + 1) doubles)
+    static_assert((SB - FNB) * LD * sizeof(float) >= (FNB * LD + H * (H + 1)) * sizeof(double),
+                  "LDS reuse");
+    __shared__ __align__(16) unsigned char smem[SB * LD * sizeof(T)];
     __shared__ int piv[FNB];
     __shared__ T rpv[FNB];
+    __shared__ double wmx[4];
+    __shared__ int wrow[4];
+    T (*D)[LD] = reinterpret_cast<T (*)[LD]>(smem);
+    double (*Ui)[LD] = reinterpret_cast<double (*)[LD]>(smem + FNB * LD * sizeof(T));
+    double (*Tm)[H + 1] = reinterpret_cast<double (*)[H + 1]>(smem + FNB * LD * sizeof(T) +
+                                                              FNB * LD * sizeof(double));
     const int f = tl.fronts[blockIdx.x];
     const FrontDesc d = fd[f];
     const int k0 = t * FNB, kb = min(FNB, d.p - k0), m = d.m;
+    const int R = min(d.p, (k0 / SB + 1) * SB) - k0;   // candidate rows: kb <= R <= SB
     T *F = arena + d.off;
-    const int c = threadIdx.x % FNB, g = threadIdx.x / FNB;
-    for (int i = g; i < FNB; i += 4)
-        D[i][c] = (i < kb && c < kb) ? F[(int64_t)(k0 + i) + (int64_t)(k0 + c) * m] : T(0);
+    const int c = threadIdx.x % FNB, g = threadIdx.x / FNB, lane = threadIdx.x % 64;
+    for (int i = g; i < R; i += 4)
+        D[i][c] = (c < kb) ? F[(int64_t)(k0 + i) + (int64_t)(k0 + c) * m] : T(0);
+    for (int i = R + g; i < FNB; i += 4) D[i][c] = T(0);
     __syncthreads();
     const T th = (T)thresh[d.seg];                   // the static-pivot threshold of its problem
     for (int j = 0; j < kb; j++) {
-        if (g == 0) {
-            // pivot: argmax over rows i >= j of |D[i][j]| (lane = row), first on
-            // ties: the wave maximum, then the lowest lane holding it
-            const double v = (c >= j && c < kb) ? (double)fabs(D[c][j]) : -1.0;
+        // pivot: argmax over rows i in [j, R) of |D[i][j]|, the lowest row on
+        // ties: per wave (64 rows) the DPP maximum and the lowest lane holding
+        // it, then across the four waves in order
+        {
+            const int i = threadIdx.x;
+            const double v = (i >= j && i < R) ? (double)fabs(D[i][j]) : -1.0;
             const double mx = __shfl(wave_max(v), 63);
-            const uint64_t hit = __ballot(v == mx);
-            const int r = __ffsll((unsigned long long)hit) - 1;
-            if (r != j && c < kb) {                  // interchange rows j and r of column c
-                T x = D[j][c];
-                D[j][c] = D[r][c];
-                D[r][c] = x;
+            const uint64_t hit = __ballot(v == mx && v >= 0.0);
+            if (lane == 0) {
+                wmx[g] = hit ? mx : -1.0;
+                wrow[g] = hit ? g * 64 + (__ffsll((unsigned long long)hit) - 1) : -1;
             }
-            if (c == 0) piv[j] = r;
         }
+        __syncthreads();
+        int r = j;
+        {
+            double best = -1.0;
+            for (int w = 0; w < 4; w++)
+                if (wrow[w] >= 0 && wmx[w] > best) { best = wmx[w]; r = wrow[w]; }
+            r = (r >= j && r < R) ? r : j;
+        }
+        if (g == 0 && r != j && c < kb) {            // interchange rows j and r of column c
+            T x = D[j][c];
+            D[j][c] = D[r][c];
+            D[r][c] = x;
+        }
+        if (threadIdx.x == 0) piv[j] = r;
         __syncthreads();
         T pv = D[j][j];
         const bool pert = fabs(pv) < th;
@@ -171,7 +202,7 @@ __global__ __launch_bounds__(256) void k_panel(T *arena, const FrontDesc *__rest
         const T rp = T(1) / pv;
         if (c > j && c < kb) {                       // trailing update of column c
             const T ujc = D[j][c];
-            for (int i = j + 1 + g; i < kb; i += 4) D[i][c] -= (D[i][j] * rp) * ujc;
+            for (int i = j + 1 + g; i < R; i += 4) D[i][c] -= (D[i][j] * rp) * ujc;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -182,13 +213,14 @@ __global__ __launch_bounds__(256) void k_panel(T *arena, const FrontDesc *__rest
     }
     __syncthreads();
     if (c < kb)
-        for (int i = c + 1 + g; i < kb; i += 4) D[i][c] *= rpv[c];      // column c of L
+        for (int i = c + 1 + g; i < R; i += 4) D[i][c] *= rpv[c];       // column c of L
     for (int i = g; i < FNB; i += 4)
         if (i >= kb && i == c) D[i][c] = T(1);                           // identity padding
     __syncthreads();
     if (c < kb)
-        for (int i = g; i < kb; i += 4) F[(int64_t)(k0 + i) + (int64_t)(k0 + c) * m] = D[i][c];
+        for (int i = g; i < R; i += 4) F[(int64_t)(k0 + i) + (int64_t)(k0 + c) * m] = D[i][c];
     if (g == 0 && c < kb) ipiv[d.first + k0 + c] = piv[c];
+    __syncthreads();                                 // rows >= FNB of D are reused below
     // U^-1 by 32 x 32 blocks: the two diagonal inverses (one column per lane of
     // waves 0 and 1), then Ui12 = -Ui11 (U12 Ui22)
     if (g < 2 && c < H) {
@@ -229,14 +261,22 @@ __global__ __launch_bounds__(256) void k_panel(T *arena, const FrontDesc *__rest
 // Row interchanges of panel t applied to every column outside the panel (so
 // that P A = L U holds with one row permutation per front), and the U rows of
 // panel t: the permuted block rows right of the panel solved with the unit
-// lower L_tt.  One thread per column.
+// lower L_tt.  One thread per column.  The interchanges move rows inside the
+// candidate window [k0, K1): position i of the window receives the row that
+// was at src[i].  Every row moved below the panel (i >= kb) comes from one of
+// the panel's own rows (src[i] < kb): a row leaves position j only through
+// interchange j, and what position j holds then is one of the first kb rows.
+// So a column's new panel rows are loaded first, then the moved rows below
+// are written (their sources, panel rows, are still unwritten), then the
+// panel rows.
 template <class T>
 __device__ __forceinline__ void trsm_u_item(T *arena, const FrontDesc *__restrict__ fd,
                                             const int32_t *__restrict__ ipiv, int2 tk, int t,
-                                            T (*Ls)[FNB + 1], int *src) {
+                                            T (*Ls)[FNB + 1], int *src, int *mrow, int *nmoved) {
     FrontDesc d = fd[tk.x];
     int chunk = tk.y;
     int k0 = t * FNB, kb = min(FNB, d.p - k0), k1 = k0 + kb, m = d.m;
+    const int R = min(d.p, (k0 / SB + 1) * SB) - k0;
     int nleft = (k0 + TRSM_U_COLS - 1) / TRSM_U_COLS;
     T *F = arena + d.off;
     for (int e = threadIdx.x; e < FNB * FNB; e += blockDim.x) {
@@ -244,11 +284,16 @@ __device__ __forceinline__ void trsm_u_item(T *arena, const FrontDesc *__restric
         Ls[i][j] = (i < kb && j < i) ? F[(int64_t)(k0 + i) + (int64_t)(k0 + j) * m] : T(0);
     }
     if (threadIdx.x == 0) {
-        for (int i = 0; i < FNB; i++) src[i] = i;
+        for (int i = 0; i < R; i++) src[i] = i;
         for (int j = 0; j < kb; j++) {
             int r = ipiv[d.first + k0 + j];
+            r = (r >= j && r < R) ? r : j;
             int a = src[j]; src[j] = src[r]; src[r] = a;
         }
+        int nm = 0;                                  // the rows moved below the panel
+        for (int i = kb; i < R; i++)
+            if (src[i] != i) mrow[nm++] = i;
+        *nmoved = nm;
     }
     __syncthreads();
     int col, lim;
@@ -261,6 +306,16 @@ __device__ __forceinline__ void trsm_u_item(T *arena, const FrontDesc *__restric
     T x[FNB];
 #pragma unroll
     for (int i = 0; i < FNB; i++) x[i] = (i < kb) ? Fc[src[i]] : T(0);
+    // the rows moved below the panel, from panel rows not yet overwritten
+    const int nm = *nmoved;
+    for (int q0 = 0; q0 < nm; q0 += 8) {
+        T y[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) y[q] = (q0 + q < nm) ? Fc[src[mrow[q0 + q]]] : T(0);
+#pragma unroll
+        for (int q = 0; q < 8; q++)
+            if (q0 + q < nm) Fc[mrow[q0 + q]] = y[q];
+    }
     if (solve) {
 #pragma unroll
         for (int i = 1; i < FNB; i++) {
@@ -299,19 +354,20 @@ __global__ __launch_bounds__(256) void k_invert_diag(T *arena, const FrontDesc *
     T *F = arena + d.off + (int64_t)b0 * m + b0;     // block origin, leading dimension m
     int nsb = (sz + ISB - 1) / ISB;
     int tid = threadIdx.x;
-    // composite row permutation of the panels inside this block
-    if (doU && tid < SB / FNB) {
-        int q0 = b0 + tid * FNB;
-        if (q0 < d.p) {
-            int kb = min(FNB, d.p - q0);
-            int src[FNB];
-            for (int i = 0; i < FNB; i++) src[i] = i;
+    // composite row permutation of the panels inside this block (their
+    // interchanges stay inside the block's rows)
+    __shared__ int src[SB];
+    if (doU && tid == 0) {
+        for (int i = 0; i < sz; i++) src[i] = i;
+        for (int q0 = 0; q0 < sz; q0 += FNB) {
+            const int kb = min(FNB, sz - q0);
             for (int j = 0; j < kb; j++) {
-                int r = ipiv[d.first + q0 + j];
-                int a = src[j]; src[j] = src[r]; src[r] = a;
+                int r = ipiv[d.first + b0 + q0 + j];
+                r = (r >= j && q0 + r < sz) ? r : j;
+                int a = src[q0 + j]; src[q0 + j] = src[q0 + r]; src[q0 + r] = a;
             }
-            for (int i = 0; i < kb; i++) prow[d.first + q0 + i] = q0 + src[i];
         }
+        for (int i = 0; i < sz; i++) prow[d.first + b0 + i] = b0 + src[i];
     }
     auto at = [&](int r, int c) -> T & { return F[(int64_t)r + (int64_t)c * m]; };
     // phase 1: diagonal 32 x 32 sub-blocks (thread = sub-block i, column j)
@@ -442,8 +498,10 @@ __device__ __forceinline__ void trsm_l_item(T *arena, const FrontDesc *__restric
                                             double (*Ui)[FNB + 1], double (*As)[FNB + 1]) {
     FrontDesc d = fd[tk.x];
     int chunk = tk.y;
-    int k0 = t * FNB, kb = min(FNB, d.p - k0), k1 = k0 + kb, m = d.m;
-    int r0 = k1 + chunk * TRSM_L_ROWS, nr = min(TRSM_L_ROWS, m - r0);
+    int k0 = t * FNB, kb = min(FNB, d.p - k0), m = d.m;
+    // the rows of the candidate window got their multipliers in k_panel
+    const int K1 = min(d.p, (k0 / SB + 1) * SB);
+    int r0 = K1 + chunk * TRSM_L_ROWS, nr = min(TRSM_L_ROWS, m - r0);
     T *F = arena + d.off;
     const double *u = uinv + (int64_t)tk.x * FNB * FNB;
     for (int e = threadIdx.x; e < FNB * FNB; e += blockDim.x) {
@@ -477,10 +535,10 @@ __global__ __launch_bounds__(256) void k_trsm(T *arena, const FrontDesc *__restr
                                               const double *__restrict__ uinv) {
     static_assert(TRSM_U_COLS == 256 && TRSM_L_ROWS == 64, "one thread per column / row quarter");
     __shared__ double smem[2][FNB][FNB + 1];
-    __shared__ int src[FNB];
+    __shared__ int src[SB], mrow[SB], nmoved;
     if ((int64_t)blockIdx.x < tu.total)
         trsm_u_item<T>(arena, fd, ipiv, tu.items[blockIdx.x], t,
-                       reinterpret_cast<T (*)[FNB + 1]>(&smem[0][0][0]), src);
+                       reinterpret_cast<T (*)[FNB + 1]>(&smem[0][0][0]), src, mrow, &nmoved);
     else
         trsm_l_item<T>(arena, fd, tlo.items[blockIdx.x - tu.total], t, uinv, smem[0], smem[1]);
 }

@@ -442,7 +442,7 @@ void Context::build_tables(Plan &p) {
                 act.push_back(f);
                 o1.push_back(1);
                 tu.push_back(cdiv64(k0, TRSM_U_COLS) + cdiv64(d.m - k1, TRSM_U_COLS));
-                rb.push_back(cdiv64(d.m - k1, TRSM_L_ROWS));
+                rb.push_back(cdiv64(d.m - K1, TRSM_L_ROWS));   // below the pivot window
                 sh.push_back((K1 > k1 ? cdiv64(d.m - k1, SCHUR_TILE) * cdiv64(K1 - k1, SCHUR_TILE) : 0) +
                              cdiv64(K1 - k1, SCHUR_TILE) * cdiv64(d.m - K1, SCHUR_TILE));
             }
@@ -995,7 +995,7 @@ void Context::refine(Plan &p, Factor<T> &f, int nrhs, const double *B, double *X
     double *r = d_r.ptr<double>(), *dd = d_d.ptr<double>();
     lu_apply<T>(p, f, nrhs, B, n, X, n);
     std::vector<double> part((size_t)RES_PARTS * nrhs * 3);
-    const double target = 1e-13;
+    const double target = refine_target;
 
     double prev = 1e300;
     int it = 0;
@@ -1098,7 +1098,7 @@ void Context::refine_batch(Plan &p, Factor<T> &f, int nrhs, const double *B, dou
     lu_apply<T>(p, f, nrhs, B, N, X, N);
     count_pass();
     std::vector<double> part((size_t)RES_PARTS * nrhs * 3 * nseg), prev(nseg, 1e300), be(nseg, 0.0);
-    const double target = 1e-13;
+    const double target = refine_target;
     for (int it = 0;; it++) {
         launch_residual_seg(nseg, n, p.rowptr.ptr<int32_t>(), p.col.ptr<int32_t>(), shifted, offv,
                             0.0, nrhs, B, X, r, d_part.ptr<double>(), RES_PARTS, s);
@@ -1809,8 +1809,12 @@ void solve_problem(Context &ctx, const mbl_problem &pr, mbl_result &res, const d
             c.hooks = q.flags & HOOKS;
             c.budget.armed = q.fail_alloc_bytes;
             c.budget.since_armed = 0;
+            c.refine_target = Context::eig_refine_target(q.tol > 0 ? q.tol : 1e-10);
         }
-        ~HookScope() { c.hooks = 0; c.budget.armed = 0; c.budget.since_armed = 0; }
+        ~HookScope() {
+            c.hooks = 0; c.budget.armed = 0; c.budget.since_armed = 0;
+            c.refine_target = Context::SOLVE_TARGET;
+        }
     } hook_scope(ctx, pr);
     double tol = pr.tol > 0 ? pr.tol : 1e-10;
     double t_start = wall_seconds(), t0 = t_start;
@@ -1931,6 +1935,11 @@ bool solve_batch(Context &ctx, int count, const mbl_problem *prs, mbl_result *re
     const double tol = a.tol > 0 ? a.tol : 1e-10;
     const int prec = a.prec;
     hipStream_t s = ctx.stream;
+    struct TargetScope {                   // refinement target of these requests
+        Context &c;
+        TargetScope(Context &cx, double tol) : c(cx) { c.refine_target = Context::eig_refine_target(tol); }
+        ~TargetScope() { c.refine_target = Context::SOLVE_TARGET; }
+    } target_scope(ctx, tol);
     try {
         double t_start = wall_seconds(), t0 = t_start;
         double tph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
