@@ -136,10 +136,12 @@ void launch_solve_step(const T *arena, const FrontDesc *fd, TaskList tl, int t, 
                        double *vec, double *yv, BwdIO bio, hipStream_t s);
 // backward: partial products U12 x_c over 64 x SB tiles, x_c (the contribution
 // rows, pivots of ancestors) read from xnew through the contribution-row
-// lists; then their fixed-order sum into the forward solution of the pivots
+// lists; then their fixed-order sum into the forward solution of the pivots.
+// ipw (here and in launch_fwd_l21): tiles per workgroup, 1 or 2 (a launch
+// shape only: the results do not depend on it)
 template <class T>
 void launch_bwd_u12(const T *arena, const FrontDesc *fd, TaskList tl, int nrhs,
-                    const int32_t *contrib, const double *xnew, int64_t n, double *part,
+                    const int32_t *contrib, const double *xnew, int64_t n, double *part, int ipw,
                     hipStream_t s);
 void launch_bwd_u12_reduce(const FrontDesc *fd, TaskList tl, int nrhs, double *yv,
                            const double *part, hipStream_t s);
@@ -147,7 +149,7 @@ void launch_bwd_u12_reduce(const FrontDesc *fd, TaskList tl, int nrhs, double *y
 // reduction into the solve vectors)
 template <class T>
 void launch_fwd_l21(const T *arena, const FrontDesc *fd, TaskList tl, int nrhs, const double *vec,
-                    double *part, hipStream_t s);
+                    double *part, int ipw, hipStream_t s);
 void launch_fwd_l21_reduce(const FrontDesc *fd, TaskList tl, int nrhs, double *vec,
                            const double *part, hipStream_t s);
 

@@ -219,68 +219,102 @@ __global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_solve_step(
     }
 }
 
-// Contribution rows of the forward pass: once every solve block of a front
-// is done, V[0:p] holds the source values of all blocks (a block's rows are
-// not touched after its own step), so V[p:m] -= L~21 V[0:p] in one pass with
-// the folded panel L~21 = L[p:m, 0:p] (per block times its inverse): tiles of
-// 64 contribution rows x SB pivot columns into partial sums, then a
-// fixed-order reduction over the column chunks (k_fwd_l21_reduce).
-template <class T, int NR>
-__global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_fwd_l21(
+// The off-diagonal products of the solves, as 64-row x SB-column tiles of
+// partial sums (a fixed-order reduction over the column chunks follows):
+//  - forward, contribution rows (U12 = false): once every solve block of a
+//    front is done, V[0:p] holds the source values of all blocks (a block's
+//    rows are not touched after its own step), so V[p:m] -= L~21 V[0:p] in one
+//    pass with the folded panel L~21 = L[p:m, 0:p] (per block times its
+//    inverse); partial sums of tile (row chunk, column chunk cc) go to part;
+//    k_fwd_l21_reduce sums them;
+//  - backward (U12 = true): Y -= U12 x_c over the pivot rows, x of the
+//    contribution rows (pivots of ancestors, already solved) read through the
+//    front's contribution-row list; k_bwd_u12_reduce sums them.
+// A workgroup takes IPW consecutive tiles of the task list (1 or 2, chosen per
+// tree level by the solve autotuner): their factor entries are all loaded
+// before any is used, so IPW = 2 keeps twice the bytes in flight per lane.
+// The arithmetic of a row does not depend on IPW: the same column split over
+// the waves and the same fixed-order sums.
+template <class T, int NR, int IPW, bool U12>
+__global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_offdiag(
     const T *__restrict__ arena, const FrontDesc *__restrict__ fd, TaskList tl,
-    const double *__restrict__ vec, double *__restrict__ part) {
+    const double *__restrict__ vec, const int32_t *__restrict__ contrib,
+    const double *__restrict__ xnew, int64_t n, double *__restrict__ part) {
     constexpr int CG = StepCfg<NR>::CG, CW = StepCfg<NR>::CWU, HG = CG / 2;
-    __shared__ double src[SB][NR];
+    __shared__ double src[IPW][SB][NR];
     __shared__ double red[HG][RW][NR];
-    const int2 tk = tl.items[xcd_item(blockIdx.x, gridDim.x)];
-    const FrontDesc d = fd[tk.x];
-    const int w = tk.y;
-    const int m = d.m, p = d.p, c = m - p;
-    const int nrc = (c + RW - 1) / RW;
-    const int rc = w % nrc, cc = w / nrc;
-    const int c0 = cc * SB, cw = min(SB, p - c0);
     const int lane = threadIdx.x % RW, wv = threadIdx.x / RW;
-    const int row = rc * RW + lane;                  // contribution row
-    double mv[CW];
-    {
-        const T *Lp = arena + d.off + p + row + (int64_t)(c0 + wv * CW) * m;
+    const int64_t base = (int64_t)xcd_item(blockIdx.x, gridDim.x) * IPW;
+    FrontDesc d[IPW];
+    int row[IPW], nr[IPW], cc[IPW], c0[IPW], cw[IPW];
+    bool live[IPW];
+    double mv[IPW][CW];
+#pragma unroll
+    for (int k = 0; k < IPW; k++) {
+        live[k] = base + k < tl.total;
+        const int2 tk = tl.items[live[k] ? base + k : base];
+        d[k] = fd[tk.x];
+        const int w = tk.y, m = d[k].m, p = d[k].p, c = m - p;
+        nr[k] = U12 ? p : c;                          // rows of the product
+        const int ncol = U12 ? c : p;                 // its columns
+        const int nrc = (nr[k] + RW - 1) / RW;
+        const int rc = w % nrc;
+        cc[k] = w / nrc;
+        c0[k] = cc[k] * SB;
+        cw[k] = min(SB, ncol - c0[k]);
+        row[k] = rc * RW + lane;
+        const T *M = U12 ? arena + d[k].off + row[k] + (int64_t)(p + c0[k] + wv * CW) * m
+                         : arena + d[k].off + p + row[k] + (int64_t)(c0[k] + wv * CW) * m;
+        const bool rok = live[k] && row[k] < nr[k];
 #pragma unroll
         for (int q = 0; q < CW; q++)
-            mv[q] = (row < c && wv * CW + q < cw) ? (double)Lp[(int64_t)q * m] : 0.0;
+            mv[k][q] = (rok && wv * CW + q < cw[k]) ? (double)M[(int64_t)q * m] : 0.0;
     }
-    const double *v = vec + d.voff;
-    for (int e = threadIdx.x; e < SB * NR; e += blockDim.x) {
-        int j = e % SB, r = e / SB;
-        src[j][r] = j < cw ? v[c0 + j + (int64_t)r * m] : 0.0;
-    }
-    __syncthreads();
-    double acc[NR];
 #pragma unroll
-    for (int r = 0; r < NR; r++) acc[r] = 0.0;
-#pragma unroll
-    for (int q = 0; q < CW; q++) {
-        const double x = mv[q];
-#pragma unroll
-        for (int r = 0; r < NR; r++) acc[r] += x * src[wv * CW + q][r];
-    }
-    if (wv >= HG) {
-#pragma unroll
-        for (int r = 0; r < NR; r++) red[wv - HG][lane][r] = acc[r];
-    }
-    __syncthreads();
-    if (wv < HG) {
-#pragma unroll
-        for (int r = 0; r < NR; r++) red[wv][lane][r] += acc[r];
-    }
-    __syncthreads();
-    if (wv == 0 && row < c)
-#pragma unroll
-        for (int r = 0; r < NR; r++) {
-            double sum = red[0][lane][r];
-#pragma unroll
-            for (int g = 1; g < HG; g++) sum += red[g][lane][r];
-            part[d.poff + ((int64_t)cc * MAXRHS + r) * c + row] = sum;
+    for (int k = 0; k < IPW; k++) {
+        if (!live[k]) continue;                       // uniform over the workgroup
+        const int32_t *cr = contrib + d[k].cptr + c0[k];
+        const double *v = vec + d[k].voff;
+        for (int e = threadIdx.x; e < SB * NR; e += blockDim.x) {
+            int j = e % SB, r = e / SB;
+            double x = 0.0;
+            if (j < cw[k]) x = U12 ? xnew[cr[j] + (int64_t)r * n] : v[c0[k] + j + (int64_t)r * d[k].m];
+            src[k][j][r] = x;
         }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IPW; k++) {
+        if (!live[k]) break;
+        double acc[NR];
+#pragma unroll
+        for (int r = 0; r < NR; r++) acc[r] = 0.0;
+#pragma unroll
+        for (int q = 0; q < CW; q++) {
+            const double x = mv[k][q];
+#pragma unroll
+            for (int r = 0; r < NR; r++) acc[r] += x * src[k][wv * CW + q][r];
+        }
+        if (k > 0) __syncthreads();                   // red of the previous tile is read
+        if (wv >= HG) {
+#pragma unroll
+            for (int r = 0; r < NR; r++) red[wv - HG][lane][r] = acc[r];
+        }
+        __syncthreads();
+        if (wv < HG) {
+#pragma unroll
+            for (int r = 0; r < NR; r++) red[wv][lane][r] += acc[r];
+        }
+        __syncthreads();
+        if (wv == 0 && row[k] < nr[k])
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                double sum = red[0][lane][r];
+#pragma unroll
+                for (int g = 1; g < HG; g++) sum += red[g][lane][r];
+                part[d[k].poff + ((int64_t)cc[k] * MAXRHS + r) * nr[k] + row[k]] = sum;
+            }
+    }
 }
 
 template <int NR>
@@ -303,69 +337,6 @@ __global__ __launch_bounds__(256) void k_fwd_l21_reduce(const FrontDesc *__restr
     double *o = vec + d.voff + p + row;
 #pragma unroll
     for (int r = 0; r < NR; r++) o[(int64_t)r * m] -= s[r];
-}
-
-// partial U12 x_c over one 64-row x SB-column tile (factor entries loaded
-// before the source block is staged)
-template <class T, int NR>
-__global__ __launch_bounds__(StepCfg<NR>::THREADS) void k_bwd_u12(
-    const T *__restrict__ arena, const FrontDesc *__restrict__ fd, TaskList tl,
-    const int32_t *__restrict__ contrib, const double *__restrict__ xnew, int64_t n,
-    double *__restrict__ part) {
-    constexpr int CG = StepCfg<NR>::CG, CW = StepCfg<NR>::CWU, HG = CG / 2;
-    __shared__ double src[SB][NR];
-    __shared__ double red[HG][RW][NR];
-    const int2 tk = tl.items[xcd_item(blockIdx.x, gridDim.x)];
-    const FrontDesc d = fd[tk.x];
-    const int w = tk.y;
-    const int m = d.m, p = d.p, c = m - p;
-    const int nrc = (p + RW - 1) / RW;
-    const int rc = w % nrc, cc = w / nrc;
-    const int c0 = cc * SB, cw = min(SB, c - c0);
-    const int lane = threadIdx.x % RW, wv = threadIdx.x / RW;
-    const int row = rc * RW + lane;
-    double mv[CW];
-    {
-        const T *U = arena + d.off + row + (int64_t)(p + c0 + wv * CW) * m;
-#pragma unroll
-        for (int q = 0; q < CW; q++)
-            mv[q] = (row < p && wv * CW + q < cw) ? (double)U[(int64_t)q * m] : 0.0;
-    }
-    // x of the contribution rows (pivots of ancestors, already solved), read
-    // through the front's contribution-row list
-    const int32_t *cr = contrib + d.cptr + c0;
-    for (int e = threadIdx.x; e < SB * NR; e += blockDim.x) {
-        int j = e % SB, r = e / SB;
-        src[j][r] = j < cw ? xnew[cr[j] + (int64_t)r * n] : 0.0;
-    }
-    __syncthreads();
-    double acc[NR];
-#pragma unroll
-    for (int r = 0; r < NR; r++) acc[r] = 0.0;
-#pragma unroll
-    for (int q = 0; q < CW; q++) {
-        const double x = mv[q];
-#pragma unroll
-        for (int r = 0; r < NR; r++) acc[r] += x * src[wv * CW + q][r];
-    }
-    if (wv >= HG) {
-#pragma unroll
-        for (int r = 0; r < NR; r++) red[wv - HG][lane][r] = acc[r];
-    }
-    __syncthreads();
-    if (wv < HG) {
-#pragma unroll
-        for (int r = 0; r < NR; r++) red[wv][lane][r] += acc[r];
-    }
-    __syncthreads();
-    if (wv == 0 && row < p)
-#pragma unroll
-        for (int r = 0; r < NR; r++) {
-            double sum = red[0][lane][r];
-#pragma unroll
-            for (int g = 1; g < HG; g++) sum += red[g][lane][r];
-            part[d.poff + ((int64_t)cc * MAXRHS + r) * p + row] = sum;
-        }
 }
 
 template <int NR>
@@ -438,25 +409,37 @@ void launch_solve_step(const T *arena, const FrontDesc *fd, TaskList tl, int t, 
 
 template <class T>
 void launch_bwd_u12(const T *arena, const FrontDesc *fd, TaskList tl, int nrhs,
-                    const int32_t *contrib, const double *xnew, int64_t n, double *part,
+                    const int32_t *contrib, const double *xnew, int64_t n, double *part, int ipw,
                     hipStream_t s) {
     if (tl.total == 0) return;
+    const unsigned g1 = (unsigned)tl.total, g2 = (unsigned)((tl.total + 1) / 2);
     rhs_dispatch(nrhs, [&](auto nr) {
         constexpr int NR = decltype(nr)::value;
-        k_bwd_u12<T, NR><<<dim3((unsigned)tl.total), dim3(StepCfg<NR>::THREADS), 0, s>>>(
-            arena, fd, tl, contrib, xnew, n, part);
+        constexpr int TH = StepCfg<NR>::THREADS;
+        if (ipw == 2)
+            k_offdiag<T, NR, 2, true><<<dim3(g2), dim3(TH), 0, s>>>(arena, fd, tl, nullptr, contrib,
+                                                                    xnew, n, part);
+        else
+            k_offdiag<T, NR, 1, true><<<dim3(g1), dim3(TH), 0, s>>>(arena, fd, tl, nullptr, contrib,
+                                                                    xnew, n, part);
     });
     MBL_CHECK_LAUNCH();
 }
 
 template <class T>
 void launch_fwd_l21(const T *arena, const FrontDesc *fd, TaskList tl, int nrhs, const double *vec,
-                    double *part, hipStream_t s) {
+                    double *part, int ipw, hipStream_t s) {
     if (tl.total == 0) return;
+    const unsigned g1 = (unsigned)tl.total, g2 = (unsigned)((tl.total + 1) / 2);
     rhs_dispatch(nrhs, [&](auto nr) {
         constexpr int NR = decltype(nr)::value;
-        k_fwd_l21<T, NR><<<dim3((unsigned)tl.total), dim3(StepCfg<NR>::THREADS), 0, s>>>(arena, fd,
-                                                                                      tl, vec, part);
+        constexpr int TH = StepCfg<NR>::THREADS;
+        if (ipw == 2)
+            k_offdiag<T, NR, 2, false><<<dim3(g2), dim3(TH), 0, s>>>(arena, fd, tl, vec, nullptr,
+                                                                     nullptr, 0, part);
+        else
+            k_offdiag<T, NR, 1, false><<<dim3(g1), dim3(TH), 0, s>>>(arena, fd, tl, vec, nullptr,
+                                                                     nullptr, 0, part);
     });
     MBL_CHECK_LAUNCH();
 }
@@ -485,9 +468,9 @@ void launch_bwd_u12_reduce(const FrontDesc *fd, TaskList tl, int nrhs, double *y
     template void launch_solve_step<T>(const T *, const FrontDesc *, TaskList, int, int, bool,    \
                                        double *, double *, BwdIO, hipStream_t);                   \
     template void launch_bwd_u12<T>(const T *, const FrontDesc *, TaskList, int, const int32_t *, \
-                                    const double *, int64_t, double *, hipStream_t);               \
+                                    const double *, int64_t, double *, int, hipStream_t);          \
     template void launch_fwd_l21<T>(const T *, const FrontDesc *, TaskList, int, const double *,  \
-                                    double *, hipStream_t);
+                                    double *, int, hipStream_t);
 
 MBL_INST_TRSV(float)
 MBL_INST_TRSV(double)

@@ -760,17 +760,19 @@ void Context::lu_apply(Plan &p, Factor<T> &f, int nrhs, const double *b, int64_t
     // timing a class of the solve launches needs events between them: eager
     const bool timed = prof_on("fwd_update") || prof_on("bwd_update") || prof_on("l21") ||
                        prof_on("u12");
+    // work buffers of the solve (before the autotuner, which launches into them)
+    d_vec.ensure(sizeof(double) * std::max<int64_t>(1, p.vec_elems), &budget);
+    d_yv.ensure(sizeof(double) * std::max<int64_t>(1, p.y_elems), &budget);
+    d_upart.ensure(sizeof(double) * std::max<int64_t>(1, p.part_elems), &budget);
+    d_xnew.ensure(sizeof(double) * n * MAXRHS, &budget);
+    const Plan::SolveTune tn = solve_tune<T>(p, f, nrhs);
     if (!use_graphs_ || timed || ldb != n || ldx != n) {
-        lu_apply_seq<T>(p, f, nrhs, b, ldb, x, ldx);
+        lu_apply_seq<T>(p, f, nrhs, b, ldb, x, ldx, tn);
         return;
     }
     // The launch sequence of one application is the same every time for a
     // given plan, factor, right-hand-side count and work buffers: it is
     // captured once as a graph between fixed staging vectors and replayed.
-    d_vec.ensure(sizeof(double) * std::max<int64_t>(1, p.vec_elems), &budget);
-    d_yv.ensure(sizeof(double) * std::max<int64_t>(1, p.y_elems), &budget);
-    d_upart.ensure(sizeof(double) * std::max<int64_t>(1, p.part_elems), &budget);
-    d_xnew.ensure(sizeof(double) * n * MAXRHS, &budget);
     d_gin.ensure(sizeof(double) * n * MAXRHS, &budget);
     d_gout.ensure(sizeof(double) * n * MAXRHS, &budget);
     GraphKey key{&p, p.L, (int)sizeof(T), nrhs,
@@ -783,7 +785,7 @@ void Context::lu_apply(Plan &p, Factor<T> &f, int nrhs, const double *b, int64_t
         hipGraph_t g = nullptr;
         MBL_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
         try {
-            lu_apply_seq<T>(p, f, nrhs, d_gin.ptr<double>(), n, d_gout.ptr<double>(), n);
+            lu_apply_seq<T>(p, f, nrhs, d_gin.ptr<double>(), n, d_gout.ptr<double>(), n, tn);
         } catch (...) {
             hipGraph_t dead = nullptr;
             (void)hipStreamEndCapture(stream, &dead);
@@ -808,8 +810,73 @@ void Context::clear_graphs() {
 }
 
 template <class T>
+Plan::SolveTune Context::solve_tune(Plan &p, Factor<T> &f, int nrhs) {
+    const int key = (int)sizeof(T) * 100 + nrhs;
+    {
+        std::lock_guard<std::recursive_mutex> lk(plans_->mu);
+        auto it = p.tune.find(key);
+        if (it != p.tune.end()) return it->second;
+    }
+    const size_t nl = p.levels.size();
+    Plan::SolveTune tn;
+    tn.l21.assign(nl, 1);
+    tn.u12.assign(nl, 1);
+    if (std::getenv("MBL_NO_TUNE") == nullptr) {
+        hipStream_t s = stream;
+        const T *A = f.arena.template ptr<T>();
+        const FrontDesc *fd = p.d_fd.ptr<FrontDesc>();
+        double *part = d_upart.ptr<double>();
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        MBL_HIP(hipEventCreate(&e0));
+        MBL_HIP(hipEventCreate(&e1));
+        try {
+            auto timed = [&](const std::function<void(int)> &run, int ipw) {
+                run(ipw);                              // warm
+                MBL_HIP(hipEventRecord(e0, s));
+                for (int r = 0; r < 3; r++) run(ipw);
+                MBL_HIP(hipEventRecord(e1, s));
+                MBL_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                MBL_HIP(hipEventElapsedTime(&ms, e0, e1));
+                return ms;
+            };
+            auto pick = [&](const std::function<void(int)> &run) -> int8_t {
+                const float t1 = timed(run, 1), t2 = timed(run, 2);
+                return (t2 < 0.97f * t1) ? 2 : 1;     // two tiles only when clearly faster
+            };
+            for (size_t l = 0; l < nl; l++) {
+                LevelTasks &lv = p.levels[l];
+                if (lv.l21.total > 0)
+                    tn.l21[l] = pick([&](int ipw) {
+                        launch_fwd_l21<T>(A, fd, lv.l21, nrhs, d_vec.ptr<double>(), part, ipw, s);
+                    });
+                if (lv.u12.total > 0)
+                    tn.u12[l] = pick([&](int ipw) {
+                        launch_bwd_u12<T>(A, fd, lv.u12, nrhs, p.d_contrib.ptr<int32_t>(),
+                                          d_xnew.ptr<double>(), p.dim, part, ipw, s);
+                    });
+            }
+        } catch (...) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            throw;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (debug_level() > 0) {
+            int n2 = 0;
+            for (size_t l = 0; l < nl; l++) n2 += (tn.l21[l] == 2) + (tn.u12[l] == 2);
+            std::fprintf(stderr, "[mbl] solve tune L=%d x%d %s nrhs=%d: %d of %zu products with 2 tiles\n",
+                         p.L, p.nseg, sizeof(T) == 4 ? "fp32" : "fp64", nrhs, n2, 2 * nl);
+        }
+    }
+    std::lock_guard<std::recursive_mutex> lk(plans_->mu);
+    return p.tune.emplace(key, tn).first->second;      // another context may have tuned it first
+}
+
+template <class T>
 void Context::lu_apply_seq(Plan &p, Factor<T> &f, int nrhs, const double *b, int64_t ldb,
-                           double *x, int64_t ldx) {
+                           double *x, int64_t ldx, const Plan::SolveTune &tn) {
     hipStream_t s = stream;
     const T *A = f.arena.template ptr<T>();
     const FrontDesc *fd = p.d_fd.ptr<FrontDesc>();
@@ -835,7 +902,7 @@ void Context::lu_apply_seq(Plan &p, Factor<T> &f, int nrhs, const double *b, int
         for (size_t t = 0; t < lv.fstep.size(); t++) step(lv.fstep[t], (int)t, true);
         bool pr = prof_on("l21") && lv.l21.total > 0;
         if (pr) prof_begin();
-        launch_fwd_l21<T>(A, fd, lv.l21, nrhs, vec, part, s);
+        launch_fwd_l21<T>(A, fd, lv.l21, nrhs, vec, part, tn.l21[l], s);
         if (pr) prof_end(lv.l21.elems * sizeof(T) + 8.0 * nrhs * lv.l21.rows, 2.0 * nrhs * lv.l21.elems);
         launch_fwd_l21_reduce(fd, lv.l21red, nrhs, vec, part, s);
     }
@@ -843,7 +910,8 @@ void Context::lu_apply_seq(Plan &p, Factor<T> &f, int nrhs, const double *b, int
         LevelTasks &lv = p.levels[l];
         bool pr = prof_on("u12") && lv.u12.total > 0;
         if (pr) prof_begin();
-        launch_bwd_u12<T>(A, fd, lv.u12, nrhs, p.d_contrib.ptr<int32_t>(), xnew, p.dim, part, s);
+        launch_bwd_u12<T>(A, fd, lv.u12, nrhs, p.d_contrib.ptr<int32_t>(), xnew, p.dim, part,
+                          tn.u12[l], s);
         if (pr) prof_end(lv.u12.elems * sizeof(T) + 8.0 * nrhs * lv.u12.rows, 2.0 * nrhs * lv.u12.elems);
         launch_bwd_u12_reduce(fd, lv.u12red, nrhs, yv, part, s);
         for (size_t t = lv.bstep.size(); t-- > 0;) step(lv.bstep[t], (int)t, false);

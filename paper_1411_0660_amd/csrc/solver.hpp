@@ -64,6 +64,14 @@ struct Plan {
     int64_t part_elems = 0;            // max over levels
     DevBuf d_fd, d_perm, d_contrib, d_pullmap, d_child_ids, d_tfronts, d_tprefix, d_titems;
     DevBuf d_efront, d_epos, d_esrc, d_inv_ptr, d_inv_src;
+    // Launch shapes of the solves chosen by the solve autotuner, per factor
+    // precision and right-hand-side count (key sizeof(T) * 100 + nrhs): tiles
+    // per workgroup of the L21 and U12 products at every tree level.  Set
+    // once, under the plan cache's lock; the results do not depend on them.
+    struct SolveTune {
+        std::vector<int8_t> l21, u12;
+    };
+    std::map<int, SolveTune> tune;
 };
 
 template <class T>
@@ -229,7 +237,13 @@ class Context {
     template <class T> void factor_t(Plan &p, Factor<T> &f, const double *diag, double sigma,
                                      const std::vector<double> &thresh, SolveStats &st);
     template <class T> void lu_apply_seq(Plan &p, Factor<T> &f, int nrhs, const double *b,
-                                         int64_t ldb, double *x, int64_t ldx);
+                                         int64_t ldb, double *x, int64_t ldx,
+                                         const Plan::SolveTune &tn);
+    // the solve launch shapes of (plan, precision, nrhs), timed on this factor
+    // at first use: every level's L21 and U12 products with one and with two
+    // tiles per workgroup (their outputs are scratch partial sums), the faster
+    // kept (MBL_NO_TUNE: one tile everywhere)
+    template <class T> Plan::SolveTune solve_tune(Plan &p, Factor<T> &f, int nrhs);
     // captured launch sequences of lu_apply (see lu_apply)
     struct GraphKey {
         const Plan *plan;              // lone and batch plans of one L differ
