@@ -16,6 +16,15 @@ constexpr int FNB = 64;
 // L11 and U11 are stored inverted after the factorisation.
 constexpr int SB = 4 * FNB;
 constexpr int SSB = 2 * SB;         // solve block: two factorization blocks merged
+// Pivot window: the pivot of a panel column is chosen among the rows of its
+// aligned PIV_WIN-row window at or below it (inside one outer block, so that
+// the interchanges stay inside the block's rows)
+constexpr int PIV_WIN = 256;
+static_assert(PIV_WIN % FNB == 0 && SB % PIV_WIN == 0, "pivot window inside an outer block");
+// end (front-local row) of the pivot window of the panel starting at row k0
+__host__ __device__ inline int piv_window_end(int k0, int p) {
+    return (k0 / PIV_WIN + 1) * PIV_WIN < p ? (k0 / PIV_WIN + 1) * PIV_WIN : p;
+}
 // Rows of one work item of a solve step (k_solve_step): 64 / STEP_RW adjacent
 // columns per wave load, so small steps still spread over many workgroups.
 #ifndef MBL_STEP_RW

@@ -122,11 +122,11 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // LU with partial pivoting of panel t (one workgroup per front): the pivot
-// of column j is the largest |entry| among all rows of the 256-row outer block
-// at or below row j (rows [k0 + j, K1), K1 = the end of the outer block or of
-// the pivot rows), not only the rows of the 64 x 64 diagonal block, which
-// keeps the element growth of the restricted pivoting small.  The candidate
-// rows (at most SB x FNB) are factored in LDS: the U rows of the panel, and the
+// of column j is the largest |entry| among all rows of its pivot window at or
+// below row j (rows [k0 + j, K1), K1 = piv_window_end), not only the rows of
+// the 64 x 64 diagonal block, which keeps the element growth of the
+// restricted pivoting small.  The candidate rows (at most PIV_WIN x FNB) are
+// factored in LDS: the U rows of the panel, and the
 // multipliers of every other candidate row, which are final L entries.  Plus
 // U_tt^-1 for the L-column solves of the rows below K1 (stored once per front
 // in uinv, FNB x FNB column major, identity beyond kb).  The multipliers of
@@ -145,9 +145,9 @@ __global__ __launch_bounds__(256) void k_panel(T *arena, const FrontDesc *__rest
     constexpr int LD = FNB + 1;
     // the candidate rows; after they are written back, the same space holds
     // U_tt^-1 (FNB x LD doubles) and a scratch block (H x (H + 1) doubles)
-    static_assert((SB - FNB) * LD * sizeof(float) >= (FNB * LD + H * (H + 1)) * sizeof(double),
-                  "LDS reuse");
-    __shared__ __align__(16) unsigned char smem[SB * LD * sizeof(T)];
+    constexpr size_t ROWS_B = (size_t)PIV_WIN * LD * sizeof(T);
+    constexpr size_t INV_B = (size_t)FNB * LD * sizeof(T) + (FNB * LD + H * (H + 1)) * sizeof(double);
+    __shared__ __align__(16) unsigned char smem[ROWS_B > INV_B ? ROWS_B : INV_B];
     __shared__ int piv[FNB];
     __shared__ T rpv[FNB];
     __shared__ double wmx[4];
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void k_panel(T *arena, const FrontDesc *__rest
     const int f = tl.fronts[blockIdx.x];
     const FrontDesc d = fd[f];
     const int k0 = t * FNB, kb = min(FNB, d.p - k0), m = d.m;
-    const int R = min(d.p, (k0 / SB + 1) * SB) - k0;   // candidate rows: kb <= R <= SB
+    const int R = piv_window_end(k0, d.p) - k0;       // candidate rows: kb <= R <= PIV_WIN
     T *F = arena + d.off;
     const int c = threadIdx.x % FNB, g = threadIdx.x / FNB, lane = threadIdx.x % 64;
     for (int i = g; i < R; i += 4)
@@ -202,7 +202,18 @@ __global__ __launch_bounds__(256) void k_panel(T *arena, const FrontDesc *__rest
         const T rp = T(1) / pv;
         if (c > j && c < kb) {                       // trailing update of column c
             const T ujc = D[j][c];
-            for (int i = j + 1 + g; i < R; i += 4) D[i][c] -= (D[i][j] * rp) * ujc;
+            // four rows at a time, all loads before the stores, so that the
+            // LDS round trips of a thread overlap
+            int i = j + 1 + g;
+            for (; i + 12 < R; i += 16) {
+                const T l0 = D[i][j], l1 = D[i + 4][j], l2 = D[i + 8][j], l3 = D[i + 12][j];
+                const T a0 = D[i][c], a1 = D[i + 4][c], a2 = D[i + 8][c], a3 = D[i + 12][c];
+                D[i][c] = a0 - (l0 * rp) * ujc;
+                D[i + 4][c] = a1 - (l1 * rp) * ujc;
+                D[i + 8][c] = a2 - (l2 * rp) * ujc;
+                D[i + 12][c] = a3 - (l3 * rp) * ujc;
+            }
+            for (; i < R; i += 4) D[i][c] -= (D[i][j] * rp) * ujc;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -276,7 +287,7 @@ __device__ __forceinline__ void trsm_u_item(T *arena, const FrontDesc *__restric
     FrontDesc d = fd[tk.x];
     int chunk = tk.y;
     int k0 = t * FNB, kb = min(FNB, d.p - k0), k1 = k0 + kb, m = d.m;
-    const int R = min(d.p, (k0 / SB + 1) * SB) - k0;
+    const int R = piv_window_end(k0, d.p) - k0;
     int nleft = (k0 + TRSM_U_COLS - 1) / TRSM_U_COLS;
     T *F = arena + d.off;
     for (int e = threadIdx.x; e < FNB * FNB; e += blockDim.x) {
@@ -500,7 +511,7 @@ __device__ __forceinline__ void trsm_l_item(T *arena, const FrontDesc *__restric
     int chunk = tk.y;
     int k0 = t * FNB, kb = min(FNB, d.p - k0), m = d.m;
     // the rows of the candidate window got their multipliers in k_panel
-    const int K1 = min(d.p, (k0 / SB + 1) * SB);
+    const int K1 = piv_window_end(k0, d.p);
     int r0 = K1 + chunk * TRSM_L_ROWS, nr = min(TRSM_L_ROWS, m - r0);
     T *F = arena + d.off;
     const double *u = uinv + (int64_t)tk.x * FNB * FNB;

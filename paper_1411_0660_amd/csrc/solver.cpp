@@ -442,7 +442,7 @@ void Context::build_tables(Plan &p) {
                 act.push_back(f);
                 o1.push_back(1);
                 tu.push_back(cdiv64(k0, TRSM_U_COLS) + cdiv64(d.m - k1, TRSM_U_COLS));
-                rb.push_back(cdiv64(d.m - K1, TRSM_L_ROWS));   // below the pivot window
+                rb.push_back(cdiv64(d.m - piv_window_end(k0, d.p), TRSM_L_ROWS));   // below the pivot window
                 sh.push_back((K1 > k1 ? cdiv64(d.m - k1, SCHUR_TILE) * cdiv64(K1 - k1, SCHUR_TILE) : 0) +
                              cdiv64(K1 - k1, SCHUR_TILE) * cdiv64(d.m - K1, SCHUR_TILE));
             }
