@@ -14,9 +14,10 @@
 // the accumulated vectors V by one thread per row.  Sweeps stop when a whole
 // sweep found no off-diagonal entry above the threshold.
 //
-// The matrix stays in LDS when it fits (m <= 128: 128 KB), otherwise in its
-// global buffer, where the workgroup's barriers order the accesses of its
-// threads (one workgroup, one L1).
+// The matrix and the accumulated rotations both stay in LDS when they fit
+// (m <= 90), the matrix alone when it does (m <= 128: 128 KB), otherwise they
+// live in their global buffers, where the workgroup's barriers order the
+// accesses of its threads (one workgroup, one L1).
 #include <cmath>
 
 #include "common.hpp"
@@ -167,6 +168,19 @@ __global__ __launch_bounds__(JT) void k_jacobi_eig(int m, double *A, double *V, 
     w += (int64_t)blockIdx.x * m;
     info += blockIdx.x;
     const double tol_abs = tol[blockIdx.x];
+    if (2 * mm <= JLDS_MAX * JLDS_MAX) {
+        // both the matrix and the accumulated rotations in LDS (m <= 90)
+        double *Vl = Tl + mm;
+        for (int it = threadIdx.x; it < m * m; it += JT) {
+            Tl[it] = A[it];
+            Vl[it] = ((it % m) == (it / m)) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        jacobi_rounds(m, Tl, Vl, w, info, tol_abs, cs_c, cs_s, cs_t, cs_a, pp, pq, &nrot);
+        __syncthreads();
+        for (int it = threadIdx.x; it < m * m; it += JT) V[it] = Vl[it];
+        return;
+    }
     for (int it = threadIdx.x; it < m * m; it += JT)
         V[it] = ((it % m) == (it / m)) ? 1.0 : 0.0;
     if (m <= JLDS_MAX) {
