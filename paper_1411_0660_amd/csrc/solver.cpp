@@ -1063,7 +1063,7 @@ void Context::refine(Plan &p, Factor<T> &f, int nrhs, const double *B, double *X
     double *r = d_r.ptr<double>(), *dd = d_d.ptr<double>();
     lu_apply<T>(p, f, nrhs, B, n, X, n);
     std::vector<double> part((size_t)RES_PARTS * nrhs * 3);
-    const double target = refine_target;
+    const double target = sizeof(T) == 8 ? refine_target : SOLVE_TARGET;
 
     double prev = 1e300;
     int it = 0;
@@ -1166,7 +1166,7 @@ void Context::refine_batch(Plan &p, Factor<T> &f, int nrhs, const double *B, dou
     lu_apply<T>(p, f, nrhs, B, N, X, N);
     count_pass();
     std::vector<double> part((size_t)RES_PARTS * nrhs * 3 * nseg), prev(nseg, 1e300), be(nseg, 0.0);
-    const double target = refine_target;
+    const double target = sizeof(T) == 8 ? refine_target : SOLVE_TARGET;
     for (int it = 0;; it++) {
         launch_residual_seg(nseg, n, p.rowptr.ptr<int32_t>(), p.col.ptr<int32_t>(), shifted, offv,
                             0.0, nrhs, B, X, r, d_part.ptr<double>(), RES_PARTS, s);
