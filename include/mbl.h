@@ -183,6 +183,19 @@ int mbl_spmv(mbl_ctx *ctx, int L, double J, const double *fields_host, int nvec,
 /* Extremal eigenvalues by Lanczos on H. */
 int mbl_extremal(mbl_ctx *ctx, int L, double J, const double *fields_host,
                  double *emin, double *emax);
+/* Eigenpairs of `count` dense symmetric matrices of order m (1 <= m <= 1024),
+ * the Rayleigh-Ritz step of the shift-invert Krylov iteration (section
+ * "Numerical method": the projected matrix), by the cyclic Jacobi method on the
+ * device, one workgroup per matrix.  A_host: count column-major m x m
+ * matrices, back to back (only the values are read; symmetry is assumed).
+ * Outputs: w_host[count * m], each matrix's eigenvalues ascending;
+ * Z_host[count * m * m], column j of matrix k's block = the unit eigenvector
+ * of w_host[k * m + j].  flags: 0, or MBL_EIG_GENERAL to run the kernel of
+ * orders above 90 also at smaller orders (it gives the same bits: a check of
+ * the two kernels).  MBL_ENUMERIC if a matrix needs more than 40 sweeps. */
+#define MBL_EIG_GENERAL 1
+int mbl_ritz_eig(mbl_ctx *ctx, int count, int m, const double *A_host, double *w_host,
+                 double *Z_host, int flags);
 /* Fill-reducing ordering and front tree for L (cached in the context). */
 int mbl_symbolic(mbl_ctx *ctx, int L, mbl_symbolic_info *info);
 /* Fill-reducing permutation: perm_host[k] = basis index eliminated k-th. */

@@ -23,6 +23,7 @@ MBL_ENUMERIC, MBL_EDEVICE, MBL_EBUSY, MBL_ENOTFOUND = -4, -5, -6, -7
 MBL_FP64, MBL_FP32_IR64 = 0, 1
 MBL_WANT_VECTORS, MBL_WANT_OBS, MBL_WANT_OBS_EXTRA = 1, 2, 4
 MBL_HOOK_IR_STALL32, MBL_HOOK_IR_STALL64, MBL_HOOK_NO_CONV = 0x100, 0x200, 0x400
+MBL_EIG_GENERAL = 1
 MBL_NBIN = 10
 BIN_NAMES = ("r", "s1", "s2", "se", "se2", "fluct", "dynfrac", "kl", "edens", "nconv")
 MBL_L_MAX = 22
@@ -30,8 +31,8 @@ MBL_L_MAX = 22
 # every symbol include/mbl.h declares
 EXPORTS = ("mbl_create", "mbl_destroy", "mbl_strerror", "mbl_last_error", "mbl_problem_init",
            "mbl_sector_dim", "mbl_fields", "mbl_basis", "mbl_rank", "mbl_hamiltonian",
-           "mbl_spmv", "mbl_extremal", "mbl_symbolic", "mbl_ordering", "mbl_front_tree",
-           "mbl_shift_solve",
+           "mbl_spmv", "mbl_extremal", "mbl_ritz_eig", "mbl_symbolic", "mbl_ordering",
+           "mbl_front_tree", "mbl_shift_solve",
            "mbl_observables", "mbl_observables_extra", "mbl_observables_noalloc", "mbl_solve",
            "mbl_solve_batch", "mbl_footprint",
            "mbl_serve_start", "mbl_serve_batch_limit", "mbl_submit", "mbl_poll", "mbl_wait", "mbl_serve_stats",
@@ -115,6 +116,7 @@ def lib() -> ctypes.CDLL:
                                   ctypes.POINTER(ctypes.c_int32), _pd, ctypes.POINTER(_i64)]
     L.mbl_spmv.argtypes = [vp, ctypes.c_int, _d, _pd, ctypes.c_int, _pd, _pd]
     L.mbl_extremal.argtypes = [vp, ctypes.c_int, _d, _pd, _pd, _pd]
+    L.mbl_ritz_eig.argtypes = [vp, ctypes.c_int, ctypes.c_int, _pd, _pd, _pd, ctypes.c_int]
     L.mbl_symbolic.argtypes = [vp, ctypes.c_int, ctypes.POINTER(mbl_symbolic_info)]
     L.mbl_ordering.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]
     _pi32 = ctypes.POINTER(ctypes.c_int32)
@@ -267,6 +269,23 @@ class Context:
         _check(lib().mbl_extremal(self._h, L, J, _pd_of(f), ctypes.byref(a), ctypes.byref(b)),
                "mbl_extremal")
         return a.value, b.value
+
+    def mbl_ritz_eig(self, A, general: bool = False):
+        """Eigenpairs of a batch of small symmetric matrices (count x m x m, or
+        one m x m): eigenvalues ascending (count x m) and unit eigenvectors
+        (count x m x m, column j for eigenvalue j)."""
+        A = np.asarray(A, dtype=np.float64)
+        one = A.ndim == 2
+        if one:
+            A = A[None]
+        count, m = A.shape[0], A.shape[1]
+        Af = np.ascontiguousarray(np.transpose(A, (0, 2, 1)))        # column-major blocks
+        w = np.zeros((count, m))
+        Z = np.zeros((count, m, m))
+        _check(lib().mbl_ritz_eig(self._h, count, m, _pd_of(Af), _pd_of(w), _pd_of(Z),
+                                  MBL_EIG_GENERAL if general else 0), "mbl_ritz_eig")
+        Z = np.transpose(Z, (0, 2, 1))
+        return (w[0], Z[0]) if one else (w, Z)
 
     def mbl_symbolic(self, L: int) -> dict:
         info = mbl_symbolic_info()

@@ -212,6 +212,26 @@ int mbl_extremal(mbl_ctx *ctx, int L, double J, const double *fields_host, doubl
     });
 }
 
+int mbl_ritz_eig(mbl_ctx *ctx, int count, int m, const double *A_host, double *w_host,
+                 double *Z_host, int flags) {
+    if (!ctx || count < 0 || m < 1 || m > 1024 || (flags & ~MBL_EIG_GENERAL)) return MBL_EINVAL;
+    if (count > 0 && (!A_host || !w_host || !Z_host)) return MBL_EINVAL;
+    return guarded([&] {
+        std::lock_guard<std::recursive_mutex> lk(ctx->c->mu);
+        Context &c = *ctx->c;
+        MBL_HIP(hipSetDevice(c.device));
+        if (count == 0) return;
+        const size_t mm = (size_t)m * m;
+        std::vector<std::vector<double>> A(count), w, Z;
+        for (int k = 0; k < count; k++) A[k].assign(A_host + mm * k, A_host + mm * (k + 1));
+        c.small_eig_batch(count, m, A, w, Z, (flags & MBL_EIG_GENERAL) != 0);
+        for (int k = 0; k < count; k++) {
+            std::copy(w[k].begin(), w[k].end(), w_host + (size_t)m * k);
+            std::copy(Z[k].begin(), Z[k].end(), Z_host + mm * k);
+        }
+    });
+}
+
 int mbl_symbolic(mbl_ctx *ctx, int L, mbl_symbolic_info *info) {
     if (!ctx) return MBL_EINVAL;
     return guarded([&] {

@@ -14,14 +14,25 @@
 // the accumulated vectors V by one thread per row.  Sweeps stop when a whole
 // sweep found no off-diagonal entry above the threshold.
 //
-// The matrix and the accumulated rotations both stay in LDS when they fit
-// (m <= 90), the matrix alone when it does (m <= 128: 128 KB), otherwise they
-// live in their global buffers, where the workgroup's barriers order the
-// accesses of its threads (one workgroup, one L1).
+// Orders up to 90 (the projected matrices of nev up to about 40) run in
+// k_jacobi_lds: matrix and accumulated rotations both in LDS, the matrix with
+// an odd leading dimension (few bank conflicts along rows as along columns),
+// work found through tables, every thread's loads of a round issued before
+// its stores.
+// Larger orders run in k_jacobi_eig: the matrix in LDS when it fits (m <= 128:
+// 128 KB), otherwise both in their global buffers, where the workgroup's
+// barriers order the accesses of its threads (one workgroup, one L1).  Both
+// kernels apply the same rotations with the same arithmetic, element by
+// element, so they give the same results bit for bit.
 #include <cmath>
 
 #include "common.hpp"
 #include "kernels.hpp"
+
+// Every fused multiply-add below is written out; no other is formed, so the
+// rounding of each update is fixed by the source and the two kernels, which
+// apply the same rotations, agree bit for bit.
+#pragma clang fp contract(off)
 
 namespace mbl {
 namespace {
@@ -40,6 +51,19 @@ __device__ __forceinline__ void round_pair(int mp, int r, int k, int &p, int &q)
     int b = 1 + (kb - 1 + r) % rot;     // kb >= 1 for every k < mp / 2
     p = min(a, b);
     q = max(a, b);
+}
+
+// J_1^T [x y; z u] J_2 for the 2 x 2 block of rows (p1, q1) and columns
+// (p2, q2): the column pair rotated by (c2, s2), then the row pair by (c1, s1)
+__device__ __forceinline__ void rotate_block(double c1, double s1, double c2, double s2, double x,
+                                             double y, double z, double u, double &x2, double &y2,
+                                             double &z2, double &u2) {
+    const double x1 = fma(c2, x, -(s2 * y)), y1 = fma(s2, x, c2 * y);
+    const double z1 = fma(c2, z, -(s2 * u)), u1 = fma(s2, z, c2 * u);
+    x2 = fma(c1, x1, -(s1 * z1));
+    z2 = fma(s1, x1, c1 * z1);
+    y2 = fma(c1, y1, -(s1 * u1));
+    u2 = fma(s1, y1, c1 * u1);
 }
 
 // Inlined at two call sites (matrix in LDS, matrix in global memory), so each
@@ -66,8 +90,8 @@ __device__ __forceinline__ void jacobi_rounds(int m, double *T, double *V, doubl
                         double theta = (aqq - app) / (2.0 * apq);
                         double at = fabs(theta);
                         t = (at > 1e150) ? 0.5 / theta
-                                         : copysign(1.0, theta) / (at + sqrt(theta * theta + 1.0));
-                        c = 1.0 / sqrt(t * t + 1.0);
+                                         : copysign(1.0, theta) / (at + sqrt(fma(theta, theta, 1.0)));
+                        c = 1.0 / sqrt(fma(t, t, 1.0));
                         s = t * c;
                     }
                 }
@@ -90,8 +114,8 @@ __device__ __forceinline__ void jacobi_rounds(int m, double *T, double *V, doubl
                 const int p1 = pp[k1], q1 = pq[k1], p2 = pp[k2], q2 = pq[k2];
                 if (k1 == k2) {                  // the rotated pair itself: diagonalised
                     const double t = cs_t[k1], apq = cs_a[k1];
-                    T[p1 + (int64_t)p1 * m] -= t * apq;
-                    T[q1 + (int64_t)q1 * m] += t * apq;
+                    T[p1 + (int64_t)p1 * m] = fma(-t, apq, T[p1 + (int64_t)p1 * m]);
+                    T[q1 + (int64_t)q1 * m] = fma(t, apq, T[q1 + (int64_t)q1 * m]);
                     T[p1 + (int64_t)q1 * m] = 0.0;
                     T[q1 + (int64_t)p1 * m] = 0.0;
                     continue;
@@ -102,12 +126,8 @@ __device__ __forceinline__ void jacobi_rounds(int m, double *T, double *V, doubl
                 double y = vq2 ? T[p1 + (int64_t)q2 * m] : 0.0;
                 double z = vq1 ? T[q1 + (int64_t)p2 * m] : 0.0;
                 double u = (vq1 && vq2) ? T[q1 + (int64_t)q2 * m] : 0.0;
-                // columns (p2, q2)
-                double x1 = c2 * x - s2 * y, y1 = s2 * x + c2 * y;
-                double z1 = c2 * z - s2 * u, u1 = s2 * z + c2 * u;
-                // rows (p1, q1)
-                double x2 = c1 * x1 - s1 * z1, z2 = s1 * x1 + c1 * z1;
-                double y2 = c1 * y1 - s1 * u1, u2 = s1 * y1 + c1 * u1;
+                double x2, y2, z2, u2;
+                rotate_block(c1, s1, c2, s2, x, y, z, u, x2, y2, z2, u2);
                 T[p1 + (int64_t)p2 * m] = x2;
                 T[p2 + (int64_t)p1 * m] = x2;
                 if (vq2) { T[p1 + (int64_t)q2 * m] = y2; T[q2 + (int64_t)p1 * m] = y2; }
@@ -139,8 +159,8 @@ __device__ __forceinline__ void jacobi_rounds(int m, double *T, double *V, doubl
                     const double s = cs_s[k];
                     if (s == 0.0) continue;
                     const double c = cs_c[k];
-                    V[(int64_t)pp[k] * m + i] = c * va[u] - s * vb[u];
-                    V[(int64_t)pq[k] * m + i] = s * va[u] + c * vb[u];
+                    V[(int64_t)pp[k] * m + i] = fma(c, va[u], -(s * vb[u]));
+                    V[(int64_t)pq[k] * m + i] = fma(s, va[u], c * vb[u]);
                 }
             }
             __syncthreads();
@@ -193,13 +213,191 @@ __global__ __launch_bounds__(JT) void k_jacobi_eig(int m, double *A, double *V, 
     }
 }
 
+constexpr int JL_T = 1024;              // threads of the LDS kernel
+constexpr int JL_MAX = 90;              // largest order it takes
+constexpr int JL_NH = JL_MAX / 2;       // pairs of a round at that order
+constexpr int JL_ITEMS = JL_NH * (JL_NH + 1) / 2;
+constexpr int JL_IT = (JL_ITEMS + JL_T - 1) / JL_T;      // 2 x 2 blocks per thread
+constexpr int JL_VI = (JL_MAX * JL_NH + JL_T - 1) / JL_T; // V items per thread
+static_assert(JL_NH <= 64, "the rotations of a round are computed by one wave");
+static_assert(JL_NH < 256, "item table packs two pair indices in 8 bits each");
+
+// Pair k (< mp / 2) of round r of the circle schedule over mp (even) indices.
+__device__ __forceinline__ void circle_pair(int mp, int r, int k, int &p, int &q) {
+    const int rot = mp - 1;
+    int a = 0;
+    if (k > 0) {
+        a = k - 1 + r;
+        if (a >= rot) a -= rot;
+        a += 1;
+    }
+    int b = mp - 2 - k + r;
+    if (b >= rot) b -= rot;
+    b += 1;
+    p = min(a, b);
+    q = max(a, b);
+}
+
+// Same contract and results as k_jacobi_eig, for m <= JL_MAX.  The matrix is
+// kept with an odd leading dimension ld, so that a row of it, like a column,
+// spreads over the LDS banks: the 2 x 2 block update reads blocks along
+// columns and stores their transposes along rows.  The blocks (and the V
+// items) are numbered once, in tables, so a thread finds its work without
+// division; each thread issues all loads of its items before any store.
+__global__ __launch_bounds__(JL_T) void k_jacobi_lds(int m, const double *A, double *V, double *w,
+                                                     int *info, const double *tol) {
+    __shared__ double T[JL_MAX * (JL_MAX + 1)], Vl[JL_MAX * JL_MAX];
+    __shared__ double2 cs[JL_NH], ta[JL_NH];       // (c, s) and (t, a_pq) of each pair
+    __shared__ int pp[JL_NH], pq[JL_NH];
+    __shared__ uint16_t item[JL_ITEMS];            // block k1 | k2 << 8, k1 <= k2
+    __shared__ int moved;
+    const int64_t mm = (int64_t)m * m;
+    A += blockIdx.x * mm;
+    V += blockIdx.x * mm;
+    w += (int64_t)blockIdx.x * m;
+    info += blockIdx.x;
+    const double tol_abs = tol[blockIdx.x];
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int mp = m + (m & 1), nh = mp / 2, rot = mp - 1, ld = m | 1;
+    const int nitems = nh * (nh + 1) / 2, nvi = m * nh;
+    for (int it = tid; it < m * m; it += JL_T) {
+        const int i = it % m, j = it / m;
+        T[i + j * ld] = A[it];
+        Vl[it] = (i == j) ? 1.0 : 0.0;
+    }
+    for (int it = tid; it < nitems; it += JL_T) {
+        int k2 = (int)((sqrtf(8.0f * (float)it + 1.0f) - 1.0f) * 0.5f);
+        while (k2 * (k2 + 1) / 2 > it) k2--;
+        while ((k2 + 1) * (k2 + 2) / 2 <= it) k2++;
+        item[it] = (uint16_t)((it - k2 * (k2 + 1) / 2) | (k2 << 8));
+    }
+    // V items of this thread: row vi_i[j] of pair vi_k[j] (-1: none)
+    int vi_i[JL_VI], vi_k[JL_VI];
+#pragma unroll
+    for (int j = 0; j < JL_VI; j++) {
+        const int it = tid + j * JL_T;
+        vi_i[j] = it < nvi ? it % m : 0;
+        vi_k[j] = it < nvi ? it / m : -1;
+    }
+    int sweep = 0;
+    for (; sweep < JMAX_SWEEPS; sweep++) {
+        if (tid == 0) moved = 0;
+        __syncthreads();
+        for (int r = 0; r < rot; r++) {
+            if (wv == 0) {
+                double c = 1.0, s = 0.0, t = 0.0, apq = 0.0;
+                if (lane < nh) {
+                    int p, q;
+                    circle_pair(mp, r, lane, p, q);
+                    if (q < m) {
+                        apq = T[p + q * ld];
+                        if (fabs(apq) > tol_abs) {
+                            double app = T[p + p * ld], aqq = T[q + q * ld];
+                            double theta = (aqq - app) / (2.0 * apq);
+                            double at = fabs(theta);
+                            t = (at > 1e150) ? 0.5 / theta
+                                             : copysign(1.0, theta) /
+                                                   (at + sqrt(fma(theta, theta, 1.0)));
+                            c = 1.0 / sqrt(fma(t, t, 1.0));
+                            s = t * c;
+                        }
+                    }
+                    cs[lane] = make_double2(c, s);
+                    ta[lane] = make_double2(t, apq);
+                    pp[lane] = p;
+                    pq[lane] = q;
+                }
+                if (__ballot(s != 0.0) && lane == 0) moved = 1;
+            }
+            __syncthreads();
+            // T <- J^T T J by 2 x 2 blocks: all loads first (the blocks of a
+            // round are disjoint), then the stores
+            {
+                double x[JL_IT], y[JL_IT], z[JL_IT], u[JL_IT];
+                int kk[JL_IT];
+#pragma unroll
+                for (int j = 0; j < JL_IT; j++) {
+                    const int it = tid + j * JL_T;
+                    kk[j] = -1;
+                    if (it >= nitems) continue;
+                    const int k1 = item[it] & 255, k2 = item[it] >> 8;
+                    if (cs[k1].y == 0.0 && cs[k2].y == 0.0) continue;
+                    kk[j] = item[it];
+                    if (k1 == k2) continue;
+                    const int p1 = pp[k1], q1 = pq[k1], p2 = pp[k2], q2 = pq[k2];
+                    const bool vq1 = q1 < m, vq2 = q2 < m;
+                    x[j] = T[p1 + p2 * ld];
+                    y[j] = vq2 ? T[p1 + q2 * ld] : 0.0;
+                    z[j] = vq1 ? T[q1 + p2 * ld] : 0.0;
+                    u[j] = (vq1 && vq2) ? T[q1 + q2 * ld] : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < JL_IT; j++) {
+                    if (kk[j] < 0) continue;
+                    const int k1 = kk[j] & 255, k2 = kk[j] >> 8;
+                    const int p1 = pp[k1], q1 = pq[k1];
+                    if (k1 == k2) {              // the rotated pair itself: diagonalised
+                        const double2 tq = ta[k1];
+                        T[p1 + p1 * ld] = fma(-tq.x, tq.y, T[p1 + p1 * ld]);
+                        T[q1 + q1 * ld] = fma(tq.x, tq.y, T[q1 + q1 * ld]);
+                        T[p1 + q1 * ld] = 0.0;
+                        T[q1 + p1 * ld] = 0.0;
+                        continue;
+                    }
+                    const int p2 = pp[k2], q2 = pq[k2];
+                    const bool vq1 = q1 < m, vq2 = q2 < m;
+                    const double2 r1 = cs[k1], r2 = cs[k2];
+                    double x2, y2, z2, u2;
+                    rotate_block(r1.x, r1.y, r2.x, r2.y, x[j], y[j], z[j], u[j], x2, y2, z2, u2);
+                    T[p1 + p2 * ld] = x2;
+                    T[p2 + p1 * ld] = x2;
+                    if (vq2) { T[p1 + q2 * ld] = y2; T[q2 + p1 * ld] = y2; }
+                    if (vq1) { T[q1 + p2 * ld] = z2; T[p2 + q1 * ld] = z2; }
+                    if (vq1 && vq2) { T[q1 + q2 * ld] = u2; T[q2 + q1 * ld] = u2; }
+                }
+            }
+            // V <- V J, one row of one column pair per item
+            {
+                double va[JL_VI], vb[JL_VI];
+#pragma unroll
+                for (int j = 0; j < JL_VI; j++) {
+                    va[j] = vb[j] = 0.0;
+                    const int k = vi_k[j];
+                    if (k >= 0 && cs[k].y != 0.0) {
+                        va[j] = Vl[pp[k] * m + vi_i[j]];
+                        vb[j] = Vl[pq[k] * m + vi_i[j]];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < JL_VI; j++) {
+                    const int k = vi_k[j];
+                    if (k < 0) continue;
+                    const double2 r2 = cs[k];
+                    if (r2.y == 0.0) continue;
+                    Vl[pp[k] * m + vi_i[j]] = fma(r2.x, va[j], -(r2.y * vb[j]));
+                    Vl[pq[k] * m + vi_i[j]] = fma(r2.y, va[j], r2.x * vb[j]);
+                }
+            }
+            __syncthreads();
+        }
+        if (moved == 0) break;
+        __syncthreads();
+    }
+    for (int i = tid; i < m; i += JL_T) w[i] = T[i + i * ld];
+    for (int it = tid; it < m * m; it += JL_T) V[it] = Vl[it];
+    if (tid == 0) *info = (sweep < JMAX_SWEEPS) ? sweep : -1;
+}
+
 }  // namespace
 
 void launch_jacobi_eig_batch(int count, int m, double *A, double *V, double *w, int *info,
-                             const double *tol_abs, hipStream_t s) {
+                             const double *tol_abs, hipStream_t s, bool general) {
     MBL_REQUIRE(m >= 1 && m <= JMAX, MBL_EINVAL, "Jacobi eigensolver: order out of range");
     if (count == 0) return;
-    hipLaunchKernelGGL(k_jacobi_eig, dim3(count), dim3(JT), 0, s, m, A, V, w, info, tol_abs);
+    if (m <= JL_MAX && !general)
+        hipLaunchKernelGGL(k_jacobi_lds, dim3(count), dim3(JL_T), 0, s, m, A, V, w, info, tol_abs);
+    else
+        hipLaunchKernelGGL(k_jacobi_eig, dim3(count), dim3(JT), 0, s, m, A, V, w, info, tol_abs);
     MBL_CHECK_LAUNCH();
 }
 

@@ -1240,7 +1240,7 @@ void Context::shift_solve_batch(Plan &bp, int prec, int nrhs, const double *B, d
 // (m x m) the unit eigenvectors in the same order.
 void Context::small_eig_batch(int count, int m, const std::vector<std::vector<double>> &A,
                               std::vector<std::vector<double>> &w,
-                              std::vector<std::vector<double>> &Z) {
+                              std::vector<std::vector<double>> &Z, bool general) {
     hipStream_t s = stream;
     const size_t mm = (size_t)m * m;
     d_ritz.ensure(sizeof(double) * ((2 * mm + m + 2) * (size_t)count + 8), &budget);
@@ -1257,7 +1257,7 @@ void Context::small_eig_batch(int count, int m, const std::vector<std::vector<do
         h2d(dA + mm * k, A[k].data(), mm, s);
     }
     h2d(dtol, tol.data(), (size_t)count, s);
-    launch_jacobi_eig_batch(count, m, dA, dV, dw, dinfo, dtol, s);
+    launch_jacobi_eig_batch(count, m, dA, dV, dw, dinfo, dtol, s, general);
     std::vector<double> wu((size_t)m * count), Vu(mm * count);
     std::vector<int> info(count);
     d2h(wu.data(), dw, wu.size(), s);

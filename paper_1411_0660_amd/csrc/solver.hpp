@@ -179,7 +179,7 @@ class Context {
     // device Jacobi, one workgroup each)
     void small_eig_batch(int count, int m, const std::vector<std::vector<double>> &A,
                          std::vector<std::vector<double>> &w,
-                         std::vector<std::vector<double>> &Z);
+                         std::vector<std::vector<double>> &Z, bool general = false);
     // block Krylov-Schur on nseg problems of order n with packed vectors (ld
     // nseg n); conv(problem, theta, rho); seeds[nseg]; out: nseg n x nwant
     // op(X, Y, nb, finished): Y = Op X for nb packed columns; finished[s] != 0

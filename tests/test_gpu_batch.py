@@ -167,3 +167,31 @@ def test_problem_leaving_the_batch(ctx):
     assert [o["batch"] for o in out[:2]] == [3, 3]
     a = ctx.mbl_solve(L, its[0]["h"], its[0]["seed"], its[0]["eps"], nev)
     assert np.array_equal(out[0]["evals"], a["evals"])
+
+
+def test_batch_graph_replays_match_eager(ctx):
+    """Block expansions of the Krylov and extremal-energy iterations run as
+    captured graphs, replayed at every expansion with host reads of their
+    staged coefficients between the replays; batches solved twice in one
+    context (so the second call replays graphs captured by the first) equal
+    the eager launch sequence bitwise."""
+    import os
+    sets = [(12, 5, mbl.MBL_FP64), (14, 3, mbl.MBL_FP32_IR64)]
+    graphed = []
+    for L, count, prec in sets:
+        its = items(count, 40 + L)
+        first = ctx.mbl_solve_batch(L, 16, its, prec=prec, vectors=True, extra=True)
+        again = ctx.mbl_solve_batch(L, 16, its, prec=prec, vectors=True, extra=True)
+        for a, b in zip(first, again):
+            assert_same(a, b, ("replay", L))
+        graphed.append((L, its, prec, first))
+    os.environ["MBL_NO_GRAPH"] = "1"
+    try:
+        eager = mbl.Context(0)
+    finally:
+        del os.environ["MBL_NO_GRAPH"]
+    with eager:
+        for L, its, prec, first in graphed:
+            out = eager.mbl_solve_batch(L, 16, its, prec=prec, vectors=True, extra=True)
+            for a, b in zip(first, out):
+                assert_same(a, b, ("eager", L))
