@@ -191,7 +191,7 @@ int mbl_extremal(mbl_ctx *ctx, int L, double J, const double *fields_host,
  * Outputs: w_host[count * m], each matrix's eigenvalues ascending;
  * Z_host[count * m * m], column j of matrix k's block = the unit eigenvector
  * of w_host[k * m + j].  flags: 0, or MBL_EIG_GENERAL to run the kernel of
- * orders above 90 also at smaller orders (it gives the same bits: a check of
+ * orders above 128 also at smaller orders (it gives the same bits: a check of
  * the two kernels).  MBL_ENUMERIC if a matrix needs more than 40 sweeps. */
 #define MBL_EIG_GENERAL 1
 int mbl_ritz_eig(mbl_ctx *ctx, int count, int m, const double *A_host, double *w_host,

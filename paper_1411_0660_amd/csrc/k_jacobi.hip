@@ -14,16 +14,15 @@
 // the accumulated vectors V by one thread per row.  Sweeps stop when a whole
 // sweep found no off-diagonal entry above the threshold.
 //
-// Orders up to 90 (the projected matrices of nev up to about 40) run in
-// k_jacobi_lds: matrix and accumulated rotations both in LDS, the matrix with
-// an odd leading dimension (few bank conflicts along rows as along columns),
-// work found through tables, every thread's loads of a round issued before
-// its stores.
-// Larger orders run in k_jacobi_eig: the matrix in LDS when it fits (m <= 128:
-// 128 KB), otherwise both in their global buffers, where the workgroup's
-// barriers order the accesses of its threads (one workgroup, one L1).  Both
-// kernels apply the same rotations with the same arithmetic, element by
-// element, so they give the same results bit for bit.
+// Orders up to 128 (the projected matrices of nev up to about 55) run in
+// k_jacobi_lds: the matrix in LDS with an odd leading dimension (few bank
+// conflicts along rows as along columns), the accumulated rotations in LDS
+// too up to order 90, work found through tables, every thread's loads of a
+// round issued before its stores.
+// Larger orders run in k_jacobi_eig, with the matrix and the rotations in
+// their global buffers (it also keeps the matrix in LDS when asked to run an
+// order up to 128).  Both kernels apply the same rotations with the same
+// arithmetic, element by element, so they give the same results bit for bit.
 #include <cmath>
 
 #include "common.hpp"
@@ -214,13 +213,8 @@ __global__ __launch_bounds__(JT) void k_jacobi_eig(int m, double *A, double *V, 
 }
 
 constexpr int JL_T = 1024;              // threads of the LDS kernel
-constexpr int JL_MAX = 90;              // largest order it takes
-constexpr int JL_NH = JL_MAX / 2;       // pairs of a round at that order
-constexpr int JL_ITEMS = JL_NH * (JL_NH + 1) / 2;
-constexpr int JL_IT = (JL_ITEMS + JL_T - 1) / JL_T;      // 2 x 2 blocks per thread
-constexpr int JL_VI = (JL_MAX * JL_NH + JL_T - 1) / JL_T; // V items per thread
-static_assert(JL_NH <= 64, "the rotations of a round are computed by one wave");
-static_assert(JL_NH < 256, "item table packs two pair indices in 8 bits each");
+constexpr int JL_VMAX = 90;             // largest order with the rotations in LDS too
+constexpr int JL_MAX = 128;             // largest order of the matrix in LDS
 
 // Pair k (< mp / 2) of round r of the circle schedule over mp (even) indices.
 __device__ __forceinline__ void circle_pair(int mp, int r, int k, int &p, int &q) {
@@ -238,18 +232,28 @@ __device__ __forceinline__ void circle_pair(int mp, int r, int k, int &p, int &q
     q = max(a, b);
 }
 
-// Same contract and results as k_jacobi_eig, for m <= JL_MAX.  The matrix is
+// Same contract and results as k_jacobi_eig, for m <= MAXM.  The matrix is
 // kept with an odd leading dimension ld, so that a row of it, like a column,
 // spreads over the LDS banks: the 2 x 2 block update reads blocks along
-// columns and stores their transposes along rows.  The blocks (and the V
-// items) are numbered once, in tables, so a thread finds its work without
-// division; each thread issues all loads of its items before any store.
+// columns and stores their transposes along rows.  The accumulated rotations
+// are in LDS too (VL) when both fit, else in their global buffer (the
+// workgroup's barriers order its threads' accesses: one workgroup, one L1).
+// The blocks (and the V items) are numbered once, in tables, so a thread
+// finds its work without division; each thread issues all loads of its items
+// before any store.
+template <int MAXM, bool VL>
 __global__ __launch_bounds__(JL_T) void k_jacobi_lds(int m, const double *A, double *V, double *w,
                                                      int *info, const double *tol) {
-    __shared__ double T[JL_MAX * (JL_MAX + 1)], Vl[JL_MAX * JL_MAX];
-    __shared__ double2 cs[JL_NH], ta[JL_NH];       // (c, s) and (t, a_pq) of each pair
-    __shared__ int pp[JL_NH], pq[JL_NH];
-    __shared__ uint16_t item[JL_ITEMS];            // block k1 | k2 << 8, k1 <= k2
+    constexpr int NH = MAXM / 2;                              // pairs of a round
+    constexpr int ITEMS = NH * (NH + 1) / 2;
+    constexpr int IT = (ITEMS + JL_T - 1) / JL_T;             // 2 x 2 blocks per thread
+    constexpr int VI = (MAXM * NH + JL_T - 1) / JL_T;         // V items per thread
+    static_assert(NH <= 64, "the rotations of a round are computed by one wave");
+    static_assert(NH < 256, "item table packs two pair indices in 8 bits each");
+    __shared__ double T[MAXM * (MAXM + 1)], Vs[VL ? MAXM * MAXM : 1];
+    __shared__ double2 cs[NH], ta[NH];             // (c, s) and (t, a_pq) of each pair
+    __shared__ int pp[NH], pq[NH];
+    __shared__ uint16_t item[ITEMS];               // block k1 | k2 << 8, k1 <= k2
     __shared__ int moved;
     const int64_t mm = (int64_t)m * m;
     A += blockIdx.x * mm;
@@ -260,6 +264,7 @@ __global__ __launch_bounds__(JL_T) void k_jacobi_lds(int m, const double *A, dou
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int mp = m + (m & 1), nh = mp / 2, rot = mp - 1, ld = m | 1;
     const int nitems = nh * (nh + 1) / 2, nvi = m * nh;
+    double *Vl = VL ? Vs : V;
     for (int it = tid; it < m * m; it += JL_T) {
         const int i = it % m, j = it / m;
         T[i + j * ld] = A[it];
@@ -272,9 +277,9 @@ __global__ __launch_bounds__(JL_T) void k_jacobi_lds(int m, const double *A, dou
         item[it] = (uint16_t)((it - k2 * (k2 + 1) / 2) | (k2 << 8));
     }
     // V items of this thread: row vi_i[j] of pair vi_k[j] (-1: none)
-    int vi_i[JL_VI], vi_k[JL_VI];
+    int vi_i[VI], vi_k[VI];
 #pragma unroll
-    for (int j = 0; j < JL_VI; j++) {
+    for (int j = 0; j < VI; j++) {
         const int it = tid + j * JL_T;
         vi_i[j] = it < nvi ? it % m : 0;
         vi_k[j] = it < nvi ? it / m : -1;
@@ -313,10 +318,10 @@ __global__ __launch_bounds__(JL_T) void k_jacobi_lds(int m, const double *A, dou
             // T <- J^T T J by 2 x 2 blocks: all loads first (the blocks of a
             // round are disjoint), then the stores
             {
-                double x[JL_IT], y[JL_IT], z[JL_IT], u[JL_IT];
-                int kk[JL_IT];
+                double x[IT], y[IT], z[IT], u[IT];
+                int kk[IT];
 #pragma unroll
-                for (int j = 0; j < JL_IT; j++) {
+                for (int j = 0; j < IT; j++) {
                     const int it = tid + j * JL_T;
                     kk[j] = -1;
                     if (it >= nitems) continue;
@@ -332,7 +337,7 @@ __global__ __launch_bounds__(JL_T) void k_jacobi_lds(int m, const double *A, dou
                     u[j] = (vq1 && vq2) ? T[q1 + q2 * ld] : 0.0;
                 }
 #pragma unroll
-                for (int j = 0; j < JL_IT; j++) {
+                for (int j = 0; j < IT; j++) {
                     if (kk[j] < 0) continue;
                     const int k1 = kk[j] & 255, k2 = kk[j] >> 8;
                     const int p1 = pp[k1], q1 = pq[k1];
@@ -358,9 +363,9 @@ __global__ __launch_bounds__(JL_T) void k_jacobi_lds(int m, const double *A, dou
             }
             // V <- V J, one row of one column pair per item
             {
-                double va[JL_VI], vb[JL_VI];
+                double va[VI], vb[VI];
 #pragma unroll
-                for (int j = 0; j < JL_VI; j++) {
+                for (int j = 0; j < VI; j++) {
                     va[j] = vb[j] = 0.0;
                     const int k = vi_k[j];
                     if (k >= 0 && cs[k].y != 0.0) {
@@ -369,7 +374,7 @@ __global__ __launch_bounds__(JL_T) void k_jacobi_lds(int m, const double *A, dou
                     }
                 }
 #pragma unroll
-                for (int j = 0; j < JL_VI; j++) {
+                for (int j = 0; j < VI; j++) {
                     const int k = vi_k[j];
                     if (k < 0) continue;
                     const double2 r2 = cs[k];
@@ -384,7 +389,8 @@ __global__ __launch_bounds__(JL_T) void k_jacobi_lds(int m, const double *A, dou
         __syncthreads();
     }
     for (int i = tid; i < m; i += JL_T) w[i] = T[i + i * ld];
-    for (int it = tid; it < m * m; it += JL_T) V[it] = Vl[it];
+    if (VL)
+        for (int it = tid; it < m * m; it += JL_T) V[it] = Vl[it];
     if (tid == 0) *info = (sweep < JMAX_SWEEPS) ? sweep : -1;
 }
 
@@ -394,8 +400,12 @@ void launch_jacobi_eig_batch(int count, int m, double *A, double *V, double *w, 
                              const double *tol_abs, hipStream_t s, bool general) {
     MBL_REQUIRE(m >= 1 && m <= JMAX, MBL_EINVAL, "Jacobi eigensolver: order out of range");
     if (count == 0) return;
-    if (m <= JL_MAX && !general)
-        hipLaunchKernelGGL(k_jacobi_lds, dim3(count), dim3(JL_T), 0, s, m, A, V, w, info, tol_abs);
+    if (m <= JL_VMAX && !general)
+        hipLaunchKernelGGL((k_jacobi_lds<JL_VMAX, true>), dim3(count), dim3(JL_T), 0, s, m, A, V, w,
+                           info, tol_abs);
+    else if (m <= JL_MAX && !general)
+        hipLaunchKernelGGL((k_jacobi_lds<JL_MAX, false>), dim3(count), dim3(JL_T), 0, s, m, A, V, w,
+                           info, tol_abs);
     else
         hipLaunchKernelGGL(k_jacobi_eig, dim3(count), dim3(JT), 0, s, m, A, V, w, info, tol_abs);
     MBL_CHECK_LAUNCH();

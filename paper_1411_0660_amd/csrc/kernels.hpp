@@ -104,7 +104,7 @@ void launch_sub_scaled_cols(int64_t n, int ncol, const double *e, const double *
 // m <= 1024.
 // count independent matrices at strides m^2 (A, V), m (w), 1 (info), each
 // with its own threshold tol_abs[k] (device), one workgroup each.  general:
-// use the kernel of the larger orders also for m <= 90 (same results; a
+// use the kernel of the larger orders also for m <= 128 (same results; a
 // check of the two kernels against each other)
 void launch_jacobi_eig_batch(int count, int m, double *A, double *V, double *w, int *info,
                              const double *tol_abs, hipStream_t s, bool general = false);

@@ -1,8 +1,8 @@
 """The Rayleigh-Ritz eigensolver of the Krylov iteration (mbl_ritz_eig): the
 device Jacobi kernels against the oracle's Householder + QL eigenvalues, the
 eigenpair residual and orthogonality of the returned vectors, and the two
-kernels (orders up to 90 in LDS, the general one) against each other bit for
-bit.  Matrices: dense random, degenerate (repeated eigenvalues in a random
+kernels (orders up to 128 in LDS, the general one) against each other bit
+for bit.  Matrices: dense random, degenerate (repeated eigenvalues in a random
 basis), and the shape of a restarted Krylov-Schur projection (diagonal of kept
 Ritz values, a coupling row block, then block-tridiagonal expansion blocks)."""
 import sys
@@ -78,10 +78,11 @@ def test_eigenpairs(ctx, kind, m):
     assert np.abs(Z.T @ Z - np.eye(m)).max() <= 1e-13
 
 
-@pytest.mark.parametrize("m", [2, 5, 33, 60, 64, 68, 90])
+@pytest.mark.parametrize("m", [2, 5, 33, 60, 64, 68, 90, 91, 101, 127, 128])
 def test_lds_kernel_equals_general_kernel(ctx, m):
-    """Orders up to 90 run in the LDS kernel; the general kernel applies the
-    same rotations with the same arithmetic, so the bits agree."""
+    """Orders up to 128 run in the LDS kernel (rotations in LDS up to 90, in
+    global memory above); the general kernel applies the same rotations with
+    the same arithmetic, so the bits agree."""
     rng = np.random.default_rng(m)
     As = np.stack([KINDS[k](m, rng) for k in sorted(KINDS)])
     w1, Z1 = ctx.mbl_ritz_eig(As)
