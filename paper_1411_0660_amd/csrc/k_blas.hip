@@ -390,12 +390,12 @@ __global__ __launch_bounds__(BS) void k_bcomb(int64_t n, int nb, int nrhs,
 // floored there, so the factor stays finite).
 __global__ void k_small_chol(int b, const double *__restrict__ G, double *__restrict__ Rout,
                              double *__restrict__ Rinv, int *__restrict__ flag, double rel_tiny,
-                             int64_t segG, int64_t segR, int64_t segF) {
+                             int64_t segG, int64_t segR, int64_t segRi, int64_t segF) {
     __shared__ double R[16 * 16], Ri[16 * 16];
     if (threadIdx.x != 0) return;
     G += blockIdx.x * segG;                          // matrix blockIdx.x
     Rout += blockIdx.x * segR;
-    Rinv += blockIdx.x * segR;
+    Rinv += blockIdx.x * segRi;
     flag += blockIdx.x * segF;
     double dmax = 0.0;
     for (int i = 0; i < b; i++) dmax = fmax(dmax, G[i * b + i]);
@@ -457,17 +457,18 @@ void launch_sub_scaled_cols(int64_t n, int ncol, const double *e, const double *
 }
 
 void launch_small_chol_batch(int count, int b, const double *G, int64_t segG, double *R,
-                             double *Rinv, int64_t segR, int *flag, int64_t segF, double rel_tiny,
-                             hipStream_t s) {
+                             int64_t segR, double *Rinv, int64_t segRi, int *flag, int64_t segF,
+                             double rel_tiny, hipStream_t s) {
     MBL_REQUIRE(b >= 1 && b <= 16, MBL_EINVAL, "small_chol: b must be 1..16");
     if (count == 0) return;
-    k_small_chol<<<dim3(count), dim3(64), 0, s>>>(b, G, R, Rinv, flag, rel_tiny, segG, segR, segF);
+    k_small_chol<<<dim3(count), dim3(64), 0, s>>>(b, G, R, Rinv, flag, rel_tiny, segG, segR, segRi,
+                                                  segF);
     MBL_CHECK_LAUNCH();
 }
 
 void launch_small_chol(int b, const double *G, double *R, double *Rinv, int *flag,
                        double rel_tiny, hipStream_t s) {
-    launch_small_chol_batch(1, b, G, 0, R, Rinv, 0, flag, 0, rel_tiny, s);
+    launch_small_chol_batch(1, b, G, 0, R, 0, Rinv, 0, flag, 0, rel_tiny, s);
 }
 
 void launch_bdot(int64_t n, int nb, int nrhs, const double *V, int64_t bs, const double *W,

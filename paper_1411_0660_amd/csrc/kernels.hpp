@@ -41,8 +41,8 @@ void launch_gemm_nn_seg(int nseg, int64_t n, int k, int b, double alpha, const d
                         int64_t lda, int64_t segA, const double *Y, int ldy, int64_t segY,
                         double beta, double *C, int64_t ldc, int64_t segC, hipStream_t s);
 void launch_small_chol_batch(int count, int b, const double *G, int64_t segG, double *R,
-                             double *Rinv, int64_t segR, int *flag, int64_t segF, double rel_tiny,
-                             hipStream_t s);
+                             int64_t segR, double *Rinv, int64_t segRi, int *flag, int64_t segF,
+                             double rel_tiny, hipStream_t s);
 void launch_fill_start_seg(int nseg, int64_t n, int nvec, const uint64_t *seeds, double *v,
                            int64_t ld, hipStream_t s);
 void launch_coldot_seg(int nseg, int64_t n, int ncol, const double *A, int64_t lda,

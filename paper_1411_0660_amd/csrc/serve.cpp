@@ -42,6 +42,7 @@ size_t footprint_bytes(const Plan &p, int prec, int nev, int block) {
     // partial sums of the tall-skinny products (at most 512 row ranges)
     const size_t c = cols + 16;
     bytes += 8 * (2 * c * c) + 8 * (2 * c * c + c + 1) + 8 * 512 * c * 16;
+    bytes += 8 * (2 * c * c + 2 * c * 16) + 4 * 2 * c;     // device staging of the expansions
     bytes += (size_t)1 << 20;                               // small per-request buffers
     return bytes;
 }

@@ -87,7 +87,7 @@ void Context::trim() {
     clear_graphs();
     for (DevBuf *b : {&f32_.arena, &f32_.ipiv, &f32_.prow, &f32_.npert, &f64_.arena, &f64_.ipiv,
                       &f64_.prow, &f64_.npert, &d_vec, &d_yv, &d_upart, &d_xnew, &d_r, &d_d,
-                      &d_part, &d_V, &d_V2, &d_W, &d_small, &d_ritz, &d_tnpart, &d_gV, &d_gZ, &d_gpart,
+                      &d_part, &d_V, &d_V2, &d_W, &d_small, &d_ritz, &d_tnpart, &d_stage, &d_gV, &d_gZ, &d_gpart,
                       &d_gcoef, &d_psi, &d_psi2, &d_hpsi, &d_e, &d_cpart, &d_obs, &d_r_out,
                       &d_se})
         b->reset();
@@ -1310,16 +1310,15 @@ void Context::krylov_schur(int64_t n, int nseg, int b, int ncv, int nkeep, int n
     d_V.ensure(sizeof(double) * ldv * cols, &budget);
     d_V2.ensure(sizeof(double) * ldv * cols, &budget);
     d_W.ensure(sizeof(double) * ldv * b, &budget);
-    // per problem: coefficient / projection block, Gram matrix, R, R^-1
-    const int64_t SMS = (int64_t)cols * std::max(cols, b) + 3 * (int64_t)b * b;
-    d_small.ensure(sizeof(double) * SMS * nseg + sizeof(int) * 2 * nseg + 64, &budget);
+    // per problem: coefficient / projection block, Gram matrix, R^-1
+    const int64_t SMS = (int64_t)cols * std::max(cols, b) + 2 * (int64_t)b * b;
+    d_small.ensure(sizeof(double) * SMS * nseg + 64, &budget);
     int nparts = gemm_tn_parts(n);
     d_tnpart.ensure(sizeof(double) * (size_t)nparts * cols * b * nseg, &budget);
     double *V = d_V.ptr<double>(), *V2 = d_V2.ptr<double>(), *W = d_W.ptr<double>();
     double *sm = d_small.ptr<double>();
     double *tnp = d_tnpart.ptr<double>();
-    double *smG = sm + (int64_t)cols * std::max(cols, b), *smR = smG + b * b, *smRi = smR + b * b;
-    int *dflag = reinterpret_cast<int *>(sm + SMS * nseg);
+    double *smG = sm + (int64_t)cols * std::max(cols, b), *smRi = smG + b * b;
     std::vector<std::vector<double>> T(nseg, std::vector<double>((size_t)cols * cols, 0.0));
     auto Tat = [&](int sg, int i, int j) -> double & { return T[sg][(size_t)j * cols + i]; };
 
@@ -1381,40 +1380,46 @@ void Context::krylov_schur(int64_t n, int nseg, int b, int ncv, int nkeep, int n
     if (async) h_stage.ensure(sizeof(double) * stage_max + sizeof(int) * flag_max);
     double *hp = h_stage.ptr<double>();
     int *hflag = async ? reinterpret_cast<int *>(hp + stage_max) : nullptr;
+    // The same layout on the device: the kernels write the coefficient blocks,
+    // R factors and breakdown flags of every block expansion straight into it,
+    // and one copy per restart cycle brings the used part to page-locked
+    // memory (a copy per block would stall the stream on the copy engine).
+    if (async) d_stage.ensure(sizeof(double) * stage_max + sizeof(int) * flag_max, &budget);
+    double *ds = async ? d_stage.ptr<double>() : nullptr;
+    int *dsflag = async ? reinterpret_cast<int *>(ds + stage_max) : nullptr;
     size_t hoff = 0, foff = 0;
-    // copy one block of `count` doubles per problem from the device (stride SMS)
-    // to consecutive host blocks at hp + hoff
-    auto stage_copy = [&](const double *src, size_t count) {
-        if (count == 0) return hoff;
-        MBL_HIP(hipMemcpy2DAsync(hp + hoff, sizeof(double) * count, src, sizeof(double) * SMS,
-                                 sizeof(double) * count, nseg, hipMemcpyDeviceToHost, s));
-        size_t at = hoff;
-        hoff += count * nseg;
-        return at;
-    };
     auto stage_block = [&](int c0, double *blk, double *dst) {
         Stage stg{c0, 0, 0, 0, 0, 0};
+        const size_t hb = (size_t)c0 * b * nseg, rb = (size_t)b * b * nseg;
+        stg.h1 = hoff;
+        stg.h2 = hoff + hb;
+        stg.r1 = hoff + 2 * hb;
+        stg.r2 = hoff + 2 * hb + rb;
+        stg.fl = foff;
+        hoff += 2 * (hb + rb);
+        foff += 2 * (size_t)nseg;
+        const int64_t hs = (int64_t)c0 * b;            // per problem: c0 x b, ld c0
         for (int pass = 0; pass < 2; pass++) {             // CGS2 against V[:, 0:c0]
-            launch_gemm_tn_seg(nseg, n, c0, b, V, ldv, n, blk, ldv, n, sm, SMS, tnp, nparts, s);
-            launch_gemm_nn_seg(nseg, n, c0, b, -1.0, V, ldv, n, sm, c0, SMS, 1.0, blk, ldv, n, s);
-            (pass ? stg.h2 : stg.h1) = stage_copy(sm, (size_t)c0 * b);
+            double *h = ds + (pass ? stg.h2 : stg.h1);
+            launch_gemm_tn_seg(nseg, n, c0, b, V, ldv, n, blk, ldv, n, h, hs, tnp, nparts, s);
+            launch_gemm_nn_seg(nseg, n, c0, b, -1.0, V, ldv, n, h, c0, hs, 1.0, blk, ldv, n, s);
         }
         double *from = blk, *to = dst;                      // Cholesky QR, twice
         for (int pass = 0; pass < 2; pass++) {
             launch_gemm_tn_seg(nseg, n, b, b, from, ldv, n, from, ldv, n, smG, SMS, tnp, nparts, s);
-            launch_small_chol_batch(nseg, b, smG, SMS, smR, smRi, SMS, dflag + pass, 2, 1e-24, s);
-            (pass ? stg.r2 : stg.r1) = stage_copy(smR, (size_t)b * b);
+            launch_small_chol_batch(nseg, b, smG, SMS, ds + (pass ? stg.r2 : stg.r1), (int64_t)b * b,
+                                    smRi, SMS, dsflag + stg.fl + pass, 2, 1e-24, s);
             launch_gemm_nn_seg(nseg, n, b, b, 1.0, from, ldv, n, smRi, b, SMS, 0.0, to, ldv, n, s);
             std::swap(from, to);
         }
         launch_copy(ldv * b, from, dst, s);                 // from == blk after two passes
-        MBL_HIP(hipMemcpyAsync(hflag + foff, dflag, sizeof(int) * 2 * nseg, hipMemcpyDeviceToHost,
-                               s));
-        stg.fl = foff;
-        foff += 2 * nseg;
         stages.push_back(stg);
     };
     auto assemble_stages = [&]() {
+        if (hoff > 0)
+            MBL_HIP(hipMemcpyAsync(hp, ds, sizeof(double) * hoff, hipMemcpyDeviceToHost, s));
+        if (foff > 0)
+            MBL_HIP(hipMemcpyAsync(hflag, dsflag, sizeof(int) * foff, hipMemcpyDeviceToHost, s));
         MBL_HIP(hipStreamSynchronize(s));
         for (size_t k = 0; k < stages.size(); k++) {
             const Stage &stg = stages[k];

@@ -234,7 +234,8 @@ class Context {
     DevBuf d_on;                       // per problem of a batch: still refining
     DevBuf d_vec, d_yv, d_upart, d_xnew, d_r, d_d, d_part, d_V, d_V2, d_W, d_small, d_ritz, d_tnpart;
     DevBuf d_gV, d_gZ, d_gpart, d_gcoef;   // GMRES refinement: bases, partials, coefficients
-    PinnedBuf h_stage;                     // Krylov coefficients copied back asynchronously
+    DevBuf d_stage;                        // Krylov coefficients, R factors, flags per restart cycle
+    PinnedBuf h_stage;                     // their copy in page-locked memory
     // LU of the plan's matrix with diagonal diag - sigma; thresh: static-pivot
     // threshold of each problem of the plan
     template <class T> void factor_t(Plan &p, Factor<T> &f, const double *diag, double sigma,
