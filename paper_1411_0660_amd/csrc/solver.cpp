@@ -1243,33 +1243,37 @@ void Context::small_eig_batch(int count, int m, const std::vector<std::vector<do
                               std::vector<std::vector<double>> &Z, bool general) {
     hipStream_t s = stream;
     const size_t mm = (size_t)m * m;
-    d_ritz.ensure(sizeof(double) * ((2 * mm + m + 2) * (size_t)count + 8), &budget);
-    double *dA = d_ritz.ptr<double>(), *dV = dA + mm * count, *dw = dV + mm * count;
-    double *dtol = dw + (size_t)m * count;
-    int *dinfo = reinterpret_cast<int *>(dtol + count);
-    std::vector<double> tol(count);
+    // device and page-locked host layout: thresholds and matrices (copied in
+    // one transfer), then vectors, values and sweep counts (copied back in one)
+    const size_t in_n = (size_t)count * (1 + mm), out_n = (size_t)count * (mm + m);
+    const size_t bytes = sizeof(double) * (in_n + out_n) + sizeof(int) * (size_t)count;
+    d_ritz.ensure(bytes + 64, &budget);
+    h_ritz.ensure(bytes);
+    double *dtol = d_ritz.ptr<double>(), *dA = dtol + count, *dV = dA + mm * count;
+    double *dw = dV + mm * count;
+    int *dinfo = reinterpret_cast<int *>(dw + (size_t)m * count);
+    double *htol = h_ritz.ptr<double>(), *hA = htol + count, *hV = hA + mm * count;
+    double *hw = hV + mm * count;
+    int *hinfo = reinterpret_cast<int *>(hw + (size_t)m * count);
     for (int k = 0; k < count; k++) {
         double fro = 0.0;
         for (double x : A[k]) fro += x * x;
         // off-diagonal entries at or below 1e-17 ||A||_F are left in place:
         // their effect on the eigenvalues is below the rounding of ||A||
-        tol[k] = 1e-17 * std::sqrt(fro);
-        h2d(dA + mm * k, A[k].data(), mm, s);
+        htol[k] = 1e-17 * std::sqrt(fro);
+        std::copy(A[k].begin(), A[k].begin() + mm, hA + mm * k);
     }
-    h2d(dtol, tol.data(), (size_t)count, s);
+    h2d(dtol, htol, in_n, s);
     launch_jacobi_eig_batch(count, m, dA, dV, dw, dinfo, dtol, s, general);
-    std::vector<double> wu((size_t)m * count), Vu(mm * count);
-    std::vector<int> info(count);
-    d2h(wu.data(), dw, wu.size(), s);
-    d2h(Vu.data(), dV, Vu.size(), s);
-    d2h(info.data(), dinfo, (size_t)count, s);
+    MBL_HIP(hipMemcpyAsync(hV, dV, sizeof(double) * out_n + sizeof(int) * (size_t)count,
+                           hipMemcpyDeviceToHost, s));
     MBL_HIP(hipStreamSynchronize(s));
     w.assign(count, {});
     Z.assign(count, {});
     for (int k = 0; k < count; k++) {
-        if (info[k] < 0) throw Error(MBL_ENUMERIC, "Jacobi eigensolver: sweep limit reached");
-        if (debug_level() > 1) std::fprintf(stderr, "[mbl] jacobi m=%d sweeps=%d\n", m, info[k]);
-        const double *wk = wu.data() + (size_t)m * k, *vk = Vu.data() + mm * k;
+        if (hinfo[k] < 0) throw Error(MBL_ENUMERIC, "Jacobi eigensolver: sweep limit reached");
+        if (debug_level() > 1) std::fprintf(stderr, "[mbl] jacobi m=%d sweeps=%d\n", m, hinfo[k]);
+        const double *wk = hw + (size_t)m * k, *vk = hV + mm * k;
         std::vector<int> perm(m);
         std::iota(perm.begin(), perm.end(), 0);
         std::stable_sort(perm.begin(), perm.end(), [&](int a, int c) { return wk[a] < wk[c]; });
@@ -1534,6 +1538,22 @@ void Context::krylov_schur(int64_t n, int nseg, int b, int ncv, int nkeep, int n
         small_eig_batch((int)live.size(), m, Tm, wall, Z);
         std::vector<std::vector<double>> CYs(nseg);
         std::vector<int> to_finish;
+        // the restart coefficients of every problem (its kept Ritz vectors, or
+        // the identity for one that finished earlier: its unused columns stay
+        // orthonormal and bounded), gathered for one copy to the device
+        const size_t ycount = (size_t)m * nkeep;
+        h_coef.ensure(sizeof(double) * ycount * nseg);
+        double *hc = h_coef.ptr<double>();
+        if ((int)live.size() < nseg) {
+            std::vector<char> is_live(nseg, 0);
+            for (int sg : live) is_live[sg] = 1;
+            for (int sg = 0; sg < nseg; sg++) {
+                if (is_live[sg]) continue;
+                double *I = hc + ycount * sg;
+                std::fill(I, I + ycount, 0.0);
+                for (int k = 0; k < nkeep; k++) I[(size_t)k * m + k] = 1.0;
+            }
+        }
         for (size_t q = 0; q < live.size(); q++) {
             const int sg = live[q];
             KSOut &res = result[sg];
@@ -1576,9 +1596,11 @@ void Context::krylov_schur(int64_t n, int nseg, int b, int ncv, int nkeep, int n
             for (int k = 0; k < nwant; k++) nconv += conv(sg, res.theta[k], res.rho[k]) ? 1 : 0;
             res.nconv = nconv;
             res.restarts = restart;
-            h2d(sm + SMS * sg, Y.data(), Y.size(), s);
+            std::copy(Y.begin(), Y.end(), hc + ycount * sg);
             if (nconv == nwant || restart >= max_restarts) to_finish.push_back(sg);
         }
+        MBL_HIP(hipMemcpy2DAsync(sm, sizeof(double) * SMS, hc, sizeof(double) * ycount,
+                                 sizeof(double) * ycount, nseg, hipMemcpyHostToDevice, s));
         for (int sg : to_finish) {
             launch_gemm_nn_seg(1, n, m, nwant, 1.0, V + (int64_t)sg * n, ldv, 0, sm + SMS * sg, m, 0,
                                0.0, out + (int64_t)sg * n, ldv, 0, s);
@@ -1593,15 +1615,7 @@ void Context::krylov_schur(int64_t n, int nseg, int b, int ncv, int nkeep, int n
         }
         // thick restart: kept Ritz vectors, then the residual block.  Every
         // problem moves; one that finished earlier keeps the first nkeep
-        // columns of its basis (identity coefficients), so its unused columns
-        // stay orthonormal and bounded.
-        if ((int)live.size() < nseg) {
-            std::vector<double> I((size_t)m * nkeep, 0.0);
-            for (int k = 0; k < nkeep; k++) I[(size_t)k * m + k] = 1.0;
-            for (int sg = 0; sg < nseg; sg++)
-                if (std::find(live.begin(), live.end(), sg) == live.end())
-                    h2d(sm + SMS * sg, I.data(), I.size(), s);
-        }
+        // columns of its basis (identity coefficients, copied above).
         launch_gemm_nn_seg(nseg, n, m, nkeep, 1.0, V, ldv, n, sm, m, SMS, 0.0, V2, ldv, n, s);
         launch_copy(ldv * b, V + (int64_t)m * ldv, V2 + (int64_t)nkeep * ldv, s);
         std::swap(V, V2);

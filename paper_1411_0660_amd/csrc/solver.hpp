@@ -236,6 +236,8 @@ class Context {
     DevBuf d_gV, d_gZ, d_gpart, d_gcoef;   // GMRES refinement: bases, partials, coefficients
     DevBuf d_stage;                        // Krylov coefficients, R factors, flags per restart cycle
     PinnedBuf h_stage;                     // their copy in page-locked memory
+    PinnedBuf h_ritz;                      // Rayleigh-Ritz matrices and their eigenpairs
+    PinnedBuf h_coef;                      // restart coefficients of every problem
     // LU of the plan's matrix with diagonal diag - sigma; thresh: static-pivot
     // threshold of each problem of the plan
     template <class T> void factor_t(Plan &p, Factor<T> &f, const double *diag, double sigma,
