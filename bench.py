@@ -11,10 +11,10 @@ grid seed 0.., h in {2, 3, 4}, eps in {0.2, 0.5, 0.8} (first K of the 45
 solves); at L = 18 they are seeds 0..K-1 at h = 3, eps = 0.5.  nev = 50.
 ``value`` counts eigenpairs with ||H psi - E psi|| <= 1e-9 ||H|| per second of
 wall time.  The timed steps are independent solves; they run ``--slots`` at a
-time (default 2) through the library's serving layer (one solver context and
-HIP stream per slot, so the latency-bound kernels of one solve overlap the
-matrix-core and streaming kernels of the other; results are bitwise those of
-a lone solve).  ``sequential`` holds the same K steps run one at a time on one
+time (default 3: three L = 20 FP64 solves fit in HBM together) through the
+library's serving layer (one solver context and HIP stream per slot, so the
+latency-bound kernels of one solve overlap the matrix-core and streaming
+kernels of the others; results are bitwise those of a lone solve).  ``sequential`` holds the same K steps run one at a time on one
 context, with the single-solve latency, the roofline kernel measurement and the
 phase times.
 
@@ -422,7 +422,7 @@ def refine_child(spec):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--L", type=int, default=20)
     ap.add_argument("--l18-steps", type=int, default=10)
@@ -435,7 +435,7 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--sweep-realizations", type=int, default=2)
     ap.add_argument("--l19-steps", type=int, default=5)
-    ap.add_argument("--slots", type=int, default=2,
+    ap.add_argument("--slots", type=int, default=3,
                     help="timed steps run this many at a time (1: one at a time only)")
     ap.add_argument("--l18-slots", type=int, default=4)
     ap.add_argument("--refine-diagnostics", action="store_true",
