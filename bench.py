@@ -137,6 +137,8 @@ def run_served(mbl, reqs, prec, rate, slots, nev=20, max_batch=16, vectors_for=(
             while i >= len(tickets):
                 time.sleep(0.0005)
             outs[i] = ctx.mbl_wait(tickets[i])
+            if len(reqs) >= 2048 and (i + 1) % 1024 == 0:
+                log(f"  {i + 1} of {len(reqs)} requests done")
         done_evt.set()
 
     th = threading.Thread(target=collect)

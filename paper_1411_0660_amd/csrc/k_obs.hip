@@ -485,19 +485,36 @@ void ObsWork::prepare(int L_, const uint32_t *basis, int64_t dim_, int nvec_max,
     if (L == L_ && dim == dim_ && nvec_max <= nvmax) return;
     const SeLayout lay = se_layout(L_);
     MBL_REQUIRE(lay.dim == dim_, MBL_EINVAL, "observables: sector dimension mismatch");
+    // unprepared until every buffer is in place: DevBuf::alloc frees before it
+    // allocates, so an allocation refused part way leaves empty buffers, and a
+    // size recorded before it would let the next call skip straight to kernels
+    // on them
+    L = -1;
+    dim = 0;
+    nvmax = 0;
+    gkl_stride_ = 0;
+    d_dst.alloc(sizeof(int32_t) * dim_, bud);
+    hipLaunchKernelGGL(k_block_index, dim3(cdiv(dim_, 256)), dim3(256), 0, s, lay, basis,
+                       d_dst.ptr<int32_t>());
+    MBL_CHECK_LAUNCH();
+    d_M.alloc(sizeof(double) * dim_ * nvec_max, bud);
+    d_gkl.alloc(sizeof(double) * lay.gstride * nvec_max, bud);
+    d_part.alloc(sizeof(double) * (size_t)std::max<int64_t>((int64_t)(lay.la + 1) * nvec_max,
+                                                            (int64_t)OBS_PARTS * NQ * nvec_max),
+                 bud);
+    d_out.alloc(sizeof(double) * NQ * nvec_max + sizeof(double) * 4 * nvec_max, bud);
     L = L_;
     dim = dim_;
     nvmax = nvec_max;
     gkl_stride_ = lay.gstride;
-    d_dst.alloc(sizeof(int32_t) * dim, bud);
-    hipLaunchKernelGGL(k_block_index, dim3(cdiv(dim, 256)), dim3(256), 0, s, lay, basis,
-                       d_dst.ptr<int32_t>());
-    MBL_CHECK_LAUNCH();
-    d_M.alloc(sizeof(double) * dim * nvmax, bud);
-    d_gkl.alloc(sizeof(double) * gkl_stride_ * nvmax, bud);
-    d_part.alloc(sizeof(double) * (size_t)std::max<int64_t>((int64_t)(lay.la + 1) * nvmax,
-                                                            (int64_t)OBS_PARTS * NQ * nvmax), bud);
-    d_out.alloc(sizeof(double) * NQ * nvmax + sizeof(double) * 4 * nvmax, bud);
+}
+
+void ObsWork::release() {
+    L = -1;
+    dim = 0;
+    nvmax = 0;
+    gkl_stride_ = 0;
+    for (DevBuf *b : {&d_dst, &d_M, &d_gkl, &d_part, &d_out}) b->reset();
 }
 
 void ObsWork::entanglement(const double *psi, int64_t ldpsi, int nvec, const double *norms2,

@@ -27,6 +27,8 @@ class ObsWork {
                       double *se_dev, hipStream_t s);
     void gap_ratios(int nev, const double *E_dev, double *r_dev, hipStream_t s);
     const double *norms_dev() const { return d_out.ptr<double>() + OBS_NQ * nvmax; }
+    // frees every buffer; the next prepare allocates again
+    void release();
 
   private:
     int L = -1, nvmax = 0;

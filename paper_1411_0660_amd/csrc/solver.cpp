@@ -96,6 +96,7 @@ void Context::trim() {
                       &fb32_.ipiv, &fb32_.prow, &fb32_.npert, &fb32_.uinv, &fb32_.thr, &d_on,
                       &d_bdiag, &d_bshift})
         b->reset();
+    obs.release();
     fb64_.valid = false;
     fb64_.L = -1;
     fb32_.valid = false;

@@ -123,3 +123,38 @@ def test_allocation_failure_in_fp32_path(ref):
         assert ei.value.code == mbl.MBL_ENOMEM
         g = c.mbl_solve(L, h, seed, eps, nev, prec=mbl.MBL_FP32_IR64)
         assert np.abs(g["evals"] - o["evals"]).max() <= EIG_TOL * o["hnorm"]
+
+
+def test_observables_workspace_after_refused_allocation():
+    """The observables workspace grows when a call brings more vectors than it
+    holds.  A budget that admits the vectors but not the grown workspace
+    refuses the growth part way; the workspace is then unprepared, so the next
+    call with the original vector count allocates again and returns the same
+    bits as before the refusal."""
+    L = 12
+    b = oracle.basis(L)
+    n = b.size
+    rng = np.random.default_rng(3)
+    Z = rng.standard_normal((n, 5))
+    Z /= np.linalg.norm(Z, axis=0)
+    E = np.sort(rng.standard_normal(5))
+    big = 4096
+    S = 8 * n * big                         # bytes of the big vector block, and of the
+    budget = S + S // 2 + (4 << 20)         # workspace's first buffer that grows with it
+    say("hook observables workspace, budget", budget)
+    with mbl.Context(0, hbm_budget=budget) as c:
+        r0, s10, se0 = c.mbl_observables(L, E, Z)
+        Zb = np.asfortranarray(np.tile(Z, (1, big // 5 + 1))[:, :big])
+        Eb = np.sort(rng.standard_normal(big))
+        with pytest.raises(mbl.MblError) as ei:
+            c.mbl_observables(L, Eb, Zb)
+        assert ei.value.code == mbl.MBL_ENOMEM
+        # refused after the vectors were resident: inside the workspace growth
+        msg = str(ei.value)
+        assert f"need {S} B with " in msg
+        in_use = int(msg.split(f"need {S} B with ")[1].split(" ")[0])
+        assert in_use >= S
+        r1, s11, se1 = c.mbl_observables(L, E, Z)
+        assert np.array_equal(r0, r1) and np.array_equal(s10, s11) and np.array_equal(se0, se1)
+        for j in range(5):
+            assert abs(se1[j] - oracle.entanglement_entropy(L, Z[:, j], b)) <= 1e-10
