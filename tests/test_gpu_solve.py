@@ -1,7 +1,7 @@
 """GPU parity of the whole shift-invert path (mbl_solve) against the oracle:
 eigenvalues within 1e-10 ||H||, residuals <= 1e-9 ||H||, r / S_1 / S_E within
-1e-8 where the levels are separated (the readings of the comparison rules are
-listed in the design doc), at sizes the oracle finishes in seconds."""
+1e-8 where a level is at least 1e-6 ||H|| from its neighbours (closer levels
+are compared as subspaces), at sizes the oracle finishes in seconds."""
 import math
 import sys
 
