@@ -110,6 +110,7 @@ int merge_tri_items(int p);
 constexpr int TRSM_U_COLS = 256;   // columns per work item of the U12 solve
 constexpr int TRSM_L_ROWS = 64;    // rows per work item of the L21 solve
 constexpr int SCHUR_TILE = 128;    // square tile of the Schur update
+constexpr int SCHUR_THREADS = 512; // eight waves per Schur tile, each a 64 x 32 strip
 int64_t schur_tiles(int64_t rest);
 
 // L~ = L[., t] Linv_tt below each diagonal block, U~ = U[., t] Uinv_tt above it

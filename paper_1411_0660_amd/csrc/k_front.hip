@@ -555,10 +555,13 @@ __global__ __launch_bounds__(256) void k_trsm(T *arena, const FrontDesc *__restr
 }
 
 // trailing update F[k1:m, k1:m] -= F[k1:m, k0:k1] F[k0:k1, k1:m] on the matrix
-// cores: 128 x 128 output tile per workgroup, each wave a 64 x 64 quarter as
-// 4 x 4 MFMA 16x16x4 blocks (FP64 or FP32 by T), the A and B panels staged in
-// LDS k-major, and the read-modify-write of C routed through LDS so that it
-// is coalesced down the columns.
+// cores: 128 x 128 output tile per workgroup of eight waves, each wave a
+// 64 x 32 strip as 4 x 2 MFMA 16x16x4 blocks (FP64 or FP32 by T), the A and B
+// panels staged in LDS k-major.  Eight waves with 64 accumulators each leave
+// four waves per SIMD (two workgroups per CU): one wave issues the FP64
+// instruction at most every other slot of its SIMD's matrix core, so the
+// core stays busy while any two of the four have operands ready, which two
+// waves of 128 accumulators (a 64 x 64 quarter each) could not ensure.
 template <class T> struct MfmaAcc;
 // Operand layout of both 16x16x4 instructions: lane l holds A[l%16][l/16] and
 // B[l/16][l%16].  Result element v of lane l is row_of(l/16, v), column l%16
@@ -581,11 +584,11 @@ template <> struct MfmaAcc<float> {
 
 constexpr int ST = SCHUR_TILE;       // 128
 // K columns staged per pass (FP64 half as many, to keep the prefetch, the two
-// operand sets and the 64 accumulators of a lane inside the register budget of
-// two waves per SIMD)
+// operand sets and the 32 accumulator elements of a lane inside the register
+// budget of four waves per SIMD)
 template <class T> struct SchurCfg {
     static constexpr int KC = sizeof(T) == 8 ? 16 : 32;
-    static constexpr int PF = ST * KC / 256;   // elements of A (and of B) per thread
+    static constexpr int PF = ST * KC / SCHUR_THREADS;   // elements of A (and of B) per thread
     // LDS layouts (64 banks of 4 bytes).  A as [k][row], rows padded to 144
     // elements, so the four k-rows one operand read touches sit half the banks
     // apart (FP64) or a quarter apart (FP32).  B as [column][k], as it lies in
@@ -621,7 +624,7 @@ template <class T> struct SchurCfg {
 // The next K chunk is fetched from HBM into registers while the current one
 // feeds the matrix cores from LDS.
 template <class T, int BIG>
-__global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__restrict__ fd,
+__global__ __launch_bounds__(SCHUR_THREADS, 4) void k_schur(T *arena, const FrontDesc *__restrict__ fd,
                                                   TaskList tl, int t) {
     typedef typename MfmaAcc<T>::v4 v4;
     constexpr int KC = SchurCfg<T>::KC, PF = SchurCfg<T>::PF;
@@ -660,7 +663,7 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
     int r0 = rlo + ti * ST, c0 = clo + tj * ST;
     T *F = arena + d.off;
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int wr = (w & 1) * 64, wc = (w >> 1) * 64;
+    int wr = (w & 1) * 64, wc = (w >> 1) * 32;
     int li = lane & 15, lk = lane >> 4;
     // global -> register prefetch of one K chunk: A rows i = e % ST (coalesced
     // down the column), B k = e % KC (contiguous k of one column).  Each load
@@ -676,12 +679,12 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
         const char *Bb = reinterpret_cast<const char *>(F + (kc0 + kc) + (int64_t)c0 * m);
 #pragma unroll
         for (int q = 0; q < PF; q++) {
-            const int kk = tid / ST + q * (256 / ST), j = tid / KC + q * (256 / KC);
+            const int kk = tid / ST + q * (SCHUR_THREADS / ST), j = tid / KC + q * (SCHUR_THREADS / KC);
             pa[q] = (rok && kk < kn)
-                        ? *reinterpret_cast<const T *>(Ab + (int64_t)q * (256 / ST) * m * sizeof(T) + aoff)
+                        ? *reinterpret_cast<const T *>(Ab + (int64_t)q * (SCHUR_THREADS / ST) * m * sizeof(T) + aoff)
                         : T(0);
             pb[q] = (c0 + j < chi && tid % KC < kn)
-                        ? *reinterpret_cast<const T *>(Bb + (int64_t)q * (256 / KC) * m * sizeof(T) + boff)
+                        ? *reinterpret_cast<const T *>(Bb + (int64_t)q * (SCHUR_THREADS / KC) * m * sizeof(T) + boff)
                         : T(0);
         }
     };
@@ -689,7 +692,7 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
         T *As = smem + buf * STAGE, *Bs = As + SchurCfg<T>::ABUF;
 #pragma unroll
         for (int q = 0; q < PF; q++) {
-            int e = tid + q * 256;
+            int e = tid + q * SCHUR_THREADS;
             As[(e / ST) * SPA + (e % ST)] = pa[q];
             Bs[SchurCfg<T>::bpos(e / KC, e % KC)] = pb[q];
         }
@@ -701,16 +704,16 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
     auto issue = [&](int kc, int buf) {
         T *As = smem + buf * STAGE, *Bs = As + SchurCfg<T>::ABUF;
 #pragma unroll
-        for (int i = 0; i < KC / 4; i++) {
-            const int k = w + 4 * i;
+        for (int i = 0; i < KC / 8; i++) {
+            const int k = w + 8 * i;
             const T *src = F + r0 + 2 * lane + (int64_t)(kc0 + kc + k) * m;
             __builtin_amdgcn_global_load_lds((const void *)src,
                                              (__attribute__((address_space(3))) void *)(As + k * SPA),
                                              16, 0, 0);
         }
 #pragma unroll
-        for (int i = 0; i < ST / 32; i++) {
-            const int ib = w + 4 * i, c = ib * 8 + (lane >> 3), slot = lane & 7;
+        for (int i = 0; i < ST / 64; i++) {
+            const int ib = w + 8 * i, c = ib * 8 + (lane >> 3), slot = lane & 7;
             const int kp = slot ^ ((c >> 1) & 7);
             const T *src = F + (kc0 + kc + 2 * kp) + (int64_t)(c0 + c) * m;
             __builtin_amdgcn_global_load_lds((const void *)src,
@@ -720,23 +723,23 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
     };
     // operands of one 4-deep k-step: A rows wr + 16 a + li (negated: the tile
     // computes C - A B), B columns wc + 16 b + li, k = 4 ks + lk
-    auto operands = [&](int buf, int ks, T (&av)[4], T (&bv)[4]) {
+    auto operands = [&](int buf, int ks, T (&av)[4], T (&bv)[2]) {
         const T *As = smem + buf * STAGE, *Bs = As + SchurCfg<T>::ABUF;
         const int kk = ks * 4 + lk;
 #pragma unroll
         for (int a = 0; a < 4; a++) av[a] = -As[kk * SPA + wr + a * 16 + li];
 #pragma unroll
-        for (int b = 0; b < 4; b++) bv[b] = Bs[SchurCfg<T>::bpos(wc + b * 16 + li, kk)];
+        for (int b = 0; b < 2; b++) bv[b] = Bs[SchurCfg<T>::bpos(wc + b * 16 + li, kk)];
     };
     // The accumulators start from the C tile itself and A enters negated, so
     // the matrix cores leave C - A B in registers: the tile is read once at
     // the start (while the first chunk is in flight) and only written at the
     // end.  Lane (li, lk) holds rows wr + 16 a + row_of(lk, v) and columns
     // wc + 16 b + li.
-    v4 acc[4][4];
+    v4 acc[4][2];
     auto load_c = [&]() {
 #pragma unroll
-        for (int b = 0; b < 4; b++) {
+        for (int b = 0; b < 2; b++) {
             const int c = c0 + wc + b * 16 + li;
             const T *Fc = F + (int64_t)min(c, chi - 1) * m;
 #pragma unroll
@@ -748,16 +751,16 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
                 }
         }
     };
-    auto mma = [&](const T (&av)[4], const T (&bv)[4]) {
+    auto mma = [&](const T (&av)[4], const T (&bv)[2]) {
 #pragma unroll
         for (int a = 0; a < 4; a++)
 #pragma unroll
-            for (int b = 0; b < 4; b++) acc[a][b] = MfmaAcc<T>::mma(av[a], bv[b], acc[a][b]);
+            for (int b = 0; b < 2; b++) acc[a][b] = MfmaAcc<T>::mma(av[a], bv[b], acc[a][b]);
     };
     // all KC / 4 k-steps of the chunk in `buf` (a partial chunk's missing k are
     // zeros), the operands of k-step ks + 1 read while k-step ks runs
     auto steps = [&](int buf) {
-        T av0[4], bv0[4], av1[4], bv1[4];
+        T av0[4], bv0[2], av1[4], bv1[2];
         operands(buf, 0, av0, bv0);
 #pragma unroll
         for (int ks = 0; ks < KC / 4; ks += 2) {
@@ -796,7 +799,7 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
         // flight since the previous one) is stashed into the idle stage and
         // the one after it fetched, while the reads land.
         for (int kc = 0, buf = 0; kc < kd; kc += KC, buf ^= 1) {
-            T av0[4], bv0[4], av1[4], bv1[4];
+            T av0[4], bv0[2], av1[4], bv1[2];
             operands(buf, 0, av0, bv0);
             if (kc + KC < kd) {
                 stash(buf ^ 1);
@@ -813,7 +816,7 @@ __global__ __launch_bounds__(256, 2) void k_schur(T *arena, const FrontDesc *__r
         }
     }
 #pragma unroll
-    for (int b = 0; b < 4; b++) {
+    for (int b = 0; b < 2; b++) {
         const int c = c0 + wc + b * 16 + li;
         if (c >= chi) continue;
         T *Fc = F + (int64_t)c * m;
@@ -1082,7 +1085,7 @@ void launch_xform(T *arena, const FrontDesc *fd, TaskList tl, hipStream_t s) {
 template <class T>
 void launch_schur(T *arena, const FrontDesc *fd, TaskList tl, int t, int kind, hipStream_t s) {
     if (tl.total == 0) return;
-    const dim3 g((unsigned)tl.total), b(256);
+    const dim3 g((unsigned)tl.total), b(SCHUR_THREADS);
     switch (kind) {
         case 0: k_schur<T, 0><<<g, b, 0, s>>>(arena, fd, tl, t); break;
         case 1: k_schur<T, 1><<<g, b, 0, s>>>(arena, fd, tl, t); break;
