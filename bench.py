@@ -43,8 +43,8 @@ HBM_PEAK_GBS = 8000.0
 # counters (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain copy
 # of known size); valid only for the kernel source it was measured on
 SCHUR_SRC = os.path.join(HERE, "paper_1411_0660_amd", "csrc", "k_front.hip")
-SCHUR_TRAFFIC = {"sha256": "ede0f1f2f41d2d9cad8c0ac0a8a9dea22d45e3c22d89728905e183cb227fe4f0",
-                 "bytes_per_launch": 2.508910e+10}
+SCHUR_TRAFFIC = {"sha256": "a780c77d1e557877f3ab767690b0eb21947fd7b1823ce7559f58e526d01397e4",
+                 "bytes_per_launch": 2.582315e+10}
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
