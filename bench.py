@@ -41,9 +41,10 @@ METRIC = "converged interior eigenpairs/sec (resid≤1e-9) at L=18/20; p50/p99 s
 HBM_PEAK_GBS = 8000.0
 # HBM traffic of the outer Schur update per launch at L = 20 from rocprofv3 PMC
 # counters (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain copy
-# of known size); valid only for the kernel source it was measured on
+# of known size); valid only for the kernel source and the ordering code it was
+# measured with
 SCHUR_SRC = os.path.join(HERE, "paper_1411_0660_amd", "csrc", "k_front.hip")
-SCHUR_TRAFFIC = {"sha256": "a780c77d1e557877f3ab767690b0eb21947fd7b1823ce7559f58e526d01397e4",
+SCHUR_TRAFFIC = {"sha256": "95dd1c064e5365e231ee8fba44a6e2ee71a8f76f0b0852b95badeb88ff0a3130",
                  "bytes_per_launch": 2.582315e+10}
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
@@ -64,14 +65,22 @@ def percentile(xs, q):
 
 
 def schur_source_sha():
-    """sha256 of the Schur kernel's source: from its MFMA helpers to the end of
-    k_schur (the counters stay valid while this text is unchanged)."""
+    """sha256 of what the counted traffic depends on: the Schur kernel's source
+    (from its MFMA helpers to the end of k_schur) and the ordering that sets
+    the fronts it runs on (symbolic.cpp and Context::ensure_symbolic); the
+    counters stay valid while these texts are unchanged."""
     import hashlib
     with open(SCHUR_SRC) as fh:
         src = fh.read()
     a = src.index("template <class T> struct MfmaAcc;")
     b = src.index("\n}\n", src.index("void k_schur(", a)) + 3
-    return hashlib.sha256(src[a:b].encode()).hexdigest()
+    with open(os.path.join(HERE, "paper_1411_0660_amd", "csrc", "symbolic.cpp")) as fh:
+        sym = fh.read()
+    with open(os.path.join(HERE, "paper_1411_0660_amd", "csrc", "solver.cpp")) as fh:
+        sol = fh.read()
+    c = sol.index("void Context::ensure_symbolic(")
+    d = sol.index("\n}\n", c) + 3
+    return hashlib.sha256((src[a:b] + sym + sol[c:d]).encode()).hexdigest()
 
 
 def schur_traffic():
