@@ -44,7 +44,7 @@ HBM_PEAK_GBS = 8000.0
 # of known size); valid only for the kernel source and the ordering code it was
 # measured with
 SCHUR_SRC = os.path.join(HERE, "paper_1411_0660_amd", "csrc", "k_front.hip")
-SCHUR_TRAFFIC = {"sha256": "95dd1c064e5365e231ee8fba44a6e2ee71a8f76f0b0852b95badeb88ff0a3130",
+SCHUR_TRAFFIC = {"sha256": "9e129c4945da53ecb1e2ecd6dad82173f9f2092bbdb125fbab434d5560e53463",
                  "bytes_per_launch": 2.582315e+10}
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3

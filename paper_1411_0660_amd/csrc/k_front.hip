@@ -606,6 +606,12 @@ template <class T> struct SchurCfg {
     }
 };
 
+static_assert(SCHUR_THREADS == 512 && ST == 128,
+              "eight waves, as two rows of 64 and four columns of 32, cover the 128 x 128 tile");
+static_assert((ST * SchurCfg<double>::KC) % SCHUR_THREADS == 0 &&
+                  (ST * SchurCfg<float>::KC) % SCHUR_THREADS == 0 && SchurCfg<double>::KC % 8 == 0,
+              "a K chunk splits evenly over the threads, and its k-rows over the eight waves");
+
 // BIG = 0: update after panel t inside its outer SB block, K = the panel's kb
 //          columns: the first tiles cover the rows below the panel and the
 //          columns up to the end of the outer block, the rest the remaining
