@@ -82,6 +82,26 @@ def test_odd_solve_matches_oracle(ctx, L, h, seed, eps, nev):
     assert np.abs(g["r"] - o["r"]).max() <= 1e-8
 
 
+def test_odd_solve_through_a_front_without_pivots(ctx):
+    """L = 17 (S^z = 1/2, dim 24310): one front of its tree has no pivots (its
+    subgraph was split with an empty separator), so the factorization, the
+    solves and the extend-add pass its children's updates straight through it.
+    Certified by the oracle's residuals and Rayleigh quotients of every pair."""
+    L, h, seed, eps, nev = 17, 3.0, 0, 0.5, 20
+    say("odd solve through a front without pivots, L", L)
+    ft = ctx.mbl_front_tree(L)
+    assert (ft["npiv"] == 0).any()
+    g = ctx.mbl_solve(L, h, seed, eps, nev, vectors=True)
+    Z, E, hn = g["evecs"], g["evals"], g["hnorm"]
+    assert g["nconv"] == nev and g["max_resid"] <= 1e-9
+    f = oracle.fields(L, h, seed)
+    b = oracle.basis(L)
+    for k in range(nev):
+        assert oracle.residual(L, 1.0, f, Z[:, k], E[k], b) <= 1e-9 * hn, k
+        assert abs(oracle.rayleigh(L, 1.0, f, Z[:, k], b) - E[k]) <= 1e-10 * hn, k
+    assert np.abs(Z.T @ Z - np.eye(nev)).max() <= 1e-12
+
+
 def test_odd_tiny_sector_full_space(ctx):
     # L = 3: dim 3, every eigenpair; r of the three levels
     g = ctx.mbl_solve(3, 1.5, 5, 0.5, 3, extra=True)
